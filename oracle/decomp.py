@@ -1,0 +1,187 @@
+"""Randomized t-product decompositions in float64 (oracle; test
+infrastructure only).
+
+* rtprod      Algorithm 2 given the picked slices and their scales.
+* tproject    Algorithm 3, t-CX (Algorithm 4) given picked lateral slices.
+* tpinv_r     per-Fourier-slice rank-r truncated pseudo-inverse.
+* tcur        Algorithm 5 given picked lateral and horizontal slices.
+* tsvt        singular value thresholding of every Fourier slice, the
+              closed-form L-update of Algorithm 7 with the tensor nuclear norm.
+* admm_complete  Algorithm 7 adapted to the completion problem (eq. tlow6).
+
+Readings where the paper is silent or garbled:
+* S and D carry their entries in the first frontal slice only and are zero
+  elsewhere, so in the Fourier domain every slice uses the same selection
+  and the same diagonal scaling (Algorithms 4-5 state "defined in the
+  Fourier domain" and set slices 2..n3 to zero; taken literally that would
+  zero every Fourier slice but the first).
+* Algorithm 5 takes a rank parameter r but never uses it; here the core is
+  the rank-r truncated pseudo-inverse of every Fourier slice of D S^T C,
+  additionally dropping singular values at or below max(l, c) eps sigma_1.
+* The completion variant of Algorithm 7 ("with a small modification") keeps
+  X = L + E exactly with E supported on the unobserved entries; the L-update
+  is the tensor-nuclear-norm prox, i.e. a per-Fourier-slice threshold of
+  exactly 1/mu (both the nuclear norm and the squared Frobenius norm carry
+  the same 1/n3 factor in the Fourier domain).
+
+Pins (tests/test_oracle_decomp.py): c = n2 with uniform weights gives the
+exact product; unbiasedness and the exact second moment of the estimator by
+Monte Carlo; exact-rank inputs are reproduced exactly by t-CX and t-CUR;
+t-CX is the least-squares optimum (eq. ell2reg); n3 = 1 reduces to matrix
+CX/CUR; circ(tsvt(M, tau)) equals the matrix SVT of circ(M) with the same
+tau; tau = 0 is the identity; prox optimality under random perturbations;
+ADMM residuals shrink.
+"""
+
+import numpy as np
+
+from . import tensor as T
+
+
+def _is_real_slice(k, n3):
+    return k == 0 or (n3 % 2 == 0 and k == n3 // 2)
+
+
+def _mirror(Zh, K, n3):
+    for k in range(K, n3):
+        Zh[:, :, k] = Zh[:, :, n3 - k].conj()
+    return Zh
+
+
+def rtprod(A, B, idx, scale):
+    """Algorithm 2 given its picks: C = A*S*D (picked lateral slices of A,
+    each times its scale), R = D*S^T*B (the matching horizontal slices of B)
+    and Z = C*R, the latter by the t-product definition."""
+    idx = np.asarray(idx, dtype=np.int64)
+    scale = np.asarray(scale, dtype=np.float64)
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    if idx.size == 0:
+        return np.zeros((A.shape[0], B.shape[1], A.shape[2]))
+    C = A[:, idx, :] * scale[None, :, None]
+    R = B[idx, :, :] * scale[:, None, None]
+    return T.tprod_bcirc(C, R)
+
+
+def pinv_r(W, r=None):
+    """Rank-r truncated Moore-Penrose pseudo-inverse of one matrix."""
+    u, s, vh = np.linalg.svd(W, full_matrices=False)
+    if s.size == 0:
+        return np.zeros((W.shape[1], W.shape[0]), dtype=W.dtype)
+    keep = s > max(W.shape) * np.finfo(float).eps * s[0]
+    if r is not None:
+        keep[int(r):] = False
+    inv = np.zeros_like(s)
+    inv[keep] = 1.0 / s[keep]
+    return (vh.conj().T * inv[None, :]) @ u.conj().T
+
+
+def tproject(X, C):
+    """Algorithm 3: Zhat_k = Chat_k Chat_k^+ Xhat_k for every Fourier slice."""
+    n3 = X.shape[2]
+    K = T.half_spectrum_count(n3)
+    Xh, Ch = T.fft3(X), T.fft3(C)
+    Zh = np.zeros(Xh.shape, dtype=complex)
+    for k in range(K):
+        Ck = Ch[:, :, k].real if _is_real_slice(k, n3) else Ch[:, :, k]
+        Xk = Xh[:, :, k].real if _is_real_slice(k, n3) else Xh[:, :, k]
+        Zh[:, :, k] = Ck @ (np.linalg.pinv(Ck) @ Xk)
+    return T._real_part_checked(T.ifft3(_mirror(Zh, K, n3)))
+
+
+def tcx(A, idx, scale):
+    """Algorithm 4 given its picks: Chat_k = Ahat_k S D, Zhat_k = Chat_k
+    Chat_k^+ Ahat_k."""
+    idx = np.asarray(idx, dtype=np.int64)
+    C = np.asarray(A, dtype=np.float64)[:, idx, :] * np.asarray(scale)[None, :, None]
+    return tproject(A, C)
+
+
+def tcur(A, cidx, cscale, ridx, rscale, r=None):
+    """Algorithm 5 given its picks. Returns (Z, core) where core[k] is the
+    (c x l) matrix Uhat_k for the non-redundant Fourier slices k."""
+    A = np.asarray(A, dtype=np.float64)
+    n1, n2, n3 = A.shape
+    cidx = np.asarray(cidx, dtype=np.int64)
+    ridx = np.asarray(ridx, dtype=np.int64)
+    cscale = np.asarray(cscale, dtype=np.float64)
+    rscale = np.asarray(rscale, dtype=np.float64)
+    K = T.half_spectrum_count(n3)
+    Ah = T.fft3(A)
+    Zh = np.zeros((n1, n2, n3), dtype=complex)
+    core = np.zeros((K, cidx.size, ridx.size), dtype=complex)
+    for k in range(K):
+        Ak = Ah[:, :, k].real if _is_real_slice(k, n3) else Ah[:, :, k]
+        Ck = Ak[:, cidx] * cscale[None, :]          # Chat_k = Ahat_k S D
+        Rk = rscale[:, None] * Ak[ridx, :]          # Rhat_k = D S^T Ahat_k
+        Wk = rscale[:, None] * Ck[ridx, :]          # D S^T Chat_k
+        Uk = pinv_r(Wk, r)
+        core[k] = Uk
+        Zh[:, :, k] = Ck @ Uk @ Rk
+    Z = T._real_part_checked(T.ifft3(_mirror(Zh, K, n3)))
+    return Z, core
+
+
+def svt_matrix(M, tau):
+    """Matrix singular value thresholding U max(S - tau, 0) V^H and the
+    number of singular values above tau."""
+    u, s, vh = np.linalg.svd(M, full_matrices=False)
+    st = np.maximum(s - tau, 0.0)
+    return (u * st[None, :]) @ vh, int(np.sum(s > tau))
+
+
+def tsvt(M, tau):
+    """Per-Fourier-slice SVT with threshold tau. Returns (L, ranks) with
+    ranks[k] the number of singular values above tau in Fourier slice k for
+    the non-redundant slices."""
+    M = np.asarray(M, dtype=np.float64)
+    n3 = M.shape[2]
+    K = T.half_spectrum_count(n3)
+    Mh = T.fft3(M)
+    Lh = np.zeros(Mh.shape, dtype=complex)
+    ranks = np.zeros(K, dtype=np.int64)
+    for k in range(K):
+        Mk = Mh[:, :, k].real if _is_real_slice(k, n3) else Mh[:, :, k]
+        Lh[:, :, k], ranks[k] = svt_matrix(Mk, tau)
+    L = T._real_part_checked(T.ifft3(_mirror(Lh, K, n3)))
+    return L, ranks
+
+
+def admm_complete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None):
+    """Algorithm 7 for the completion problem: minimise ||L||_TNN subject to
+    X = L + E with E zero on the observed entries.
+
+    X holds the observed values and zeros elsewhere; mask is 1 where
+    observed. Starting from L = E = Y = 0 each iteration does
+        L <- tsvt(X - E - Y/mu, 1/mu)
+        E <- P_unobserved(X - L - Y/mu)
+        Y <- Y + mu (L + E - X)
+        mu <- min(rho mu, mu_max)
+    Returns (L, E, Y, history) where history holds, per iteration, the three
+    infinity-norm stop quantities of Algorithm 7, the per-slice ranks, and
+    the relative error against L_true when given.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    W = np.asarray(mask, dtype=np.float64)
+    L = np.zeros_like(X)
+    E = np.zeros_like(X)
+    Y = np.zeros_like(X)
+    mu = float(mu0)
+    hist = []
+    for _ in range(int(iters)):
+        Lprev, Eprev = L, E
+        L, ranks = tsvt(X - E - Y / mu, 1.0 / mu)
+        E = (1.0 - W) * (X - L - Y / mu)
+        Y = Y + mu * (L + E - X)
+        rec = {
+            "dL": float(np.max(np.abs(L - Lprev))),
+            "dE": float(np.max(np.abs(E - Eprev))),
+            "res": float(np.max(np.abs(L + E - X))),
+            "ranks": ranks,
+            "mu": mu,
+        }
+        if L_true is not None:
+            rec["rse"] = T.rel_fro(L, L_true)
+        hist.append(rec)
+        mu = min(rho * mu, mu_max)
+    return L, E, Y, hist

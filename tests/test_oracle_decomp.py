@@ -1,0 +1,194 @@
+"""Pins of the oracle's randomized decompositions."""
+import numpy as np
+import pytest
+
+from oracle import decomp as D
+from oracle import sampling as S
+from oracle import tensor as T
+
+rs = np.random.default_rng(4242)
+
+
+def _lowrank(n1, n2, n3, r, seed=0):
+    g = np.random.default_rng(seed)
+    return T.tprod_bcirc(g.standard_normal((n1, r, n3)), g.standard_normal((r, n2, n3)))
+
+
+def test_rtprod_full_budget_is_exact():
+    A = rs.standard_normal((6, 9, 5))
+    B = rs.standard_normal((9, 4, 5))
+    idx, sc = S.sample_bernoulli(np.ones(9), 9, seed=0)
+    assert T.rel_fro(D.rtprod(A, B, idx, sc), T.tprod_bcirc(A, B)) < 1e-13
+
+
+def test_rtprod_empty_pick_is_zero():
+    A = rs.standard_normal((3, 4, 2))
+    B = rs.standard_normal((4, 5, 2))
+    Z = D.rtprod(A, B, np.array([], dtype=np.int64), np.array([]))
+    assert Z.shape == (3, 5, 2) and not Z.any()
+
+
+def _gammas(A, B):
+    return np.array([np.sum(T.tprod_bcirc(A[:, j:j + 1, :], B[j:j + 1, :, :]) ** 2) for j in range(A.shape[1])])
+
+
+@pytest.mark.parametrize("mode", ["bernoulli", "iid"])
+def test_rtprod_unbiased_with_exact_second_moment(mode):
+    # Z - A*B is a sum of independent (Bernoulli) or i.i.d. (IID) terms, so its
+    # mean is 0 and its expected squared norm has a closed form in
+    # gamma_j = ||A_{:j:} * B_{j::}||_F^2.
+    n1, n2, n4, n3, c, reps = 4, 10, 3, 4, 4, 1500
+    A = rs.standard_normal((n1, n2, n3)) * np.exp(rs.standard_normal(n2))[None, :, None]
+    B = rs.standard_normal((n2, n4, n3))
+    w = S.weights_norm2(A)
+    AB = T.tprod_bcirc(A, B)
+    gam = _gammas(A, B)
+    q, Ssum = S.quantize(w)
+    p = np.array(q, dtype=float) / Ssum
+    if mode == "bernoulli":
+        pi = np.minimum(1.0, c * p)
+        m = pi < 1
+        expect = float(np.sum((1.0 / pi[m] - 1.0) * gam[m]))
+    else:
+        expect = float((np.sum(gam / p) - np.sum(AB ** 2)) / c)
+    acc = np.zeros_like(AB)
+    errs = []
+    for seed in range(reps):
+        idx, sc = S.sample(w, c, mode, seed=seed, stream=2)
+        Z = D.rtprod(A, B, idx, sc)
+        acc += Z
+        errs.append(np.sum((Z - AB) ** 2))
+    errs = np.array(errs)
+    mean_err = np.mean(errs)
+    assert abs(mean_err - expect) < 5 * np.std(errs) / np.sqrt(reps)
+    bias = acc / reps - AB
+    assert np.sum(bias ** 2) < 10 * expect / reps
+
+
+def test_rtprod_meets_paper_bound_on_white_inputs():
+    # Theorem theorem:matmult-main-exact with norm-squared probabilities
+    # (beta = 1): E||AB - CR||_F <= ||A||_F ||B||_F / sqrt(c). Gaussian tubes
+    # are spectrally flat in expectation, where the bound's proof applies.
+    A = rs.standard_normal((8, 40, 6))
+    B = rs.standard_normal((40, 7, 6))
+    c = 10
+    AB = T.tprod_bcirc(A, B)
+    w = S.weights_norm2(A)
+    errs = [np.linalg.norm((D.rtprod(A, B, *S.sample_bernoulli(w, c, seed=s)) - AB).ravel()) for s in range(100)]
+    assert np.mean(errs) <= np.linalg.norm(A.ravel()) * np.linalg.norm(B.ravel()) / np.sqrt(c)
+
+
+def test_tcx_reproduces_exact_rank():
+    A = _lowrank(12, 15, 6, 3)
+    w = S.weights_lateral_leverage(A, 3)
+    idx, sc = S.sample_iid(w, 6, seed=1)
+    assert T.rel_fro(D.tcx(A, idx, sc), A) < 1e-10
+
+
+def test_tcx_is_least_squares_optimal():
+    # eq. ell2reg: C * C^+ * X minimises ||X - C * Y||_F; compare with a
+    # per-Fourier-slice least-squares solve and with random perturbations
+    A = rs.standard_normal((8, 10, 5))
+    idx = np.array([1, 4, 7])
+    Z = D.tcx(A, idx, np.ones(3))
+    Ah = T.fft3(A)
+    Ch = Ah[:, idx, :]
+    Zh = np.zeros_like(Ah)
+    for k in range(5):
+        Y, *_ = np.linalg.lstsq(Ch[:, :, k], Ah[:, :, k], rcond=None)
+        Zh[:, :, k] = Ch[:, :, k] @ Y
+    assert T.rel_fro(Z, np.real(T.ifft3(Zh))) < 1e-12
+    base = np.linalg.norm((A - Z).ravel())
+    C = A[:, idx, :]
+    for _ in range(5):
+        Yp = rs.standard_normal((3, 10, 5))
+        assert np.linalg.norm((A - T.tprod_bcirc(C, Yp)).ravel()) >= base - 1e-12
+
+
+def test_tcx_scale_cancels():
+    A = rs.standard_normal((7, 9, 4))
+    idx = np.array([0, 2, 5])
+    Z1 = D.tcx(A, idx, np.ones(3))
+    Z2 = D.tcx(A, idx, np.array([0.3, 5.0, 2.0]))
+    assert T.rel_fro(Z2, Z1) < 1e-12
+
+
+def test_tcur_reproduces_exact_rank():
+    n1, n2, n3, r = 14, 16, 6, 3
+    A = _lowrank(n1, n2, n3, r, seed=5)
+    ci, cs = S.sample_iid(S.weights_lateral_leverage(A, r), 7, seed=2)
+    C = A[:, ci, :] * cs[None, :, None]
+    ri, rsc = S.sample_iid(S.weights_horizontal_leverage(C, r), 7, seed=3, stream=1)
+    Z, core = D.tcur(A, ci, cs, ri, rsc, r=r)
+    assert T.rel_fro(Z, A) < 1e-9
+    assert core.shape == (4, 7, 7)
+
+
+def test_tcur_n3_one_is_matrix_cur():
+    M = rs.standard_normal((9, 3)) @ rs.standard_normal((3, 11)) + 1e-3 * rs.standard_normal((9, 11))
+    ci, ri = np.array([0, 3, 5, 8]), np.array([1, 2, 6, 7])
+    cs, rsc = np.array([1.0, 2.0, 0.5, 1.5]), np.array([1.0, 0.7, 1.3, 2.0])
+    Z, _ = D.tcur(M[:, :, None], ci, cs, ri, rsc, r=3)
+    Cm = M[:, ci] * cs
+    Wm = rsc[:, None] * Cm[ri, :]
+    u, s, vh = np.linalg.svd(Wm)
+    Wp = vh[:3].T @ np.diag(1 / s[:3]) @ u[:, :3].T
+    ref = Cm @ Wp @ (rsc[:, None] * M[ri, :])
+    np.testing.assert_allclose(Z[:, :, 0], ref, atol=1e-12)
+
+
+def test_pinv_r_properties():
+    W = rs.standard_normal((6, 5)) + 1j * rs.standard_normal((6, 5))
+    P = D.pinv_r(W)
+    np.testing.assert_allclose(P, np.linalg.pinv(W), atol=1e-12)
+    P2 = D.pinv_r(W, 2)
+    u, s, vh = np.linalg.svd(W)
+    np.testing.assert_allclose(P2, vh[:2].conj().T @ np.diag(1 / s[:2]) @ u[:, :2].conj().T, atol=1e-12)
+
+
+def test_tsvt_matches_matrix_svt_of_circ():
+    # the t-SVT with threshold tau is the matrix SVT of circ(M) with the same
+    # tau: the DFT block-diagonalisation (eq. circ1) is a unitary similarity
+    # once scaled by 1/sqrt(n3)
+    M = rs.standard_normal((5, 4, 6))
+    tau = 1.3
+    L, ranks = D.tsvt(M, tau)
+    ref, _ = D.svt_matrix(T.circ(M), tau)
+    np.testing.assert_allclose(T.circ(L), ref, atol=1e-12)
+    assert ranks.shape == (4,)
+
+
+def test_tsvt_zero_threshold_and_large_threshold():
+    M = rs.standard_normal((4, 6, 5))
+    L, ranks = D.tsvt(M, 0.0)
+    assert T.rel_fro(L, M) < 1e-13
+    assert np.all(ranks == 4)
+    L2, r2 = D.tsvt(M, 1e6)
+    assert not np.any(np.abs(L2) > 1e-12) and np.all(r2 == 0)
+
+
+def test_tsvt_is_the_tnn_prox():
+    # L minimises ||L||_TNN + 1/(2 tau) ||L - M||_F^2
+    M = rs.standard_normal((4, 5, 4))
+    tau = 0.8
+    L, _ = D.tsvt(M, tau)
+
+    def obj(X):
+        return T.tnn(X) + np.sum((X - M) ** 2) / (2 * tau)
+
+    base = obj(L)
+    for _ in range(20):
+        assert obj(L + 1e-3 * rs.standard_normal(M.shape)) >= base - 1e-12
+
+
+def test_admm_completion_recovers_low_rank():
+    n1, n2, n3, r = 20, 20, 6, 2
+    Ls = _lowrank(n1, n2, n3, r, seed=8)
+    mask = (rs.random(Ls.shape) < 0.6).astype(np.uint8)
+    X = Ls * mask
+    L, E, Y, hist = D.admm_complete(X, mask, iters=80, L_true=Ls)
+    assert hist[-1]["rse"] < 1e-2
+    assert hist[-1]["rse"] < 0.1 * hist[5]["rse"]
+    # E stays on the unobserved entries
+    assert not np.any(E[mask == 1])
+    assert hist[-1]["res"] < hist[20]["res"]
