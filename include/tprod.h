@@ -1,0 +1,195 @@
+/*
+ * tprod.h - C ABI of the MI355X (gfx950) t-product library.
+ *
+ * Tensors are third-order real arrays X of size n1 x n2 x n3 stored
+ * contiguously, element (i, j, k) at offset (i*n2 + j)*n3 + k: every tube
+ * X_{ij:} is contiguous ("tube-major"). Fourier-domain data ("spectra") hold
+ * the K = floor(n3/2) + 1 non-redundant frontal slices of fft(X, [], 3)
+ * (slice K-1 is the Nyquist slice when n3 is even; the others are the
+ * conjugates of these, so they are never stored) in planar form:
+ * re[k][row][col] and im[k][row][col], each a contiguous K x rows x cols
+ * array. The transform follows the MATLAB convention of Section 2.1: the
+ * forward transform is unscaled, the inverse carries 1/n3.
+ *
+ * Ownership: the caller allocates and frees every buffer (inputs, outputs
+ * and the workspace, whose size the *_workspace functions return). Unless a
+ * parameter says "host", pointers are device pointers on the current HIP
+ * device. The library keeps no per-call state; its only global state is a
+ * per-device table of transform twiddles set up on first use.
+ *
+ * Asynchrony: every call enqueues its work on `stream` (a hipStream_t;
+ * NULL is the default stream) and returns without synchronising. Values a
+ * call writes to device memory (sample counts, ranks) are valid once the
+ * stream has reached that point.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued;
+ * on failure a negative tp_status is returned, nothing is enqueued and
+ * tp_last_error() describes the problem (thread-local). A failed kernel
+ * launch returns TP_EHIP.
+ *
+ * Determinism: the same inputs, seed and precision give bitwise identical
+ * outputs: no reduction uses floating-point atomics.
+ */
+#ifndef TPROD_H
+#define TPROD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TP_OK = 0,
+  TP_EINVAL = -1,      /* bad scalar argument or null pointer          */
+  TP_ESHAPE = -2,      /* shapes do not match                          */
+  TP_EDTYPE = -3,      /* unsupported dtype / precision combination    */
+  TP_EWORKSPACE = -4,  /* workspace missing or too small               */
+  TP_EHIP = -5,        /* a HIP runtime call or kernel launch failed    */
+  TP_ENOCONV = -6,     /* iteration cap reached (result still written) */
+  TP_EUNSUPPORTED = -7 /* size outside what the kernels implement      */
+} tp_status;
+
+typedef enum { TP_F32 = 0, TP_F64 = 1 } tp_dtype;
+
+/* Arithmetic of the per-slice contractions.
+ *  TP_PREC_F64    float64 operands and accumulation (TP_F64 storage).
+ *  TP_PREC_F32    float32 operands and accumulation.
+ *  TP_PREC_BF16X3 float32 operands split as x = hi + lo, hi = bf16(x),
+ *                 lo = bf16(x - hi) (round to nearest even), products
+ *                 hi*hi + hi*lo + lo*hi on the bf16 matrix cores with
+ *                 float32 accumulation; complex products as three real
+ *                 products (Re = P1 - P2, Im = P3 - P1 - P2 with
+ *                 P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi)).
+ *  TP_PREC_BF16   single bf16 product (hi*hi only), float32 accumulation. */
+typedef enum { TP_PREC_F64 = 0, TP_PREC_F32 = 1, TP_PREC_BF16X3 = 2, TP_PREC_BF16 = 3 } tp_prec;
+
+/* A dense tube-major tensor. */
+typedef struct {
+  void* data;
+  int32_t dtype; /* tp_dtype */
+  int64_t n1, n2, n3;
+} tp_tensor;
+
+/* A half spectrum: planar re/im arrays of K x rows x cols. */
+typedef struct {
+  void* re;
+  void* im;
+  int32_t dtype; /* tp_dtype */
+  int64_t K, rows, cols;
+} tp_spectrum;
+
+/* Where sampling probabilities come from (Section 3).
+ *  TP_P_USER      caller-supplied non-negative weights w[n] (host or device
+ *                 per the call's documentation), p_i = w_i / sum w.
+ *  TP_P_UNIFORM   p_i = 1/n.
+ *  TP_P_NORM2     p_j ~ ||A_{:j:}||_F^2, eq. nonoptimal_probs (lateral) or
+ *                 ||A_{i::}||_F^2 (horizontal).
+ *  TP_P_NORMPROD  p_j ~ ||A_{:j:}||_F ||B_{j::}||_F, eq. nearly_optimal_probs.
+ *  TP_P_LEV       tubal leverage scores: lateral ||Vhat_{j::}||_F^2 from the
+ *                 top-r right singular slices (eq. cur-col-prob); horizontal
+ *                 ||Uhat_{i::}||_F^2 from the top-r left singular slices of C
+ *                 (eq. colprob_rows_exact, read with the squared norm). */
+typedef enum {
+  TP_P_USER = 0, TP_P_UNIFORM = 1, TP_P_NORM2 = 2, TP_P_NORMPROD = 3, TP_P_LEV = 4
+} tp_prob_kind;
+
+/* How slices are picked.
+ *  TP_S_BERNOULLI  Algorithm 2: slice i kept with probability min(1, c p_i),
+ *                  scale 1/sqrt(min(1, c p_i)); ascending slice order; the
+ *                  number kept is random (expected sum_i min(1, c p_i)).
+ *  TP_S_IID        exactly c draws with replacement from p, scale
+ *                  1/sqrt(c p_j); draw order.
+ *  TP_S_UNIFORM    c distinct slices uniformly without replacement
+ *                  (Corollaries cor:proj-main, cor:gnys-main), scale
+ *                  sqrt(n/c); ascending order.
+ * Decisions are exact integer comparisons on weights quantised to
+ * q_i = floor(w_i 2^(B-e)) (e the binary exponent of max w, B = 62 -
+ * ceil(log2 n)) against Philox4x64-10 draws keyed by (seed, stream_id) at
+ * counter (i or draw number, 0, 0, 0), word 0. */
+typedef enum { TP_S_BERNOULLI = 0, TP_S_IID = 1, TP_S_UNIFORM = 2 } tp_sample_mode;
+
+/* A device-resident pick: idx[0..*count) slice indices, scale[] their
+ * rescaling factors; cap is the capacity of idx and scale. */
+typedef struct {
+  int32_t* idx;
+  double* scale;
+  int64_t cap;
+  int64_t* count;
+} tp_sample;
+
+const char* tp_status_string(int status);
+const char* tp_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int tp_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Fourier engine (Section 2.1 operators; Algorithm 1 steps 2-3 and 7).
+ * ------------------------------------------------------------------------- */
+
+/* Forward transform of every tube: Xh = first K slices of fft(X, [], 3).
+ * Xh must be K x n1 x n2 with X's dtype. n3 >= 1. */
+int tp_tfft(const tp_tensor* X, tp_spectrum* Xh, void* stream);
+
+/* Inverse transform: X = ifft of the conjugate-symmetric extension of Xh.
+ * The imaginary parts of slice 0 and (n3 even) slice n3/2 are ignored, as
+ * for a real signal they are zero. X is rows x cols x n3. */
+int tp_tifft(const tp_spectrum* Xh, tp_tensor* X, void* stream);
+
+/* Per-slice products of two spectra, C_k = op(A_k) op(B_k), k < K.
+ * op_a / op_b: 0 = as stored, 1 = conjugate transpose. Slices 0 and (when
+ * real_last != 0) K-1 are treated as real: their imaginary parts are neither
+ * read nor computed, and C's are set to zero. `prec` selects the arithmetic
+ * (TP_PREC_F64 needs TP_F64 spectra, the others TP_F32). */
+int tp_spectrum_matmul(const tp_spectrum* A, int op_a, const tp_spectrum* B, int op_b, tp_spectrum* C,
+                       int real_last, int prec, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Slice statistics (eqs. nearly_optimal_probs, nonoptimal_probs).
+ * ------------------------------------------------------------------------- */
+
+/* out[j] = ||A_{:j:}||_F^2 (mode 0, lateral, n2 values) or
+ * out[i] = ||A_{i::}||_F^2 (mode 1, horizontal, n1 values), accumulated in
+ * float64 in a fixed order. out is a device array of float64. */
+int tp_slice_norms(const tp_tensor* A, int mode, double* out, void* ws, size_t ws_bytes, void* stream);
+size_t tp_slice_norms_workspace(const tp_tensor* A, int mode);
+
+/* ---------------------------------------------------------------------------
+ * Sampling (Algorithm 2 lines 4-11, Algorithm 4 lines 5-12, Algorithm 5
+ * lines 6-13).
+ * ------------------------------------------------------------------------- */
+
+/* Picks slices of a set of n candidates.
+ *  kind TP_P_USER:     w is a device array of n float64 weights; A, B unused.
+ *  kind TP_P_UNIFORM:  only n is used.
+ *  kind TP_P_NORM2:    lateral slices of A (n = A->n2).
+ *  kind TP_P_NORMPROD: lateral slices of A with horizontal slices of B
+ *                      (n = A->n2 = B->n1).
+ * c: 1 <= c <= n. out->cap must be >= c (TP_S_IID, TP_S_UNIFORM) or >= n
+ * (TP_S_BERNOULLI). Weights must be finite, non-negative and not all zero;
+ * for device weights this is checked on the device, and a violation yields
+ * *count = -1. */
+int tp_tsample(int kind, const tp_tensor* A, const tp_tensor* B, const double* w, int64_t n, int64_t c, int mode,
+               uint64_t seed, uint64_t stream_id, tp_sample* out, void* ws, size_t ws_bytes, void* stream);
+size_t tp_tsample_workspace(int64_t n);
+
+/* ---------------------------------------------------------------------------
+ * t-product (Algorithm 1) and rt-product (Algorithm 2 lines 12-17).
+ * ------------------------------------------------------------------------- */
+
+/* C = A * B (sample == NULL), or C = (A*S*D) * (D*S^T*B) where S, D are the
+ * picks in `sample` (the lateral slices idx of A and the matching
+ * horizontal slices of B, each times scale; only the first *count entries
+ * are used). A is n1 x n2 x n3, B is n2 x n4 x n3, C is n1 x n4 x n3, all of
+ * the same dtype. prec: TP_PREC_F64 with TP_F64 data; TP_PREC_F32,
+ * TP_PREC_BF16X3 or TP_PREC_BF16 with TP_F32 data. */
+int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp_tensor* C, int prec, void* ws,
+             size_t ws_bytes, void* stream);
+size_t tp_tprod_workspace(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, int prec);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPROD_H */

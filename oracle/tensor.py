@@ -222,3 +222,35 @@ def rel_fro(X, Y):
     den = np.linalg.norm(np.asarray(Y, dtype=np.float64).ravel())
     num = np.linalg.norm((np.asarray(X, dtype=np.float64) - np.asarray(Y, dtype=np.float64)).ravel())
     return num / den if den > 0 else num
+
+
+# ---------------------------------------------------------------------------
+# Views used to check the Fourier engine and full-size products.
+# ---------------------------------------------------------------------------
+
+def half_spectrum(X):
+    """The K = floor(n3/2)+1 non-redundant Fourier slices of X as a
+    (K, n1, n2) complex array (slice-major)."""
+    K = X.shape[2] // 2 + 1
+    return np.ascontiguousarray(np.transpose(fft3(X)[:, :, :K], (2, 0, 1)))
+
+
+def from_half_spectrum(H, n3):
+    """Real tensor whose Fourier slices k <= n3/2 are H[k] and whose other
+    slices are their conjugates (the imaginary parts of slice 0 and, for
+    even n3, slice n3/2 do not belong to a real signal and are dropped)."""
+    H = np.asarray(H)
+    return np.ascontiguousarray(np.fft.irfft(np.transpose(H, (1, 2, 0)), n=n3, axis=2))
+
+
+def tprod_entries(A, B, ii, jj, kk):
+    """Selected entries C[i, j, k] of C = A * B straight from eq. tprod:
+    C_{ij k} = sum_t sum_s A_{i s (k-t) mod n3} B_{s j t}."""
+    n3 = A.shape[2]
+    out = np.empty(len(ii))
+    for e, (i, j, k) in enumerate(zip(ii, jj, kk)):
+        acc = 0.0
+        for t in range(n3):
+            acc += float(np.dot(A[i, :, (k - t) % n3].astype(np.float64), B[:, j, t].astype(np.float64)))
+        out[e] = acc
+    return out

@@ -1,0 +1,156 @@
+"""Thin torch binding of the C ABI (argument marshalling only).
+
+Every function takes and returns torch tensors on the current HIP device and
+enqueues its work on torch's current stream. Outputs and the workspace are
+allocated with torch; all arithmetic runs in the HIP kernels of libtprod.so.
+There is no CPU path: CPU tensors are rejected.
+"""
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.float32: L.TP_F32, torch.float64: L.TP_F64}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_gpu(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+def _tensor(x):
+    if x.dim() != 3:
+        raise ValueError("expected a 3-way tensor")
+    if x.dtype not in _DT:
+        raise ValueError("dtype must be float32 or float64")
+    return L.Tensor(x.data_ptr(), _DT[x.dtype], x.shape[0], x.shape[1], x.shape[2])
+
+
+def _spectrum(re, im):
+    return L.Spectrum(re.data_ptr(), im.data_ptr(), _DT[re.dtype], re.shape[0], re.shape[1], re.shape[2])
+
+
+def _ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def half_count(n3):
+    return n3 // 2 + 1
+
+
+def tfft(X):
+    """Half spectrum (re, im), each K x n1 x n2, of fft(X, [], 3)."""
+    _need_gpu(X)
+    K = half_count(X.shape[2])
+    re = torch.empty((K, X.shape[0], X.shape[1]), dtype=X.dtype, device=X.device)
+    im = torch.empty_like(re)
+    L.check(L.load().tp_tfft(C.byref(_tensor(X)), C.byref(_spectrum(re, im)), _stream()))
+    return re, im
+
+
+def tifft(re, im, n3):
+    """Real tensor rows x cols x n3 whose half spectrum is (re, im)."""
+    _need_gpu(re, im)
+    X = torch.empty((re.shape[1], re.shape[2], n3), dtype=re.dtype, device=re.device)
+    L.check(L.load().tp_tifft(C.byref(_spectrum(re, im)), C.byref(_tensor(X)), _stream()))
+    return X
+
+
+def spectrum_matmul(a, b, op_a=0, op_b=0, real_last=True, prec="f32"):
+    """Per-slice products C_k = op(A_k) op(B_k); a and b are (re, im) pairs."""
+    are, aim = a
+    bre, bim = b
+    _need_gpu(are, aim, bre, bim)
+    M = are.shape[2] if op_a else are.shape[1]
+    N = bre.shape[1] if op_b else bre.shape[2]
+    cre = torch.empty((are.shape[0], M, N), dtype=are.dtype, device=are.device)
+    cim = torch.empty_like(cre)
+    L.check(L.load().tp_spectrum_matmul(C.byref(_spectrum(are, aim)), int(op_a), C.byref(_spectrum(bre, bim)),
+                                         int(op_b), C.byref(_spectrum(cre, cim)), int(bool(real_last)),
+                                         L.PREC[prec], _stream()))
+    return cre, cim
+
+
+def slice_norms(A, mode="lateral"):
+    """Squared Frobenius norms of lateral (mode "lateral") or horizontal
+    slices, float64."""
+    _need_gpu(A)
+    m = 0 if mode == "lateral" else 1
+    n = A.shape[1] if m == 0 else A.shape[0]
+    out = torch.empty(n, dtype=torch.float64, device=A.device)
+    t = _tensor(A)
+    lib = L.load()
+    ws = _ws(lib.tp_slice_norms_workspace(C.byref(t), m), A.device)
+    L.check(lib.tp_slice_norms(C.byref(t), m, out.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return out
+
+
+class Picks:
+    """Device-resident picks: idx (int32), scale (float64), count (int64[1])."""
+
+    def __init__(self, cap, device):
+        self.idx = torch.empty(cap, dtype=torch.int32, device=device)
+        self.scale = torch.empty(cap, dtype=torch.float64, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.cap = cap
+
+    def struct(self):
+        return L.Sample(self.idx.data_ptr(), self.scale.data_ptr(), self.cap, self.count.data_ptr())
+
+    def host(self):
+        """(idx, scale) trimmed to the live count, as CPU tensors (syncs)."""
+        n = int(self.count.item())
+        if n < 0:
+            raise ValueError("sampling rejected the weights (non-finite, negative or all zero)")
+        return self.idx[:n].cpu(), self.scale[:n].cpu()
+
+
+def tsample(kind, c, mode="iid", seed=0, stream_id=0, A=None, B=None, w=None, n=None, cap=None, out=None):
+    """Pick c slices (see tp_tsample). kind in {"user", "uniform", "norm2",
+    "normprod"}; for "user" pass float64 device weights w."""
+    _need_gpu(A, B, w)
+    if n is None:
+        n = A.shape[1] if A is not None else w.numel()
+    device = (A if A is not None else w).device if (A is not None or w is not None) else torch.device("cuda")
+    if out is None:
+        out = Picks(cap if cap is not None else (n if mode == "bernoulli" else c), device)
+    lib = L.load()
+    ta = C.byref(_tensor(A)) if A is not None else None
+    tb = C.byref(_tensor(B)) if B is not None else None
+    ws_bytes = lib.tp_tsample_workspace(n)
+    if A is not None:
+        ws_bytes += lib.tp_slice_norms_workspace(C.byref(_tensor(A)), 0)
+    ws = _ws(ws_bytes, device)
+    s = out.struct()
+    L.check(lib.tp_tsample(L.KIND[kind], ta, tb, w.data_ptr() if w is not None else None, int(n), int(c),
+                           L.MODE[mode], int(seed), int(stream_id), C.byref(s), ws.data_ptr(), ws.numel(),
+                           _stream()))
+    return out
+
+
+def tprod(A, B, picks=None, prec=None, out=None):
+    """t-product A * B (Algorithm 1), or the rt-product of Algorithm 2 when
+    picks (from tsample over A's lateral slices) are given."""
+    _need_gpu(A, B)
+    if prec is None:
+        prec = "f64" if A.dtype == torch.float64 else "f32"
+    C_ = out if out is not None else torch.empty((A.shape[0], B.shape[1], A.shape[2]), dtype=A.dtype,
+                                                  device=A.device)
+    lib = L.load()
+    ta, tb, tc = _tensor(A), _tensor(B), _tensor(C_)
+    ps = picks.struct() if picks is not None else None
+    sp = C.byref(ps) if ps is not None else None
+    ws = _ws(lib.tp_tprod_workspace(C.byref(ta), C.byref(tb), sp, L.PREC[prec]), A.device)
+    L.check(lib.tp_tprod(C.byref(ta), C.byref(tb), sp, C.byref(tc), L.PREC[prec], ws.data_ptr(), ws.numel(),
+                         _stream()))
+    return C_

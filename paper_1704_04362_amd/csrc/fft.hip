@@ -1,0 +1,513 @@
+// Tube transforms along the third mode (Section 2.1 "Operators": fft/ifft
+// along mode 3, MATLAB convention; Algorithm 1 steps 2-3 and 7).
+//
+// Layout: the tensor is tube-major (each tube X_{ij:} is n3 contiguous
+// values); the spectrum is slice-major planar, re[k][tube] / im[k][tube],
+// holding the K = n3/2 + 1 non-redundant slices.
+//
+// Forward kernel (one wavefront = 64 tubes):
+//   1. the 64 tubes are read with 16-byte loads, consecutive lanes reading
+//      consecutive pieces of a tube, and staged in LDS with a row stride of
+//      n3 + 1 words so that the transposed read in step 2 is conflict free;
+//      gathers of picked slices and their scales are applied here;
+//   2. every lane packs its real tube as z[m] = x[2m] + i x[2m+1] and runs a
+//      length-n3/2 complex FFT in registers (radix 4/2/5/3 Cooley-Tukey,
+//      fully unrolled, twiddles from a per-device constant table);
+//   3. the half spectrum of the real tube is separated from Z by conjugate
+//      symmetry, X[k] = (Z[k] + conj Z[M-k])/2 + W_n3^k (Z[k] - conj Z[M-k])/2i,
+//      and each slice k is written with one coalesced store per wavefront.
+// The inverse kernel runs these steps backwards. Lengths without a
+// specialised kernel use a direct O(n3^2) transform per tube.
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tp {
+namespace {
+
+// --------------------------------------------------------------------------
+// Twiddle tables: W_L^e = exp(-2 pi i e / L) for the lengths below, stored
+// back to back (re, im interleaved), computed on the host in long double.
+// --------------------------------------------------------------------------
+constexpr int kTwLens[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 5, 10, 20, 25, 50, 100, 200};
+constexpr int kTwCount = sizeof(kTwLens) / sizeof(int);
+
+constexpr int tw_offset(int L) {
+  int off = 0;
+  for (int i = 0; i < kTwCount; ++i) {
+    if (kTwLens[i] == L) return off;
+    off += kTwLens[i];
+  }
+  return -1;
+}
+constexpr int kTwTotal = tw_offset(200) + 200;
+
+__constant__ double g_tw64[2 * kTwTotal];
+__constant__ float g_tw32[2 * kTwTotal];
+
+template <typename T>
+__device__ __forceinline__ T tw_re(int L, int e);
+template <typename T>
+__device__ __forceinline__ T tw_im(int L, int e);
+template <>
+__device__ __forceinline__ double tw_re<double>(int L, int e) { return g_tw64[2 * (tw_offset(L) + e)]; }
+template <>
+__device__ __forceinline__ double tw_im<double>(int L, int e) { return g_tw64[2 * (tw_offset(L) + e) + 1]; }
+template <>
+__device__ __forceinline__ float tw_re<float>(int L, int e) { return g_tw32[2 * (tw_offset(L) + e)]; }
+template <>
+__device__ __forceinline__ float tw_im<float>(int L, int e) { return g_tw32[2 * (tw_offset(L) + e) + 1]; }
+
+std::mutex g_tw_mutex;
+std::vector<int> g_tw_ready;  // per device
+
+int ensure_twiddles() {
+  int dev = 0;
+  TP_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tw_mutex);
+  if (dev < (int)g_tw_ready.size() && g_tw_ready[dev]) return TP_OK;
+  std::vector<double> t64(2 * kTwTotal);
+  std::vector<float> t32(2 * kTwTotal);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int i = 0; i < kTwCount; ++i) {
+    int L = kTwLens[i], off = tw_offset(L);
+    for (int e = 0; e < L; ++e) {
+      long double ang = two_pi * (long double)e / (long double)L;
+      long double c = cosl(ang), s = -sinl(ang);
+      // exact values where the angle is a multiple of pi/2
+      if ((4 * e) % L == 0) {
+        int q = (4 * e) / L;
+        c = (q == 0) ? 1.0L : (q == 2 ? -1.0L : 0.0L);
+        s = (q == 1) ? -1.0L : (q == 3 ? 1.0L : 0.0L);
+      }
+      t64[2 * (off + e)] = (double)c;
+      t64[2 * (off + e) + 1] = (double)s;
+      t32[2 * (off + e)] = (float)c;
+      t32[2 * (off + e) + 1] = (float)s;
+    }
+  }
+  TP_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(g_tw64), t64.data(), t64.size() * sizeof(double)));
+  TP_HIP_CHECK(hipMemcpyToSymbol(HIP_SYMBOL(g_tw32), t32.data(), t32.size() * sizeof(float)));
+  if (dev >= (int)g_tw_ready.size()) g_tw_ready.resize(dev + 1, 0);
+  g_tw_ready[dev] = 1;
+  return TP_OK;
+}
+
+// --------------------------------------------------------------------------
+// In-register complex FFT of length M (decimation in time).
+// --------------------------------------------------------------------------
+constexpr int radix_of(int M) {
+  return (M % 4 == 0) ? 4 : (M % 2 == 0) ? 2 : (M % 5 == 0) ? 5 : (M % 3 == 0) ? 3 : M;
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void cfft(T (&re)[M], T (&im)[M]) {
+  if constexpr (M > 1) {
+    constexpr int p = radix_of(M);
+    constexpr int Q = M / p;
+    T sr[p][Q], si[p][Q];
+#pragma unroll
+    for (int r = 0; r < p; ++r)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        sr[r][q] = re[q * p + r];
+        si[r][q] = im[q * p + r];
+      }
+#pragma unroll
+    for (int r = 0; r < p; ++r) cfft<T, Q>(sr[r], si[r]);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      T tr[p], ti[p];
+#pragma unroll
+      for (int r = 0; r < p; ++r) {
+        const int e = (r * k) % M;
+        if (e == 0) {
+          tr[r] = sr[r][k];
+          ti[r] = si[r][k];
+        } else {
+          const T wr = tw_re<T>(M, e), wi = tw_im<T>(M, e);
+          tr[r] = sr[r][k] * wr - si[r][k] * wi;
+          ti[r] = sr[r][k] * wi + si[r][k] * wr;
+        }
+      }
+      if constexpr (p == 2) {
+        re[k] = tr[0] + tr[1];
+        im[k] = ti[0] + ti[1];
+        re[k + Q] = tr[0] - tr[1];
+        im[k + Q] = ti[0] - ti[1];
+      } else if constexpr (p == 4) {
+        const T ar = tr[0] + tr[2], ai = ti[0] + ti[2];
+        const T br = tr[0] - tr[2], bi = ti[0] - ti[2];
+        const T cr = tr[1] + tr[3], ci = ti[1] + ti[3];
+        // (t1 - t3) * (-i)
+        const T dr = ti[1] - ti[3], di = tr[3] - tr[1];
+        re[k] = ar + cr;
+        im[k] = ai + ci;
+        re[k + 2 * Q] = ar - cr;
+        im[k + 2 * Q] = ai - ci;
+        re[k + Q] = br + dr;
+        im[k + Q] = bi + di;
+        re[k + 3 * Q] = br - dr;
+        im[k + 3 * Q] = bi - di;
+      } else {
+        // generic p-point DFT with W_p^{rs} = W_M^{r s Q}
+#pragma unroll
+        for (int s = 0; s < p; ++s) {
+          T accr = tr[0], acci = ti[0];
+#pragma unroll
+          for (int r = 1; r < p; ++r) {
+            const int e = (r * s * Q) % M;
+            if (e == 0) {
+              accr += tr[r];
+              acci += ti[r];
+            } else {
+              const T wr = tw_re<T>(M, e), wi = tw_im<T>(M, e);
+              accr += tr[r] * wr - ti[r] * wi;
+              acci += tr[r] * wi + ti[r] * wr;
+            }
+          }
+          re[k + s * Q] = accr;
+          im[k + s * Q] = acci;
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+
+struct FwdArgs {
+  int64_t rows, cols, in_cols;
+  int64_t ntubes;  // rows * cols
+  const int32_t* row_idx;
+  const int32_t* col_idx;
+  const double* row_scale;
+  const double* col_scale;
+  const int64_t* count;
+};
+
+// Input tube offset and scale of output tube t; returns false for a tube
+// that is to be written as zeros (beyond the live sample count).
+__device__ __forceinline__ bool tube_source(const FwdArgs& a, int64_t t, int64_t& src, double& s) {
+  const int64_t ra = t / a.cols, cb = t - ra * a.cols;
+  int64_t lim = a.count ? *a.count : INT64_MAX;
+  if (a.row_idx && ra >= lim) return false;
+  if (a.col_idx && cb >= lim) return false;
+  const int64_t ir = a.row_idx ? a.row_idx[ra] : ra;
+  const int64_t ic = a.col_idx ? a.col_idx[cb] : cb;
+  src = ir * a.in_cols + ic;
+  s = (a.row_scale ? a.row_scale[ra] : 1.0) * (a.col_scale ? a.col_scale[cb] : 1.0);
+  return true;
+}
+
+constexpr int kTile = 64;  // tubes per workgroup (one wavefront)
+
+template <typename T, int N>
+__global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, FwdArgs a, T* __restrict__ ore,
+                                                     T* __restrict__ oim) {
+  constexpr int M = N / 2;
+  constexpr int PAD = N + 1;
+  constexpr int VN = Vec16<T>::n;
+  using V = typename Vec16<T>::type;
+  __shared__ T lds[kTile * PAD];
+  __shared__ int64_t s_src[kTile];
+  __shared__ double s_scl[kTile];
+  const int lane = threadIdx.x;
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  {
+    const int64_t t = tile0 + lane;
+    int64_t src = -1;
+    double s = 0.0;
+    if (!(t < a.ntubes && tube_source(a, t, src, s))) src = -1;
+    s_src[lane] = src;
+    s_scl[lane] = s;
+  }
+  __syncthreads();
+
+  if constexpr (N % VN == 0) {
+    constexpr int CH = N / VN;
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int f = it * kTile + lane;
+      const int tl = f / CH, part = f - tl * CH;
+      const int64_t src = s_src[tl];
+      const double s = s_scl[tl];
+      T v[VN];
+#pragma unroll
+      for (int e = 0; e < VN; ++e) v[e] = T(0);
+      if (src >= 0) {
+        const V w = *reinterpret_cast<const V*>(x + src * N + part * VN);
+        const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) v[e] = (s == 1.0) ? wp[e] : (T)((double)wp[e] * s);
+      }
+#pragma unroll
+      for (int e = 0; e < VN; ++e) lds[tl * PAD + part * VN + e] = v[e];
+    }
+  } else {
+    for (int it = 0; it < N; ++it) {
+      const int f = it * kTile + lane;
+      const int tl = f / N, e = f - tl * N;
+      const int64_t src = s_src[tl];
+      const double s = s_scl[tl];
+      T v = T(0);
+      if (src >= 0) v = (s == 1.0) ? x[src * N + e] : (T)((double)x[src * N + e] * s);
+      lds[tl * PAD + e] = v;
+    }
+  }
+  __syncthreads();
+
+  const int64_t t = tile0 + lane;
+  if (t >= a.ntubes) return;
+  const int64_t ks = a.ntubes;
+  if constexpr (N == 1) {
+    ore[t] = lds[lane * PAD];
+    oim[t] = T(0);
+  } else {
+    T zr[M], zi[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      zr[m] = lds[lane * PAD + 2 * m];
+      zi[m] = lds[lane * PAD + 2 * m + 1];
+    }
+    cfft<T, M>(zr, zi);
+    ore[t] = zr[0] + zi[0];
+    oim[t] = T(0);
+    ore[(int64_t)M * ks + t] = zr[0] - zi[0];
+    oim[(int64_t)M * ks + t] = T(0);
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+      const int j = M - k;
+      const T er = (zr[k] + zr[j]) * T(0.5), ei = (zi[k] - zi[j]) * T(0.5);
+      const T orr = (zi[k] + zi[j]) * T(0.5), oi = (zr[j] - zr[k]) * T(0.5);
+      const T wr = tw_re<T>(N, k), wi = tw_im<T>(N, k);
+      ore[(int64_t)k * ks + t] = er + (orr * wr - oi * wi);
+      oim[(int64_t)k * ks + t] = ei + (orr * wi + oi * wr);
+    }
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kTile) void irfft_kernel(const T* __restrict__ xre, const T* __restrict__ xim,
+                                                      int64_t ntubes, T* __restrict__ y) {
+  constexpr int M = N / 2;
+  constexpr int PAD = N + 1;
+  constexpr int VN = Vec16<T>::n;
+  using V = typename Vec16<T>::type;
+  __shared__ T lds[kTile * PAD];
+  const int lane = threadIdx.x;
+  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  const int64_t t = tile0 + lane;
+  const int64_t ks = ntubes;
+  if (t < ntubes) {
+    if constexpr (N == 1) {
+      lds[lane * PAD] = xre[t];
+    } else {
+      T Xr[M + 1], Xi[M + 1];
+#pragma unroll
+      for (int k = 0; k <= M; ++k) {
+        Xr[k] = xre[(int64_t)k * ks + t];
+        Xi[k] = (k == 0 || k == M) ? T(0) : xim[(int64_t)k * ks + t];
+      }
+      // Z[k] = E[k] + i O[k]; build conj(Z) for the forward-FFT-based inverse
+      T zr[M], zi[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const int j = M - k;
+        const T er = (Xr[k] + Xr[j]) * T(0.5), ei = (Xi[k] - Xi[j]) * T(0.5);
+        const T dr = (Xr[k] - Xr[j]) * T(0.5), di = (Xi[k] + Xi[j]) * T(0.5);
+        // O = d * conj(W_N^k)
+        const T wr = tw_re<T>(N, k), wi = -tw_im<T>(N, k);
+        const T orr = dr * wr - di * wi, oi = dr * wi + di * wr;
+        // Z = E + i O ; store conj(Z)
+        zr[k] = er - oi;
+        zi[k] = -(ei + orr);
+      }
+      cfft<T, M>(zr, zi);
+      const T inv = T(1) / T(M);
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        lds[lane * PAD + 2 * m] = zr[m] * inv;
+        lds[lane * PAD + 2 * m + 1] = -zi[m] * inv;
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (N % VN == 0) {
+    constexpr int CH = N / VN;
+#pragma unroll
+    for (int it = 0; it < CH; ++it) {
+      const int f = it * kTile + lane;
+      const int tl = f / CH, part = f - tl * CH;
+      const int64_t tt = tile0 + tl;
+      if (tt < ntubes) {
+        V w;
+        T* wp = reinterpret_cast<T*>(&w);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) wp[e] = lds[tl * PAD + part * VN + e];
+        *reinterpret_cast<V*>(y + tt * N + part * VN) = w;
+      }
+    }
+  } else {
+    for (int it = 0; it < N; ++it) {
+      const int f = it * kTile + lane;
+      const int tl = f / N, e = f - tl * N;
+      const int64_t tt = tile0 + tl;
+      if (tt < ntubes) y[tt * N + e] = lds[tl * PAD + e];
+    }
+  }
+}
+
+// Direct transforms for lengths without a specialised kernel.
+template <typename T>
+__global__ void rdft_direct_kernel(const T* __restrict__ x, int N, FwdArgs a, T* __restrict__ ore,
+                                   T* __restrict__ oim) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.ntubes) return;
+  const int K = N / 2 + 1;
+  int64_t src;
+  double s;
+  const bool live = tube_source(a, t, src, s);
+  for (int k = 0; k < K; ++k) {
+    double accr = 0, acci = 0;
+    if (live) {
+      for (int n = 0; n < N; ++n) {
+        double sn, cs;
+        sincospi(2.0 * (double)((int64_t)k * n % N) / (double)N, &sn, &cs);
+        const double v = (double)(T)((double)x[src * N + n] * s);
+        accr += v * cs;
+        acci -= v * sn;
+      }
+    }
+    ore[(int64_t)k * a.ntubes + t] = (T)accr;
+    oim[(int64_t)k * a.ntubes + t] = (k == 0 || 2 * k == N) ? T(0) : (T)acci;
+  }
+}
+
+template <typename T>
+__global__ void irdft_direct_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int N, int64_t ntubes,
+                                    T* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntubes) return;
+  const int K = N / 2 + 1;
+  for (int n = 0; n < N; ++n) {
+    double acc = 0;
+    for (int k = 0; k < K; ++k) {
+      const double wk = (k == 0 || 2 * k == N) ? 1.0 : 2.0;
+      double sn, cs;
+      sincospi(2.0 * (double)((int64_t)k * n % N) / (double)N, &sn, &cs);
+      const double xr = (double)xre[(int64_t)k * ntubes + t];
+      const double xi = (k == 0 || 2 * k == N) ? 0.0 : (double)xim[(int64_t)k * ntubes + t];
+      acc += wk * (xr * cs - xi * sn);
+    }
+    y[t * N + n] = (T)(acc / N);
+  }
+}
+
+template <typename T>
+using FwdKernel = void (*)(const T*, FwdArgs, T*, T*);
+template <typename T>
+using InvKernel = void (*)(const T*, const T*, int64_t, T*);
+
+template <typename T>
+FwdKernel<T> pick_fwd(int64_t n) {
+  switch (n) {
+    case 1: return rfft_kernel<T, 1>;
+    case 2: return rfft_kernel<T, 2>;
+    case 4: return rfft_kernel<T, 4>;
+    case 8: return rfft_kernel<T, 8>;
+    case 16: return rfft_kernel<T, 16>;
+    case 32: return rfft_kernel<T, 32>;
+    case 64: return rfft_kernel<T, 64>;
+    case 128: return rfft_kernel<T, 128>;
+    case 10: return rfft_kernel<T, 10>;
+    case 20: return rfft_kernel<T, 20>;
+    case 50: return rfft_kernel<T, 50>;
+    case 100: return rfft_kernel<T, 100>;
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+InvKernel<T> pick_inv(int64_t n) {
+  switch (n) {
+    case 1: return irfft_kernel<T, 1>;
+    case 2: return irfft_kernel<T, 2>;
+    case 4: return irfft_kernel<T, 4>;
+    case 8: return irfft_kernel<T, 8>;
+    case 16: return irfft_kernel<T, 16>;
+    case 32: return irfft_kernel<T, 32>;
+    case 64: return irfft_kernel<T, 64>;
+    case 128: return irfft_kernel<T, 128>;
+    case 10: return irfft_kernel<T, 10>;
+    case 20: return irfft_kernel<T, 20>;
+    case 50: return irfft_kernel<T, 50>;
+    case 100: return irfft_kernel<T, 100>;
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+int fwd_impl(const T* x, int64_t n3, const TubeGather& g, T* re, T* im, hipStream_t st) {
+  FwdArgs a{g.rows, g.cols, g.in_cols, g.rows * g.cols, g.row_idx, g.col_idx, g.row_scale, g.col_scale, g.count};
+  if (a.ntubes == 0) return TP_OK;
+  if (auto k = pick_fwd<T>(n3)) {
+    const int64_t blocks = (a.ntubes + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTile), 0, st, x, a, re, im);
+  } else {
+    const int64_t blocks = (a.ntubes + 127) / 128;
+    hipLaunchKernelGGL(rdft_direct_kernel<T>, dim3((unsigned)blocks), dim3(128), 0, st, x, (int)n3, a, re, im);
+  }
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+template <typename T>
+int inv_impl(const T* re, const T* im, int64_t n3, int64_t ntubes, T* y, hipStream_t st) {
+  if (ntubes == 0) return TP_OK;
+  if (auto k = pick_inv<T>(n3)) {
+    const int64_t blocks = (ntubes + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTile), 0, st, re, im, ntubes, y);
+  } else {
+    const int64_t blocks = (ntubes + 127) / 128;
+    hipLaunchKernelGGL(irdft_direct_kernel<T>, dim3((unsigned)blocks), dim3(128), 0, st, re, im, (int)n3, ntubes,
+                       y);
+  }
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+}  // namespace
+
+bool fft_supported(int64_t n3) { return pick_fwd<float>(n3) != nullptr; }
+
+int fft_forward(const void* x, int dtype, int64_t n3, const TubeGather& g, void* re, void* im, hipStream_t st) {
+  if (int rc = ensure_twiddles()) return rc;
+  if ((g.rows * g.cols + kTile - 1) / kTile > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+  if (dtype == TP_F64)
+    return fwd_impl<double>((const double*)x, n3, g, (double*)re, (double*)im, st);
+  return fwd_impl<float>((const float*)x, n3, g, (float*)re, (float*)im, st);
+}
+
+int fft_inverse(const void* re, const void* im, int dtype, int64_t n3, int64_t rows, int64_t cols, void* x,
+                hipStream_t st) {
+  if (int rc = ensure_twiddles()) return rc;
+  if (dtype == TP_F64)
+    return inv_impl<double>((const double*)re, (const double*)im, n3, rows * cols, (double*)x, st);
+  return inv_impl<float>((const float*)re, (const float*)im, n3, rows * cols, (float*)x, st);
+}
+
+}  // namespace tp

@@ -1,0 +1,175 @@
+// Per-Fourier-slice complex matrix products (Algorithm 1 step 5, Algorithm 2
+// step 15, the Fourier-domain products of Algorithms 3-5).
+//
+// Spectra are planar (separate re / im arrays, slice-major). Every slice k
+// is an independent product C_k = op(A_k) op(B_k); slices 0 and, for even
+// tube length, the Nyquist slice are real and skip the imaginary work.
+//
+// This file holds the general kernel (any op, any size, float or double,
+// LDS-tiled on the vector ALUs). The matrix-core kernels for the large
+// float32 products live in gemm_mfma.hip.
+#include "common.hpp"
+
+namespace tp {
+int cgemm_mfma(const CGemm& p, int prec, hipStream_t st, bool* handled);
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+struct GemmArgs {
+  int64_t M, N, Kd;
+  const void *are, *aim, *bre, *bim;
+  void *cre, *cim;
+  int64_t lda, ldb, ldc, sa, sb, sc;
+  int op_a, op_b;
+  int64_t K;
+  int real_last;
+  const int64_t* kdim_dev;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
+  __shared__ T As_re[BK][BM + 1], As_im[BK][BM + 1];
+  __shared__ T Bs_re[BK][BN + 1], Bs_im[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const int64_t k = blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  const bool real = (k == 0) || (g.real_last && k == g.K - 1);
+  int64_t Kd = g.Kd;
+  if (g.kdim_dev) {
+    const int64_t lim = *g.kdim_dev;
+    Kd = lim < Kd ? (lim < 0 ? 0 : lim) : Kd;
+  }
+  const T* are = (const T*)g.are + k * g.sa;
+  const T* aim = (const T*)g.aim + k * g.sa;
+  const T* bre = (const T*)g.bre + k * g.sb;
+  const T* bim = (const T*)g.bim + k * g.sb;
+
+  T cr[4][4], ci[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cr[i][j] = ci[i][j] = T(0);
+
+  for (int64_t k0 = 0; k0 < Kd; k0 += BK) {
+    // op(A) tile: BM x BK
+#pragma unroll
+    for (int r = 0; r < (BM * BK) / NT; ++r) {
+      int mm, kk;
+      if (g.op_a == 0) {
+        kk = tid % BK;
+        mm = tid / BK + r * (NT / BK);
+      } else {
+        mm = tid % BM;
+        kk = tid / BM + r * (NT / BM);
+      }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      T vr = T(0), vi = T(0);
+      if (gm < g.M && gk < Kd) {
+        const int64_t off = g.op_a == 0 ? gm * g.lda + gk : gk * g.lda + gm;
+        vr = are[off];
+        if (!real) vi = g.op_a == 0 ? aim[off] : -aim[off];
+      }
+      As_re[kk][mm] = vr;
+      As_im[kk][mm] = vi;
+    }
+    // op(B) tile: BK x BN
+#pragma unroll
+    for (int r = 0; r < (BN * BK) / NT; ++r) {
+      int nn, kk;
+      if (g.op_b == 0) {
+        nn = tid % BN;
+        kk = tid / BN + r * (NT / BN);
+      } else {
+        kk = tid % BK;
+        nn = tid / BK + r * (NT / BK);
+      }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      T vr = T(0), vi = T(0);
+      if (gn < g.N && gk < Kd) {
+        const int64_t off = g.op_b == 0 ? gk * g.ldb + gn : gn * g.ldb + gk;
+        vr = bre[off];
+        if (!real) vi = g.op_b == 0 ? bim[off] : -bim[off];
+      }
+      Bs_re[kk][nn] = vr;
+      Bs_im[kk][nn] = vi;
+    }
+    __syncthreads();
+    if (real) {
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        T a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = As_re[kk][ty + 16 * i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = Bs_re[kk][tx + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) cr[i][j] += a[i] * b[j];
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        T ar[4], ai[4], br[4], bi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ar[i] = As_re[kk][ty + 16 * i];
+          ai[i] = As_im[kk][ty + 16 * i];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          br[j] = Bs_re[kk][tx + 16 * j];
+          bi[j] = Bs_im[kk][tx + 16 * j];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            cr[i][j] += ar[i] * br[j] - ai[i] * bi[j];
+            ci[i][j] += ar[i] * bi[j] + ai[i] * br[j];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  T* cre = (T*)g.cre + k * g.sc;
+  T* cim = (T*)g.cim + k * g.sc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gm = m0 + ty + 16 * i;
+    if (gm >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gn = n0 + tx + 16 * j;
+      if (gn >= g.N) continue;
+      cre[gm * g.ldc + gn] = cr[i][j];
+      cim[gm * g.ldc + gn] = real ? T(0) : ci[i][j];
+    }
+  }
+}
+
+}  // namespace
+
+int cgemm(const CGemm& p, int dtype, int prec, hipStream_t st) {
+  if (p.K == 0 || p.M == 0 || p.N == 0) return TP_OK;
+  if (dtype == TP_F32 && prec != TP_PREC_F64) {
+    bool handled = false;
+    if (int rc = cgemm_mfma(p, prec, st, &handled)) return rc;
+    if (handled) return TP_OK;
+  }
+  GemmArgs g{p.M, p.N, p.Kd, p.are, p.aim, p.bre, p.bim, p.cre, p.cim, p.lda, p.ldb, p.ldc,
+             p.sa, p.sb, p.sc, p.op_a, p.op_b, p.K, p.real_last ? 1 : 0, p.kdim_dev};
+  if (p.K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
+  dim3 grid((unsigned)((p.N + BN - 1) / BN), (unsigned)((p.M + BM - 1) / BM), (unsigned)p.K);
+  if (dtype == TP_F64)
+    hipLaunchKernelGGL(cgemm_simt_kernel<double>, grid, dim3(NT), 0, st, g);
+  else
+    hipLaunchKernelGGL(cgemm_simt_kernel<float>, grid, dim3(NT), 0, st, g);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+}  // namespace tp

@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports what include/tprod.h declares; host
+argument validation rejects bad calls before touching the GPU."""
+import ctypes as C
+import subprocess
+
+import pytest
+
+from paper_1704_04362_amd import _lib as L
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = L.header_symbols()
+    assert "tp_tprod" in names and "tp_tsample" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert f" T {n}" in out, n
+
+
+def test_status_strings_and_version():
+    lib = L.load()
+    assert lib.tp_version() >= 100
+    assert lib.tp_status_string(0) == b"ok"
+    assert lib.tp_status_string(-2) == b"shape mismatch"
+
+
+def _t(n1, n2, n3, dtype=L.TP_F32, data=0x1000):
+    return L.Tensor(data, dtype, n1, n2, n3)
+
+
+@pytest.mark.parametrize("case", ["null", "inner", "tube", "outC", "dtype", "prec", "ws"])
+def test_tprod_validation(case):
+    lib = L.load()
+    A, B, Cc = _t(4, 5, 6), _t(5, 3, 6), _t(4, 3, 6)
+    prec = L.PREC["f32"]
+    ws, wsb = C.c_void_p(0x2000), 1 << 30
+    if case == "null":
+        A = _t(4, 5, 6, data=0)
+        want = -1
+    elif case == "inner":
+        B = _t(6, 3, 6)
+        want = -2
+    elif case == "tube":
+        B = _t(5, 3, 7)
+        want = -2
+    elif case == "outC":
+        Cc = _t(4, 4, 6)
+        want = -2
+    elif case == "dtype":
+        B = _t(5, 3, 6, dtype=L.TP_F64)
+        want = -3
+    elif case == "prec":
+        prec = L.PREC["f64"]
+        want = -3
+    else:
+        wsb = 16
+        want = -4
+    rc = lib.tp_tprod(C.byref(A), C.byref(B), None, C.byref(Cc), prec, ws, wsb, None)
+    assert rc == want, lib.tp_last_error()
+    assert lib.tp_last_error()
+
+
+def test_tsample_validation():
+    lib = L.load()
+    s = L.Sample(0x1000, 0x2000, 10, 0x3000)
+    ws = C.c_void_p(0x4000)
+    # c out of range
+    assert lib.tp_tsample(0, None, None, C.c_void_p(0x5000), 10, 11, 1, 0, 0, C.byref(s), ws, 1 << 20, None) == -1
+    assert lib.tp_tsample(0, None, None, C.c_void_p(0x5000), 10, 0, 1, 0, 0, C.byref(s), ws, 1 << 20, None) == -1
+    # Bernoulli needs capacity n
+    s2 = L.Sample(0x1000, 0x2000, 5, 0x3000)
+    assert lib.tp_tsample(0, None, None, C.c_void_p(0x5000), 10, 3, 0, 0, 0, C.byref(s2), ws, 1 << 20, None) == -1
+    # user weights missing
+    assert lib.tp_tsample(0, None, None, None, 10, 3, 1, 0, 0, C.byref(s), ws, 1 << 20, None) == -1
+    # workspace too small
+    assert lib.tp_tsample(0, None, None, C.c_void_p(0x5000), 10, 3, 1, 0, 0, C.byref(s), ws, 8, None) == -4
+    # norm2 with mismatched n
+    A = _t(4, 5, 6)
+    assert lib.tp_tsample(2, C.byref(A), None, None, 7, 3, 1, 0, 0, C.byref(s), ws, 1 << 20, None) == -2
+
+
+def test_spectrum_and_transform_validation():
+    lib = L.load()
+    X = _t(4, 5, 8)
+    bad = L.Spectrum(0x1000, 0x2000, L.TP_F32, 4, 4, 5)   # K should be 5
+    assert lib.tp_tfft(C.byref(X), C.byref(bad), None) == -2
+    good = L.Spectrum(0x1000, 0x2000, L.TP_F32, 5, 4, 5)
+    X64 = _t(4, 5, 8, dtype=L.TP_F64)
+    assert lib.tp_tfft(C.byref(X64), C.byref(good), None) == -3
+    A = L.Spectrum(0x1000, 0x2000, L.TP_F32, 3, 4, 5)
+    B = L.Spectrum(0x1000, 0x2000, L.TP_F32, 3, 6, 2)
+    Cs = L.Spectrum(0x1000, 0x2000, L.TP_F32, 3, 4, 2)
+    assert lib.tp_spectrum_matmul(C.byref(A), 0, C.byref(B), 0, C.byref(Cs), 1, 1, None) == -2
+    assert lib.tp_spectrum_matmul(C.byref(A), 2, C.byref(B), 0, C.byref(Cs), 1, 1, None) == -1

@@ -168,3 +168,28 @@ def test_tubal_rank_of_factor_product():
     G2 = rs.standard_normal((3, 9, 6))
     ranks = T.tubal_multirank(T.tprod_bcirc(G1, G2))
     assert max(ranks) == 3
+
+
+@pytest.mark.parametrize("n3", [1, 2, 5, 8])
+def test_half_spectrum_roundtrip_and_conjugate_symmetry(n3):
+    X = rs.standard_normal((3, 4, n3))
+    H = T.half_spectrum(X)
+    full = T.fft3(X)
+    for k in range(n3):
+        ref = H[k] if k < H.shape[0] else np.conj(H[n3 - k])
+        np.testing.assert_allclose(full[:, :, k], ref, atol=1e-12)
+    np.testing.assert_allclose(T.from_half_spectrum(H, n3), X, atol=1e-13)
+    # imaginary parts of the real slices are ignored by the inverse
+    H2 = H.copy()
+    H2[0] += 1j
+    if n3 % 2 == 0:
+        H2[-1] -= 2j
+    np.testing.assert_allclose(T.from_half_spectrum(H2, n3), X, atol=1e-13)
+
+
+def test_tprod_entries_match_definition():
+    A = rs.standard_normal((5, 6, 7))
+    B = rs.standard_normal((6, 4, 7))
+    Cref = T.tprod_bcirc(A, B)
+    ii, jj, kk = rs.integers(0, 5, 20), rs.integers(0, 4, 20), rs.integers(0, 7, 20)
+    np.testing.assert_allclose(T.tprod_entries(A, B, ii, jj, kk), Cref[ii, jj, kk], atol=1e-12)
