@@ -61,11 +61,13 @@ def tprod_bcirc(Z, X):
     X = np.asarray(X, dtype=np.float64)
     if n1 * n3 * n2 * n3 <= 4_000_000:
         return fold(circ(Z) @ unfold(X), n3)
+    Zs = [np.ascontiguousarray(Z[:, :, t]) for t in range(n3)]
+    Xs = [np.ascontiguousarray(X[:, :, t]) for t in range(n3)]
     C = np.zeros((n1, n4, n3))
     for k in range(n3):
         acc = np.zeros((n1, n4))
         for t in range(n3):
-            acc += Z[:, :, (k - t) % n3] @ X[:, :, t]
+            acc += Zs[(k - t) % n3] @ Xs[t]
         C[:, :, k] = acc
     return C
 
@@ -254,3 +256,18 @@ def tprod_entries(A, B, ii, jj, kk):
             acc += float(np.dot(A[i, :, (k - t) % n3].astype(np.float64), B[:, j, t].astype(np.float64)))
         out[e] = acc
     return out
+
+
+def tprod_slices(A, B, ks):
+    """Frontal slices C_{::k}, k in ks, of C = A * B by the block-row sum of
+    eq. tprod: C_{::k} = sum_t A_{::(k-t) mod n3} B_{::t}."""
+    n3 = A.shape[2]
+    As = [np.ascontiguousarray(A[:, :, t], dtype=np.float64) for t in range(n3)]
+    Bs = [np.ascontiguousarray(B[:, :, t], dtype=np.float64) for t in range(n3)]
+    out = []
+    for k in ks:
+        acc = np.zeros((A.shape[0], B.shape[1]))
+        for t in range(n3):
+            acc += As[(k - t) % n3] @ Bs[t]
+        out.append(acc)
+    return np.stack(out, axis=2)

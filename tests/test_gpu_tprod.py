@@ -236,3 +236,57 @@ def test_rtprod_bad_weights_give_zero():
     picks = api.tsample("user", 2, mode="iid", w=dev(np.zeros(3)))
     Z = api.tprod(dev(A), dev(B), picks=picks, prec="f64")
     assert not Z.any()
+
+
+# Split-precision products: each float32 value is hi + lo in bf16 and the
+# lo*lo term is dropped, a relative error of at most ~2^-16 per product
+# (2^-8 for each of the two dropped parts); summed over random signs the
+# relative Frobenius error stays near 2^-17 ~ 8e-6. The stated bound is 5e-5.
+# Plain bf16 (hi*hi only) carries ~2^-8 per operand: 1e-2.
+BF_TOL = {"bf16x3": 5e-5, "bf16": 1e-2}
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("K,M,N,Kd", [(5, 128, 128, 64), (3, 200, 130, 76), (2, 17, 300, 260), (33, 256, 128, 512)])
+def test_spectrum_matmul_split_bf16(prec, K, M, N, Kd):
+    rs = np.random.default_rng(M + N + Kd)
+    a = rs.standard_normal((K, M, Kd)) + 1j * rs.standard_normal((K, M, Kd))
+    b = rs.standard_normal((K, Kd, N)) + 1j * rs.standard_normal((K, Kd, N))
+    a = (a.real.astype(np.float32) + 1j * a.imag.astype(np.float32))
+    b = (b.real.astype(np.float32) + 1j * b.imag.astype(np.float32))
+    cre, cim = api.spectrum_matmul((dev(a.real), dev(a.imag)), (dev(b.real), dev(b.imag)), 0, 0, True, prec)
+    got = cre.cpu().numpy() + 1j * cim.cpu().numpy()
+    ref = _ref_matmul(a.astype(np.complex128), b.astype(np.complex128), 0, 0, True)
+    err = rel(got, ref)
+    assert err < BF_TOL[prec], err
+    assert not cim[0].any() and not cim[-1].any()
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("shape", [(96, 130, 70, 64), (128, 256, 128, 16), (40, 52, 30, 100)])
+def test_tprod_split_bf16_matches_bcirc(prec, shape):
+    n1, n2, n4, n3 = shape
+    rs = np.random.default_rng(sum(shape) + 3)
+    A = rs.standard_normal((n1, n2, n3)).astype(np.float32)
+    B = rs.standard_normal((n2, n4, n3)).astype(np.float32)
+    Cg = api.tprod(dev(A), dev(B), prec=prec).cpu().numpy()
+    assert rel(Cg, T.tprod_bcirc(A, B)) < BF_TOL[prec]
+
+
+def test_tprod_full_size_bf16x3_sampled_entries():
+    A, B = W.rtprod_pair()
+    Cg = api.tprod(dev(A), dev(B), prec="bf16x3").cpu().numpy()
+    rs = np.random.default_rng(12)
+    ii, jj, kk = rs.integers(0, 512, 256), rs.integers(0, 512, 256), rs.integers(0, 64, 256)
+    assert rel(Cg[ii, jj, kk], T.tprod_entries(A, B, ii, jj, kk)) < BF_TOL["bf16x3"]
+
+
+@pytest.mark.parametrize("mode", ["iid", "bernoulli"])
+def test_rtprod_bf16x3_matches_oracle(mode):
+    A, B = W.rtprod_pair(n1=256, n2=1024, n4=128, n3=64)
+    picks = api.tsample("norm2", 128, mode=mode, seed=11, A=dev(A))
+    Z = api.tprod(dev(A), dev(B), picks=picks, prec="bf16x3").cpu().numpy()
+    ridx, rsc = S.sample(S.weights_norm2(A), 128, mode, seed=11)
+    idx, _ = picks.host()
+    np.testing.assert_array_equal(idx.numpy(), ridx)
+    assert rel(Z, D.rtprod(A, B, ridx, rsc)) < BF_TOL["bf16x3"]

@@ -193,3 +193,9 @@ def test_tprod_entries_match_definition():
     Cref = T.tprod_bcirc(A, B)
     ii, jj, kk = rs.integers(0, 5, 20), rs.integers(0, 4, 20), rs.integers(0, 7, 20)
     np.testing.assert_allclose(T.tprod_entries(A, B, ii, jj, kk), Cref[ii, jj, kk], atol=1e-12)
+
+
+def test_tprod_slices_match_definition():
+    A = rs.standard_normal((4, 6, 5))
+    B = rs.standard_normal((6, 3, 5))
+    np.testing.assert_allclose(T.tprod_slices(A, B, [0, 3]), T.tprod_bcirc(A, B)[:, :, [0, 3]], atol=1e-12)
