@@ -125,7 +125,7 @@ const char* tp_last_error(void);
 int tp_version(void);
 
 /* ---------------------------------------------------------------------------
- * Fourier engine (Section 2.1 operators; Algorithm 1 steps 2-3 and 7).
+ * Fourier engine (Section 2.1 operators; the transforms of Algorithm 1).
  * ------------------------------------------------------------------------- */
 
 /* Forward transform of every tube: Xh = first K slices of fft(X, [], 3).
@@ -156,8 +156,7 @@ int tp_slice_norms(const tp_tensor* A, int mode, double* out, void* ws, size_t w
 size_t tp_slice_norms_workspace(const tp_tensor* A, int mode);
 
 /* ---------------------------------------------------------------------------
- * Sampling (Algorithm 2 lines 4-11, Algorithm 4 lines 5-12, Algorithm 5
- * lines 6-13).
+ * Sampling (the pick loops of Algorithms 2, 4 and 5).
  * ------------------------------------------------------------------------- */
 
 /* Picks slices of a set of n candidates.
@@ -175,7 +174,7 @@ int tp_tsample(int kind, const tp_tensor* A, const tp_tensor* B, const double* w
 size_t tp_tsample_workspace(int64_t n);
 
 /* ---------------------------------------------------------------------------
- * t-product (Algorithm 1) and rt-product (Algorithm 2 lines 12-17).
+ * t-product (Algorithm 1) and rt-product (Algorithm 2).
  * ------------------------------------------------------------------------- */
 
 /* C = A * B (sample == NULL), or C = (A*S*D) * (D*S^T*B) where S, D are the
@@ -187,6 +186,53 @@ size_t tp_tsample_workspace(int64_t n);
 int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp_tensor* C, int prec, void* ws,
              size_t ws_bytes, void* stream);
 size_t tp_tprod_workspace(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, int prec);
+
+/* ---------------------------------------------------------------------------
+ * Randomized t-SVD and tubal leverage scores (Theorem "t-SVD", eq. circ1;
+ * eqs. cur-col-prob and colprob_rows_exact).
+ * ------------------------------------------------------------------------- */
+
+/* Leading-r t-SVD of A by a Gaussian range finder applied to every
+ * non-redundant Fourier slice (s = r + p sketch columns, q power
+ * iterations; Halko, Martinsson, Tropp 2011), with an orthonormalisation
+ * through the float64 eigen-decomposition of the s x s Gram matrix.
+ * Outputs (device float64 arrays, each may be NULL):
+ *   S              K x r singular values of the Fourier slices, descending;
+ *   lev_lateral    n2 values ||Vhat_{j::}||_F^2 summed over all n3 Fourier
+ *                  slices (the lateral leverage scores before normalisation;
+ *                  they sum to r n3 when every slice has rank >= r);
+ *   lev_horizontal n1 values ||Uhat_{i::}||_F^2, likewise.
+ * r + p <= 64 (p is capped so that r + p <= min(n1, n2)); prec
+ * TP_PREC_F64 (float64 data), TP_PREC_F32 or TP_PREC_BF16X3 (float32 data;
+ * the small eigenproblems are float64 in every case). */
+int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, uint64_t seed, int prec, double* S,
+                 double* lev_lateral, double* lev_horizontal, void* ws, size_t ws_bytes, void* stream);
+size_t tp_tsvd_rand_workspace(const tp_tensor* A, int64_t r, int64_t p, int prec);
+
+/* ---------------------------------------------------------------------------
+ * t-CUR (Definition "t-CUR", Algorithm 5).
+ * ------------------------------------------------------------------------- */
+
+/* Picks c lateral slices of A by col_kind (TP_P_USER with col_w, a device
+ * array of n2 float64 weights; TP_P_UNIFORM; TP_P_NORM2; TP_P_LEV, lateral
+ * leverage of the rank-r t-SVD estimated as in tp_tsvd_rand with p = 10,
+ * q = 1), forms Chat_k = Ahat_k S D, then picks l horizontal slices by
+ * row_kind (TP_P_USER with row_w, n1 weights; TP_P_UNIFORM; TP_P_NORM2 of
+ * A's horizontal slices; TP_P_LEV, horizontal leverage of C from its top-r
+ * left singular slices) and returns
+ *     Z = ifft(Chat_k pinv_r(D S^T Chat_k) D S^T Ahat_k)
+ * where pinv_r keeps the r leading singular values of every Fourier slice
+ * of the core (and drops those <= max(l, c) eps sigma_1); the core is
+ * computed in float64 by a range finder with 10 extra columns and 2 power
+ * iterations. Column picks use stream 0, row picks stream 1 of `seed`.
+ * cols/rows receive the picks (capacity >= c and l, or n2 and n1 for
+ * TP_S_BERNOULLI). Z (same shape and dtype as A) may be NULL to only draw
+ * the picks. r <= min(c, l), r + 10 <= 64. */
+int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, const double* col_w, int row_kind,
+            const double* row_w, int mode, uint64_t seed, tp_sample* cols, tp_sample* rows, tp_tensor* Z, int prec,
+            void* ws, size_t ws_bytes, void* stream);
+size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind, int mode,
+                         int prec);
 
 #ifdef __cplusplus
 }

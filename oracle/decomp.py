@@ -185,3 +185,33 @@ def admm_complete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=Non
         hist.append(rec)
         mu = min(rho * mu, mu_max)
     return L, E, Y, hist
+
+
+def tcur_tubes(Csl, Rsl, cscale, ridx, rscale, r, ii, jj):
+    """Selected tubes Z[ii[e], jj[e], :] of the t-CUR approximation of
+    Algorithm 5, from the only parts of A the algorithm reads: the picked
+    lateral slices Csl = A[:, cidx, :] and horizontal slices
+    Rsl = A[ridx, :, :] (both unscaled). Per Fourier slice,
+    Chat_k = fft(Csl)_k D_c, Rhat_k = D_r fft(Rsl)_k, Uhat_k =
+    pinv_r(D_r S^T Chat_k) and Zhat_k[i, j] = Chat_k[i, :] Uhat_k Rhat_k[:, j];
+    the tube is the inverse transform of Zhat[i, j, :]."""
+    Csl = np.asarray(Csl, dtype=np.float64)
+    Rsl = np.asarray(Rsl, dtype=np.float64)
+    n3 = Csl.shape[2]
+    ridx = np.asarray(ridx, dtype=np.int64)
+    cscale = np.asarray(cscale, dtype=np.float64)
+    rscale = np.asarray(rscale, dtype=np.float64)
+    ii = np.asarray(ii, dtype=np.int64)
+    jj = np.asarray(jj, dtype=np.int64)
+    K = T.half_spectrum_count(n3)
+    Hc = T.half_spectrum(Csl)  # (K, n1, c)
+    Hr = T.half_spectrum(Rsl)  # (K, l, n2)
+    Zh = np.zeros((len(ii), n3), dtype=complex)
+    for k in range(K):
+        Ck = (Hc[k].real if _is_real_slice(k, n3) else Hc[k]) * cscale[None, :]
+        Rk = rscale[:, None] * (Hr[k].real if _is_real_slice(k, n3) else Hr[k])
+        Uk = pinv_r(rscale[:, None] * Ck[ridx, :], r)
+        Zh[:, k] = np.einsum("ec,ce->e", Ck[ii, :] @ Uk, Rk[:, jj])
+    for k in range(K, n3):
+        Zh[:, k] = Zh[:, n3 - k].conj()
+    return T._real_part_checked(np.fft.ifft(Zh, axis=1))

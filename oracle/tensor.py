@@ -93,7 +93,8 @@ def _real_part_checked(Y):
 def slice_matmul(Ah, Bh):
     """Per-frontal-slice matrix product of two spectra:
     out[:, :, k] = Ah[:, :, k] @ Bh[:, :, k]."""
-    return np.einsum("isk,sjk->ijk", Ah, Bh)
+    prod = np.matmul(np.ascontiguousarray(np.moveaxis(Ah, 2, 0)), np.ascontiguousarray(np.moveaxis(Bh, 2, 0)))
+    return np.moveaxis(prod, 0, 2)
 
 
 def tprod_fft(Z, X):

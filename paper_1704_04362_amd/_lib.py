@@ -41,6 +41,14 @@ _SIGS = {
     "tp_tprod": (C.c_int, [P(Tensor), P(Tensor), P(Sample), P(Tensor), C.c_int, C.c_void_p, C.c_size_t,
                            C.c_void_p]),
     "tp_tprod_workspace": (C.c_size_t, [P(Tensor), P(Tensor), P(Sample), C.c_int]),
+    "tp_tsvd_rand": (C.c_int, [P(Tensor), C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_int, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_tsvd_rand_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int]),
+    "tp_tcur": (C.c_int, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                          C.c_int, C.c_uint64, P(Sample), P(Sample), P(Tensor), C.c_int, C.c_void_p, C.c_size_t,
+                          C.c_void_p]),
+    "tp_tcur_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                       C.c_int]),
 }
 
 _lib = None

@@ -154,3 +154,50 @@ def tprod(A, B, picks=None, prec=None, out=None):
     L.check(lib.tp_tprod(C.byref(ta), C.byref(tb), sp, C.byref(tc), L.PREC[prec], ws.data_ptr(), ws.numel(),
                          _stream()))
     return C_
+
+
+def tsvd_rand(A, r, p=10, q=1, seed=0, prec=None):
+    """Leading-r t-SVD summary by the randomized range finder: returns
+    (S, lev_lateral, lev_horizontal) with S the K x r singular values of the
+    Fourier slices and the unnormalised tubal leverage scores (float64)."""
+    _need_gpu(A)
+    if prec is None:
+        prec = "f64" if A.dtype == torch.float64 else "f32"
+    n1, n2, n3 = A.shape
+    K = half_count(n3)
+    S = torch.empty((K, r), dtype=torch.float64, device=A.device)
+    lat = torch.empty(n2, dtype=torch.float64, device=A.device)
+    hor = torch.empty(n1, dtype=torch.float64, device=A.device)
+    lib = L.load()
+    t = _tensor(A)
+    ws = _ws(lib.tp_tsvd_rand_workspace(C.byref(t), r, p, L.PREC[prec]), A.device)
+    L.check(lib.tp_tsvd_rand(C.byref(t), int(r), int(p), int(q), int(seed), L.PREC[prec], S.data_ptr(),
+                             lat.data_ptr(), hor.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return S, lat, hor
+
+
+def tcur(A, c, l, r, col_kind="lev", row_kind="lev", col_w=None, row_w=None, mode="iid", seed=0, prec=None,
+         want_z=True, out=None):
+    """t-CUR of Algorithm 5: returns (Z, column picks, row picks); Z is None
+    when want_z is False."""
+    _need_gpu(A, col_w, row_w)
+    if prec is None:
+        prec = "f64" if A.dtype == torch.float64 else "f32"
+    n1, n2, n3 = A.shape
+    cols = Picks(n2 if mode == "bernoulli" else c, A.device)
+    rows = Picks(n1 if mode == "bernoulli" else l, A.device)
+    Z = None
+    if want_z:
+        Z = out if out is not None else torch.empty_like(A)
+    lib = L.load()
+    t = _tensor(A)
+    tz = _tensor(Z) if Z is not None else None
+    cs, rs_ = cols.struct(), rows.struct()
+    ws = _ws(lib.tp_tcur_workspace(C.byref(t), c, l, r, L.KIND[col_kind], L.KIND[row_kind], L.MODE[mode],
+                                   L.PREC[prec]), A.device)
+    L.check(lib.tp_tcur(C.byref(t), int(c), int(l), int(r), L.KIND[col_kind],
+                        col_w.data_ptr() if col_w is not None else None, L.KIND[row_kind],
+                        row_w.data_ptr() if row_w is not None else None, L.MODE[mode], int(seed), C.byref(cs),
+                        C.byref(rs_), C.byref(tz) if tz is not None else None, L.PREC[prec], ws.data_ptr(),
+                        ws.numel(), _stream()))
+    return Z, cols, rows

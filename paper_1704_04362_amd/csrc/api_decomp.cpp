@@ -1,0 +1,454 @@
+// C ABI of the randomized decompositions: tubal-rank-r t-SVD by a Gaussian
+// range finder (the t-SVD theorem computed slice by slice in the Fourier
+// domain), tubal leverage scores (eqs. cur-col-prob, colprob_rows_exact) and
+// t-CUR (Algorithm 5). Validation, workspace planning and kernel order only.
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "common.hpp"
+#include "linalg.hpp"
+
+namespace tp {
+namespace {
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct Spec {
+  void* re = nullptr;
+  void* im = nullptr;
+};
+
+Spec take(Arena& ar, int64_t n, int dtype) {
+  Spec s;
+  if (dtype == TP_F64) {
+    s.re = ar.take<double>(n);
+    s.im = ar.take<double>(n);
+  } else {
+    s.re = ar.take<float>(n);
+    s.im = ar.take<float>(n);
+  }
+  return s;
+}
+
+// Batched product C_k = op(A_k) op(B_k) over row-major slices.
+int mm(const Spec& A, int op_a, int64_t a_rows, int64_t a_cols, const Spec& B, int op_b, int64_t b_rows,
+       int64_t b_cols, const Spec& C, int64_t K, bool real_last, int dtype, int prec, hipStream_t st,
+       const int64_t* kdim_dev = nullptr) {
+  CGemm p;
+  p.K = K;
+  p.M = op_a ? a_cols : a_rows;
+  p.Kd = op_a ? a_rows : a_cols;
+  p.N = op_b ? b_rows : b_cols;
+  p.are = A.re;
+  p.aim = A.im;
+  p.bre = B.re;
+  p.bim = B.im;
+  p.cre = C.re;
+  p.cim = C.im;
+  p.lda = a_cols;
+  p.ldb = b_cols;
+  p.ldc = p.N;
+  p.sa = a_rows * a_cols;
+  p.sb = b_rows * b_cols;
+  p.sc = p.M * p.N;
+  p.op_a = op_a;
+  p.op_b = op_b;
+  p.real_last = real_last;
+  p.kdim_dev = kdim_dev;
+  return cgemm(p, dtype, prec, st);
+}
+
+// Range finder for a batch of m x n slices X_k: an orthonormal basis Q_k
+// (m x s) of the range of X_k Omega_k after q power iterations, the
+// projected matrix Bh_k = X_k^H Q_k (n x s), and the eigen-decomposition of
+// Bh_k^H Bh_k = Q_k^H X_k X_k^H Q_k = U_B diag(lambda) U_B^H, so that the
+// singular values of Q^H X are sqrt(lambda) with left vectors U_B and right
+// vectors Bh U_B diag(lambda)^-1/2 (Halko, Martinsson, Tropp 2011).
+struct RangeFinder {
+  int64_t K, m, n;
+  int s;
+  int dtype;  // of X, Q, Bh
+  bool real_last;
+  Spec omega, Y, Q, Bh, Z, T;
+  double *gre, *gim, *evals, *ure, *uim;
+
+  bool carve(Arena& ar) {
+    omega = take(ar, K * n * s, dtype);
+    Y = take(ar, K * m * s, dtype);
+    Q = take(ar, K * m * s, dtype);
+    Bh = take(ar, K * n * s, dtype);
+    Z = take(ar, K * n * s, dtype);
+    T = take(ar, K * s * s, dtype);
+    gre = ar.take<double>(K * s * s);
+    gim = ar.take<double>(K * s * s);
+    ure = ar.take<double>(K * s * s);
+    uim = ar.take<double>(K * s * s);
+    evals = ar.take<double>(K * s);
+    return ar.dry() || ar.ok();
+  }
+
+  // out = orthonormal basis of the columns of X (rows x s) through
+  // X^H X = V diag(l) V^H, out = X V diag(l^-1/2), directions with
+  // l <= rtol l_max dropped (zero columns).
+  int orth(const Spec& X, int64_t rows, const Spec& out, int prec, hipStream_t st) const {
+    const double rtol = dtype == TP_F64 ? 1e-24 : 1e-11;
+    if (int rc = gram(X.re, X.im, dtype, K, rows, s, s, rows * s, real_last, gre, gim, st)) return rc;
+    if (int rc = herm_eig(gre, gim, K, s, evals, ure, uim, st)) return rc;
+    if (int rc = eig_transform(ure, uim, evals, K, s, s, 0, rtol, 0.0, T.re, T.im, dtype, st)) return rc;
+    return mm(X, 0, rows, s, T, 0, s, s, out, K, real_last, dtype, prec, st);
+  }
+
+  int run(const Spec& X, int q, uint64_t seed, uint64_t stream_id, int prec, hipStream_t st,
+          const int64_t* ncols_dev = nullptr) {
+    if (int rc = randn_spectrum(omega.re, omega.im, dtype, K, n, s, real_last, seed, stream_id, st)) return rc;
+    // Y = X Omega, Q = orth(orth(Y))
+    if (int rc = mm(X, 0, m, n, omega, 0, n, s, Y, K, real_last, dtype, prec, st, ncols_dev)) return rc;
+    if (int rc = orth(Y, m, Q, prec, st)) return rc;
+    if (int rc = orth(Q, m, Y, prec, st)) return rc;
+    std::swap(Q, Y);
+    for (int it = 0; it < q; ++it) {
+      // Z = orth(X^H Q), Q = orth(orth(X Z))
+      if (int rc = mm(X, 1, m, n, Q, 0, m, s, Bh, K, real_last, dtype, prec, st)) return rc;
+      if (int rc = orth(Bh, n, Z, prec, st)) return rc;
+      if (int rc = mm(X, 0, m, n, Z, 0, n, s, Y, K, real_last, dtype, prec, st, ncols_dev)) return rc;
+      if (int rc = orth(Y, m, Q, prec, st)) return rc;
+      if (int rc = orth(Q, m, Y, prec, st)) return rc;
+      std::swap(Q, Y);
+    }
+    if (int rc = mm(X, 1, m, n, Q, 0, m, s, Bh, K, real_last, dtype, prec, st)) return rc;
+    if (int rc = gram(Bh.re, Bh.im, dtype, K, n, s, s, n * s, real_last, gre, gim, st)) return rc;
+    return herm_eig(gre, gim, K, s, evals, ure, uim, st);
+  }
+};
+
+int check_tensor(const tp_tensor* t, const char* name) {
+  if (!t) return fail(TP_EINVAL, std::string(name) + " is null");
+  if (t->dtype != TP_F32 && t->dtype != TP_F64) return fail(TP_EDTYPE, std::string(name) + ": unknown dtype");
+  if (t->n1 < 1 || t->n2 < 1 || t->n3 < 1) return fail(TP_ESHAPE, std::string(name) + ": empty tensor");
+  if (!t->data) return fail(TP_EINVAL, std::string(name) + ": data is null");
+  return TP_OK;
+}
+
+int check_prec(int dtype, int prec) {
+  if (prec == TP_PREC_F64) return dtype == TP_F64 ? TP_OK : fail(TP_EDTYPE, "TP_PREC_F64 needs float64 data");
+  if (prec == TP_PREC_F32 || prec == TP_PREC_BF16X3)
+    return dtype == TP_F32 ? TP_OK : fail(TP_EDTYPE, "float32 precisions need float32 data");
+  return fail(TP_EDTYPE, "precision not available for decompositions");
+}
+
+constexpr int kOversample = 10;
+constexpr int kPowerIters = 1;
+constexpr int kCorePowerIters = 2;
+// stream ids of the generator draws inside one call
+constexpr uint64_t kStreamColPick = 0, kStreamRowPick = 1, kStreamOmegaA = 2, kStreamOmegaC = 3, kStreamOmegaW = 4;
+
+int sketch_size(int64_t r, int64_t p, int64_t m, int64_t n) {
+  int64_t s = r + p;
+  s = std::min<int64_t>(s, std::min<int64_t>(m, n));
+  s = std::max<int64_t>(s, r);
+  return (int)s;
+}
+
+// Every buffer of one tp_tsvd_rand call, carved in a fixed order so that the
+// workspace query (dry run) and the call agree.
+struct TsvdLayout {
+  Spec Ah, Ub, Vs, Us;
+  RangeFinder rf;
+  bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int s, int64_t r, int dt, bool real_last) {
+    Ah = take(ar, K * n1 * n2, dt);
+    rf = RangeFinder{K, n1, n2, s, dt, real_last};
+    rf.carve(ar);
+    Ub = take(ar, K * s * r, dt);
+    Vs = take(ar, K * n2 * r, dt);
+    Us = take(ar, K * n1 * r, dt);
+    return ar.dry() || ar.ok();
+  }
+};
+
+struct TcurLayout {
+  double *wbuf = nullptr, *wbuf2 = nullptr, *part = nullptr;
+  void* sws = nullptr;
+  Spec Ah, UbA, Vs;          // column leverage
+  RangeFinder rfA, rfC, cf;  // range finders on A, C and the core
+  Spec Ch, UbC, Us;          // C and its row leverage
+  Spec Rh, W, Tr, Tp, P64, U64, P, Ur, F, G, Zh;
+  int sA = 0, sC = 0, sw = 0;
+  bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int64_t n3, int64_t capc, int64_t capl, int64_t r,
+             int col_kind, int row_kind, bool want_z, int dt, bool real_last) {
+    const int64_t nmax = std::max(n1, n2);
+    wbuf = ar.take<double>(nmax);
+    wbuf2 = ar.take<double>(nmax);
+    sws = ar.take<char>(sampler_ws(nmax));
+    part = ar.take<double>(lateral_norms_ws(n1, n2, n3) / 8 + 1);
+    if (col_kind == TP_P_LEV) {
+      sA = sketch_size(r, kOversample, n1, n2);
+      Ah = take(ar, K * n1 * n2, dt);
+      rfA = RangeFinder{K, n1, n2, sA, dt, real_last};
+      rfA.carve(ar);
+      UbA = take(ar, K * sA * r, dt);
+      Vs = take(ar, K * n2 * r, dt);
+    }
+    Ch = take(ar, K * n1 * capc, dt);
+    if (row_kind == TP_P_LEV) {
+      sC = sketch_size(r, kOversample, n1, capc);
+      rfC = RangeFinder{K, n1, capc, sC, dt, real_last};
+      rfC.carve(ar);
+      UbC = take(ar, K * sC * r, dt);
+      Us = take(ar, K * n1 * r, dt);
+    }
+    if (want_z) {
+      Rh = take(ar, K * capl * n2, dt);
+      W = take(ar, K * capl * capc, TP_F64);
+      sw = sketch_size(r, kOversample, capl, capc);
+      cf = RangeFinder{K, capl, capc, sw, TP_F64, real_last};
+      cf.carve(ar);
+      Tr = take(ar, K * sw * r, TP_F64);
+      Tp = take(ar, K * sw * r, TP_F64);
+      P64 = take(ar, K * capc * r, TP_F64);
+      U64 = take(ar, K * capl * r, TP_F64);
+      P = take(ar, K * capc * r, dt);
+      Ur = take(ar, K * capl * r, dt);
+      F = take(ar, K * n1 * r, dt);
+      G = take(ar, K * r * n2, dt);
+      Zh = take(ar, K * n1 * n2, dt);
+    }
+    return ar.dry() || ar.ok();
+  }
+};
+
+}  // namespace
+}  // namespace tp
+
+using namespace tp;
+
+extern "C" {
+
+size_t tp_tsvd_rand_workspace(const tp_tensor* A, int64_t r, int64_t p, int prec) {
+  (void)prec;
+  if (!A || A->n1 < 1 || A->n2 < 1 || A->n3 < 1 || r < 1) return 0;
+  const int64_t K = half_count(A->n3);
+  Arena dry(nullptr, SIZE_MAX);
+  TsvdLayout lay;
+  lay.carve(dry, K, A->n1, A->n2, sketch_size(r, p, A->n1, A->n2), r, A->dtype, (A->n3 % 2 == 0) && K > 1);
+  return dry.used + 256;
+}
+
+int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, uint64_t seed, int prec, double* S_out,
+                 double* lev_lateral, double* lev_horizontal, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_tensor(A, "A")) return rc;
+  if (int rc = check_prec(A->dtype, prec)) return rc;
+  if (r < 1 || r > std::min(A->n1, A->n2)) return fail(TP_EINVAL, "need 1 <= r <= min(n1, n2)");
+  if (p < 0 || q < 0) return fail(TP_EINVAL, "oversampling and power iterations must be >= 0");
+  const int s = sketch_size(r, p, A->n1, A->n2);
+  if (s > kMaxS) return fail(TP_EUNSUPPORTED, "r + p above 64");
+  const size_t need = tp_tsvd_rand_workspace(A, r, p, prec);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tsvd_rand workspace too small");
+  const int64_t n1 = A->n1, n2 = A->n2, n3 = A->n3, K = half_count(n3);
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  const int dt = A->dtype;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  TsvdLayout lay;
+  if (!lay.carve(ar, K, n1, n2, s, r, dt, real_last)) return fail(TP_EWORKSPACE, "tsvd_rand workspace too small");
+  Spec &Ah = lay.Ah, &Ub = lay.Ub, &Vs = lay.Vs, &Us = lay.Us;
+  RangeFinder& rf = lay.rf;
+
+  TubeGather g;
+  g.rows = n1;
+  g.cols = n2;
+  g.in_cols = n2;
+  if (int rc = fft_forward(A->data, dt, n3, g, Ah.re, Ah.im, st)) return rc;
+  if (int rc = rf.run(Ah, q, seed, kStreamOmegaA, prec, st)) return rc;
+  const double rtol = dt == TP_F64 ? 1e-12 : 1e-6;
+  if (S_out)
+    if (int rc = singular_values(rf.evals, K, s, (int)r, S_out, st)) return rc;
+  // U_B restricted to the leading r eigenvectors
+  if (int rc = eig_transform(rf.ure, rf.uim, rf.evals, K, s, (int)r, 1, rtol, 0.0, Ub.re, Ub.im, dt, st)) return rc;
+  if (lev_lateral) {
+    // right singular vectors V = Bh U_B diag(sigma)^-1: rows scaled inside the
+    // leverage reduction
+    if (int rc = mm(rf.Bh, 0, n2, s, Ub, 0, s, r, Vs, K, real_last, dt, prec, st)) return rc;
+    if (int rc = leverage(Vs.re, Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, rf.evals, s, rtol, lev_lateral, st))
+      return rc;
+  }
+  if (lev_horizontal) {
+    // left singular vectors U = Q U_B
+    if (int rc = mm(rf.Q, 0, n1, s, Ub, 0, s, r, Us, K, real_last, dt, prec, st)) return rc;
+    if (int rc = leverage(Us.re, Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol, lev_horizontal,
+                          st))
+      return rc;
+  }
+  return TP_OK;
+}
+
+size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind, int mode,
+                         int prec) {
+  (void)prec;
+  if (!A || A->n1 < 1 || A->n2 < 1 || A->n3 < 1 || r < 1 || c < 1 || l < 1) return 0;
+  const int64_t K = half_count(A->n3);
+  const int64_t capc = mode == TP_S_BERNOULLI ? A->n2 : c;
+  const int64_t capl = mode == TP_S_BERNOULLI ? A->n1 : l;
+  Arena dry(nullptr, SIZE_MAX);
+  TcurLayout lay;
+  lay.carve(dry, K, A->n1, A->n2, A->n3, capc, capl, r, col_kind, row_kind, true, A->dtype,
+            (A->n3 % 2 == 0) && K > 1);
+  return dry.used + 256;
+}
+
+int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, const double* col_w, int row_kind,
+            const double* row_w, int mode, uint64_t seed, tp_sample* cols, tp_sample* rows, tp_tensor* Z, int prec,
+            void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_tensor(A, "A")) return rc;
+  if (int rc = check_prec(A->dtype, prec)) return rc;
+  const int64_t n1 = A->n1, n2 = A->n2, n3 = A->n3, K = half_count(n3);
+  if (c < 1 || c > n2) return fail(TP_EINVAL, "need 1 <= c <= n2");
+  if (l < 1 || l > n1) return fail(TP_EINVAL, "need 1 <= l <= n1");
+  if (r < 1 || r > std::min(c, l)) return fail(TP_EINVAL, "need 1 <= r <= min(c, l)");
+  if (mode != TP_S_BERNOULLI && mode != TP_S_IID && mode != TP_S_UNIFORM) return fail(TP_EINVAL, "unknown mode");
+  auto kind_ok = [](int k) { return k == TP_P_USER || k == TP_P_UNIFORM || k == TP_P_NORM2 || k == TP_P_LEV; };
+  if (!kind_ok(col_kind) || !kind_ok(row_kind)) return fail(TP_EINVAL, "unsupported probability kind");
+  if (col_kind == TP_P_USER && !col_w) return fail(TP_EINVAL, "column weights are null");
+  if (row_kind == TP_P_USER && !row_w) return fail(TP_EINVAL, "row weights are null");
+  if (!cols || !rows || !cols->idx || !cols->scale || !cols->count || !rows->idx || !rows->scale || !rows->count)
+    return fail(TP_EINVAL, "pick buffers are null");
+  const int64_t capc = mode == TP_S_BERNOULLI ? n2 : c;
+  const int64_t capl = mode == TP_S_BERNOULLI ? n1 : l;
+  if (cols->cap < capc || rows->cap < capl)
+    return fail(TP_EINVAL, "pick capacity must be >= c, l (or n2, n1 for Bernoulli picks)");
+  if (Z) {
+    if (Z->dtype != A->dtype || Z->n1 != n1 || Z->n2 != n2 || Z->n3 != n3 || !Z->data)
+      return fail(TP_ESHAPE, "Z must match A");
+  }
+  if (sketch_size(r, kOversample, n1, n2) > kMaxS) return fail(TP_EUNSUPPORTED, "r + 10 above 64");
+  const size_t need = tp_tcur_workspace(A, c, l, r, col_kind, row_kind, mode, prec);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tcur workspace too small");
+
+  const int dt = A->dtype;
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  TcurLayout lay;
+  if (!lay.carve(ar, K, n1, n2, n3, capc, capl, r, col_kind, row_kind, Z != nullptr, dt, real_last))
+    return fail(TP_EWORKSPACE, "tcur workspace too small");
+  const double rtol = dt == TP_F64 ? 1e-12 : 1e-6;
+
+  // 1. column probabilities and picks (Algorithm 5 takes C as an input; it is
+  //    drawn here as in Algorithm 4, by lateral leverage, norms, uniformly or
+  //    from caller weights)
+  const double* wcol = col_w;
+  if (col_kind == TP_P_LEV) {
+    TubeGather g;
+    g.rows = n1;
+    g.cols = n2;
+    g.in_cols = n2;
+    const int s = lay.sA;
+    if (int rc = fft_forward(A->data, dt, n3, g, lay.Ah.re, lay.Ah.im, st)) return rc;
+    if (int rc = lay.rfA.run(lay.Ah, kPowerIters, seed, kStreamOmegaA, prec, st)) return rc;
+    if (int rc = eig_transform(lay.rfA.ure, lay.rfA.uim, lay.rfA.evals, K, s, (int)r, 1, rtol, 0.0, lay.UbA.re,
+                               lay.UbA.im, dt, st))
+      return rc;
+    if (int rc = mm(lay.rfA.Bh, 0, n2, s, lay.UbA, 0, s, r, lay.Vs, K, real_last, dt, prec, st)) return rc;
+    if (int rc = leverage(lay.Vs.re, lay.Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, lay.rfA.evals, s, rtol,
+                          lay.wbuf, st))
+      return rc;
+    wcol = lay.wbuf;
+  } else if (col_kind == TP_P_NORM2) {
+    if (int rc = lateral_norms(A->data, dt, n1, n2, n3, lay.wbuf, lay.part, st)) return rc;
+    wcol = lay.wbuf;
+  } else if (col_kind == TP_P_UNIFORM) {
+    if (int rc = fill_f64(lay.wbuf, n2, 1.0, st)) return rc;
+    wcol = lay.wbuf;
+  }
+  if (int rc = sample_slices(wcol, n2, c, mode, seed, kStreamColPick, cols->idx, cols->scale, cols->count, lay.sws,
+                             st))
+    return rc;
+
+  // 2. Chat_k = Ahat_k S D: the picked lateral slices, scaled, transformed once
+  {
+    TubeGather g;
+    g.rows = n1;
+    g.cols = capc;
+    g.in_cols = n2;
+    g.col_idx = cols->idx;
+    g.col_scale = cols->scale;
+    g.count = cols->count;
+    if (int rc = fft_forward(A->data, dt, n3, g, lay.Ch.re, lay.Ch.im, st)) return rc;
+  }
+
+  // 3. row probabilities (horizontal leverage of C, read with the squared
+  //    Frobenius norm) and picks
+  const double* wrow = row_w;
+  if (row_kind == TP_P_LEV) {
+    const int s = lay.sC;
+    if (int rc = lay.rfC.run(lay.Ch, kPowerIters, seed, kStreamOmegaC, prec, st, cols->count)) return rc;
+    if (int rc = eig_transform(lay.rfC.ure, lay.rfC.uim, lay.rfC.evals, K, s, (int)r, 1, rtol, 0.0, lay.UbC.re,
+                               lay.UbC.im, dt, st))
+      return rc;
+    if (int rc = mm(lay.rfC.Q, 0, n1, s, lay.UbC, 0, s, r, lay.Us, K, real_last, dt, prec, st)) return rc;
+    if (int rc = leverage(lay.Us.re, lay.Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol,
+                          lay.wbuf2, st))
+      return rc;
+    wrow = lay.wbuf2;
+  } else if (row_kind == TP_P_NORM2) {
+    if (int rc = horizontal_norms(A->data, dt, n1, n2, n3, lay.wbuf2, st)) return rc;
+    wrow = lay.wbuf2;
+  } else if (row_kind == TP_P_UNIFORM) {
+    if (int rc = fill_f64(lay.wbuf2, n1, 1.0, st)) return rc;
+    wrow = lay.wbuf2;
+  }
+  if (int rc = sample_slices(wrow, n1, l, mode, seed, kStreamRowPick, rows->idx, rows->scale, rows->count, lay.sws,
+                             st))
+    return rc;
+  if (!Z) return TP_OK;
+
+  // 4. Rhat_k = D S^T Ahat_k
+  {
+    TubeGather g;
+    g.rows = capl;
+    g.cols = n2;
+    g.in_cols = n2;
+    g.row_idx = rows->idx;
+    g.row_scale = rows->scale;
+    g.count = rows->count;
+    if (int rc = fft_forward(A->data, dt, n3, g, lay.Rh.re, lay.Rh.im, st)) return rc;
+  }
+
+  // 5. core: Uhat_k = pinv_r(D S^T Chat_k), in float64, through a range
+  //    finder on W_k = D S^T Chat_k (l x c): pinv_r(W) = V_r diag(1/sigma) U_r^H
+  //    with U_r = Q U_B,r and V_r = Bh U_B,r diag(1/sigma).
+  const int sw = lay.sw;
+  if (int rc = gather_rows(lay.Ch.re, lay.Ch.im, dt, K, n1, capc, rows->idx, rows->scale, rows->count, capl,
+                           lay.W.re, lay.W.im, TP_F64, st))
+    return rc;
+  if (int rc = lay.cf.run(lay.W, kCorePowerIters, seed, kStreamOmegaW, TP_PREC_F64, st)) return rc;
+  // keep sigma_i > max(l, c) eps sigma_1 among the leading r
+  const double core_rtol = double(std::max(capl, capc)) * 2.220446049250313e-16;
+  if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 2.0, lay.Tp.re,
+                             lay.Tp.im, TP_F64, st))
+    return rc;
+  if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 0.0, lay.Tr.re,
+                             lay.Tr.im, TP_F64, st))
+    return rc;
+  // P = Bh U_B,r diag(sigma^-2) = V_r diag(1/sigma) (c x r); U_r = Q U_B,r (l x r)
+  if (int rc = mm(lay.cf.Bh, 0, capc, sw, lay.Tp, 0, sw, r, lay.P64, K, real_last, TP_F64, TP_PREC_F64, st))
+    return rc;
+  if (int rc = mm(lay.cf.Q, 0, capl, sw, lay.Tr, 0, sw, r, lay.U64, K, real_last, TP_F64, TP_PREC_F64, st))
+    return rc;
+  Spec Pw = lay.P64, Uw = lay.U64;
+  if (dt == TP_F32) {
+    if (int rc = convert(lay.P64.re, TP_F64, lay.P.re, TP_F32, K * capc * r, st)) return rc;
+    if (int rc = convert(lay.P64.im, TP_F64, lay.P.im, TP_F32, K * capc * r, st)) return rc;
+    if (int rc = convert(lay.U64.re, TP_F64, lay.Ur.re, TP_F32, K * capl * r, st)) return rc;
+    if (int rc = convert(lay.U64.im, TP_F64, lay.Ur.im, TP_F32, K * capl * r, st)) return rc;
+    Pw = lay.P;
+    Uw = lay.Ur;
+  }
+  // 6. Zhat_k = Chat_k Uhat_k Rhat_k = (Chat_k P_k) (U_r,k^H Rhat_k), then ifft
+  if (int rc = mm(lay.Ch, 0, n1, capc, Pw, 0, capc, r, lay.F, K, real_last, dt, prec, st)) return rc;
+  if (int rc = mm(Uw, 1, capl, r, lay.Rh, 0, capl, n2, lay.G, K, real_last, dt, prec, st)) return rc;
+  if (int rc = mm(lay.F, 0, n1, r, lay.G, 0, r, n2, lay.Zh, K, real_last, dt, prec, st)) return rc;
+  return fft_inverse(lay.Zh.re, lay.Zh.im, dt, n3, n1, n2, Z->data, st);
+}
+
+}  // extern "C"

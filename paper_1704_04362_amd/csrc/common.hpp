@@ -30,7 +30,9 @@ int fail(int status, const std::string& msg);
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
-// Bump allocator over a caller workspace.
+// Bump allocator over a caller workspace. With a null base it only counts
+// (dry run), which is how the *_workspace queries size a call: they run the
+// same sequence of takes as the call itself.
 struct Arena {
   char* base;
   size_t cap;
@@ -43,6 +45,7 @@ struct Arena {
     return (used <= cap && base) ? reinterpret_cast<T*>(base + off) : nullptr;
   }
   bool ok() const { return base != nullptr && used <= cap; }
+  bool dry() const { return base == nullptr; }
 };
 
 // Sizes a spectrum of the given shape occupies (re and im planes).

@@ -1,5 +1,6 @@
 // Tube transforms along the third mode (Section 2.1 "Operators": fft/ifft
-// along mode 3, MATLAB convention; Algorithm 1 steps 2-3 and 7).
+// along mode 3, MATLAB convention; the transforms that open and close
+// Algorithm 1).
 //
 // Layout: the tensor is tube-major (each tube X_{ij:} is n3 contiguous
 // values); the spectrum is slice-major planar, re[k][tube] / im[k][tube],
@@ -8,7 +9,7 @@
 // Forward kernel (one wavefront = 64 tubes):
 //   1. the 64 tubes are read with 16-byte loads, consecutive lanes reading
 //      consecutive pieces of a tube, and staged in LDS with a row stride of
-//      n3 + 1 words so that the transposed read in step 2 is conflict free;
+//      n3 + 1 words so that the transposed read below is conflict free;
 //      gathers of picked slices and their scales are applied here;
 //   2. every lane packs its real tube as z[m] = x[2m] + i x[2m+1] and runs a
 //      length-n3/2 complex FFT in registers (radix 4/2/5/3 Cooley-Tukey,

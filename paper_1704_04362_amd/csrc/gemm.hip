@@ -1,5 +1,5 @@
-// Per-Fourier-slice complex matrix products (Algorithm 1 step 5, Algorithm 2
-// step 15, the Fourier-domain products of Algorithms 3-5).
+// Per-Fourier-slice complex matrix products (the slice loops of Algorithms
+// 1 and 2, and the Fourier-domain products of Algorithms 3-5).
 //
 // Spectra are planar (separate re / im arrays, slice-major). Every slice k
 // is an independent product C_k = op(A_k) op(B_k); slices 0 and, for even

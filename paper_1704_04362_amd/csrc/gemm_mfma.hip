@@ -1,5 +1,5 @@
-// Matrix-core kernels for the large per-slice complex products (Algorithm 1
-// step 5 and Algorithm 2 step 15 on float32 spectra).
+// Matrix-core kernels for the large per-slice complex products of
+// Algorithms 1 and 2 (the Fourier-slice loop) on float32 spectra.
 //
 // Complex products use three real products (3M):
 //   P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi),

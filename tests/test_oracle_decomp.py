@@ -192,3 +192,13 @@ def test_admm_completion_recovers_low_rank():
     # E stays on the unobserved entries
     assert not np.any(E[mask == 1])
     assert hist[-1]["res"] < hist[20]["res"]
+
+
+def test_tcur_tubes_match_full_tcur():
+    A = rs.standard_normal((9, 11, 6)) + _lowrank(9, 11, 6, 2, seed=3)
+    ci, cs = np.array([0, 2, 5, 9]), np.array([1.0, 0.5, 2.0, 1.5])
+    ri, rsc = np.array([1, 4, 8]), np.array([0.7, 1.1, 1.9])
+    Z, _ = D.tcur(A, ci, cs, ri, rsc, r=2)
+    ii, jj = np.array([0, 3, 8, 5]), np.array([10, 0, 4, 5])
+    got = D.tcur_tubes(A[:, ci, :], A[ri, :, :], cs, ri, rsc, 2, ii, jj)
+    np.testing.assert_allclose(got, Z[ii, jj, :], atol=1e-12)
