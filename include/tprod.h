@@ -234,6 +234,38 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
 size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind, int mode,
                          int prec);
 
+/* ---------------------------------------------------------------------------
+ * Singular value thresholding and completion (Algorithm 7; eqs. tnuc, tlow6).
+ * ------------------------------------------------------------------------- */
+
+/* L = t-SVT(M, tau): in every Fourier slice, U max(Sigma - tau, 0) V^H, the
+ * proximal map of tau times the tensor nuclear norm of eq. tnuc (both that
+ * norm and the squared Frobenius norm carry 1/n3 in the Fourier domain, so
+ * the slice threshold is tau itself). ranks (device, K int32 values, may be
+ * NULL) receives the number of singular values above tau in each
+ * non-redundant slice. The slice SVDs are computed exactly (block one-sided
+ * Jacobi to a largest normalised row inner product of 1e-6). float32 data,
+ * prec TP_PREC_F32. */
+int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
+            void* stream);
+size_t tp_tsvt_workspace(const tp_tensor* M);
+
+/* Tensor completion by the ADMM of Algorithm 7 with the constraint
+ * X = L + E, E zero on the observed entries (mask[i] != 0; X holds the
+ * observed values, anything elsewhere). From L = E = Y = 0 and mu = mu0,
+ * every iteration does
+ *   L <- t-SVT(X - E - Y/mu, 1/mu); E <- P_unobserved(X - L - Y/mu);
+ *   Y <- Y + mu (L + E - X);        mu <- min(rho mu, mu_max)
+ * for exactly `iters` iterations (the paper's values are rho = 1.1,
+ * mu0 = 1e-3, mu_max = 1e10). L, E, Y are outputs (tube-major float32, the
+ * shape of X); ranks (may be NULL) gets the last iteration's per-slice
+ * ranks. Each iteration's slice SVDs start from the previous iteration's
+ * left singular vectors. */
+int tp_tcomplete(const tp_tensor* X, const uint8_t* mask, int32_t iters, double rho, double mu0, double mu_max,
+                 tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
+                 void* stream);
+size_t tp_tcomplete_workspace(const tp_tensor* X);
+
 #ifdef __cplusplus
 }
 #endif

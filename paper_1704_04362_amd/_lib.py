@@ -49,6 +49,12 @@ _SIGS = {
                           C.c_void_p]),
     "tp_tcur_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
                                        C.c_int]),
+    "tp_tsvt": (C.c_int, [P(Tensor), C.c_double, P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
+                          C.c_void_p]),
+    "tp_tsvt_workspace": (C.c_size_t, [P(Tensor)]),
+    "tp_tcomplete": (C.c_int, [P(Tensor), C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
+                               P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_tcomplete_workspace": (C.c_size_t, [P(Tensor)]),
 }
 
 _lib = None

@@ -40,8 +40,21 @@ def _spectrum(re, im):
     return L.Spectrum(re.data_ptr(), im.data_ptr(), _DT[re.dtype], re.shape[0], re.shape[1], re.shape[2])
 
 
+_WS_CACHE = {}
+
+
 def _ws(nbytes, device):
-    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    """Workspace for one call. One buffer is kept per (device, stream) and
+    reused: calls on the same stream run in order, so a buffer is never in use
+    by two calls at once; it grows when a call needs more."""
+    nbytes = max(int(nbytes), 1)
+    key = (torch.device(device).index, torch.cuda.current_stream(device).cuda_stream)
+    buf = _WS_CACHE.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _WS_CACHE.pop(key, None)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _WS_CACHE[key] = buf
+    return buf
 
 
 def half_count(n3):
@@ -201,3 +214,35 @@ def tcur(A, c, l, r, col_kind="lev", row_kind="lev", col_w=None, row_w=None, mod
                         C.byref(rs_), C.byref(tz) if tz is not None else None, L.PREC[prec], ws.data_ptr(),
                         ws.numel(), _stream()))
     return Z, cols, rows
+
+
+def tsvt(M, tau, out=None):
+    """Per-Fourier-slice singular value thresholding with threshold tau:
+    returns (L, ranks)."""
+    _need_gpu(M)
+    L_ = out if out is not None else torch.empty_like(M)
+    ranks = torch.empty(half_count(M.shape[2]), dtype=torch.int32, device=M.device)
+    lib = L.load()
+    tm, tl = _tensor(M), _tensor(L_)
+    ws = _ws(lib.tp_tsvt_workspace(C.byref(tm)), M.device)
+    L.check(lib.tp_tsvt(C.byref(tm), float(tau), C.byref(tl), ranks.data_ptr(), L.PREC["f32"], ws.data_ptr(),
+                        ws.numel(), _stream()))
+    return L_, ranks
+
+
+def tcomplete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
+    """ADMM tensor completion (Algorithm 7, completion variant): returns
+    (L, E, Y, ranks of the last iteration). mask is a uint8 tensor of X's
+    shape, nonzero where observed."""
+    _need_gpu(X, mask)
+    if mask.dtype != torch.uint8 or mask.shape != X.shape:
+        raise ValueError("mask must be uint8 with X's shape")
+    L_, E, Y = torch.empty_like(X), torch.empty_like(X), torch.empty_like(X)
+    ranks = torch.empty(half_count(X.shape[2]), dtype=torch.int32, device=X.device)
+    lib = L.load()
+    tx = _tensor(X)
+    ws = _ws(lib.tp_tcomplete_workspace(C.byref(tx)), X.device)
+    L.check(lib.tp_tcomplete(C.byref(tx), mask.data_ptr(), int(iters), float(rho), float(mu0), float(mu_max),
+                             C.byref(_tensor(L_)), C.byref(_tensor(E)), C.byref(_tensor(Y)), ranks.data_ptr(),
+                             L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream()))
+    return L_, E, Y, ranks

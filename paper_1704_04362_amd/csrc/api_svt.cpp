@@ -1,0 +1,203 @@
+// C ABI of the per-Fourier-slice singular value thresholding (the
+// tensor-nuclear-norm prox, i.e. the L-update of Algorithm 7) and of the
+// ADMM completion loop (Algorithm 7 adapted to the completion problem of
+// eq. tlow6). Validation, workspace layout and kernel order only.
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "common.hpp"
+#include "svt.hpp"
+
+namespace tp {
+namespace {
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+constexpr double kSvtTol = 1e-6;   // largest normalised off-diagonal of a converged pair
+constexpr int kColdSweeps = 30;
+constexpr int kWarmSweeps = 12;
+
+struct SvtLayout {
+  float *xre = nullptr, *xim = nullptr, *ure = nullptr, *uim = nullptr, *lre = nullptr, *lim = nullptr;
+  float* ratio = nullptr;
+  int* conv = nullptr;
+  double* sig = nullptr;
+  float* m = nullptr;  // completion only: M = X - E - Y/mu, tube-major
+  bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int64_t n3, bool completion) {
+    xre = ar.take<float>(K * n1 * n2);
+    xim = ar.take<float>(K * n1 * n2);
+    ure = ar.take<float>(K * n1 * n1);
+    uim = ar.take<float>(K * n1 * n1);
+    lre = ar.take<float>(K * n1 * n2);
+    lim = ar.take<float>(K * n1 * n2);
+    ratio = ar.take<float>(svt_ratio_count(K, n1));
+    conv = ar.take<int>(K);
+    sig = ar.take<double>(K * n1);
+    if (completion) m = ar.take<float>(n1 * n2 * n3);
+    return ar.dry() || ar.ok();
+  }
+};
+
+int check_f32_tensor(const tp_tensor* t, const char* name) {
+  if (!t) return fail(TP_EINVAL, std::string(name) + " is null");
+  if (t->dtype != TP_F32) return fail(TP_EDTYPE, std::string(name) + ": thresholding runs on float32 data");
+  if (t->n1 < 1 || t->n2 < 1 || t->n3 < 1) return fail(TP_ESHAPE, std::string(name) + ": empty tensor");
+  if (!t->data) return fail(TP_EINVAL, std::string(name) + ": data is null");
+  return TP_OK;
+}
+
+// L = ifft(Uh^H D X) after the Jacobi sweeps have made the rows of X
+// orthogonal.
+int finish_svt(SvtLayout& lay, int64_t K, int64_t n1, int64_t n2, int64_t n3, double tau, bool real_last,
+               int32_t* ranks, void* Lout, hipStream_t st) {
+  if (int rc = svt_shrink(lay.xre, lay.xim, K, n1, n2, tau, real_last, lay.sig, ranks, st)) return rc;
+  CGemm p;
+  p.K = K;
+  p.M = n1;
+  p.N = n2;
+  p.Kd = n1;
+  p.are = lay.ure;
+  p.aim = lay.uim;
+  p.bre = lay.xre;
+  p.bim = lay.xim;
+  p.cre = lay.lre;
+  p.cim = lay.lim;
+  p.lda = n1;
+  p.ldb = n2;
+  p.ldc = n2;
+  p.sa = n1 * n1;
+  p.sb = n1 * n2;
+  p.sc = n1 * n2;
+  p.op_a = 1;
+  p.real_last = real_last;
+  if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
+  return fft_inverse(lay.lre, lay.lim, TP_F32, n3, n1, n2, Lout, st);
+}
+
+}  // namespace
+}  // namespace tp
+
+using namespace tp;
+
+extern "C" {
+
+size_t tp_tsvt_workspace(const tp_tensor* M) {
+  if (!M || M->n1 < 1 || M->n2 < 1 || M->n3 < 1) return 0;
+  Arena dry(nullptr, SIZE_MAX);
+  SvtLayout lay;
+  lay.carve(dry, half_count(M->n3), M->n1, M->n2, M->n3, false);
+  return dry.used + 256;
+}
+
+int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
+            void* stream) {
+  if (int rc = check_f32_tensor(M, "M")) return rc;
+  if (int rc = check_f32_tensor(L, "L")) return rc;
+  if (prec != TP_PREC_F32) return fail(TP_EDTYPE, "thresholding supports TP_PREC_F32");
+  if (L->n1 != M->n1 || L->n2 != M->n2 || L->n3 != M->n3) return fail(TP_ESHAPE, "L must match M");
+  if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(TP_EINVAL, "tau must be finite and >= 0");
+  const size_t need = tp_tsvt_workspace(M);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tsvt workspace too small");
+  const int64_t n1 = M->n1, n2 = M->n2, n3 = M->n3, K = half_count(n3);
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  SvtLayout lay;
+  if (!lay.carve(ar, K, n1, n2, n3, false)) return fail(TP_EWORKSPACE, "tsvt workspace too small");
+  TubeGather g;
+  g.rows = n1;
+  g.cols = n2;
+  g.in_cols = n2;
+  if (int rc = fft_forward(M->data, TP_F32, n3, g, lay.xre, lay.xim, st)) return rc;
+  if (int rc = svt_identity(lay.ure, lay.uim, K, n1, st)) return rc;
+  if (int rc = svt_jacobi(lay.xre, lay.xim, lay.ure, lay.uim, K, n1, n2, real_last, kColdSweeps, kSvtTol, lay.ratio,
+                          lay.conv, st))
+    return rc;
+  return finish_svt(lay, K, n1, n2, n3, tau, real_last, ranks, L->data, st);
+}
+
+size_t tp_tcomplete_workspace(const tp_tensor* X) {
+  if (!X || X->n1 < 1 || X->n2 < 1 || X->n3 < 1) return 0;
+  Arena dry(nullptr, SIZE_MAX);
+  SvtLayout lay;
+  lay.carve(dry, half_count(X->n3), X->n1, X->n2, X->n3, true);
+  return dry.used + 256;
+}
+
+int tp_tcomplete(const tp_tensor* X, const uint8_t* mask, int32_t iters, double rho, double mu0, double mu_max,
+                 tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
+                 void* stream) {
+  if (int rc = check_f32_tensor(X, "X")) return rc;
+  if (int rc = check_f32_tensor(L, "L")) return rc;
+  if (int rc = check_f32_tensor(E, "E")) return rc;
+  if (int rc = check_f32_tensor(Y, "Y")) return rc;
+  if (!mask) return fail(TP_EINVAL, "mask is null");
+  if (prec != TP_PREC_F32) return fail(TP_EDTYPE, "completion supports TP_PREC_F32");
+  for (const tp_tensor* t : {L, E, Y})
+    if (t->n1 != X->n1 || t->n2 != X->n2 || t->n3 != X->n3) return fail(TP_ESHAPE, "L, E, Y must match X");
+  if (iters < 1) return fail(TP_EINVAL, "need at least one iteration");
+  if (!(rho >= 1.0) || !(mu0 > 0.0) || !(mu_max >= mu0) || !std::isfinite(rho) || !std::isfinite(mu_max))
+    return fail(TP_EINVAL, "need rho >= 1 and 0 < mu0 <= mu_max");
+  const size_t need = tp_tcomplete_workspace(X);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tcomplete workspace too small");
+  const int64_t n1 = X->n1, n2 = X->n2, n3 = X->n3, K = half_count(n3), n = n1 * n2 * n3;
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  SvtLayout lay;
+  if (!lay.carve(ar, K, n1, n2, n3, true)) return fail(TP_EWORKSPACE, "tcomplete workspace too small");
+  float* x = (float*)X->data;
+  float* l = (float*)L->data;
+  float* e = (float*)E->data;
+  float* y = (float*)Y->data;
+  // L_0 = E_0 = Y_0 = 0
+  if (int rc = zero_f32(e, n, st)) return rc;
+  if (int rc = zero_f32(y, n, st)) return rc;
+  if (int rc = zero_f32(l, n, st)) return rc;
+  if (int rc = svt_identity(lay.ure, lay.uim, K, n1, st)) return rc;
+  double mu = mu0;
+  TubeGather g;
+  g.rows = n1;
+  g.cols = n2;
+  g.in_cols = n2;
+  for (int it = 0; it < iters; ++it) {
+    const float inv_mu = (float)(1.0 / mu);
+    // M = X - E - Y / mu, then its spectrum
+    if (int rc = admm_pre(x, e, y, inv_mu, n, lay.m, st)) return rc;
+    if (int rc = fft_forward(lay.m, TP_F32, n3, g, lay.lre, lay.lim, st)) return rc;
+    // warm start: rotate the new spectrum by the previous iteration's U^H
+    CGemm p;
+    p.K = K;
+    p.M = n1;
+    p.N = n2;
+    p.Kd = n1;
+    p.are = lay.ure;
+    p.aim = lay.uim;
+    p.bre = lay.lre;
+    p.bim = lay.lim;
+    p.cre = lay.xre;
+    p.cim = lay.xim;
+    p.lda = n1;
+    p.ldb = n2;
+    p.ldc = n2;
+    p.sa = n1 * n1;
+    p.sb = n1 * n2;
+    p.sc = n1 * n2;
+    p.real_last = real_last;
+    if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
+    if (int rc = svt_jacobi(lay.xre, lay.xim, lay.ure, lay.uim, K, n1, n2, real_last,
+                            it == 0 ? kColdSweeps : kWarmSweeps, kSvtTol, lay.ratio, lay.conv, st))
+      return rc;
+    // L = SVT(M, 1/mu); the shrink leaves X scaled, so the next warm start
+    // uses Uh only
+    if (int rc = finish_svt(lay, K, n1, n2, n3, 1.0 / mu, real_last, it == iters - 1 ? ranks : nullptr, l, st))
+      return rc;
+    // E = P_unobs(X - L - Y/mu), Y = Y + mu (L + E - X)
+    if (int rc = admm_post(x, mask, l, (float)mu, inv_mu, n, e, y, st)) return rc;
+    mu = std::min(rho * mu, mu_max);
+  }
+  return TP_OK;
+}
+
+}  // extern "C"

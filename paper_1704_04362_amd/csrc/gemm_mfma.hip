@@ -60,17 +60,10 @@ __device__ __forceinline__ void split4(const float (&x)[4], bf16x4& hi, bf16x4& 
 }
 
 template <int SPLIT, bool REAL>
-__global__ __launch_bounds__(NT, 1) void cgemm_bf16_kernel(MArgs g) {
-  // LDS: [value r/i/s][split][row][LDK]
-  __shared__ __attribute__((aligned(16))) __bf16 sA[3 * SPLIT * BM * LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 sB[3 * SPLIT * BN * LDK];
-
+__device__ __forceinline__ void cgemm_bf16_body(const MArgs& g, int64_t k, __bf16* sA, __bf16* sB) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  // REAL launches cover slice 0 and (real_last) slice K-1; complex launches
-  // cover slices 1 .. K-1 (or K-2)
-  const int64_t k = REAL ? (blockIdx.z == 0 ? 0 : g.K - 1) : (int64_t)blockIdx.z + 1;
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   constexpr bool real = REAL;
   int64_t Kd = g.Kd;
@@ -201,20 +194,22 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16_kernel(MArgs g) {
 #pragma unroll
         for (int sp = 0; sp < SPLIT; ++sp)
           b[j].v[sp] = *reinterpret_cast<const bf16x8*>(&sB[((v * SPLIT + sp) * BN + wc * 64 + j * 16 + fr) * LDK + fk]);
+      Frag<SPLIT> a[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        Frag<SPLIT> a;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int sp = 0; sp < SPLIT; ++sp)
-          a.v[sp] = *reinterpret_cast<const bf16x8*>(&sA[((v * SPLIT + sp) * BM + wr * 64 + i * 16 + fr) * LDK + fk]);
+          a[i].v[sp] = *reinterpret_cast<const bf16x8*>(&sA[((v * SPLIT + sp) * BM + wr * 64 + i * 16 + fr) * LDK + fk]);
+      // one split term over all 16 tiles before the next, so consecutive
+      // MFMAs never wait on each other's accumulator
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[v][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v[0], b[j].v[0], acc[v][i][j], 0, 0, 0);
-          if constexpr (SPLIT == 2) {
-            acc[v][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v[0], b[j].v[1], acc[v][i][j], 0, 0, 0);
-            acc[v][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v[1], b[j].v[0], acc[v][i][j], 0, 0, 0);
-          }
-        }
+      for (int term = 0; term < (SPLIT == 2 ? 3 : 1); ++term) {
+        const int sa = term == 2 ? 1 : 0, sb = term == 1 ? 1 : 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[v][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i].v[sa], b[j].v[sb], acc[v][i][j], 0, 0, 0);
       }
     };
     pass(std::integral_constant<int, 0>{});
@@ -249,6 +244,24 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16_kernel(MArgs g) {
       }
 }
 
+// One launch covers every Fourier slice; each workgroup runs the real or the
+// complex body for its slice (the branch is uniform and taken once).
+template <int SPLIT>
+__global__ __launch_bounds__(NT, 1) void cgemm_bf16_kernel(MArgs g) {
+  // LDS: [value r/i/s][split][row][LDK]
+  __shared__ __attribute__((aligned(16))) __bf16 sA[3 * SPLIT * BM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[3 * SPLIT * BN * LDK];
+  // complex slices first in launch order, the two cheaper real slices last
+  const int64_t z = blockIdx.z;
+  const int64_t nreal = (g.real_last && g.K > 1) ? 2 : 1;
+  const int64_t ncomplex = g.K - nreal;
+  if (z < ncomplex) {
+    cgemm_bf16_body<SPLIT, false>(g, z + 1, sA, sB);
+  } else {
+    cgemm_bf16_body<SPLIT, true>(g, z == ncomplex ? 0 : g.K - 1, sA, sB);
+  }
+}
+
 }  // namespace
 
 // Takes the product when it is an as-stored (NN) product of float32 spectra
@@ -268,18 +281,10 @@ int cgemm_mfma(const CGemm& p, int prec, hipStream_t st, bool* handled) {
           (float*)p.cre, (float*)p.cim, p.lda, p.ldb, p.ldc, p.sa, p.sb, p.sc, p.K, p.real_last ? 1 : 0,
           p.kdim_dev};
   const unsigned gx = (unsigned)((p.N + BN - 1) / BN), gy = (unsigned)((p.M + BM - 1) / BM);
-  const int64_t nreal = (p.real_last && p.K > 1) ? 2 : 1;
-  const int64_t ncomplex = p.K - nreal;
-  auto launch = [&](auto split) {
-    constexpr int S = decltype(split)::value;
-    if (ncomplex > 0)
-      hipLaunchKernelGGL((cgemm_bf16_kernel<S, false>), dim3(gx, gy, (unsigned)ncomplex), dim3(NT), 0, st, g);
-    hipLaunchKernelGGL((cgemm_bf16_kernel<S, true>), dim3(gx, gy, (unsigned)nreal), dim3(NT), 0, st, g);
-  };
   if (prec == TP_PREC_BF16X3)
-    launch(std::integral_constant<int, 2>{});
+    hipLaunchKernelGGL(cgemm_bf16_kernel<2>, dim3(gx, gy, (unsigned)p.K), dim3(NT), 0, st, g);
   else
-    launch(std::integral_constant<int, 1>{});
+    hipLaunchKernelGGL(cgemm_bf16_kernel<1>, dim3(gx, gy, (unsigned)p.K), dim3(NT), 0, st, g);
   TP_LAUNCH_CHECK();
   *handled = true;
   return TP_OK;

@@ -4,9 +4,8 @@
 // pseudo-inverse (Algorithm 5):
 //  * Gaussian test matrices drawn per slice (Philox4x64-10 + Box-Muller);
 //  * Gram matrices X^H X of tall slices, accumulated in float64;
-//  * a Hermitian eigensolver for s x s Gram matrices (s <= 64): parallel
-//    cyclic Jacobi in float64, one workgroup per slice, the matrix and the
-//    accumulated rotations held in LDS;
+//  * a Hermitian eigensolver for s x s Gram matrices (s <= 64): the LDS
+//    Jacobi solver of jacobi.hpp in float64, one workgroup per slice;
 //  * the derived small transforms (orthonormalisation V diag(lambda^-1/2),
 //    truncation to the leading r directions with singular-value scaling);
 //  * leverage reductions summed over the half spectrum with conjugate
@@ -14,6 +13,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "jacobi.hpp"
 #include "linalg.hpp"
 
 namespace tp {
@@ -121,168 +121,30 @@ __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ xre, co
   }
 }
 
-// Parallel cyclic Jacobi for Hermitian s x s matrices (one workgroup per
-// slice). Each sweep visits every index pair once through a round-robin
-// tournament: in a round the s/2 disjoint pairs are rotated together, rows
-// first, then columns, which applies the product of the disjoint rotations.
-// For a pair (p, q) with H_pq = |h| e^{i phi}, the rotation is
-// J = diag(1, e^{-i phi}) R(theta), R the real Jacobi rotation
-// [[c, s], [-s, c]] with t = tan(theta) the smaller root of
-// t^2 + 2 tau t - 1 = 0, tau = (H_qq - H_pp) / (2 |h|).
+// Eigen-decomposition of one s x s Hermitian matrix per workgroup with the
+// LDS Jacobi solver; eigenvalues are returned in descending order (ties by
+// index) with the matching eigenvector columns.
 __global__ __launch_bounds__(256) void herm_eig_kernel(const double* __restrict__ gre,
                                                        const double* __restrict__ gim, int s, int max_sweeps,
                                                        double* __restrict__ evals, double* __restrict__ vre,
                                                        double* __restrict__ vim) {
-  __shared__ double Hr[kMaxS][kMaxS + 1], Hi[kMaxS][kMaxS + 1];
-  __shared__ double Vr[kMaxS][kMaxS + 1], Vi[kMaxS][kMaxS + 1];
-  __shared__ double rc[kMaxS / 2], rs[kMaxS / 2], rpr[kMaxS / 2], rpi[kMaxS / 2];
-  __shared__ int pp[kMaxS / 2], qq[kMaxS / 2];
-  __shared__ int perm[kMaxS + 1];
-  __shared__ double red[256];
-  __shared__ int sdone;
+  __shared__ JacobiShared<kMaxS, 256> sh;
+  __shared__ int order[kMaxS];
   const int64_t k = blockIdx.x;
   const int ne = s * s;
   const int tid = threadIdx.x;
   for (int e = tid; e < ne; e += 256) {
     const int i = e / s, j = e - i * s;
-    Hr[i][j] = gre[k * ne + e];
-    Hi[i][j] = gim[k * ne + e];
-    Vr[i][j] = (i == j) ? 1.0 : 0.0;
-    Vi[i][j] = 0.0;
-  }
-  const int n = (s % 2) ? s + 1 : s;  // padded to even; index s is a dummy
-  for (int i = tid; i < n; i += 256) perm[i] = i;
-  __syncthreads();
-  // Hermitian symmetrisation of the input (Gram accumulation is symmetric up
-  // to rounding)
-  for (int e = tid; e < ne; e += 256) {
-    const int i = e / s, j = e - i * s;
-    if (i < j) {
-      const double ar = 0.5 * (Hr[i][j] + Hr[j][i]), ai = 0.5 * (Hi[i][j] - Hi[j][i]);
-      Hr[i][j] = ar;
-      Hi[i][j] = ai;
-      Hr[j][i] = ar;
-      Hi[j][i] = -ai;
-    } else if (i == j) {
-      Hi[i][i] = 0.0;
-    }
+    sh.Hr[i][j] = gre[k * ne + e];
+    sh.Hi[i][j] = gim[k * ne + e];
   }
   __syncthreads();
-  const int npairs = n / 2;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // convergence test: off-diagonal vs total Frobenius mass
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < ne; e += 256) {
-      const int i = e / s, j = e - i * s;
-      const double m = Hr[i][j] * Hr[i][j] + Hi[i][j] * Hi[i][j];
-      tot += m;
-      if (i != j) off += m;
-    }
-    red[tid] = off;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double offsum = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double totsum = red[0];
-    if (tid == 0) sdone = (offsum <= 1e-30 * totsum) || totsum == 0.0;
-    __syncthreads();
-    if (sdone) break;
-    for (int round = 0; round < n - 1; ++round) {
-      // tournament pairing: position 0 fixed, the others rotate
-      if (tid < npairs) {
-        int a = perm[tid], b = perm[n - 1 - tid];
-        if (a > b) {
-          const int t = a;
-          a = b;
-          b = t;
-        }
-        pp[tid] = a;
-        qq[tid] = b;
-        double c = 1.0, sn = 0.0, pr = 1.0, pi = 0.0;
-        if (b < s) {
-          const double hr = Hr[a][b], hi = Hi[a][b];
-          const double habs = sqrt(hr * hr + hi * hi);
-          const double diag = fabs(Hr[a][a]) + fabs(Hr[b][b]);
-          if (habs > 1e-300 && habs > 1e-18 * diag) {
-            const double tau = (Hr[b][b] - Hr[a][a]) / (2.0 * habs);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-            pr = hr / habs;  // e^{i phi}
-            pi = hi / habs;
-          }
-        }
-        rc[tid] = c;
-        rs[tid] = sn;
-        rpr[tid] = pr;
-        rpi[tid] = pi;
-      }
-      __syncthreads();
-      // rows: H <- J^H H. For column j: x = H_pj, y = H_qj:
-      //   H_pj = c x - s e^{i phi} y,  H_qj = s x + c e^{i phi} y
-      for (int e = tid; e < npairs * s; e += 256) {
-        const int r = e / s, j = e - r * s;
-        const int p = pp[r], q = qq[r];
-        if (q >= s) continue;
-        const double c = rc[r], sn = rs[r], er = rpr[r], ei = rpi[r];
-        const double xr = Hr[p][j], xi = Hi[p][j], yr = Hr[q][j], yi = Hi[q][j];
-        const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;  // e^{i phi} y
-        Hr[p][j] = c * xr - sn * eyr;
-        Hi[p][j] = c * xi - sn * eyi;
-        Hr[q][j] = sn * xr + c * eyr;
-        Hi[q][j] = sn * xi + c * eyi;
-      }
-      __syncthreads();
-      // columns: H <- H J and V <- V J. For row i: x = M_ip, y = M_iq:
-      //   M_ip = c x - s e^{-i phi} y,  M_iq = s x + c e^{-i phi} y
-      for (int e = tid; e < npairs * s; e += 256) {
-        const int r = e / s, i = e - r * s;
-        const int p = pp[r], q = qq[r];
-        if (q >= s) continue;
-        const double c = rc[r], sn = rs[r], er = rpr[r], ei = -rpi[r];
-        {
-          const double xr = Hr[i][p], xi = Hi[i][p], yr = Hr[i][q], yi = Hi[i][q];
-          const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
-          Hr[i][p] = c * xr - sn * eyr;
-          Hi[i][p] = c * xi - sn * eyi;
-          Hr[i][q] = sn * xr + c * eyr;
-          Hi[i][q] = sn * xi + c * eyi;
-        }
-        {
-          const double xr = Vr[i][p], xi = Vi[i][p], yr = Vr[i][q], yi = Vi[i][q];
-          const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
-          Vr[i][p] = c * xr - sn * eyr;
-          Vi[i][p] = c * xi - sn * eyi;
-          Vr[i][q] = sn * xr + c * eyr;
-          Vi[i][q] = sn * xi + c * eyi;
-        }
-      }
-      __syncthreads();
-      // rotate the tournament (positions 1..n-1)
-      if (tid == 0) {
-        const int last = perm[n - 1];
-        for (int i = n - 1; i > 1; --i) perm[i] = perm[i - 1];
-        perm[1] = last;
-      }
-      __syncthreads();
-    }
-  }
-  // order eigenvalues descending (ties by index) through ranks
-  __shared__ int order[kMaxS];
+  jacobi_eig_lds<kMaxS, 256>(sh, s, max_sweeps, 1e-15);
   if (tid < s) {
-    const double lt = Hr[tid][tid];
+    const double lt = sh.Hr[tid][tid];
     int rank = 0;
     for (int j = 0; j < s; ++j) {
-      const double lj = Hr[j][j];
+      const double lj = sh.Hr[j][j];
       if (lj > lt || (lj == lt && j < tid)) ++rank;
     }
     order[rank] = tid;
@@ -291,10 +153,10 @@ __global__ __launch_bounds__(256) void herm_eig_kernel(const double* __restrict_
   for (int e = tid; e < ne; e += 256) {
     const int i = e / s, j = e - i * s;  // row i, sorted column j
     const int src = order[j];
-    vre[k * ne + e] = Vr[i][src];
-    vim[k * ne + e] = Vi[i][src];
+    vre[k * ne + e] = sh.Vr[i][src];
+    vim[k * ne + e] = sh.Vi[i][src];
   }
-  if (tid < s) evals[k * s + tid] = Hr[order[tid]][order[tid]];
+  if (tid < s) evals[k * s + tid] = sh.Hr[order[tid]][order[tid]];
 }
 
 // Small transforms from an eigen-decomposition G = V diag(lambda) V^H.

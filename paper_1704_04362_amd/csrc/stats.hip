@@ -11,8 +11,9 @@
 namespace tp {
 namespace {
 
-constexpr int LT = 64;     // tubes (lateral slices) per workgroup
-constexpr int LROWS = 8;   // horizontal slices per workgroup
+constexpr int LT = 64;      // tubes (lateral slices) per workgroup
+constexpr int LROWS = 16;   // horizontal slices per workgroup
+constexpr int LNT = 256;    // threads per workgroup
 
 template <typename T>
 struct V16;
@@ -28,48 +29,51 @@ struct V16<double> {
 };
 
 // Workgroup (bx, by) sums rows [by*LROWS, +LROWS) for tubes [bx*LT, +LT).
-// For each row the LT tubes are one contiguous run of LT*n3 values, read
-// with coalesced 16-byte loads; per-piece partial sums go through LDS so
-// that lane l can add up the pieces of tube l in a fixed order.
+// In every row those LT tubes are one contiguous run of LT*n3 values; a
+// thread always owns the same 16-byte pieces of that run, so it accumulates
+// its pieces over all rows with independent coalesced loads, and the pieces
+// of a tube are added in a fixed order at the end through LDS.
 template <typename T>
-__global__ __launch_bounds__(LT) void lateral_partial_kernel(const T* __restrict__ a, int64_t n1, int64_t n2,
-                                                              int64_t n3, double* __restrict__ partial) {
+__global__ __launch_bounds__(LNT) void lateral_partial_kernel(const T* __restrict__ a, int64_t n1, int64_t n2,
+                                                               int64_t n3, double* __restrict__ partial) {
   using V = typename V16<T>::type;
   constexpr int VN = V16<T>::n;
   extern __shared__ double piece[];  // [LT][CH]
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.x * LT;
   const int64_t i0 = (int64_t)blockIdx.y * LROWS;
   const int64_t ntub = (n2 - j0) < LT ? (n2 - j0) : LT;
   const bool vec = (n3 % VN) == 0;
   const int64_t CH = vec ? n3 / VN : n3;
-  double acc = 0.0;
-  for (int r = 0; r < LROWS; ++r) {
-    const int64_t i = i0 + r;
-    if (i >= n1) break;
-    const T* row = a + (i * n2 + j0) * n3;
-    for (int64_t f = lane; f < ntub * CH; f += LT) {
-      double s = 0.0;
+  const int64_t npieces = ntub * CH;
+  const int64_t rows = (n1 - i0) < LROWS ? (n1 - i0) : LROWS;
+  for (int64_t f0 = 0; f0 < LT * CH; f0 += LNT) {
+    const int64_t f = f0 + tid;
+    double s = 0.0;
+    if (f < npieces) {
       if (vec) {
-        const V w = *reinterpret_cast<const V*>(row + f * VN);
-        const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll 4
+        for (int64_t r = 0; r < rows; ++r) {
+          const V w = *reinterpret_cast<const V*>(a + ((i0 + r) * n2 + j0) * n3 + f * VN);
+          const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-        for (int e = 0; e < VN; ++e) s += (double)wp[e] * (double)wp[e];
+          for (int e = 0; e < VN; ++e) s += (double)wp[e] * (double)wp[e];
+        }
       } else {
-        const double v = (double)row[f];
-        s = v * v;
+        for (int64_t r = 0; r < rows; ++r) {
+          const double v = (double)a[((i0 + r) * n2 + j0) * n3 + f];
+          s += v * v;
+        }
       }
-      piece[f] = s;
     }
-    __syncthreads();
-    if (lane < ntub) {
-      double t = 0.0;
-      for (int64_t p = 0; p < CH; ++p) t += piece[lane * CH + p];
-      acc += t;
-    }
-    __syncthreads();
+    if (f < LT * CH) piece[f] = s;
   }
-  if (lane < ntub) partial[(int64_t)blockIdx.y * n2 + j0 + lane] = acc;
+  __syncthreads();
+  if (tid < ntub) {
+    double t = 0.0;
+    for (int64_t p = 0; p < CH; ++p) t += piece[tid * CH + p];
+    partial[(int64_t)blockIdx.y * n2 + j0 + tid] = t;
+  }
 }
 
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, int64_t nb, int64_t n,
@@ -77,6 +81,7 @@ __global__ void reduce_partials_kernel(const double* __restrict__ partial, int64
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double s = 0.0;
+#pragma unroll 8
   for (int64_t b = 0; b < nb; ++b) s += partial[b * n + j];
   out[j] = s;
 }
@@ -147,9 +152,9 @@ int lateral_norms(const void* a, int dtype, int64_t n1, int64_t n2, int64_t n3, 
   }
   dim3 grid((unsigned)((n2 + LT - 1) / LT), (unsigned)nb);
   if (dtype == TP_F64)
-    hipLaunchKernelGGL(lateral_partial_kernel<double>, grid, dim3(LT), lds, st, (const double*)a, n1, n2, n3, ws);
+    hipLaunchKernelGGL(lateral_partial_kernel<double>, grid, dim3(LNT), lds, st, (const double*)a, n1, n2, n3, ws);
   else
-    hipLaunchKernelGGL(lateral_partial_kernel<float>, grid, dim3(LT), lds, st, (const float*)a, n1, n2, n3, ws);
+    hipLaunchKernelGGL(lateral_partial_kernel<float>, grid, dim3(LNT), lds, st, (const float*)a, n1, n2, n3, ws);
   TP_LAUNCH_CHECK();
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, ws, nb, n2, out);
   TP_LAUNCH_CHECK();

@@ -1,0 +1,343 @@
+// Singular value thresholding of every Fourier slice (the closed-form
+// L-update of Algorithm 7 with the tensor nuclear norm of eq. tnuc) and the
+// elementwise updates of the ADMM completion loop.
+//
+// SVD by block one-sided Jacobi on rows: every slice M (n1 x n2) is kept as
+// X = U^H M together with Uh = U^H (both row-major, float32 planar). A step
+// takes a pair of 16-row blocks (32 rows), forms their Gram matrix
+// G = X_p X_p^H in float64, diagonalises it with the LDS Jacobi solver
+// (G = V diag V^H) and rotates both X_p and Uh_p by V^H, which makes the 32
+// rows mutually orthogonal. A round-robin tournament over the blocks visits
+// all block pairs in a sweep; the disjoint pairs of a round are independent
+// workgroups. A slice is converged when every pair in a sweep had
+// max |G_st| / sqrt(G_ss G_tt) below the tolerance; later launches for it
+// return at once, so a fixed launch sequence needs no host synchronisation.
+// At the end the rows of X are U^H M = Sigma V^H: sigma_i = ||x_i||, and
+//   L = U diag(max(1 - tau / sigma_i, 0)) X = Uh^H (D X).
+#include <cmath>
+
+#include "common.hpp"
+#include "jacobi.hpp"
+#include "svt.hpp"
+
+namespace tp {
+namespace {
+
+constexpr int RB = 16;       // rows per block
+constexpr int PR = 2 * RB;   // rows per pair
+constexpr int CHC = 64;      // columns staged per chunk
+constexpr int NT = 256;
+
+struct PairArgs {
+  int64_t K, n1, n2;
+  float *xre, *xim;  // K x n1 x n2
+  float *ure, *uim;  // K x n1 x n1
+  int nb;            // number of blocks (even; the last may be partial or empty)
+  int real_last;
+  float* ratio;      // (nb-1) x K x (nb/2) ratios of this sweep, per round
+  const int* conv;   // K flags
+  double tol;
+  int inner_sweeps;
+};
+
+__device__ __forceinline__ int tournament(int pos, int round, int nb) {
+  return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (nb - 1));
+}
+
+// Rotates rows rows[0..PR) of a row-major K x nrows x ncols planar matrix by
+// V^H: out_s = sum_t conj(V_ts) in_t.
+template <typename Sh>
+__device__ void rotate_rows(Sh& sh, double (*cr)[CHC + 1], double (*ci)[CHC + 1], float* re, float* im,
+                            int64_t ncols, const int* rows, bool real) {
+  const int tid = threadIdx.x;
+  for (int64_t c0 = 0; c0 < ncols; c0 += CHC) {
+    const int nc = (int)((ncols - c0) < CHC ? (ncols - c0) : CHC);
+    for (int e = tid; e < PR * CHC; e += NT) {
+      const int s = e / CHC, j = e - s * CHC;
+      double vr = 0.0, vi = 0.0;
+      if (j < nc && rows[s] >= 0) {
+        const int64_t off = (int64_t)rows[s] * ncols + c0 + j;
+        vr = (double)re[off];
+        vi = real ? 0.0 : (double)im[off];
+      }
+      cr[s][j] = vr;
+      ci[s][j] = vi;
+    }
+    __syncthreads();
+    for (int e = tid; e < PR * CHC; e += NT) {
+      const int s = e / CHC, j = e - s * CHC;
+      if (j >= nc || rows[s] < 0) continue;
+      double ar = 0.0, ai = 0.0;
+#pragma unroll 8
+      for (int t = 0; t < PR; ++t) {
+        // conj(V_ts) * x_tj
+        const double vr = sh.Vr[t][s], vi = -sh.Vi[t][s];
+        ar += vr * cr[t][j] - vi * ci[t][j];
+        ai += vr * ci[t][j] + vi * cr[t][j];
+      }
+      const int64_t off = (int64_t)rows[s] * ncols + c0 + j;
+      re[off] = (float)ar;
+      if (!real) im[off] = (float)ai;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
+  __shared__ JacobiShared<PR, NT> sh;
+  __shared__ double cr[PR][CHC + 1], ci[PR][CHC + 1];
+  __shared__ int rows[PR];
+  __shared__ double ratio_red[NT];
+  __shared__ int skip;
+  const int64_t k = blockIdx.y;
+  const int pair = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (a.conv[k]) return;
+  const bool real = k == 0 || (a.real_last && k == a.K - 1);
+  const int ba = tournament(pair, round, a.nb), bb = tournament(a.nb - 1 - pair, round, a.nb);
+  if (tid < PR) {
+    const int blk = tid < RB ? ba : bb;
+    const int64_t r = (int64_t)blk * RB + (tid % RB);
+    rows[tid] = r < a.n1 ? (int)r : -1;
+  }
+  float* xre = a.xre + k * a.n1 * a.n2;
+  float* xim = a.xim + k * a.n1 * a.n2;
+  float* ure = a.ure + k * a.n1 * a.n1;
+  float* uim = a.uim + k * a.n1 * a.n1;
+  // Gram G_st = sum_j x_s[j] conj(x_t[j]), 4 entries per thread
+  double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < a.n2; c0 += CHC) {
+    const int nc = (int)((a.n2 - c0) < CHC ? (a.n2 - c0) : CHC);
+    for (int e = tid; e < PR * CHC; e += NT) {
+      const int s = e / CHC, j = e - s * CHC;
+      double vr = 0.0, vi = 0.0;
+      if (j < nc && rows[s] >= 0) {
+        const int64_t off = (int64_t)rows[s] * a.n2 + c0 + j;
+        vr = (double)xre[off];
+        vi = real ? 0.0 : (double)xim[off];
+      }
+      cr[s][j] = vr;
+      ci[s][j] = vi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + NT * q;
+      const int s = e / PR, t = e - s * PR;
+      double sr = gr[q], si = gi[q];
+      for (int j = 0; j < nc; ++j) {
+        sr += cr[s][j] * cr[t][j] + ci[s][j] * ci[t][j];
+        si += ci[s][j] * cr[t][j] - cr[s][j] * ci[t][j];
+      }
+      gr[q] = sr;
+      gi[q] = si;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + NT * q;
+    const int s = e / PR, t = e - s * PR;
+    sh.Hr[s][t] = gr[q];
+    sh.Hi[s][t] = gi[q];
+  }
+  __syncthreads();
+  // largest normalised off-diagonal entry
+  double mr = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + NT * q;
+    const int s = e / PR, t = e - s * PR;
+    if (s != t) {
+      const double d = sh.Hr[s][s] * sh.Hr[t][t];
+      if (d > 0.0) mr = fmax(mr, sqrt((gr[q] * gr[q] + gi[q] * gi[q]) / d));
+    }
+  }
+  ratio_red[tid] = mr;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) ratio_red[tid] = fmax(ratio_red[tid], ratio_red[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.ratio[((int64_t)round * a.K + k) * (a.nb / 2) + pair] = (float)ratio_red[0];
+    skip = ratio_red[0] < a.tol;
+  }
+  __syncthreads();
+  if (skip) return;
+  jacobi_eig_lds<PR, NT>(sh, PR, a.inner_sweeps, 1e-14);
+  rotate_rows(sh, cr, ci, xre, xim, a.n2, rows, real);
+  rotate_rows(sh, cr, ci, ure, uim, a.n1, rows, real);
+}
+
+__global__ void svt_conv_kernel(const float* __restrict__ ratio, int64_t K, int nrounds, int npairs, double tol,
+                                int* conv) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  if (conv[k]) return;
+  float m = 0.f;
+  for (int r = 0; r < nrounds; ++r)
+    for (int p = 0; p < npairs; ++p) m = fmaxf(m, ratio[((int64_t)r * K + k) * npairs + p]);
+  if (m < tol) conv[k] = 1;
+}
+
+__global__ void identity_kernel(float* re, float* im, int64_t K, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K * n * n) return;
+  const int64_t r = e % (n * n);
+  re[e] = (r / n == r % n) ? 1.f : 0.f;
+  im[e] = 0.f;
+}
+
+__global__ void zero_f32_kernel(float* p, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0.f;
+}
+
+__global__ void zero_int_kernel(int* p, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0;
+}
+
+// Row norms of X, shrink factors d_i = max(1 - tau / sigma_i, 0), X <- D X,
+// and the number of sigma_i > tau per slice. Row norms at or below
+// max(n1, n2) eps_32 sigma_max are rounding residue of rows that the
+// rotations have emptied (a slice has at most min(n1, n2) nonzero singular
+// values) and count as zero. One workgroup per slice; sig is K x n1 scratch.
+__global__ __launch_bounds__(NT) void svt_shrink_kernel(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2,
+                                                        double tau, int real_last, double* sig, int32_t* ranks) {
+  __shared__ double red[NT];
+  __shared__ int cnt[NT];
+  const int64_t k = blockIdx.x;
+  const bool real = k == 0 || (real_last && k == K - 1);
+  float* re = xre + k * n1 * n2;
+  float* im = xim + k * n1 * n2;
+  double* sg = sig + k * n1;
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < n1; i += NT) {
+    double s2 = 0.0;
+    for (int64_t j = 0; j < n2; ++j) {
+      const double a = re[i * n2 + j], b = real ? 0.0 : im[i * n2 + j];
+      s2 += a * a + b * b;
+    }
+    sg[i] = sqrt(s2);
+    mx = fmax(mx, sg[i]);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double floor_ = (double)(n1 > n2 ? n1 : n2) * 1.1920928955078125e-07 * red[0];
+  int mine = 0;
+  for (int64_t i = threadIdx.x; i < n1; i += NT) {
+    const double sgi = sg[i];
+    const bool kept = sgi > tau && sgi > floor_;
+    const double d = kept ? 1.0 - tau / sgi : 0.0;
+    if (kept) ++mine;
+    for (int64_t j = 0; j < n2; ++j) {
+      re[i * n2 + j] = (float)(d * re[i * n2 + j]);
+      if (!real) im[i * n2 + j] = (float)(d * im[i * n2 + j]);
+    }
+  }
+  cnt[threadIdx.x] = mine;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && ranks) ranks[k] = cnt[0];
+}
+
+// M = X - E - Y / mu (tube-major, elementwise)
+__global__ void admm_pre_kernel(const float* __restrict__ x, const float* __restrict__ e,
+                                const float* __restrict__ y, float inv_mu, int64_t n, float* __restrict__ m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) m[i] = x[i] - e[i] - y[i] * inv_mu;
+}
+
+// E = P_unobserved(X - L - Y/mu); Y = Y + mu (L + E - X)
+__global__ void admm_post_kernel(const float* __restrict__ x, const uint8_t* __restrict__ mask,
+                                 const float* __restrict__ l, float mu, float inv_mu, int64_t n,
+                                 float* __restrict__ e, float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float xv = x[i], lv = l[i], yv = y[i];
+  const float ev = mask[i] ? 0.f : (xv - lv - yv * inv_mu);
+  e[i] = ev;
+  y[i] = yv + mu * (lv + ev - xv);
+}
+
+unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+size_t svt_ratio_count(int64_t K, int64_t n1) {
+  const int nb = svt_blocks(n1);
+  return size_t(nb - 1) * K * (nb / 2);
+}
+
+int svt_blocks(int64_t n1) {
+  int nb = (int)((n1 + RB - 1) / RB);
+  if (nb < 2) nb = 2;
+  if (nb % 2) ++nb;
+  return nb;
+}
+
+int zero_f32(float* p, int64_t n, hipStream_t st) {
+  if (n == 0) return TP_OK;
+  hipLaunchKernelGGL(zero_f32_kernel, dim3(nblk(n)), dim3(256), 0, st, p, n);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int svt_identity(float* ure, float* uim, int64_t K, int64_t n, hipStream_t st) {
+  if (K * n * n == 0) return TP_OK;
+  hipLaunchKernelGGL(identity_kernel, dim3(nblk(K * n * n)), dim3(256), 0, st, ure, uim, K, n);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_t n1, int64_t n2, bool real_last,
+               int max_sweeps, double tol, float* ratio, int* conv, hipStream_t st) {
+  const int nb = svt_blocks(n1);
+  hipLaunchKernelGGL(zero_int_kernel, dim3(nblk(K)), dim3(256), 0, st, conv, K);
+  TP_LAUNCH_CHECK();
+  PairArgs a{K, n1, n2, xre, xim, ure, uim, nb, real_last ? 1 : 0, ratio, conv, tol, 12};
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int round = 0; round < nb - 1; ++round) {
+      hipLaunchKernelGGL(svt_pair_kernel, dim3(nb / 2, (unsigned)K), dim3(NT), 0, st, a, round);
+      TP_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(svt_conv_kernel, dim3(nblk(K)), dim3(256), 0, st, ratio, K, nb - 1, nb / 2, tol, conv);
+    TP_LAUNCH_CHECK();
+  }
+  return TP_OK;
+}
+
+int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double tau, bool real_last,
+               double* sig, int32_t* ranks, hipStream_t st) {
+  hipLaunchKernelGGL(svt_shrink_kernel, dim3((unsigned)K), dim3(NT), 0, st, xre, xim, K, n1, n2, tau,
+                     real_last ? 1 : 0, sig, ranks);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int admm_pre(const float* x, const float* e, const float* y, float inv_mu, int64_t n, float* m, hipStream_t st) {
+  if (n == 0) return TP_OK;
+  hipLaunchKernelGGL(admm_pre_kernel, dim3(nblk(n)), dim3(256), 0, st, x, e, y, inv_mu, n, m);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, float inv_mu, int64_t n, float* e,
+              float* y, hipStream_t st) {
+  if (n == 0) return TP_OK;
+  hipLaunchKernelGGL(admm_post_kernel, dim3(nblk(n)), dim3(256), 0, st, x, mask, l, mu, inv_mu, n, e, y);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+}  // namespace tp
