@@ -266,6 +266,49 @@ int tp_tcomplete(const tp_tensor* X, const uint8_t* mask, int32_t iters, double 
                  void* stream);
 size_t tp_tcomplete_workspace(const tp_tensor* X);
 
+/* ---------------------------------------------------------------------------
+ * Learned lateral-leverage proposal (not in the paper; the exact scores of
+ * eq. cur-col-prob stay its judge and fallback).
+ * ------------------------------------------------------------------------- */
+
+/* Number of float32 parameters: W1 (17 x 128) | b1 (128) | W2 (128 x 128) |
+ * b2 (128) | w3 (128) | b3 (1), with h1 = relu(x W1 + b1),
+ * h2 = relu(h1 W2 + b2), o = h2 w3 + b3. */
+int tp_mlp_param_count(void);
+
+/* Per-lateral-slice features of a float32 tensor A (n3 % 4 == 0): the
+ * sketch s_j = Phi^T vec(A_{:j:}) (vec order i n3 + k; Phi a caller-supplied
+ * device float32 (n1 n3) x 16 row-major matrix, e.g. Gaussian / 4), whitened
+ * as z_j = G^{-1/2} s_j sqrt(n2) with G = sum_j s_j s_j^T, followed by
+ * log(n2 a_j / sum a), a_j = ||A_{:j:}||_F^2. feat: device n2 x 17 float32. */
+int tp_mlp_features(const tp_tensor* A, const float* phi, float* feat, void* ws, size_t ws_bytes, void* stream);
+size_t tp_mlp_features_workspace(const tp_tensor* A);
+
+/* logits[r] = o for each of nrows feature rows (fp16 weights and activations
+ * on the matrix cores, float32 accumulation). */
+int tp_mlp_forward(const float* params, const float* feat, int64_t nrows, float* logits, void* stream);
+
+/* One training step on ntensors tensors of nslices lateral slices each
+ * (feat: (ntensors nslices) x 17 in tensor order; target: the exact leverage
+ * distribution of each tensor, ntensors x nslices, rows summing to 1). Loss:
+ * mean over tensors of KL(target || softmax(logits of the tensor)). Writes
+ * the loss (float, may be NULL) and the gradient (tp_mlp_param_count() float32 values,
+ * may be NULL), then, if step >= 1, applies Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias correction with this step number) to params with moments m, v. */
+int tp_mlp_train_step(float* params, float* m, float* v, int64_t step, double lr, const float* feat,
+                      const float* target, int64_t ntensors, int64_t nslices, float* loss, float* grad, void* ws,
+                      size_t ws_bytes, void* stream);
+size_t tp_mlp_train_workspace(int64_t ntensors, int64_t nslices);
+
+/* Sampling weights for the lateral slices of A from the network:
+ * w = (1 - alpha) softmax(logits) + alpha ||A_{:j:}||_F^2 / ||A||_F^2
+ * (device float64, n2 values; alpha keeps every slice's probability at
+ * least alpha times its squared-norm probability). Feed w to tp_tsample or
+ * tp_tcur as TP_P_USER weights. */
+int tp_mlp_proposal(const float* params, const tp_tensor* A, const float* phi, double alpha, double* w, void* ws,
+                    size_t ws_bytes, void* stream);
+size_t tp_mlp_proposal_workspace(const tp_tensor* A);
+
 #ifdef __cplusplus
 }
 #endif

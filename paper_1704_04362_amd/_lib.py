@@ -55,6 +55,17 @@ _SIGS = {
     "tp_tcomplete": (C.c_int, [P(Tensor), C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
                                P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tcomplete_workspace": (C.c_size_t, [P(Tensor)]),
+    "tp_mlp_param_count": (C.c_int, []),
+    "tp_mlp_features": (C.c_int, [P(Tensor), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_mlp_features_workspace": (C.c_size_t, [P(Tensor)]),
+    "tp_mlp_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "tp_mlp_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
+                                    C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_size_t, C.c_void_p]),
+    "tp_mlp_train_workspace": (C.c_size_t, [C.c_int64, C.c_int64]),
+    "tp_mlp_proposal": (C.c_int, [C.c_void_p, P(Tensor), C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                  C.c_size_t, C.c_void_p]),
+    "tp_mlp_proposal_workspace": (C.c_size_t, [P(Tensor)]),
 }
 
 _lib = None

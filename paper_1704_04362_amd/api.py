@@ -246,3 +246,64 @@ def tcomplete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
                              C.byref(_tensor(L_)), C.byref(_tensor(E)), C.byref(_tensor(Y)), ranks.data_ptr(),
                              L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream()))
     return L_, E, Y, ranks
+
+
+# ---------------------------------------------------------------------------
+# learned leverage proposal
+# ---------------------------------------------------------------------------
+
+def mlp_param_count():
+    return int(L.load().tp_mlp_param_count())
+
+
+def mlp_pack(P, device="cuda"):
+    """Flat float32 device parameter vector from a dict with W1 (17x128), b1,
+    W2 (128x128), b2, w3 (128), b3 (1)."""
+    import numpy as np
+    flat = np.concatenate([np.asarray(P[k], dtype=np.float64).ravel() for k in ("W1", "b1", "W2", "b2", "w3", "b3")])
+    return torch.from_numpy(flat.astype(np.float32)).to(device)
+
+
+def mlp_features(A, phi):
+    """n2 x 17 float32 features of A's lateral slices (phi: (n1 n3) x 16)."""
+    _need_gpu(A, phi)
+    feat = torch.empty((A.shape[1], 17), dtype=torch.float32, device=A.device)
+    lib = L.load()
+    t = _tensor(A)
+    ws = _ws(lib.tp_mlp_features_workspace(C.byref(t)), A.device)
+    L.check(lib.tp_mlp_features(C.byref(t), phi.data_ptr(), feat.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return feat
+
+
+def mlp_forward(params, feat):
+    _need_gpu(params, feat)
+    out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+    L.check(L.load().tp_mlp_forward(params.data_ptr(), feat.data_ptr(), feat.shape[0], out.data_ptr(), _stream()))
+    return out
+
+
+def mlp_train_step(params, m, v, step, lr, feat, target, want_grad=False):
+    """One step (see tp_mlp_train_step); returns (loss tensor, grad or None)."""
+    _need_gpu(params, m, v, feat, target)
+    T, n = target.shape
+    loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    grad = torch.empty_like(params) if want_grad else None
+    lib = L.load()
+    ws = _ws(lib.tp_mlp_train_workspace(T, n), feat.device)
+    L.check(lib.tp_mlp_train_step(params.data_ptr(), m.data_ptr(), v.data_ptr(), int(step), float(lr),
+                                  feat.data_ptr(), target.data_ptr(), T, n, loss.data_ptr(),
+                                  grad.data_ptr() if grad is not None else None, ws.data_ptr(), ws.numel(),
+                                  _stream()))
+    return loss, grad
+
+
+def mlp_proposal(params, A, phi, alpha=0.1):
+    """float64 sampling weights for A's lateral slices from the network."""
+    _need_gpu(params, A, phi)
+    w = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+    lib = L.load()
+    t = _tensor(A)
+    ws = _ws(lib.tp_mlp_proposal_workspace(C.byref(t)), A.device)
+    L.check(lib.tp_mlp_proposal(params.data_ptr(), C.byref(t), phi.data_ptr(), float(alpha), w.data_ptr(),
+                                ws.data_ptr(), ws.numel(), _stream()))
+    return w

@@ -1,0 +1,515 @@
+// Learned lateral-leverage proposal: cheap per-slice features, a small MLP
+// (17 -> 128 -> 128 -> 1, ReLU) on the fp16 matrix cores with float32
+// accumulation, per-tensor softmax with a KL loss against the exact
+// leverage distribution, backward pass and Adam. Not part of the paper,
+// which estimates leverage with a randomized routine it cites without
+// describing; the exact scores (eq. cur-col-prob) stay the fallback.
+//
+// Features of lateral slice j of an n1 x n2 x n3 tensor A: the sketch
+// s_j = Phi^T vec(A_{:j:}) with a caller-supplied (n1 n3) x 16 matrix Phi,
+// whitened as z_j = G^{-1/2} s_j sqrt(n2), G = sum_j s_j s_j^T, and
+// f_j = log(n2 a_j / sum a), a_j = ||A_{:j:}||_F^2.
+//
+// Parameters are one float32 array (the master copy) laid out as
+//   W1 (17 x 128) | b1 (128) | W2 (128 x 128) | b2 (128) | w3 (128) | b3 (1)
+// (h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), o = h2 w3 + b3); the
+// forward and backward passes use fp16 copies of W1 and W2 and fp16
+// activations as matrix-core operands.
+#include <cmath>
+
+#include "common.hpp"
+#include "jacobi.hpp"
+#include "mlp.hpp"
+
+namespace tp {
+namespace {
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int DS = 16, DIN = 17, KIN = 32, HID = 128;
+constexpr int OFF_W1 = 0, OFF_B1 = DIN * HID, OFF_W2 = OFF_B1 + HID, OFF_B2 = OFF_W2 + HID * HID,
+              OFF_W3 = OFF_B2 + HID, OFF_B3 = OFF_W3 + HID;
+constexpr int NPARAM = OFF_B3 + 1;
+static_assert(NPARAM == kMlpParams, "parameter layout");
+
+// ---------------------------------------------------------------------------
+// features
+// ---------------------------------------------------------------------------
+constexpr int FROWS = 16;  // horizontal slices per workgroup
+constexpr int FNT = 256;
+
+// Partial sketches and squared norms over FROWS rows for the FT = 256 / CH
+// lateral slices of one workgroup (CH = n3 / 4 pieces of 4 values per tube).
+// In every row those tubes are one contiguous run; thread t always owns
+// piece t of the run and accumulates it over the rows (float64), then the
+// pieces of a tube are added in a fixed order through LDS.
+// partial layout: [rowblock][n2][DS + 1] (float64).
+__global__ __launch_bounds__(FNT) void sketch_partial_kernel(const float* __restrict__ a, const float* __restrict__ phi,
+                                                              int64_t n1, int64_t n2, int64_t n3,
+                                                              double* __restrict__ partial) {
+  extern __shared__ double sm[];  // [FNT][DS+1] pieces, then the phi row (n3 x DS floats)
+  const int tid = threadIdx.x;
+  const int64_t CH = n3 / 4;
+  const int64_t FT = FNT / CH;
+  const int64_t j0 = (int64_t)blockIdx.x * FT, i0 = (int64_t)blockIdx.y * FROWS;
+  const int64_t ntub = (n2 - j0) < FT ? (n2 - j0) : FT;
+  const int64_t rows = (n1 - i0) < FROWS ? (n1 - i0) : FROWS;
+  float* sphi = reinterpret_cast<float*>(sm + FNT * (DS + 1));
+  const bool live = tid < ntub * CH;
+  const int64_t k0 = (tid % CH) * 4;
+  double acc[DS + 1];
+#pragma unroll
+  for (int d = 0; d <= DS; ++d) acc[d] = 0.0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const int64_t i = i0 + r;
+    __syncthreads();
+    for (int64_t e = tid; e < n3 * DS; e += FNT) sphi[e] = phi[i * n3 * DS + e];
+    __syncthreads();
+    if (live) {
+      const float4 x = *reinterpret_cast<const float4*>(a + (i * n2 + j0) * n3 + (int64_t)tid * 4);
+      const float xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double v = (double)xv[e];
+        acc[DS] += v * v;
+#pragma unroll
+        for (int d = 0; d < DS; ++d) acc[d] += v * (double)sphi[(k0 + e) * DS + d];
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d <= DS; ++d) sm[tid * (DS + 1) + d] = acc[d];
+  __syncthreads();
+  for (int64_t e = tid; e < ntub * (DS + 1); e += FNT) {
+    const int64_t t = e / (DS + 1), d = e % (DS + 1);
+    double s = 0.0;
+    for (int64_t p = 0; p < CH; ++p) s += sm[(t * CH + p) * (DS + 1) + d];
+    partial[((int64_t)blockIdx.y * n2 + j0 + t) * (DS + 1) + d] = s;
+  }
+}
+
+// Sums the row-block partials, whitens the sketch with G^{-1/2} (float64
+// Jacobi on the 16 x 16 Gram) and writes the 17 features per slice.
+__global__ __launch_bounds__(256) void sketch_finish_kernel(const double* __restrict__ partial, int64_t nb,
+                                                             int64_t n2, double* __restrict__ sk,
+                                                             float* __restrict__ feat) {
+  __shared__ JacobiShared<DS, 256> sh;
+  __shared__ double T[DS][DS];
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < n2 * (DS + 1); e += 256) {
+    double s = 0.0;
+    for (int64_t b = 0; b < nb; ++b) s += partial[b * n2 * (DS + 1) + e];
+    sk[e] = s;
+  }
+  __syncthreads();
+  // G = S^T S, total squared norm
+  {
+    const int i = tid / DS, j = tid % DS;  // 256 = 16 x 16 entries
+    double g = 0.0;
+    for (int64_t r = 0; r < n2; ++r) g += sk[r * (DS + 1) + i] * sk[r * (DS + 1) + j];
+    sh.Hr[i][j] = g;
+    sh.Hi[i][j] = 0.0;
+  }
+  double at = 0.0;
+  for (int64_t r = tid; r < n2; r += 256) at += sk[r * (DS + 1) + DS];
+  red[tid] = at;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double atot = red[0];
+  jacobi_eig_lds<DS, 256>(sh, DS, 30, 1e-15);
+  {
+    const int i = tid / DS, j = tid % DS;
+    double t = 0.0;
+    for (int q = 0; q < DS; ++q) {
+      const double l = sh.Hr[q][q];
+      if (l > 0.0) t += sh.Vr[i][q] * sh.Vr[j][q] / sqrt(l);
+    }
+    T[i][j] = t * sqrt((double)n2);
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < n2 * DIN; e += 256) {
+    const int64_t r = e / DIN;
+    const int d = (int)(e % DIN);
+    double v;
+    if (d < DS) {
+      v = 0.0;
+      for (int q = 0; q < DS; ++q) v += sk[r * (DS + 1) + q] * T[q][d];
+    } else {
+      v = log((double)n2 * sk[r * (DS + 1) + DS] / atot);
+    }
+    feat[e] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MLP on the matrix cores
+// ---------------------------------------------------------------------------
+constexpr int TR = 64;  // rows per tile
+constexpr int NT = 256;
+constexpr int LX = KIN + 8, LH = HID + 8;
+
+// acc += A[16 rows][K] * B[K][16 cols] with element strides:
+// A(i, k) = A[i * asi + k * ask], B(k, j) = B[k * bsk + j * bsj].
+__device__ __forceinline__ f32x4 mfma_tile(const _Float16* A, int asi, int ask, const _Float16* B, int bsk, int bsj,
+                                           int K, f32x4 acc) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kq = 4 * (lane >> 4);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    half4 a, b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      a[e] = A[r * asi + (k0 + kq + e) * ask];
+      b[e] = B[(k0 + kq + e) * bsk + r * bsj];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+struct MlpShared {
+  _Float16 X[TR][LX];    // input tile, features padded to KIN
+  _Float16 W1[KIN][LH];  // W1 padded (rows 17..31 zero)
+  _Float16 W2[HID][LH];
+  _Float16 H1[TR][LH];
+  _Float16 H2[TR][LH];
+  _Float16 D[TR][LH];    // dH2, then dH1
+  float b1[HID], b2[HID], w3[HID];
+  float z[TR][HID + 4];  // staging for row sums
+  float dout[TR];
+};
+
+// Forward pass of one tile; leaves H1, H2 (post-ReLU, fp16) in LDS and the
+// logits in out (when set). Pre-activations are positive exactly where the
+// stored post-activations are, which the backward pass uses as the masks.
+__device__ void mlp_tile_forward(MlpShared& s, const float* __restrict__ P, const float* __restrict__ feat,
+                                 int64_t nrows, int64_t r0, float* out) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < TR * KIN; e += NT) {
+    const int r = e / KIN, c = e % KIN;
+    const int64_t row = r0 + r;
+    s.X[r][c] = (_Float16)((c < DIN && row < nrows) ? feat[row * DIN + c] : 0.f);
+  }
+  for (int e = tid; e < KIN * HID; e += NT) {
+    const int r = e / HID, c = e % HID;
+    s.W1[r][c] = (_Float16)(r < DIN ? P[OFF_W1 + r * HID + c] : 0.f);
+  }
+  for (int e = tid; e < HID * HID; e += NT) s.W2[e / HID][e % HID] = (_Float16)P[OFF_W2 + e];
+  for (int e = tid; e < HID; e += NT) {
+    s.b1[e] = P[OFF_B1 + e];
+    s.b2[e] = P[OFF_B2 + e];
+    s.w3[e] = P[OFF_W3 + e];
+  }
+  __syncthreads();
+  // layer 1: wave w owns rows 16w..16w+15, all 8 column tiles
+  for (int nt = 0; nt < HID / 16; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma_tile(&s.X[16 * wave][0], LX, 1, &s.W1[0][16 * nt], LH, 1, KIN, acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * wave + 4 * (lane >> 4) + e, col = 16 * nt + (lane & 15);
+      s.H1[row][col] = (_Float16)fmaxf(acc[e] + s.b1[col], 0.f);
+    }
+  }
+  __syncthreads();
+  for (int nt = 0; nt < HID / 16; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma_tile(&s.H1[16 * wave][0], LH, 1, &s.W2[0][16 * nt], LH, 1, HID, acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * wave + 4 * (lane >> 4) + e, col = 16 * nt + (lane & 15);
+      const float h = fmaxf(acc[e] + s.b2[col], 0.f);
+      s.H2[row][col] = (_Float16)h;
+      s.z[row][col] = h * s.w3[col];
+    }
+  }
+  __syncthreads();
+  if (out && tid < TR) {
+    float o = P[OFF_B3];
+    for (int c = 0; c < HID; ++c) o += s.z[tid][c];
+    if (r0 + tid < nrows) out[r0 + tid] = o;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(NT) void mlp_forward_kernel(const float* __restrict__ P, const float* __restrict__ feat,
+                                                         int64_t nrows, float* __restrict__ out) {
+  __shared__ MlpShared s;
+  mlp_tile_forward(s, P, feat, nrows, (int64_t)blockIdx.x * TR, out);
+}
+
+// Per tensor: p = softmax(o), loss = KL(p* || p), dO = (p - p*) / T.
+__global__ __launch_bounds__(256) void softmax_grad_kernel(const float* __restrict__ o,
+                                                           const float* __restrict__ target, int64_t nsl, int64_t T,
+                                                           float* __restrict__ dout, float* __restrict__ loss_part) {
+  __shared__ double red[256];
+  const int64_t t = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* ot = o + t * nsl;
+  const float* pt = target + t * nsl;
+  double m = -INFINITY;
+  for (int64_t j = tid; j < nsl; j += 256) m = fmax(m, (double)ot[j]);
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double mx = red[0];
+  __syncthreads();
+  double se = 0.0;
+  for (int64_t j = tid; j < nsl; j += 256) se += exp((double)ot[j] - mx);
+  red[tid] = se;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double lse = mx + log(red[0]);
+  __syncthreads();
+  double kl = 0.0;
+  for (int64_t j = tid; j < nsl; j += 256) {
+    const double lp = (double)ot[j] - lse;
+    const double q = (double)pt[j];
+    if (q > 0) kl += q * (log(q) - lp);
+    dout[t * nsl + j] = (float)((exp(lp) - q) / (double)T);
+  }
+  red[tid] = kl;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) loss_part[t] = (float)(red[0] / (double)T);
+}
+
+// Backward of one tile: recomputes the forward pass, then writes this
+// tile's gradient contribution (parameter layout) to partial[tile].
+__global__ __launch_bounds__(NT) void mlp_backward_kernel(const float* __restrict__ P, const float* __restrict__ feat,
+                                                          const float* __restrict__ dout, int64_t nrows,
+                                                          float* __restrict__ partial) {
+  __shared__ MlpShared s;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * TR;
+  mlp_tile_forward(s, P, feat, nrows, r0, nullptr);
+  float* g = partial + (int64_t)blockIdx.x * NPARAM;
+  if (tid < TR) s.dout[tid] = (r0 + tid < nrows) ? dout[r0 + tid] : 0.f;
+  __syncthreads();
+  // w3, b3 and dH2 = dO w3 (.) [h2 > 0]
+  for (int c = tid; c < HID; c += NT) {
+    float gw = 0.f;
+    for (int r = 0; r < TR; ++r) gw += (float)s.H2[r][c] * s.dout[r];
+    g[OFF_W3 + c] = gw;
+  }
+  if (tid == 0) {
+    float gb = 0.f;
+    for (int r = 0; r < TR; ++r) gb += s.dout[r];
+    g[OFF_B3] = gb;
+  }
+  for (int e = tid; e < TR * HID; e += NT) {
+    const int r = e / HID, c = e % HID;
+    s.D[r][c] = (_Float16)((float)s.H2[r][c] > 0.f ? s.dout[r] * s.w3[c] : 0.f);
+  }
+  __syncthreads();
+  // b2 = column sums of dH2; W2 = H1^T dH2
+  for (int c = tid; c < HID; c += NT) {
+    float gb = 0.f;
+    for (int r = 0; r < TR; ++r) gb += (float)s.D[r][c];
+    g[OFF_B2 + c] = gb;
+  }
+  for (int t = wave; t < (HID / 16) * (HID / 16); t += NT / 64) {
+    const int it = t / (HID / 16), jt = t % (HID / 16);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma_tile(&s.H1[0][16 * it], 1, LH, &s.D[0][16 * jt], LH, 1, TR, acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * it + 4 * (lane >> 4) + e, col = 16 * jt + (lane & 15);
+      g[OFF_W2 + row * HID + col] = acc[e];
+    }
+  }
+  // dH1 = (dH2 W2^T) (.) [h1 > 0], staged in z as float
+  for (int nt = 0; nt < HID / 16; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma_tile(&s.D[16 * wave][0], LH, 1, &s.W2[16 * nt][0], 1, LH, HID, acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * wave + 4 * (lane >> 4) + e, col = 16 * nt + (lane & 15);
+      s.z[row][col] = (float)s.H1[row][col] > 0.f ? acc[e] : 0.f;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < TR * HID; e += NT) s.D[e / HID][e % HID] = (_Float16)s.z[e / HID][e % HID];
+  __syncthreads();
+  // b1 = column sums of dH1 (float); W1 = X^T dH1
+  for (int c = tid; c < HID; c += NT) {
+    float gb = 0.f;
+    for (int r = 0; r < TR; ++r) gb += s.z[r][c];
+    g[OFF_B1 + c] = gb;
+  }
+  for (int t = wave; t < (KIN / 16) * (HID / 16); t += NT / 64) {
+    const int it = t / (HID / 16), jt = t % (HID / 16);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma_tile(&s.X[0][16 * it], 1, LX, &s.D[0][16 * jt], LH, 1, TR, acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * it + 4 * (lane >> 4) + e, col = 16 * jt + (lane & 15);
+      if (row < DIN) g[OFF_W1 + row * HID + col] = acc[e];
+    }
+  }
+}
+
+__global__ void grad_reduce_kernel(const float* __restrict__ partial, int64_t ntiles, float* __restrict__ grad) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  float s = 0.f;
+  for (int64_t t = 0; t < ntiles; ++t) s += partial[t * NPARAM + p];
+  grad[p] = s;
+}
+
+__global__ void loss_reduce_kernel(const float* __restrict__ part, int64_t T, float* __restrict__ loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.f;
+    for (int64_t t = 0; t < T; ++t) s += part[t];
+    *loss = s;
+  }
+}
+
+__global__ void adam_kernel(float* __restrict__ P, float* __restrict__ M, float* __restrict__ V,
+                            const float* __restrict__ G, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  const float g = G[p];
+  const float m = b1 * M[p] + (1.f - b1) * g;
+  const float v = b2 * V[p] + (1.f - b2) * g * g;
+  M[p] = m;
+  V[p] = v;
+  P[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// w = (1 - alpha) softmax(o) + alpha a / sum(a), float64, one workgroup.
+__global__ __launch_bounds__(256) void proposal_kernel(const float* __restrict__ o, const double* __restrict__ a,
+                                                       int64_t n, double alpha, double* __restrict__ w) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double m = -INFINITY, at = 0.0;
+  for (int64_t j = tid; j < n; j += 256) {
+    m = fmax(m, (double)o[j]);
+  }
+  red[tid] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double mx = red[0];
+  __syncthreads();
+  double se = 0.0;
+  for (int64_t j = tid; j < n; j += 256) {
+    se += exp((double)o[j] - mx);
+    at += a[j];
+  }
+  red[tid] = se;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double z = red[0];
+  __syncthreads();
+  red[tid] = at;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double asum = red[0];
+  for (int64_t j = tid; j < n; j += 256)
+    w[j] = (1.0 - alpha) * exp((double)o[j] - mx) / z + alpha * (asum > 0 ? a[j] / asum : 1.0 / (double)n);
+}
+
+unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+size_t mlp_features_ws(int64_t n1, int64_t n2) {
+  const int64_t nb = (n1 + FROWS - 1) / FROWS;
+  return align_up(size_t(nb) * n2 * (DS + 1) * 8) + align_up(size_t(n2) * (DS + 1) * 8) + 512;
+}
+
+int mlp_features(const float* a, int64_t n1, int64_t n2, int64_t n3, const float* phi, float* feat, void* ws,
+                 hipStream_t st) {
+  if (n3 % 4 || n3 / 4 > FNT) return fail(TP_EUNSUPPORTED, "feature extraction needs n3 divisible by 4, <= 1024");
+  const int64_t CH = n3 / 4, FT = FNT / CH;
+  const size_t lds = size_t(FNT) * (DS + 1) * 8 + size_t(n3) * DS * 4;
+  if (lds > 64 * 1024) return fail(TP_EUNSUPPORTED, "tube length too large for feature extraction");
+  const int64_t nb = (n1 + FROWS - 1) / FROWS;
+  Arena ar(ws, mlp_features_ws(n1, n2));
+  double* part = ar.take<double>(nb * n2 * (DS + 1));
+  double* sk = ar.take<double>(n2 * (DS + 1));
+  if (!ar.ok()) return fail(TP_EWORKSPACE, "feature workspace too small");
+  hipLaunchKernelGGL(sketch_partial_kernel, dim3((unsigned)((n2 + FT - 1) / FT), (unsigned)nb), dim3(FNT), lds, st, a,
+                     phi, n1, n2, n3, part);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sketch_finish_kernel, dim3(1), dim3(256), 0, st, part, nb, n2, sk, feat);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int mlp_forward(const float* P, const float* feat, int64_t nrows, float* out, hipStream_t st) {
+  if (nrows == 0) return TP_OK;
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((nrows + TR - 1) / TR)), dim3(NT), 0, st, P, feat, nrows,
+                     out);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+size_t mlp_train_ws(int64_t ntensors, int64_t nslices) {
+  const int64_t rows = ntensors * nslices, ntiles = (rows + TR - 1) / TR;
+  return 3 * align_up(size_t(rows) * 4) + align_up(size_t(ntiles) * NPARAM * 4) + align_up(size_t(NPARAM) * 4) +
+         align_up(size_t(ntensors) * 4) + 2048;
+}
+
+int mlp_train_step(float* P, float* M, float* V, int64_t step, double lr, const float* feat, const float* target,
+                   int64_t T, int64_t nsl, float* loss, float* grad_out, void* ws, hipStream_t st) {
+  const int64_t rows = T * nsl, ntiles = (rows + TR - 1) / TR;
+  Arena ar(ws, mlp_train_ws(T, nsl));
+  float* o = ar.take<float>(rows);
+  float* dout = ar.take<float>(rows);
+  float* part = ar.take<float>(ntiles * NPARAM);
+  float* grad = ar.take<float>(NPARAM);
+  float* lpart = ar.take<float>(T);
+  if (!ar.ok()) return fail(TP_EWORKSPACE, "training workspace too small");
+  if (int rc = mlp_forward(P, feat, rows, o, st)) return rc;
+  hipLaunchKernelGGL(softmax_grad_kernel, dim3((unsigned)T), dim3(256), 0, st, o, target, nsl, T, dout, lpart);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(mlp_backward_kernel, dim3((unsigned)ntiles), dim3(NT), 0, st, P, feat, dout, rows, part);
+  TP_LAUNCH_CHECK();
+  float* g = grad_out ? grad_out : grad;
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3(nblk(NPARAM)), dim3(256), 0, st, part, ntiles, g);
+  TP_LAUNCH_CHECK();
+  if (loss) {
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, st, lpart, T, loss);
+    TP_LAUNCH_CHECK();
+  }
+  if (step > 0) {
+    const double b1 = 0.9, b2 = 0.999;
+    const double c1 = 1.0 - std::pow(b1, (double)step), c2 = 1.0 - std::pow(b2, (double)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(nblk(NPARAM)), dim3(256), 0, st, P, M, V, g, (float)lr, (float)b1,
+                       (float)b2, 1e-8f, (float)c1, (float)c2);
+    TP_LAUNCH_CHECK();
+  }
+  return TP_OK;
+}
+
+int mlp_proposal(const float* logits, const double* a, int64_t n, double alpha, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(proposal_kernel, dim3(1), dim3(256), 0, st, logits, a, n, alpha, w);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+}  // namespace tp
