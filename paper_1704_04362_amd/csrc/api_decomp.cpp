@@ -72,6 +72,7 @@ struct RangeFinder {
   bool real_last;
   Spec omega, Y, Q, Bh, Z, T;
   double *gre, *gim, *evals, *ure, *uim;
+  double *pre = nullptr, *pim = nullptr;  // partial Gram matrices of tall slices
 
   bool carve(Arena& ar) {
     omega = take(ar, K * n * s, dtype);
@@ -85,17 +86,21 @@ struct RangeFinder {
     ure = ar.take<double>(K * s * s);
     uim = ar.take<double>(K * s * s);
     evals = ar.take<double>(K * s);
+    const size_t np = gram_part_doubles(K, std::max(m, n), s);
+    if (np) {
+      pre = ar.take<double>(np);
+      pim = ar.take<double>(np);
+    }
     return ar.dry() || ar.ok();
   }
 
-  // out = orthonormal basis of the columns of X (rows x s) through
-  // X^H X = V diag(l) V^H, out = X V diag(l^-1/2), directions with
-  // l <= rtol l_max dropped (zero columns).
+  // out = orthonormal basis of the columns of X (rows x s) by CholeskyQR:
+  // X^H X = R^H R, out = X R^{-1}, with pivots at or below rtol times the
+  // largest diagonal entry dropped (zero columns).
   int orth(const Spec& X, int64_t rows, const Spec& out, int prec, hipStream_t st) const {
     const double rtol = dtype == TP_F64 ? 1e-24 : 1e-11;
-    if (int rc = gram(X.re, X.im, dtype, K, rows, s, s, rows * s, real_last, gre, gim, st)) return rc;
-    if (int rc = herm_eig(gre, gim, K, s, evals, ure, uim, st)) return rc;
-    if (int rc = eig_transform(ure, uim, evals, K, s, s, 0, rtol, 0.0, T.re, T.im, dtype, st)) return rc;
+    if (int rc = gram(X.re, X.im, dtype, K, rows, s, s, rows * s, real_last, gre, gim, pre, pim, st)) return rc;
+    if (int rc = chol_inv(gre, gim, K, s, rtol, real_last, T.re, T.im, dtype, st)) return rc;
     return mm(X, 0, rows, s, T, 0, s, s, out, K, real_last, dtype, prec, st);
   }
 
@@ -117,7 +122,7 @@ struct RangeFinder {
       std::swap(Q, Y);
     }
     if (int rc = mm(X, 1, m, n, Q, 0, m, s, Bh, K, real_last, dtype, prec, st)) return rc;
-    if (int rc = gram(Bh.re, Bh.im, dtype, K, n, s, s, n * s, real_last, gre, gim, st)) return rc;
+    if (int rc = gram(Bh.re, Bh.im, dtype, K, n, s, s, n * s, real_last, gre, gim, pre, pim, st)) return rc;
     return herm_eig(gre, gim, K, s, evals, ure, uim, st);
   }
 };
@@ -143,8 +148,12 @@ constexpr int kCorePowerIters = 2;
 // stream ids of the generator draws inside one call
 constexpr uint64_t kStreamColPick = 0, kStreamRowPick = 1, kStreamOmegaA = 2, kStreamOmegaC = 3, kStreamOmegaW = 4;
 
+// r + p columns, rounded up to a multiple of 4 (row strides the matrix-core
+// products accept) when that still fits the slices and the small solvers.
 int sketch_size(int64_t r, int64_t p, int64_t m, int64_t n) {
   int64_t s = r + p;
+  const int64_t s4 = (s + 3) / 4 * 4;
+  if (s4 <= std::min<int64_t>(m, n) && s4 <= kMaxS) s = s4;
   s = std::min<int64_t>(s, std::min<int64_t>(m, n));
   s = std::max<int64_t>(s, r);
   return (int)s;
@@ -155,8 +164,10 @@ int sketch_size(int64_t r, int64_t p, int64_t m, int64_t n) {
 struct TsvdLayout {
   Spec Ah, Ub, Vs, Us;
   RangeFinder rf;
+  double* lpart = nullptr;
   bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int s, int64_t r, int dt, bool real_last) {
     Ah = take(ar, K * n1 * n2, dt);
+    lpart = ar.take<double>(K * std::max(n1, n2));
     rf = RangeFinder{K, n1, n2, s, dt, real_last};
     rf.carve(ar);
     Ub = take(ar, K * s * r, dt);
@@ -167,7 +178,7 @@ struct TsvdLayout {
 };
 
 struct TcurLayout {
-  double *wbuf = nullptr, *wbuf2 = nullptr, *part = nullptr;
+  double *wbuf = nullptr, *wbuf2 = nullptr, *part = nullptr, *lpart = nullptr;
   void* sws = nullptr;
   Spec Ah, UbA, Vs;          // column leverage
   RangeFinder rfA, rfC, cf;  // range finders on A, C and the core
@@ -181,6 +192,7 @@ struct TcurLayout {
     wbuf2 = ar.take<double>(nmax);
     sws = ar.take<char>(sampler_ws(nmax));
     part = ar.take<double>(lateral_norms_ws(n1, n2, n3) / 8 + 1);
+    lpart = ar.take<double>(K * nmax);
     if (col_kind == TP_P_LEV) {
       sA = sketch_size(r, kOversample, n1, n2);
       Ah = take(ar, K * n1 * n2, dt);
@@ -269,14 +281,15 @@ int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, uint64_t s
     // right singular vectors V = Bh U_B diag(sigma)^-1: rows scaled inside the
     // leverage reduction
     if (int rc = mm(rf.Bh, 0, n2, s, Ub, 0, s, r, Vs, K, real_last, dt, prec, st)) return rc;
-    if (int rc = leverage(Vs.re, Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, rf.evals, s, rtol, lev_lateral, st))
+    if (int rc = leverage(Vs.re, Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, rf.evals, s, rtol, lay.lpart,
+                          lev_lateral, st))
       return rc;
   }
   if (lev_horizontal) {
     // left singular vectors U = Q U_B
     if (int rc = mm(rf.Q, 0, n1, s, Ub, 0, s, r, Us, K, real_last, dt, prec, st)) return rc;
-    if (int rc = leverage(Us.re, Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol, lev_horizontal,
-                          st))
+    if (int rc = leverage(Us.re, Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol, lay.lpart,
+                          lev_horizontal, st))
       return rc;
   }
   return TP_OK;
@@ -350,7 +363,7 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
       return rc;
     if (int rc = mm(lay.rfA.Bh, 0, n2, s, lay.UbA, 0, s, r, lay.Vs, K, real_last, dt, prec, st)) return rc;
     if (int rc = leverage(lay.Vs.re, lay.Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, lay.rfA.evals, s, rtol,
-                          lay.wbuf, st))
+                          lay.lpart, lay.wbuf, st))
       return rc;
     wcol = lay.wbuf;
   } else if (col_kind == TP_P_NORM2) {
@@ -387,7 +400,7 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
       return rc;
     if (int rc = mm(lay.rfC.Q, 0, n1, s, lay.UbC, 0, s, r, lay.Us, K, real_last, dt, prec, st)) return rc;
     if (int rc = leverage(lay.Us.re, lay.Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol,
-                          lay.wbuf2, st))
+                          lay.lpart, lay.wbuf2, st))
       return rc;
     wrow = lay.wbuf2;
   } else if (row_kind == TP_P_NORM2) {

@@ -1,14 +1,20 @@
 // Workgroup-level Hermitian Jacobi eigensolver on matrices held in LDS
-// (float64). Shared by the batched small eigensolver and the block Jacobi
-// SVD of the singular value thresholding.
+// (float64). Shared by the batched small eigensolver, the feature whitening
+// of the learned proposal and the block Jacobi SVD of the singular value
+// thresholding.
 //
 // Parallel cyclic Jacobi: each sweep visits every index pair once through a
-// round-robin tournament; in a round the n/2 disjoint pairs are rotated
-// together, rows first, then columns (and the accumulated vectors), which
-// applies the product of the disjoint rotations. For a pair (p, q) with
-// H_pq = |h| e^{i phi} the rotation is J = diag(1, e^{-i phi}) R(theta), R the
-// real Jacobi rotation [[c, s], [-s, c]] with t = tan(theta) the smaller root
-// of t^2 + 2 tau t - 1 = 0, tau = (H_qq - H_pp) / (2 |h|) (the classical
+// round-robin tournament (index m-1 fixed, the others rotating; for odd n
+// the extra index n is a dummy that pairs with nobody). In a round the m/2
+// disjoint pairs are rotated together. Because the rotations are disjoint,
+// the two-sided update J^H H J splits into independent 2 x 2 blocks
+// (rows of pair u, columns of pair v), so one pass updates H and the
+// accumulated vectors without intermediate barriers.
+//
+// For a pair (p, q) with H_pq = |h| e^{i phi} the rotation is
+// J = diag(1, e^{-i phi}) R(theta), R the real Jacobi rotation
+// [[c, s], [-s, c]] with t = tan(theta) the smaller root of
+// t^2 + 2 tau t - 1 = 0, tau = (H_qq - H_pp) / (2 |h|) (the classical
 // symmetric Schur step of Golub and Van Loan, made Hermitian by the phase).
 #pragma once
 
@@ -18,14 +24,34 @@ namespace tp {
 
 template <int MAXN, int NT>
 struct JacobiShared {
+  static_assert(NT % 64 == 0, "whole wavefronts");
   double Hr[MAXN][MAXN + 1], Hi[MAXN][MAXN + 1];
   double Vr[MAXN][MAXN + 1], Vi[MAXN][MAXN + 1];
-  double rc[MAXN / 2], rs[MAXN / 2], rpr[MAXN / 2], rpi[MAXN / 2];
-  int pp[MAXN / 2], qq[MAXN / 2];
-  int perm[MAXN + 1];
-  double red[NT];
+  double rc[MAXN / 2 + 1], rs[MAXN / 2 + 1], rpr[MAXN / 2 + 1], rpi[MAXN / 2 + 1];
+  int pp[MAXN / 2 + 1], qq[MAXN / 2 + 1];
+  double red[2][NT / 64];
   int done;
 };
+
+// Pair t of round rho in the tournament over m (even) indices.
+__device__ __forceinline__ void jacobi_pair(int m, int rho, int t, int& p, int& q) {
+  int a, b;
+  if (t == 0) {
+    a = m - 1;
+    b = rho;
+  } else {
+    a = (rho + t) % (m - 1);
+    b = (rho + m - 1 - t) % (m - 1);
+  }
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 // Diagonalises the n x n Hermitian matrix in sh.H (n <= MAXN) in place,
 // accumulating the unitary in sh.V (initialised here to the identity).
@@ -40,8 +66,6 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
     sh.Vr[i][j] = (i == j) ? 1.0 : 0.0;
     sh.Vi[i][j] = 0.0;
   }
-  const int m = (n % 2) ? n + 1 : n;  // even count; index n is a dummy
-  for (int i = tid; i < m; i += NT) sh.perm[i] = i;
   __syncthreads();
   // exact Hermitian symmetry of the input
   for (int e = tid; e < ne; e += NT) {
@@ -57,50 +81,49 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
     }
   }
   __syncthreads();
+  const int m = (n % 2) ? n + 1 : n;  // even count; index n is a dummy
   const int npairs = m / 2;
+  const int nblk = npairs * npairs;
   const double tol2 = rel_tol * rel_tol;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < ne; e += NT) {
-      const int i = e / n, j = e - i * n;
-      const double v = sh.Hr[i][j] * sh.Hr[i][j] + sh.Hi[i][j] * sh.Hi[i][j];
-      tot += v;
-      if (i != j) off += v;
-    }
-    sh.red[tid] = off;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-      if (tid < w) sh.red[tid] += sh.red[tid + w];
+    {
+      double off = 0.0, tot = 0.0;
+      for (int e = tid; e < ne; e += NT) {
+        const int i = e / n, j = e - i * n;
+        const double v = sh.Hr[i][j] * sh.Hr[i][j] + sh.Hi[i][j] * sh.Hi[i][j];
+        tot += v;
+        if (i != j) off += v;
+      }
+      off = wave_sum(off);
+      tot = wave_sum(tot);
+      if ((tid & 63) == 0) {
+        sh.red[0][tid >> 6] = off;
+        sh.red[1][tid >> 6] = tot;
+      }
       __syncthreads();
-    }
-    const double offsum = sh.red[0];
-    __syncthreads();
-    sh.red[tid] = tot;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-      if (tid < w) sh.red[tid] += sh.red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) sh.done = (offsum <= tol2 * sh.red[0]) || sh.red[0] == 0.0;
-    __syncthreads();
-    if (sh.done) break;
-    for (int round = 0; round < m - 1; ++round) {
-      if (tid < npairs) {
-        int a = sh.perm[tid], b = sh.perm[m - 1 - tid];
-        if (a > b) {
-          const int t = a;
-          a = b;
-          b = t;
+      if (tid == 0) {
+        double o = 0.0, t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+          o += sh.red[0][w];
+          t += sh.red[1][w];
         }
-        sh.pp[tid] = a;
-        sh.qq[tid] = b;
+        sh.done = (o <= tol2 * t) || t == 0.0;
+      }
+      __syncthreads();
+      if (sh.done) break;
+    }
+    for (int rho = 0; rho < m - 1; ++rho) {
+      // rotation of every pair of the round, from the current H
+      if (tid < npairs) {
+        int p, q;
+        jacobi_pair(m, rho, tid, p, q);
         double c = 1.0, sn = 0.0, pr = 1.0, pi = 0.0;
-        if (b < n) {
-          const double hr = sh.Hr[a][b], hi = sh.Hi[a][b];
+        if (q < n) {
+          const double hr = sh.Hr[p][q], hi = sh.Hi[p][q];
           const double habs = sqrt(hr * hr + hi * hi);
-          const double diag = fabs(sh.Hr[a][a]) + fabs(sh.Hr[b][b]);
+          const double diag = fabs(sh.Hr[p][p]) + fabs(sh.Hr[q][q]);
           if (habs > 1e-300 && habs > 1e-18 * diag) {
-            const double tau = (sh.Hr[b][b] - sh.Hr[a][a]) / (2.0 * habs);
+            const double tau = (sh.Hr[q][q] - sh.Hr[p][p]) / (2.0 * habs);
             const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             sn = t * c;
@@ -108,56 +131,82 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
             pi = hi / habs;
           }
         }
+        sh.pp[tid] = p;
+        sh.qq[tid] = q;
         sh.rc[tid] = c;
         sh.rs[tid] = sn;
         sh.rpr[tid] = pr;
         sh.rpi[tid] = pi;
       }
       __syncthreads();
-      // rows: H <- J^H H; for column j with x = H_pj, y = H_qj:
-      //   H_pj = c x - s e^{i phi} y,  H_qj = s x + c e^{i phi} y
-      for (int e = tid; e < npairs * n; e += NT) {
-        const int r = e / n, j = e - r * n;
-        const int p = sh.pp[r], q = sh.qq[r];
-        if (q >= n) continue;
-        const double c = sh.rc[r], sn = sh.rs[r], er = sh.rpr[r], ei = sh.rpi[r];
-        const double xr = sh.Hr[p][j], xi = sh.Hi[p][j], yr = sh.Hr[q][j], yi = sh.Hi[q][j];
-        const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
-        sh.Hr[p][j] = c * xr - sn * eyr;
-        sh.Hi[p][j] = c * xi - sn * eyi;
-        sh.Hr[q][j] = sn * xr + c * eyr;
-        sh.Hi[q][j] = sn * xi + c * eyi;
-      }
-      __syncthreads();
-      // columns: H <- H J, V <- V J; for row i with x = M_ip, y = M_iq:
-      //   M_ip = c x - s e^{-i phi} y,  M_iq = s x + c e^{-i phi} y
-      for (int e = tid; e < npairs * n; e += NT) {
-        const int r = e / n, i = e - r * n;
-        const int p = sh.pp[r], q = sh.qq[r];
-        if (q >= n) continue;
-        const double c = sh.rc[r], sn = sh.rs[r], er = sh.rpr[r], ei = -sh.rpi[r];
-        {
-          const double xr = sh.Hr[i][p], xi = sh.Hi[i][p], yr = sh.Hr[i][q], yi = sh.Hi[i][q];
-          const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
-          sh.Hr[i][p] = c * xr - sn * eyr;
-          sh.Hi[i][p] = c * xi - sn * eyi;
-          sh.Hr[i][q] = sn * xr + c * eyr;
-          sh.Hi[i][q] = sn * xi + c * eyi;
-        }
-        {
+      // H <- J^H H J by 2 x 2 blocks, then V <- V J by row pairs. Row
+      // transform of pair u on a column (x = H_pj, y = H_qj):
+      //   H_pj = c x - s e^{i phi} y,  H_qj = s x + c e^{i phi} y;
+      // column transform of pair v on a row (x = M_ip, y = M_iq):
+      //   M_ip = c x - s e^{-i phi} y,  M_iq = s x + c e^{-i phi} y.
+      for (int e = tid; e < nblk + n * npairs; e += NT) {
+        if (e < nblk) {
+          const int u = e / npairs, v = e - u * npairs;
+          const int p0 = sh.pp[u], q0 = sh.qq[u], p1 = sh.pp[v], q1 = sh.qq[v];
+          const bool r2 = q0 < n, c2 = q1 < n;
+          if (!r2 && !c2) continue;  // 1 x 1 block of two idle indices
+          double ar = sh.Hr[p0][p1], ai = sh.Hi[p0][p1];               // (p0, p1)
+          double br = c2 ? sh.Hr[p0][q1] : 0.0, bi = c2 ? sh.Hi[p0][q1] : 0.0;  // (p0, q1)
+          double cr = r2 ? sh.Hr[q0][p1] : 0.0, ci = r2 ? sh.Hi[q0][p1] : 0.0;  // (q0, p1)
+          double dr = (r2 && c2) ? sh.Hr[q0][q1] : 0.0, di = (r2 && c2) ? sh.Hi[q0][q1] : 0.0;
+          if (r2) {
+            const double c = sh.rc[u], s = sh.rs[u], er = sh.rpr[u], ei = sh.rpi[u];
+            // column p1: x = a, y = c
+            double eyr = er * cr - ei * ci, eyi = er * ci + ei * cr;
+            const double nar = c * ar - s * eyr, nai = c * ai - s * eyi;
+            const double ncr = s * ar + c * eyr, nci = s * ai + c * eyi;
+            // column q1: x = b, y = d
+            eyr = er * dr - ei * di;
+            eyi = er * di + ei * dr;
+            const double nbr = c * br - s * eyr, nbi = c * bi - s * eyi;
+            const double ndr = s * br + c * eyr, ndi = s * bi + c * eyi;
+            ar = nar, ai = nai, cr = ncr, ci = nci, br = nbr, bi = nbi, dr = ndr, di = ndi;
+          }
+          if (c2) {
+            const double c = sh.rc[v], s = sh.rs[v], er = sh.rpr[v], ei = -sh.rpi[v];
+            // row p0: x = a, y = b
+            double eyr = er * br - ei * bi, eyi = er * bi + ei * br;
+            const double nar = c * ar - s * eyr, nai = c * ai - s * eyi;
+            const double nbr = s * ar + c * eyr, nbi = s * ai + c * eyi;
+            // row q0: x = c, y = d
+            eyr = er * dr - ei * di;
+            eyi = er * di + ei * dr;
+            const double ncr = c * cr - s * eyr, nci = c * ci - s * eyi;
+            const double ndr = s * cr + c * eyr, ndi = s * ci + c * eyi;
+            ar = nar, ai = nai, br = nbr, bi = nbi, cr = ncr, ci = nci, dr = ndr, di = ndi;
+          }
+          sh.Hr[p0][p1] = ar;
+          sh.Hi[p0][p1] = ai;
+          if (c2) {
+            sh.Hr[p0][q1] = br;
+            sh.Hi[p0][q1] = bi;
+          }
+          if (r2) {
+            sh.Hr[q0][p1] = cr;
+            sh.Hi[q0][p1] = ci;
+          }
+          if (r2 && c2) {
+            sh.Hr[q0][q1] = dr;
+            sh.Hi[q0][q1] = di;
+          }
+        } else {
+          const int f = e - nblk;
+          const int v = f / n, i = f - v * n;
+          const int p = sh.pp[v], q = sh.qq[v];
+          if (q >= n) continue;
+          const double c = sh.rc[v], s = sh.rs[v], er = sh.rpr[v], ei = -sh.rpi[v];
           const double xr = sh.Vr[i][p], xi = sh.Vi[i][p], yr = sh.Vr[i][q], yi = sh.Vi[i][q];
           const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
-          sh.Vr[i][p] = c * xr - sn * eyr;
-          sh.Vi[i][p] = c * xi - sn * eyi;
-          sh.Vr[i][q] = sn * xr + c * eyr;
-          sh.Vi[i][q] = sn * xi + c * eyi;
+          sh.Vr[i][p] = c * xr - s * eyr;
+          sh.Vi[i][p] = c * xi - s * eyi;
+          sh.Vr[i][q] = s * xr + c * eyr;
+          sh.Vi[i][q] = s * xi + c * eyi;
         }
-      }
-      __syncthreads();
-      if (tid == 0) {
-        const int last = sh.perm[m - 1];
-        for (int i = m - 1; i > 1; --i) sh.perm[i] = sh.perm[i - 1];
-        sh.perm[1] = last;
       }
       __syncthreads();
     }

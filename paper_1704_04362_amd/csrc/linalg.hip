@@ -66,28 +66,34 @@ __global__ void randn_kernel(T* re, T* im, int64_t K, int64_t per_slice, int rea
   }
 }
 
-// G_k = X_k^H X_k (s x s, float64) for X_k rows x s (planar, row stride ldx).
+// Partial Gram matrices: workgroup (k, y) adds conj(x_i) x_j over the rows
+// [y rch, (y + 1) rch) of slice k (X_k rows x s, planar, row stride ldx) and
+// writes its s x s block to part[(k nch + y) s^2] (float64). With one chunk
+// the block is the Gram matrix itself.
 template <typename T>
 __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int64_t K,
                                                    int64_t rows, int s, int64_t ldx, int64_t sx, int real_last,
-                                                   double* __restrict__ gre, double* __restrict__ gim) {
+                                                   int64_t rch, double* __restrict__ gre, double* __restrict__ gim) {
   constexpr int CH = 32;
-  __shared__ double cr[CH][kMaxS], ci[CH][kMaxS];
+  __shared__ double cr[CH][kMaxS + 1], ci[CH][kMaxS + 1];
   const int64_t k = blockIdx.x;
+  const int64_t nch = gridDim.y;
   const bool real = k == 0 || (real_last && k == K - 1);
   const T* xr = xre + k * sx;
   const T* xi = xim + k * sx;
   const int ne = s * s;
+  const int64_t rbeg = (int64_t)blockIdx.y * rch;
+  const int64_t rend = (rbeg + rch) < rows ? (rbeg + rch) : rows;
   constexpr int PER = kMaxS * kMaxS / 256;
   double ar[PER], ai[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) ar[q] = ai[q] = 0.0;
-  for (int64_t r0 = 0; r0 < rows; r0 += CH) {
+  for (int64_t r0 = rbeg; r0 < rend; r0 += CH) {
     for (int e = threadIdx.x; e < CH * s; e += 256) {
       const int rr = e / s, c = e - rr * s;
       const int64_t row = r0 + rr;
       double vr = 0.0, vi = 0.0;
-      if (row < rows) {
+      if (row < rend) {
         vr = (double)xr[row * ldx + c];
         vi = real ? 0.0 : (double)xi[row * ldx + c];
       }
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ xre, co
       ci[rr][c] = vi;
     }
     __syncthreads();
-    const int nr = (int)((rows - r0) < CH ? (rows - r0) : CH);
+    const int nr = (int)((rend - r0) < CH ? (rend - r0) : CH);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + 256 * q;
@@ -112,24 +118,41 @@ __global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ xre, co
     }
     __syncthreads();
   }
+  const int64_t base = (k * nch + blockIdx.y) * ne;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + 256 * q;
     if (e >= ne) continue;
-    gre[k * ne + e] = ar[q];
-    gim[k * ne + e] = real ? 0.0 : ai[q];
+    gre[base + e] = ar[q];
+    gim[base + e] = real ? 0.0 : ai[q];
   }
+}
+
+// G[k][e] = sum over chunks y (in order) of part[k][y][e].
+__global__ void gram_reduce_kernel(const double* __restrict__ pre, const double* __restrict__ pim, int64_t K,
+                                   int64_t nch, int ne, double* __restrict__ gre, double* __restrict__ gim) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= K * ne) return;
+  const int64_t k = t / ne, e = t - k * ne;
+  double sr = 0.0, si = 0.0;
+  for (int64_t y = 0; y < nch; ++y) {
+    sr += pre[(k * nch + y) * ne + e];
+    si += pim[(k * nch + y) * ne + e];
+  }
+  gre[t] = sr;
+  gim[t] = si;
 }
 
 // Eigen-decomposition of one s x s Hermitian matrix per workgroup with the
 // LDS Jacobi solver; eigenvalues are returned in descending order (ties by
 // index) with the matching eigenvector columns.
+template <int MAXN>
 __global__ __launch_bounds__(256) void herm_eig_kernel(const double* __restrict__ gre,
                                                        const double* __restrict__ gim, int s, int max_sweeps,
                                                        double* __restrict__ evals, double* __restrict__ vre,
                                                        double* __restrict__ vim) {
-  __shared__ JacobiShared<kMaxS, 256> sh;
-  __shared__ int order[kMaxS];
+  __shared__ JacobiShared<MAXN, 256> sh;
+  __shared__ int order[MAXN];
   const int64_t k = blockIdx.x;
   const int ne = s * s;
   const int tid = threadIdx.x;
@@ -139,7 +162,7 @@ __global__ __launch_bounds__(256) void herm_eig_kernel(const double* __restrict_
     sh.Hi[i][j] = gim[k * ne + e];
   }
   __syncthreads();
-  jacobi_eig_lds<kMaxS, 256>(sh, s, max_sweeps, 1e-15);
+  jacobi_eig_lds<MAXN, 256>(sh, s, max_sweeps, 1e-15);
   if (tid < s) {
     const double lt = sh.Hr[tid][tid];
     int rank = 0;
@@ -157,6 +180,92 @@ __global__ __launch_bounds__(256) void herm_eig_kernel(const double* __restrict_
     vim[k * ne + e] = sh.Vi[i][src];
   }
   if (tid < s) evals[k * s + tid] = sh.Hr[order[tid]][order[tid]];
+}
+
+// Orthonormalising transform from a Gram matrix G = X^H X (CholeskyQR):
+// right-looking Cholesky G = R^H R in which a pivot at or below
+// rtol * max_i G_ii drops its index (that row of R is zero: the column is
+// taken as dependent on the earlier ones), then T = R^{-1} restricted to the
+// kept indices (zero rows and columns elsewhere), so that X T has
+// orthonormal columns on the kept indices and zero columns on the dropped
+// ones. One workgroup per slice; T is s x s, row-major.
+template <int MAXN, typename T>
+__global__ __launch_bounds__(128) void chol_inv_kernel(const double* __restrict__ gre,
+                                                       const double* __restrict__ gim, int64_t K, int s,
+                                                       double rtol, int real_last, T* __restrict__ tre,
+                                                       T* __restrict__ tim) {
+  __shared__ double Gr[MAXN][MAXN + 1], Gi[MAXN][MAXN + 1];
+  __shared__ double Tr[MAXN][MAXN + 1], Ti[MAXN][MAXN + 1];
+  __shared__ double rd[MAXN];
+  __shared__ double dmax;
+  const int64_t k = blockIdx.x;
+  const bool real = k == 0 || (real_last && k == K - 1);
+  const int tid = threadIdx.x;
+  const int ne = s * s;
+  for (int e = tid; e < ne; e += 128) {
+    const int i = e / s, j = e - i * s;
+    Gr[i][j] = gre[k * ne + e];
+    Gi[i][j] = real ? 0.0 : gim[k * ne + e];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < s; ++i) m = fmax(m, Gr[i][i]);
+    dmax = m;
+  }
+  __syncthreads();
+  const double tol = rtol * dmax;
+  for (int j = 0; j < s; ++j) {
+    const double d = Gr[j][j];
+    const bool keep = d > tol && d > 0.0;
+    const double inv = keep ? 1.0 / sqrt(d) : 0.0;
+    for (int l = j + 1 + tid; l < s; l += 128) {
+      Gr[j][l] *= inv;
+      Gi[j][l] *= inv;
+    }
+    if (tid == 0) rd[j] = keep ? sqrt(d) : 0.0;
+    __syncthreads();
+    if (keep) {
+      // trailing upper triangle: G_lm -= conj(R_jl) R_jm, j < l <= m
+      const int w = s - j - 1;
+      for (int e = tid; e < w * w; e += 128) {
+        const int l = j + 1 + e / w, m = j + 1 + e % w;
+        if (m < l) continue;
+        const double ar = Gr[j][l], ai = Gi[j][l], br = Gr[j][m], bi = Gi[j][m];
+        Gr[l][m] -= ar * br + ai * bi;
+        Gi[l][m] -= ar * bi - ai * br;
+      }
+    }
+    __syncthreads();
+  }
+  // T = R^{-1} on the kept indices, one column per thread (back substitution
+  // of R T = I): T_mm = 1 / R_mm, T_im = -(sum_{i<l<=m} R_il T_lm) / R_ii
+  for (int m = tid; m < s; m += 128) {
+    for (int i = 0; i < s; ++i) {
+      Tr[i][m] = 0.0;
+      Ti[i][m] = 0.0;
+    }
+    if (rd[m] > 0.0) {
+      Tr[m][m] = 1.0 / rd[m];
+      for (int i = m - 1; i >= 0; --i) {
+        if (rd[i] == 0.0) continue;
+        double ar = 0.0, ai = 0.0;
+        for (int l = i + 1; l <= m; ++l) {
+          const double rr = Gr[i][l], ri = Gi[i][l], xr = Tr[l][m], xi = Ti[l][m];
+          ar += rr * xr - ri * xi;
+          ai += rr * xi + ri * xr;
+        }
+        Tr[i][m] = -ar / rd[i];
+        Ti[i][m] = -ai / rd[i];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < ne; e += 128) {
+    const int i = e / s, j = e - i * s;
+    tre[k * ne + e] = (T)Tr[i][j];
+    tim[k * ne + e] = (T)(real ? 0.0 : Ti[i][j]);
+  }
 }
 
 // Small transforms from an eigen-decomposition G = V diag(lambda) V^H.
@@ -191,32 +300,40 @@ __global__ void transform_kernel(const double* __restrict__ vre, const double* _
   tim[e] = (T)(vim[src] * w);
 }
 
-// out[j] = sum_k w_k sum_{i<r} |X_k[j, i]|^2 * g_k[i], with g_k[i] =
-// 1/lambda_k[i] when scaled (so that X_k diag(1/sigma) is normalised), else 1;
-// w_k the conjugate weights of the half spectrum.
+// part[k][j] = w_k sum_{i<r} |X_k[j, i]|^2 g_k[i], with g_k[i] = 1/lambda_k[i]
+// when scaled (so that X_k diag(1/sigma) is normalised), else 1; w_k the
+// conjugate weights of the half spectrum (1 for the real slices, 2 for the
+// others). One thread per (row j, slice k = blockIdx.y).
 template <typename T>
 __global__ void leverage_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int64_t K, int64_t n,
                                 int64_t ldx, int64_t sx, int r, int real_last, const double* __restrict__ evals,
-                                int s, double rtol, double* __restrict__ out) {
+                                int s, double rtol, double* __restrict__ part) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = blockIdx.y;
+  if (j >= n) return;
+  const double wk = (k == 0 || (real_last && k == K - 1)) ? 1.0 : 2.0;
+  const double l0 = evals ? evals[k * s] : 0.0;
+  const double s0 = l0 > 0 ? sqrt(l0) : 0.0;
+  double sk = 0.0;
+  for (int i = 0; i < r; ++i) {
+    double g = 1.0;
+    if (evals) {
+      const double li = evals[k * s + i];
+      const double si = li > 0 ? sqrt(li) : 0.0;
+      g = (si > 0 && si > rtol * s0) ? 1.0 / li : 0.0;
+    }
+    const double a = (double)xre[k * sx + j * ldx + i], b = (double)xim[k * sx + j * ldx + i];
+    sk += (a * a + b * b) * g;
+  }
+  part[k * n + j] = wk * sk;
+}
+
+// out[j] = sum over k (in order) of part[k][j].
+__global__ void sum_slices_kernel(const double* __restrict__ part, int64_t K, int64_t n, double* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double acc = 0.0;
-  for (int64_t k = 0; k < K; ++k) {
-    const double wk = (k == 0 || (real_last && k == K - 1)) ? 1.0 : 2.0;
-    const double l0 = evals ? evals[k * s] : 0.0;
-    double sk = 0.0;
-    for (int i = 0; i < r; ++i) {
-      double g = 1.0;
-      if (evals) {
-        const double li = evals[k * s + i];
-        const double si = li > 0 ? sqrt(li) : 0.0, s0 = l0 > 0 ? sqrt(l0) : 0.0;
-        g = (si > 0 && si > rtol * s0) ? 1.0 / li : 0.0;
-      }
-      const double a = (double)xre[k * sx + j * ldx + i], b = (double)xim[k * sx + j * ldx + i];
-      sk += (a * a + b * b) * g;
-    }
-    acc += wk * sk;
-  }
+  for (int64_t k = 0; k < K; ++k) acc += part[k * n + j];
   out[j] = acc;
 }
 
@@ -278,23 +395,76 @@ int randn_spectrum(void* re, void* im, int dtype, int64_t K, int64_t rows, int64
   return TP_OK;
 }
 
+int64_t gram_chunks(int64_t rows) {
+  const int64_t c = (rows + 63) / 64;
+  return c < 1 ? 1 : (c > 16 ? 16 : c);
+}
+
+size_t gram_part_doubles(int64_t K, int64_t rows, int s) {
+  const int64_t nch = gram_chunks(rows);
+  return nch > 1 ? (size_t)(K * nch * s * s) : 0;
+}
+
 int gram(const void* xre, const void* xim, int dtype, int64_t K, int64_t rows, int s, int64_t ldx, int64_t sx,
-         bool real_last, double* gre, double* gim, hipStream_t st) {
+         bool real_last, double* gre, double* gim, double* pre, double* pim, hipStream_t st) {
   if (s < 1 || s > kMaxS) return fail(TP_EUNSUPPORTED, "Gram size outside 1..64");
+  if (K == 0) return TP_OK;
+  const int64_t nch = gram_chunks(rows);
+  if (nch > 1 && (!pre || !pim)) return fail(TP_EWORKSPACE, "Gram partial buffer missing");
+  const int64_t rch = (rows + nch - 1) / nch;
+  double* ore = nch > 1 ? pre : gre;
+  double* oim = nch > 1 ? pim : gim;
+  const dim3 grid((unsigned)K, (unsigned)nch);
   if (dtype == TP_F64)
-    hipLaunchKernelGGL(gram_kernel<double>, dim3((unsigned)K), dim3(256), 0, st, (const double*)xre,
-                       (const double*)xim, K, rows, s, ldx, sx, real_last ? 1 : 0, gre, gim);
+    hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, st, (const double*)xre, (const double*)xim, K,
+                       rows, s, ldx, sx, real_last ? 1 : 0, rch, ore, oim);
   else
-    hipLaunchKernelGGL(gram_kernel<float>, dim3((unsigned)K), dim3(256), 0, st, (const float*)xre,
-                       (const float*)xim, K, rows, s, ldx, sx, real_last ? 1 : 0, gre, gim);
+    hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, st, (const float*)xre, (const float*)xim, K, rows,
+                       s, ldx, sx, real_last ? 1 : 0, rch, ore, oim);
   TP_LAUNCH_CHECK();
+  if (nch > 1) {
+    const int ne = s * s;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(K * ne)), dim3(256), 0, st, pre, pim, K, nch, ne, gre,
+                       gim);
+    TP_LAUNCH_CHECK();
+  }
   return TP_OK;
 }
 
 int herm_eig(const double* gre, const double* gim, int64_t K, int s, double* evals, double* vre, double* vim,
              hipStream_t st) {
   if (s < 1 || s > kMaxS) return fail(TP_EUNSUPPORTED, "eigenproblem size outside 1..64");
-  hipLaunchKernelGGL(herm_eig_kernel, dim3((unsigned)K), dim3(256), 0, st, gre, gim, s, 40, evals, vre, vim);
+  if (K == 0) return TP_OK;
+  if (s <= 32)
+    hipLaunchKernelGGL(herm_eig_kernel<32>, dim3((unsigned)K), dim3(256), 0, st, gre, gim, s, 40, evals, vre, vim);
+  else
+    hipLaunchKernelGGL(herm_eig_kernel<kMaxS>, dim3((unsigned)K), dim3(256), 0, st, gre, gim, s, 40, evals, vre,
+                       vim);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int chol_inv(const double* gre, const double* gim, int64_t K, int s, double rtol, bool real_last, void* tre,
+             void* tim, int out_dtype, hipStream_t st) {
+  if (s < 1 || s > kMaxS) return fail(TP_EUNSUPPORTED, "Cholesky size outside 1..64");
+  if (K == 0) return TP_OK;
+  const int rl = real_last ? 1 : 0;
+  const dim3 g((unsigned)K), b(128);
+  if (out_dtype == TP_F64) {
+    if (s <= 32)
+      hipLaunchKernelGGL((chol_inv_kernel<32, double>), g, b, 0, st, gre, gim, K, s, rtol, rl, (double*)tre,
+                         (double*)tim);
+    else
+      hipLaunchKernelGGL((chol_inv_kernel<kMaxS, double>), g, b, 0, st, gre, gim, K, s, rtol, rl, (double*)tre,
+                         (double*)tim);
+  } else {
+    if (s <= 32)
+      hipLaunchKernelGGL((chol_inv_kernel<32, float>), g, b, 0, st, gre, gim, K, s, rtol, rl, (float*)tre,
+                         (float*)tim);
+    else
+      hipLaunchKernelGGL((chol_inv_kernel<kMaxS, float>), g, b, 0, st, gre, gim, K, s, rtol, rl, (float*)tre,
+                         (float*)tim);
+  }
   TP_LAUNCH_CHECK();
   return TP_OK;
 }
@@ -314,14 +484,18 @@ int eig_transform(const double* vre, const double* vim, const double* evals, int
 }
 
 int leverage(const void* xre, const void* xim, int dtype, int64_t K, int64_t n, int64_t ldx, int64_t sx, int r,
-             bool real_last, const double* evals, int s, double rtol, double* out, hipStream_t st) {
+             bool real_last, const double* evals, int s, double rtol, double* part, double* out, hipStream_t st) {
   if (n == 0) return TP_OK;
+  if (K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
+  const dim3 grid(blocks_for(n), (unsigned)K);
   if (dtype == TP_F64)
-    hipLaunchKernelGGL(leverage_kernel<double>, dim3(blocks_for(n)), dim3(256), 0, st, (const double*)xre,
-                       (const double*)xim, K, n, ldx, sx, r, real_last ? 1 : 0, evals, s, rtol, out);
+    hipLaunchKernelGGL(leverage_kernel<double>, grid, dim3(256), 0, st, (const double*)xre, (const double*)xim, K,
+                       n, ldx, sx, r, real_last ? 1 : 0, evals, s, rtol, part);
   else
-    hipLaunchKernelGGL(leverage_kernel<float>, dim3(blocks_for(n)), dim3(256), 0, st, (const float*)xre,
-                       (const float*)xim, K, n, ldx, sx, r, real_last ? 1 : 0, evals, s, rtol, out);
+    hipLaunchKernelGGL(leverage_kernel<float>, grid, dim3(256), 0, st, (const float*)xre, (const float*)xim, K, n,
+                       ldx, sx, r, real_last ? 1 : 0, evals, s, rtol, part);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sum_slices_kernel, dim3(blocks_for(n)), dim3(256), 0, st, part, K, n, out);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

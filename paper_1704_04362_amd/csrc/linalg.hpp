@@ -9,17 +9,26 @@ constexpr int kMaxS = 64;  // largest sketch / eigenproblem size
 
 int randn_spectrum(void* re, void* im, int dtype, int64_t K, int64_t rows, int64_t cols, bool real_last,
                    uint64_t seed, uint64_t stream_id, hipStream_t st);
-// G_k = X_k^H X_k, X_k rows x s (row stride ldx, slice stride sx), float64 out
+// G_k = X_k^H X_k, X_k rows x s (row stride ldx, slice stride sx), float64 out.
+// Tall slices are split over row chunks whose partial Gram matrices go to
+// (pre, pim), gram_part_doubles(K, rows, s) doubles each (none needed when 0),
+// and are then added in a fixed order.
+size_t gram_part_doubles(int64_t K, int64_t rows, int s);
 int gram(const void* xre, const void* xim, int dtype, int64_t K, int64_t rows, int s, int64_t ldx, int64_t sx,
-         bool real_last, double* gre, double* gim, hipStream_t st);
+         bool real_last, double* gre, double* gim, double* pre, double* pim, hipStream_t st);
 // eigenvalues descending (K x s) and eigenvectors as columns (K x s x s)
 int herm_eig(const double* gre, const double* gim, int64_t K, int s, double* evals, double* vre, double* vim,
              hipStream_t st);
+// T_k (s x s) with X_k T_k orthonormal on the kept columns, from G_k = X_k^H X_k
+// by Cholesky with pivots <= rtol max diag(G_k) dropped (CholeskyQR)
+int chol_inv(const double* gre, const double* gim, int64_t K, int s, double rtol, bool real_last, void* tre,
+             void* tim, int out_dtype, hipStream_t st);
 // mode 0: T = V diag(lambda^-1/2) (s x s); mode 1: T = V[:, :r] diag(sigma^-power) (s x r)
 int eig_transform(const double* vre, const double* vim, const double* evals, int64_t K, int s, int r, int mode,
                   double rtol, double power, void* tre, void* tim, int out_dtype, hipStream_t st);
+// out[j] = sum_k w_k sum_{i<r} |X_k[j, i]|^2 g_k[i]; part holds K x n doubles
 int leverage(const void* xre, const void* xim, int dtype, int64_t K, int64_t n, int64_t ldx, int64_t sx, int r,
-             bool real_last, const double* evals, int s, double rtol, double* out, hipStream_t st);
+             bool real_last, const double* evals, int s, double rtol, double* part, double* out, hipStream_t st);
 int singular_values(const double* evals, int64_t K, int s, int r, double* sv, hipStream_t st);
 int gather_rows(const void* xre, const void* xim, int in_dtype, int64_t K, int64_t rows, int64_t cols,
                 const int32_t* idx, const double* scale, const int64_t* count, int64_t out_rows, void* wre,

@@ -36,114 +36,155 @@ static_assert(NPARAM == kMlpParams, "parameter layout");
 // ---------------------------------------------------------------------------
 // features
 // ---------------------------------------------------------------------------
-constexpr int FROWS = 16;  // horizontal slices per workgroup
-constexpr int FNT = 256;
+// The sketch is the contraction S = X Phi with X (n2 x n1 n3), row j =
+// vec(A_{:j:}). In the tube-major layout horizontal slice i of A is an
+// n2 x n3 row-major block, so S = sum_i A_{i::} Phi_i with Phi_i the rows
+// i n3 .. i n3 + n3 - 1 of Phi: per horizontal slice a (64 slices x n3) by
+// (n3 x 16) product on the fp32 matrix cores (v_mfma_f32_16x16x4f32), one
+// 16-slice tile per wavefront. Lane l of a wavefront owns row l % 16 of the
+// tile and tube entries 4 (l / 16) .. 4 (l / 16) + 3 of every 16-entry tube
+// block (one float4 load); its four values feed four matrix-core steps,
+// with Phi_i read at the same tube positions from a transposed LDS copy.
+constexpr int SJ = 64;   // lateral slices per workgroup (4 tiles of 16)
+constexpr int SIR = 16;  // horizontal slices per workgroup
+constexpr int SNT = 256;
 
-// Partial sketches and squared norms over FROWS rows for the FT = 256 / CH
-// lateral slices of one workgroup (CH = n3 / 4 pieces of 4 values per tube).
-// In every row those tubes are one contiguous run; thread t always owns
-// piece t of the run and accumulates it over the rows (float64), then the
-// pieces of a tube are added in a fixed order through LDS.
-// partial layout: [rowblock][n2][DS + 1] (float64).
-__global__ __launch_bounds__(FNT) void sketch_partial_kernel(const float* __restrict__ a, const float* __restrict__ phi,
-                                                              int64_t n1, int64_t n2, int64_t n3,
-                                                              double* __restrict__ partial) {
-  extern __shared__ double sm[];  // [FNT][DS+1] pieces, then the phi row (n3 x DS floats)
-  const int tid = threadIdx.x;
-  const int64_t CH = n3 / 4;
-  const int64_t FT = FNT / CH;
-  const int64_t j0 = (int64_t)blockIdx.x * FT, i0 = (int64_t)blockIdx.y * FROWS;
-  const int64_t ntub = (n2 - j0) < FT ? (n2 - j0) : FT;
-  const int64_t rows = (n1 - i0) < FROWS ? (n1 - i0) : FROWS;
-  float* sphi = reinterpret_cast<float*>(sm + FNT * (DS + 1));
-  const bool live = tid < ntub * CH;
-  const int64_t k0 = (tid % CH) * 4;
-  double acc[DS + 1];
-#pragma unroll
-  for (int d = 0; d <= DS; ++d) acc[d] = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const int64_t i = i0 + r;
+__device__ __forceinline__ int sketch_ldk(int64_t n3) { return (int)((n3 + 15) / 16 * 16 + 4); }
+
+// partial[(y n2 + j) (DS + 1) + d]: the chunk-y sums (float32) of the
+// sketch (d < DS) and of the squared norm (d = DS) of lateral slice j.
+__global__ __launch_bounds__(SNT) void sketch_mfma_kernel(const float* __restrict__ a, const float* __restrict__ phi,
+                                                           int64_t n1, int64_t n2, int64_t n3,
+                                                           float* __restrict__ partial) {
+  extern __shared__ float phs[];  // [2][DS][ldk]: Phi_i transposed, double buffered
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ldk = sketch_ldk(n3);
+  const int nkb = (int)((n3 + 15) / 16);
+  const int64_t j0 = (int64_t)blockIdx.x * SJ;
+  const int64_t i0 = (int64_t)blockIdx.y * SIR;
+  const int64_t rows = (n1 - i0) < SIR ? (n1 - i0) : SIR;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t j = j0 + wave * 16 + r;
+  const bool jok = j < n2;
+  // zero the tube padding of both buffers once
+  for (int e = tid; e < 2 * DS * (ldk - (int)n3); e += SNT) {
+    const int w = ldk - (int)n3;
+    const int b = e / (DS * w), rem = e - b * DS * w;
+    phs[(b * DS + rem / w) * ldk + n3 + rem % w] = 0.f;
+  }
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  float nrm = 0.f;
+  for (int64_t ii = 0; ii < rows; ++ii) {
+    const int64_t i = i0 + ii;
+    float* buf = phs + (ii & 1) * DS * ldk;
+    const float* src = phi + i * n3 * DS;
+    for (int64_t e = tid; e < n3 * DS; e += SNT) {
+      const int64_t k = e / DS;
+      const int d = (int)(e - k * DS);
+      buf[d * ldk + k] = src[e];
+    }
     __syncthreads();
-    for (int64_t e = tid; e < n3 * DS; e += FNT) sphi[e] = phi[i * n3 * DS + e];
-    __syncthreads();
-    if (live) {
-      const float4 x = *reinterpret_cast<const float4*>(a + (i * n2 + j0) * n3 + (int64_t)tid * 4);
-      const float xv[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double v = (double)xv[e];
-        acc[DS] += v * v;
-#pragma unroll
-        for (int d = 0; d < DS; ++d) acc[d] += v * (double)sphi[(k0 + e) * DS + d];
-      }
+    const float* arow = a + (i * n2 + j) * n3;
+    for (int kb = 0; kb < nkb; ++kb) {
+      const int64_t k = (int64_t)kb * 16 + 4 * g;
+      float4 x = {0.f, 0.f, 0.f, 0.f};
+      if (jok && k < n3) x = *reinterpret_cast<const float4*>(arow + k);
+      const float4 p = *reinterpret_cast<const float4*>(buf + r * ldk + k);
+      nrm += x.x * x.x + x.y * x.y + x.z * x.z + x.w * x.w;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, p.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, p.y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, p.z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, p.w, acc, 0, 0, 0);
     }
   }
+  // lane l holds S[row 4 g + v][d = l % 16] of the wavefront's tile
+  float* out = partial + ((int64_t)blockIdx.y * n2) * (DS + 1);
 #pragma unroll
-  for (int d = 0; d <= DS; ++d) sm[tid * (DS + 1) + d] = acc[d];
+  for (int v = 0; v < 4; ++v) {
+    const int64_t jj = j0 + wave * 16 + 4 * g + v;
+    if (jj < n2) out[jj * (DS + 1) + r] = acc[v];
+  }
+  nrm += __shfl_xor(nrm, 16);
+  nrm += __shfl_xor(nrm, 32);
+  if (g == 0 && jok) out[j * (DS + 1) + DS] = nrm;
+}
+
+// Per block of SJ lateral slices: the float64 sums over the row chunks
+// (sk[j][0..DS] = sketch and squared norm), and the block's share of the
+// Gram matrix G = sum_j s_j s_j^T and of sum_j a_j (gpart[blk][0..DS*DS]).
+__global__ __launch_bounds__(256) void sketch_sum_kernel(const float* __restrict__ partial, int64_t nch, int64_t n2,
+                                                          double* __restrict__ sk, double* __restrict__ gpart) {
+  __shared__ double s[SJ][DS + 1];
+  const int tid = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * SJ;
+  for (int e = tid; e < SJ * (DS + 1); e += 256) {
+    const int t = e / (DS + 1), d = e - t * (DS + 1);
+    const int64_t j = j0 + t;
+    double v = 0.0;
+    if (j < n2) {
+      for (int64_t y = 0; y < nch; ++y) v += (double)partial[(y * n2 + j) * (DS + 1) + d];
+      sk[j * (DS + 1) + d] = v;
+    }
+    s[t][d] = v;
+  }
   __syncthreads();
-  for (int64_t e = tid; e < ntub * (DS + 1); e += FNT) {
-    const int64_t t = e / (DS + 1), d = e % (DS + 1);
-    double s = 0.0;
-    for (int64_t p = 0; p < CH; ++p) s += sm[(t * CH + p) * (DS + 1) + d];
-    partial[((int64_t)blockIdx.y * n2 + j0 + t) * (DS + 1) + d] = s;
+  {
+    const int p = tid / DS, q = tid % DS;
+    double gsum = 0.0;
+    for (int t = 0; t < SJ; ++t) gsum += s[t][p] * s[t][q];
+    gpart[blockIdx.x * (DS * DS + 1) + tid] = gsum;
+  }
+  if (tid == 0) {
+    double at = 0.0;
+    for (int t = 0; t < SJ; ++t) at += s[t][DS];
+    gpart[blockIdx.x * (DS * DS + 1) + DS * DS] = at;
   }
 }
 
-// Sums the row-block partials, whitens the sketch with G^{-1/2} (float64
-// Jacobi on the 16 x 16 Gram) and writes the 17 features per slice.
-__global__ __launch_bounds__(256) void sketch_finish_kernel(const double* __restrict__ partial, int64_t nb,
-                                                             int64_t n2, double* __restrict__ sk,
-                                                             float* __restrict__ feat) {
+// G and sum a from the block shares (fixed order), then the whitening
+// W = G^{-1/2} sqrt(n2) by the float64 Jacobi solver on the 16 x 16 Gram.
+// wt[0..DS*DS) = W (row-major), wt[DS*DS] = sum a.
+__global__ __launch_bounds__(256) void sketch_whiten_kernel(const double* __restrict__ gpart, int64_t nblk,
+                                                             int64_t n2, double* __restrict__ wt) {
   __shared__ JacobiShared<DS, 256> sh;
-  __shared__ double T[DS][DS];
-  __shared__ double red[256];
   const int tid = threadIdx.x;
-  for (int64_t e = tid; e < n2 * (DS + 1); e += 256) {
-    double s = 0.0;
-    for (int64_t b = 0; b < nb; ++b) s += partial[b * n2 * (DS + 1) + e];
-    sk[e] = s;
+  const int p = tid / DS, q = tid % DS;
+  double g = 0.0;
+  for (int64_t b = 0; b < nblk; ++b) g += gpart[b * (DS * DS + 1) + tid];
+  sh.Hr[p][q] = g;
+  sh.Hi[p][q] = 0.0;
+  if (tid == 0) {
+    double at = 0.0;
+    for (int64_t b = 0; b < nblk; ++b) at += gpart[b * (DS * DS + 1) + DS * DS];
+    wt[DS * DS] = at;
   }
   __syncthreads();
-  // G = S^T S, total squared norm
-  {
-    const int i = tid / DS, j = tid % DS;  // 256 = 16 x 16 entries
-    double g = 0.0;
-    for (int64_t r = 0; r < n2; ++r) g += sk[r * (DS + 1) + i] * sk[r * (DS + 1) + j];
-    sh.Hr[i][j] = g;
-    sh.Hi[i][j] = 0.0;
-  }
-  double at = 0.0;
-  for (int64_t r = tid; r < n2; r += 256) at += sk[r * (DS + 1) + DS];
-  red[tid] = at;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  const double atot = red[0];
   jacobi_eig_lds<DS, 256>(sh, DS, 30, 1e-15);
-  {
-    const int i = tid / DS, j = tid % DS;
-    double t = 0.0;
-    for (int q = 0; q < DS; ++q) {
-      const double l = sh.Hr[q][q];
-      if (l > 0.0) t += sh.Vr[i][q] * sh.Vr[j][q] / sqrt(l);
-    }
-    T[i][j] = t * sqrt((double)n2);
+  double t = 0.0;
+  for (int c = 0; c < DS; ++c) {
+    const double l = sh.Hr[c][c];
+    if (l > 0.0) t += sh.Vr[p][c] * sh.Vr[q][c] / sqrt(l);
   }
-  __syncthreads();
-  for (int64_t e = tid; e < n2 * DIN; e += 256) {
-    const int64_t r = e / DIN;
-    const int d = (int)(e % DIN);
-    double v;
-    if (d < DS) {
-      v = 0.0;
-      for (int q = 0; q < DS; ++q) v += sk[r * (DS + 1) + q] * T[q][d];
-    } else {
-      v = log((double)n2 * sk[r * (DS + 1) + DS] / atot);
-    }
-    feat[e] = (float)v;
+  wt[tid] = t * sqrt((double)n2);
+}
+
+// feat[j] = [s_j^T W, log(n2 a_j / sum a)]; optionally a_j itself.
+__global__ void sketch_apply_kernel(const double* __restrict__ sk, const double* __restrict__ wt, int64_t n2,
+                                    float* __restrict__ feat, double* __restrict__ norms) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n2 * DIN) return;
+  const int64_t j = e / DIN;
+  const int d = (int)(e - j * DIN);
+  double v;
+  if (d < DS) {
+    v = 0.0;
+    for (int q = 0; q < DS; ++q) v += sk[j * (DS + 1) + q] * wt[q * DS + d];
+  } else {
+    const double aj = sk[j * (DS + 1) + DS];
+    v = log((double)n2 * aj / wt[DS * DS]);
+    if (norms) norms[j] = aj;
   }
+  feat[e] = (float)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -437,25 +478,34 @@ unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 }  // namespace
 
 size_t mlp_features_ws(int64_t n1, int64_t n2) {
-  const int64_t nb = (n1 + FROWS - 1) / FROWS;
-  return align_up(size_t(nb) * n2 * (DS + 1) * 8) + align_up(size_t(n2) * (DS + 1) * 8) + 512;
+  const int64_t nch = (n1 + SIR - 1) / SIR, nb = (n2 + SJ - 1) / SJ;
+  return align_up(size_t(nch) * n2 * (DS + 1) * 4) + align_up(size_t(n2) * (DS + 1) * 8) +
+         align_up(size_t(nb) * (DS * DS + 1) * 8) + align_up(size_t(DS * DS + 1) * 8) + 1024;
 }
 
 int mlp_features(const float* a, int64_t n1, int64_t n2, int64_t n3, const float* phi, float* feat, void* ws,
-                 hipStream_t st) {
-  if (n3 % 4 || n3 / 4 > FNT) return fail(TP_EUNSUPPORTED, "feature extraction needs n3 divisible by 4, <= 1024");
-  const int64_t CH = n3 / 4, FT = FNT / CH;
-  const size_t lds = size_t(FNT) * (DS + 1) * 8 + size_t(n3) * DS * 4;
+                 hipStream_t st, double* norms) {
+  if (n3 % 4) return fail(TP_EUNSUPPORTED, "feature extraction needs n3 divisible by 4");
+  const size_t lds = size_t(2) * DS * ((n3 + 15) / 16 * 16 + 4) * 4;
   if (lds > 64 * 1024) return fail(TP_EUNSUPPORTED, "tube length too large for feature extraction");
-  const int64_t nb = (n1 + FROWS - 1) / FROWS;
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(phi)) % 16)
+    return fail(TP_EINVAL, "A and phi must be 16-byte aligned");
+  const int64_t nch = (n1 + SIR - 1) / SIR, nb = (n2 + SJ - 1) / SJ;
+  if (nch > 65535) return fail(TP_EUNSUPPORTED, "too many horizontal slices");
   Arena ar(ws, mlp_features_ws(n1, n2));
-  double* part = ar.take<double>(nb * n2 * (DS + 1));
+  float* part = ar.take<float>(nch * n2 * (DS + 1));
   double* sk = ar.take<double>(n2 * (DS + 1));
+  double* gpart = ar.take<double>(nb * (DS * DS + 1));
+  double* wt = ar.take<double>(DS * DS + 1);
   if (!ar.ok()) return fail(TP_EWORKSPACE, "feature workspace too small");
-  hipLaunchKernelGGL(sketch_partial_kernel, dim3((unsigned)((n2 + FT - 1) / FT), (unsigned)nb), dim3(FNT), lds, st, a,
-                     phi, n1, n2, n3, part);
+  hipLaunchKernelGGL(sketch_mfma_kernel, dim3((unsigned)nb, (unsigned)nch), dim3(SNT), lds, st, a, phi, n1, n2, n3,
+                     part);
   TP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sketch_finish_kernel, dim3(1), dim3(256), 0, st, part, nb, n2, sk, feat);
+  hipLaunchKernelGGL(sketch_sum_kernel, dim3((unsigned)nb), dim3(256), 0, st, part, nch, n2, sk, gpart);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sketch_whiten_kernel, dim3(1), dim3(256), 0, st, gpart, nb, n2, wt);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sketch_apply_kernel, dim3(nblk(n2 * DIN)), dim3(256), 0, st, sk, wt, n2, feat, norms);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }
