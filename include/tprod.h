@@ -289,8 +289,10 @@ size_t tp_mlp_features_workspace(const tp_tensor* A);
 int tp_mlp_forward(const float* params, const float* feat, int64_t nrows, float* logits, void* stream);
 
 /* One training step on ntensors tensors of nslices lateral slices each
- * (feat: (ntensors nslices) x 17 in tensor order; target: the exact leverage
- * distribution of each tensor, ntensors x nslices, rows summing to 1). Loss:
+ * (feat: (ntensors nslices) x 17 in tensor order; target: ntensors x nslices
+ * nonnegative exact leverage scores, each row normalised to a distribution
+ * inside the call, so any positive scale is accepted; a row summing to zero
+ * is read as all-zero targets: zero loss, gradient softmax / ntensors). Loss:
  * mean over tensors of KL(target || softmax(logits of the tensor)). Writes
  * the loss (float, may be NULL) and the gradient (tp_mlp_param_count() float32 values,
  * may be NULL), then, if step >= 1, applies Adam (beta1 0.9, beta2 0.999, eps 1e-8,
@@ -301,10 +303,12 @@ int tp_mlp_train_step(float* params, float* m, float* v, int64_t step, double lr
 size_t tp_mlp_train_workspace(int64_t ntensors, int64_t nslices);
 
 /* Sampling weights for the lateral slices of A from the network:
- * w = (1 - alpha) softmax(logits) + alpha ||A_{:j:}||_F^2 / ||A||_F^2
- * (device float64, n2 values; alpha keeps every slice's probability at
- * least alpha times its squared-norm probability). Feed w to tp_tsample or
- * tp_tcur as TP_P_USER weights. */
+ * w = (1 - alpha) softmax(logits) + alpha / n2 (device float64, n2 values;
+ * a defensive mixture: every slice keeps probability >= alpha / n2, so a
+ * slice the network underrates is still reachable). One pass over A
+ * (features), the forward pass and the mixture. Feed w to tp_tsample or
+ * tp_tcur as TP_P_USER weights; the exact leverage kind stays the
+ * reference. */
 int tp_mlp_proposal(const float* params, const tp_tensor* A, const float* phi, double alpha, double* w, void* ws,
                     size_t ws_bytes, void* stream);
 size_t tp_mlp_proposal_workspace(const tp_tensor* A);

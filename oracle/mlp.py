@@ -13,7 +13,8 @@ Definitions (float64):
   [z_j, f_j] (17 values).
 * forward: h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), o = h2 w3 + b3
   (17 -> 128 -> 128 -> 1).
-* loss per tensor: p = softmax(o over its slices), KL(p* || p).
+* loss per tensor: p = softmax(o over its slices), KL(p* || p), where p*
+  is the tensor's leverage scores divided by their sum.
 * backward: analytic gradients of the mean KL over the tensors of a batch.
 * adam: Kingma & Ba's update with bias correction.
 
@@ -87,8 +88,10 @@ def loss_and_grad(P, X, targets, nslices):
     for t in range(T):
         sl = slice(t * nslices, (t + 1) * nslices)
         p = softmax(o[sl])
-        loss += kl(targets[t], p)
-        do[sl] = (p - targets[t]) / T
+        tsum = np.sum(targets[t])
+        q = np.asarray(targets[t], dtype=np.float64) / tsum if tsum > 0 else np.zeros(nslices)
+        loss += kl(q, p)
+        do[sl] = (p - q) / T
     loss /= T
     g = {}
     g["w3"] = h2.T @ do
@@ -114,7 +117,8 @@ def adam_step(P, G, M, V, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return P2, M2, V2
 
 
-def proposal(P, X, p_norm2, alpha=0.1):
-    """Sampling probabilities (1 - alpha) softmax(o) + alpha p_norm2."""
+def proposal(P, X, alpha=0.1):
+    """Sampling probabilities (1 - alpha) softmax(o) + alpha / n, the
+    network's distribution mixed with the uniform one."""
     o, _ = forward(P, X)
-    return (1 - alpha) * softmax(o) + alpha * np.asarray(p_norm2)
+    return (1 - alpha) * softmax(o) + alpha / o.size

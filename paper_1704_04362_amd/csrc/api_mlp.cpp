@@ -62,8 +62,7 @@ int tp_mlp_train_step(float* params, float* m, float* v, int64_t step, double lr
 
 size_t tp_mlp_proposal_workspace(const tp_tensor* A) {
   if (!A) return 0;
-  return mlp_features_ws(A->n1, A->n2) + align_up(size_t(A->n2) * 17 * 4) + align_up(size_t(A->n2) * 4) +
-         align_up(size_t(A->n2) * 8) + 2048;
+  return mlp_features_ws(A->n1, A->n2) + align_up(size_t(A->n2) * 17 * 4) + align_up(size_t(A->n2) * 4) + 2048;
 }
 
 int tp_mlp_proposal(const float* params, const tp_tensor* A, const float* phi, double alpha, double* w, void* ws,
@@ -77,12 +76,10 @@ int tp_mlp_proposal(const float* params, const tp_tensor* A, const float* phi, d
   void* fws = ar.take<char>(mlp_features_ws(A->n1, A->n2));
   float* feat = ar.take<float>(A->n2 * 17);
   float* logit = ar.take<float>(A->n2);
-  double* a = ar.take<double>(A->n2);
   if (!ar.ok()) return fail(TP_EWORKSPACE, "proposal workspace too small");
-  // one pass over A gives the features and the squared slice norms
-  if (int rc = mlp_features((const float*)A->data, A->n1, A->n2, A->n3, phi, feat, fws, st, a)) return rc;
+  if (int rc = mlp_features((const float*)A->data, A->n1, A->n2, A->n3, phi, feat, fws, st)) return rc;
   if (int rc = mlp_forward(params, feat, A->n2, logit, st)) return rc;
-  return mlp_proposal(logit, a, A->n2, alpha, w, st);
+  return mlp_proposal(logit, A->n2, alpha, w, st);
 }
 
 }  // extern "C"

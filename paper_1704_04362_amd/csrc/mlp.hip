@@ -312,10 +312,21 @@ __global__ __launch_bounds__(256) void softmax_grad_kernel(const float* __restri
   }
   const double lse = mx + log(red[0]);
   __syncthreads();
+  // the target row is normalised here (any positive scale is accepted)
+  double qs = 0.0;
+  for (int64_t j = tid; j < nsl; j += 256) qs += (double)pt[j];
+  red[tid] = qs;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double qinv = red[0] > 0.0 ? 1.0 / red[0] : 0.0;
+  __syncthreads();
   double kl = 0.0;
   for (int64_t j = tid; j < nsl; j += 256) {
     const double lp = (double)ot[j] - lse;
-    const double q = (double)pt[j];
+    const double q = (double)pt[j] * qinv;
     if (q > 0) kl += q * (log(q) - lp);
     dout[t * nsl + j] = (float)((exp(lp) - q) / (double)T);
   }
@@ -432,15 +443,14 @@ __global__ void adam_kernel(float* __restrict__ P, float* __restrict__ M, float*
   P[p] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-// w = (1 - alpha) softmax(o) + alpha a / sum(a), float64, one workgroup.
-__global__ __launch_bounds__(256) void proposal_kernel(const float* __restrict__ o, const double* __restrict__ a,
-                                                       int64_t n, double alpha, double* __restrict__ w) {
+// w = (1 - alpha) softmax(o) + alpha / n (a defensive mixture with the
+// uniform distribution), float64, one workgroup.
+__global__ __launch_bounds__(256) void proposal_kernel(const float* __restrict__ o, int64_t n, double alpha,
+                                                       double* __restrict__ w) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
-  double m = -INFINITY, at = 0.0;
-  for (int64_t j = tid; j < n; j += 256) {
-    m = fmax(m, (double)o[j]);
-  }
+  double m = -INFINITY;
+  for (int64_t j = tid; j < n; j += 256) m = fmax(m, (double)o[j]);
   red[tid] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -450,10 +460,7 @@ __global__ __launch_bounds__(256) void proposal_kernel(const float* __restrict__
   const double mx = red[0];
   __syncthreads();
   double se = 0.0;
-  for (int64_t j = tid; j < n; j += 256) {
-    se += exp((double)o[j] - mx);
-    at += a[j];
-  }
+  for (int64_t j = tid; j < n; j += 256) se += exp((double)o[j] - mx);
   red[tid] = se;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -461,16 +468,7 @@ __global__ __launch_bounds__(256) void proposal_kernel(const float* __restrict__
     __syncthreads();
   }
   const double z = red[0];
-  __syncthreads();
-  red[tid] = at;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double asum = red[0];
-  for (int64_t j = tid; j < n; j += 256)
-    w[j] = (1.0 - alpha) * exp((double)o[j] - mx) / z + alpha * (asum > 0 ? a[j] / asum : 1.0 / (double)n);
+  for (int64_t j = tid; j < n; j += 256) w[j] = (1.0 - alpha) * exp((double)o[j] - mx) / z + alpha / (double)n;
 }
 
 unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
@@ -556,8 +554,8 @@ int mlp_train_step(float* P, float* M, float* V, int64_t step, double lr, const 
   return TP_OK;
 }
 
-int mlp_proposal(const float* logits, const double* a, int64_t n, double alpha, double* w, hipStream_t st) {
-  hipLaunchKernelGGL(proposal_kernel, dim3(1), dim3(256), 0, st, logits, a, n, alpha, w);
+int mlp_proposal(const float* logits, int64_t n, double alpha, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(proposal_kernel, dim3(1), dim3(256), 0, st, logits, n, alpha, w);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

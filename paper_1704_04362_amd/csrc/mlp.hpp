@@ -16,6 +16,7 @@ int mlp_forward(const float* P, const float* feat, int64_t nrows, float* out, hi
 size_t mlp_train_ws(int64_t ntensors, int64_t nslices);
 int mlp_train_step(float* P, float* M, float* V, int64_t step, double lr, const float* feat, const float* target,
                    int64_t T, int64_t nsl, float* loss, float* grad_out, void* ws, hipStream_t st);
-int mlp_proposal(const float* logits, const double* a, int64_t n, double alpha, double* w, hipStream_t st);
+// w = (1 - alpha) softmax(logits) + alpha / n
+int mlp_proposal(const float* logits, int64_t n, double alpha, double* w, hipStream_t st);
 
 }  // namespace tp

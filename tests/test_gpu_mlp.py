@@ -174,6 +174,6 @@ def test_proposal_weights():
     w = api.mlp_proposal(params, dev(A), dev(phi), alpha=0.2).cpu().numpy()
     feat = M.features(A.astype(np.float64), phi.astype(np.float64))
     Q, X16 = _fp16_view(_params(9), feat)
-    ref = M.proposal(Q, X16, S.normalise(S.weights_norm2(A)), alpha=0.2)
+    ref = M.proposal(Q, X16, alpha=0.2)
     assert abs(w.sum() - 1) < 1e-12
     assert np.linalg.norm(w - ref) < 1e-2 * np.linalg.norm(ref)

@@ -70,6 +70,8 @@ def test_features_whitened_and_scale_invariant():
 def test_proposal_is_a_distribution():
     P = M.init_params(3)
     X = rs.standard_normal((25, M.D_IN))
-    pn = M.softmax(rs.standard_normal(25))
-    p = M.proposal(P, X, pn)
-    assert abs(p.sum() - 1) < 1e-12 and np.all(p >= 0.1 * pn - 1e-15)
+    p = M.proposal(P, X, alpha=0.1)
+    assert abs(p.sum() - 1) < 1e-12 and np.all(p >= 0.1 / 25 - 1e-15)
+    # alpha = 1 is the uniform distribution, alpha = 0 the network's softmax
+    np.testing.assert_allclose(M.proposal(P, X, alpha=1.0), np.full(25, 1 / 25), rtol=1e-14)
+    np.testing.assert_allclose(M.proposal(P, X, alpha=0.0), M.softmax(M.forward(P, X)[0]), rtol=1e-14)
