@@ -271,6 +271,20 @@ size_t tp_tcomplete_workspace(const tp_tensor* X);
  * eq. cur-col-prob stay its judge and fallback).
  * ------------------------------------------------------------------------- */
 
+/* Launch tracing. tp_trace_enable(1) clears earlier records and starts
+ * recording: each stage of a call (for the t-product "tprod.fft_a",
+ * "tprod.fft_b", "tprod.gemm", "tprod.ifft", with the prefix "rtprod." when
+ * picks are given) records a HIP event pair on the
+ * caller's stream around its kernels. tp_trace_enable(0) stops recording.
+ * tp_trace_count() waits for the recorded events, folds them into per-stage
+ * totals and returns the number of stages; tp_trace_entry(i, ...) reports
+ * stage i: its name (copied into name, name_cap bytes with the terminating
+ * zero), the number of recorded calls and their summed duration in
+ * milliseconds. Host-side bookkeeping only; the device work is unchanged. */
+int tp_trace_enable(int on);
+int tp_trace_count(void);
+int tp_trace_entry(int i, char* name, size_t name_cap, int64_t* calls, double* total_ms);
+
 /* Number of float32 parameters: W1 (17 x 128) | b1 (128) | W2 (128 x 128) |
  * b2 (128) | w3 (128) | b3 (1), with h1 = relu(x W1 + b1),
  * h2 = relu(h1 W2 + b2), o = h2 w3 + b3. */

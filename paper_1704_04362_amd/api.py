@@ -249,6 +249,32 @@ def tcomplete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
 
 
 # ---------------------------------------------------------------------------
+# launch tracing
+# ---------------------------------------------------------------------------
+
+def trace_enable(on=True):
+    """Start (clearing earlier records) or stop recording stage timings."""
+    L.check(L.load().tp_trace_enable(1 if on else 0))
+
+
+def trace_read():
+    """{stage name: (calls, total ms)} of the recorded stages (waits for
+    their events)."""
+    lib = L.load()
+    n = lib.tp_trace_count()
+    if n < 0:
+        L.check(n)
+    out = {}
+    for i in range(n):
+        buf = C.create_string_buffer(64)
+        calls = C.c_int64()
+        ms = C.c_double()
+        L.check(lib.tp_trace_entry(i, buf, 64, C.byref(calls), C.byref(ms)))
+        out[buf.value.decode()] = (int(calls.value), float(ms.value))
+    return out
+
+
+# ---------------------------------------------------------------------------
 # learned leverage proposal
 # ---------------------------------------------------------------------------
 

@@ -61,6 +61,14 @@ int check_sample(const tp_sample* s, int64_t n) {
 
 size_t esize(int dtype) { return dtype == TP_F64 ? 8 : 4; }
 
+int64_t round_up32(int64_t n) { return (n + 31) / 32 * 32; }
+
+// the t-product takes the split-operand matrix-core path for float32 data
+// at the bf16 precisions when the tube length has a specialised transform
+bool use_split(int dtype, int prec, int64_t n3) {
+  return dtype == TP_F32 && (prec == TP_PREC_BF16X3 || prec == TP_PREC_BF16) && fft_split_supported(n3);
+}
+
 struct Plane {
   void* re;
   void* im;
@@ -242,10 +250,15 @@ int tp_tsample(int kind, const tp_tensor* A, const tp_tensor* B, const double* w
   return sample_slices(weights, n, c, mode, seed, stream_id, out->idx, out->scale, out->count, sws, st);
 }
 
-size_t tp_tprod_workspace(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, int) {
+size_t tp_tprod_workspace(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, int prec) {
   if (!A || !B) return 0;
   const int64_t K = half_count(A->n3);
   const int64_t inner = sample ? sample->cap : A->n2;
+  if (use_split(A->dtype, prec, A->n3)) {
+    const int64_t ldk = round_up32(inner);
+    return align_up(size_t(8) * K * A->n1 * ldk) + align_up(size_t(8) * K * B->n2 * ldk) +
+           spectrum_bytes(K, A->n1, B->n2, TP_F32) + 1024;
+  }
   return spectrum_bytes(K, A->n1, inner, A->dtype) + spectrum_bytes(K, inner, B->n2, A->dtype) +
          spectrum_bytes(K, A->n1, B->n2, A->dtype) + 1024;
 }
@@ -267,12 +280,14 @@ int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp
 
   const int64_t n1 = A->n1, n2 = A->n2, n4 = B->n2, n3 = A->n3, K = half_count(n3);
   const int64_t inner = sample ? sample->cap : n2;
+  const bool real_last = (n3 % 2 == 0) && K > 1;
   hipStream_t st = S(stream);
   Arena ar(ws, ws_bytes);
-  Plane Ah = take_spectrum(ar, K, n1, inner, A->dtype);
-  Plane Bh = take_spectrum(ar, K, inner, n4, A->dtype);
-  Plane Ch = take_spectrum(ar, K, n1, n4, A->dtype);
-  if (!ar.ok()) return fail(TP_EWORKSPACE, "t-product workspace too small");
+  // stage names for launch tracing (exact product / rt-product)
+  const char* nm_fa = sample ? "rtprod.fft_a" : "tprod.fft_a";
+  const char* nm_fb = sample ? "rtprod.fft_b" : "tprod.fft_b";
+  const char* nm_mm = sample ? "rtprod.gemm" : "tprod.gemm";
+  const char* nm_if = sample ? "rtprod.ifft" : "tprod.ifft";
 
   TubeGather ga;
   ga.rows = n1;
@@ -293,7 +308,57 @@ int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp
     gb.row_scale = sample->scale;
     gb.count = sample->count;
   }
+
+  if (use_split(A->dtype, prec, n3)) {
+    // matrix-core path: both operands transformed straight into split bf16
+    // planes with the contraction index contiguous (B transposed), padded
+    // to a multiple of 32 with zeros
+    const int64_t ldk = round_up32(inner);
+    void* Ap = ar.take<char>(size_t(8) * K * n1 * ldk);
+    void* Bp = ar.take<char>(size_t(8) * K * n4 * ldk);
+    Plane Ch = take_spectrum(ar, K, n1, n4, TP_F32);
+    if (!ar.ok()) return fail(TP_EWORKSPACE, "t-product workspace too small");
+    {
+      TraceScope ts(nm_fa, st);
+      if (int rc = fft_forward_split((const float*)A->data, n3, ga, false, ldk, Ap, st)) return rc;
+    }
+    {
+      TraceScope ts(nm_fb, st);
+      if (int rc = fft_forward_split((const float*)B->data, n3, gb, true, ldk, Bp, st)) return rc;
+    }
+    SplitGemm g;
+    g.a = Ap;
+    g.b = Bp;
+    g.cre = (float*)Ch.re;
+    g.cim = (float*)Ch.im;
+    g.K = K;
+    g.M = n1;
+    g.N = n4;
+    g.Kd = ldk;
+    g.lda = ldk;
+    g.ldb = ldk;
+    g.ldc = n4;
+    g.pa = K * n1 * ldk;
+    g.pb = K * n4 * ldk;
+    g.sa = n1 * ldk;
+    g.sb = n4 * ldk;
+    g.sc = n1 * n4;
+    g.real_last = real_last;
+    g.terms = prec == TP_PREC_BF16X3 ? 3 : 1;
+    {
+      TraceScope ts(nm_mm, st);
+      if (int rc = cgemm_split(g, st)) return rc;
+    }
+    TraceScope ts(nm_if, st);
+    return fft_inverse(Ch.re, Ch.im, TP_F32, n3, n1, n4, C->data, st);
+  }
+
+  Plane Ah = take_spectrum(ar, K, n1, inner, A->dtype);
+  Plane Bh = take_spectrum(ar, K, inner, n4, A->dtype);
+  Plane Ch = take_spectrum(ar, K, n1, n4, A->dtype);
+  if (!ar.ok()) return fail(TP_EWORKSPACE, "t-product workspace too small");
   if (inner > 0) {
+    TraceScope ts(sample ? "rtprod.fft_ab" : "tprod.fft_ab", st);
     if (int rc = fft_forward(A->data, A->dtype, n3, ga, Ah.re, Ah.im, st)) return rc;
     if (int rc = fft_forward(B->data, B->dtype, n3, gb, Bh.re, Bh.im, st)) return rc;
   }
@@ -314,9 +379,13 @@ int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp
   p.sa = n1 * inner;
   p.sb = inner * n4;
   p.sc = n1 * n4;
-  p.real_last = (n3 % 2 == 0) && K > 1;
+  p.real_last = real_last;
   p.kdim_dev = sample ? sample->count : nullptr;
-  if (int rc = cgemm(p, A->dtype, prec, st)) return rc;
+  {
+    TraceScope ts(nm_mm, st);
+    if (int rc = cgemm(p, A->dtype, prec, st)) return rc;
+  }
+  TraceScope ts(nm_if, st);
   return fft_inverse(Ch.re, Ch.im, A->dtype, n3, n1, n4, C->data, st);
 }
 

@@ -81,6 +81,45 @@ int fft_forward(const void* x, int dtype, int64_t n3, const TubeGather& g, void*
 int fft_inverse(const void* re, const void* im, int dtype, int64_t n3, int64_t rows, int64_t cols, void* x,
                 hipStream_t st);
 bool fft_supported(int64_t n3);
+// Forward transform of float32 tubes into the split operand format of the
+// matrix-core products: four bf16 planes [hi re, lo re, hi im, lo im][k][slot]
+// with slot = row * ld + col (colmajor: col * ld + row); slots past the live
+// rows / columns are zero.
+bool fft_split_supported(int64_t n3);
+int fft_forward_split(const float* x, int64_t n3, const TubeGather& g, bool colmajor, int64_t ld, void* planes,
+                      hipStream_t st);
+
+// C_k = A_k B_k from split operands (gemm_mfma.hip): a holds the planes of A
+// ([4][K][M][lda]), b those of B transposed ([4][K][N][ldb]); Kd, lda, ldb are
+// multiples of 32 and the contraction entries past the live length are
+// zero. C is float32 planar [K][M][ldc]. terms: 3 (bf16x3) or 1 (bf16).
+struct SplitGemm {
+  const void* a = nullptr;
+  const void* b = nullptr;
+  float* cre = nullptr;
+  float* cim = nullptr;
+  int64_t K = 0, M = 0, N = 0, Kd = 0, lda = 0, ldb = 0, ldc = 0;
+  int64_t pa = 0, pb = 0, sa = 0, sb = 0, sc = 0;
+  bool real_last = false;
+  int terms = 3;
+};
+int cgemm_split(const SplitGemm& p, hipStream_t st);
+
+// Launch tracing (trace.cpp): with tp_trace_enable(1), a scope records HIP
+// events on its stream around the work enqueued inside it.
+class TraceScope {
+ public:
+  TraceScope(const char* name, hipStream_t st);
+  ~TraceScope();
+  TraceScope(const TraceScope&) = delete;
+  TraceScope& operator=(const TraceScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t st_;
+  hipEvent_t e0_ = nullptr, e1_ = nullptr;
+  bool live_ = false;
+};
 
 // ---------------------------------------------------------------------------
 // Per-slice complex products (gemm.hip)

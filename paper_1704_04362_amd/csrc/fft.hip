@@ -192,18 +192,22 @@ struct Vec16<double> {
 
 struct FwdArgs {
   int64_t rows, cols, in_cols;
-  int64_t ntubes;  // rows * cols
+  int64_t ntubes;  // output slots: major x ld
   const int32_t* row_idx;
   const int32_t* col_idx;
   const double* row_scale;
   const double* col_scale;
   const int64_t* count;
+  int64_t ld;    // slots per major index (>= cols, or >= rows when colmajor)
+  int colmajor;  // slot t = col * ld + row instead of row * ld + col
 };
 
-// Input tube offset and scale of output tube t; returns false for a tube
-// that is to be written as zeros (beyond the live sample count).
+// Input tube offset and scale of output slot t; returns false for a slot
+// that is to be written as zeros (padding, or beyond the live sample count).
 __device__ __forceinline__ bool tube_source(const FwdArgs& a, int64_t t, int64_t& src, double& s) {
-  const int64_t ra = t / a.cols, cb = t - ra * a.cols;
+  const int64_t maj = t / a.ld, mn = t - maj * a.ld;
+  const int64_t ra = a.colmajor ? mn : maj, cb = a.colmajor ? maj : mn;
+  if (ra >= a.rows || cb >= a.cols) return false;
   int64_t lim = a.count ? *a.count : INT64_MAX;
   if (a.row_idx && ra >= lim) return false;
   if (a.col_idx && cb >= lim) return false;
@@ -216,7 +220,27 @@ __device__ __forceinline__ bool tube_source(const FwdArgs& a, int64_t t, int64_t
 
 constexpr int kTile = 64;  // tubes per workgroup (one wavefront)
 
-template <typename T, int N>
+// Output of one spectrum value: planar float (re, im planes [k][slot]) or,
+// with SPLIT, four bf16 planes [p][k][slot] = hi(re), lo(re), hi(im), lo(im)
+// (hi = round-to-nearest-even bf16 of x, lo = bf16 of x - hi), the operand
+// format of the matrix-core products.
+template <typename T, bool SPLIT>
+__device__ __forceinline__ void emit(T* ore, T* oim, int64_t K, int64_t ks, int64_t k, int64_t t, T vr, T vi) {
+  if constexpr (SPLIT) {
+    __bf16* b = reinterpret_cast<__bf16*>(ore);
+    const __bf16 hr = (__bf16)vr, hi = (__bf16)vi;
+    const int64_t ps = K * ks, o = k * ks + t;
+    b[o] = hr;
+    b[ps + o] = (__bf16)(vr - (float)hr);
+    b[2 * ps + o] = hi;
+    b[3 * ps + o] = (__bf16)(vi - (float)hi);
+  } else {
+    ore[k * ks + t] = vr;
+    oim[k * ks + t] = vi;
+  }
+}
+
+template <typename T, int N, bool SPLIT = false>
 __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, FwdArgs a, T* __restrict__ ore,
                                                      T* __restrict__ oim) {
   constexpr int M = N / 2;
@@ -274,9 +298,9 @@ __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, Fw
   const int64_t t = tile0 + lane;
   if (t >= a.ntubes) return;
   const int64_t ks = a.ntubes;
+  constexpr int64_t K = N / 2 + 1;
   if constexpr (N == 1) {
-    ore[t] = lds[lane * PAD];
-    oim[t] = T(0);
+    emit<T, SPLIT>(ore, oim, K, ks, 0, t, lds[lane * PAD], T(0));
   } else {
     T zr[M], zi[M];
 #pragma unroll
@@ -285,18 +309,15 @@ __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, Fw
       zi[m] = lds[lane * PAD + 2 * m + 1];
     }
     cfft<T, M>(zr, zi);
-    ore[t] = zr[0] + zi[0];
-    oim[t] = T(0);
-    ore[(int64_t)M * ks + t] = zr[0] - zi[0];
-    oim[(int64_t)M * ks + t] = T(0);
+    emit<T, SPLIT>(ore, oim, K, ks, 0, t, zr[0] + zi[0], T(0));
+    emit<T, SPLIT>(ore, oim, K, ks, M, t, zr[0] - zi[0], T(0));
 #pragma unroll
     for (int k = 1; k < M; ++k) {
       const int j = M - k;
       const T er = (zr[k] + zr[j]) * T(0.5), ei = (zi[k] - zi[j]) * T(0.5);
       const T orr = (zi[k] + zi[j]) * T(0.5), oi = (zr[j] - zr[k]) * T(0.5);
       const T wr = tw_re<T>(N, k), wi = tw_im<T>(N, k);
-      ore[(int64_t)k * ks + t] = er + (orr * wr - oi * wi);
-      oim[(int64_t)k * ks + t] = ei + (orr * wi + oi * wr);
+      emit<T, SPLIT>(ore, oim, K, ks, k, t, er + (orr * wr - oi * wi), ei + (orr * wi + oi * wr));
     }
   }
 }
@@ -463,7 +484,8 @@ InvKernel<T> pick_inv(int64_t n) {
 
 template <typename T>
 int fwd_impl(const T* x, int64_t n3, const TubeGather& g, T* re, T* im, hipStream_t st) {
-  FwdArgs a{g.rows, g.cols, g.in_cols, g.rows * g.cols, g.row_idx, g.col_idx, g.row_scale, g.col_scale, g.count};
+  FwdArgs a{g.rows, g.cols, g.in_cols, g.rows * g.cols, g.row_idx, g.col_idx, g.row_scale, g.col_scale, g.count,
+            g.cols, 0};
   if (a.ntubes == 0) return TP_OK;
   if (auto k = pick_fwd<T>(n3)) {
     const int64_t blocks = (a.ntubes + kTile - 1) / kTile;
@@ -491,9 +513,46 @@ int inv_impl(const T* re, const T* im, int64_t n3, int64_t ntubes, T* y, hipStre
   return TP_OK;
 }
 
+template <bool SPLIT>
+FwdKernel<float> pick_fwd_split(int64_t n) {
+  switch (n) {
+    case 1: return rfft_kernel<float, 1, true>;
+    case 2: return rfft_kernel<float, 2, true>;
+    case 4: return rfft_kernel<float, 4, true>;
+    case 8: return rfft_kernel<float, 8, true>;
+    case 16: return rfft_kernel<float, 16, true>;
+    case 32: return rfft_kernel<float, 32, true>;
+    case 64: return rfft_kernel<float, 64, true>;
+    case 128: return rfft_kernel<float, 128, true>;
+    case 10: return rfft_kernel<float, 10, true>;
+    case 20: return rfft_kernel<float, 20, true>;
+    case 50: return rfft_kernel<float, 50, true>;
+    case 100: return rfft_kernel<float, 100, true>;
+    default: return nullptr;
+  }
+}
+
 }  // namespace
 
 bool fft_supported(int64_t n3) { return pick_fwd<float>(n3) != nullptr; }
+
+bool fft_split_supported(int64_t n3) { return pick_fwd_split<true>(n3) != nullptr; }
+
+int fft_forward_split(const float* x, int64_t n3, const TubeGather& g, bool colmajor, int64_t ld, void* planes,
+                      hipStream_t st) {
+  if (int rc = ensure_twiddles()) return rc;
+  auto k = pick_fwd_split<true>(n3);
+  if (!k) return fail(TP_EUNSUPPORTED, "no split-output transform for this tube length");
+  if (ld < (colmajor ? g.rows : g.cols)) return fail(TP_EINVAL, "split spectrum stride below its extent");
+  FwdArgs a{g.rows, g.cols, g.in_cols, (colmajor ? g.cols : g.rows) * ld, g.row_idx, g.col_idx, g.row_scale,
+            g.col_scale, g.count, ld, colmajor ? 1 : 0};
+  if (a.ntubes == 0) return TP_OK;
+  const int64_t blocks = (a.ntubes + kTile - 1) / kTile;
+  if (blocks > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTile), 0, st, x, a, (float*)planes, (float*)nullptr);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
 
 int fft_forward(const void* x, int dtype, int64_t n3, const TubeGather& g, void* re, void* im, hipStream_t st) {
   if (int rc = ensure_twiddles()) return rc;

@@ -262,6 +262,242 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16_kernel(MArgs g) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Products of pre-split operands (the t-product path).
+//
+// The forward transforms write each operand as four bf16 planes
+// hi(re), lo(re), hi(im), lo(im) [p][k][major][ld] with the contraction index
+// contiguous (A as rows x ld, B transposed as columns x ld; ld a multiple of
+// 32, zero beyond the live contraction length), so the products stream
+// ready-made matrix-core fragments: no conversion in the main loop. Complex
+// slices use four real products (4M: Re C = Ar Br - Ai Bi, Im C = Ar Bi +
+// Ai Br, the minus sign applied by negating the Ai fragments), each as
+// hi*hi + hi*lo + lo*hi for TERMS = 3 (bf16x3) or hi*hi for TERMS = 1;
+// the real slices (DC, Nyquist) take Ar Br only.
+//
+// Tiling: 512 threads (8 wavefronts, two per SIMD so that one wavefront's
+// waits are covered by the other's products) own a 128 x 128 tile; the
+// wavefronts form a 2 x 4 grid, each owning 64 x 32 (4 x 2 tiles of
+// v_mfma_f32_16x16x32_bf16). A 32-deep k step of both operands (4 planes x
+// 128 rows x 64 bytes each, 64 KB) is staged through registers into one of
+// two LDS buffers while the other is consumed, so each step ends with a
+// single barrier. LDS rows are 64 bytes with the four 16-byte chunks
+// XOR-swizzled by ((row >> 2) ^ (row & 2)) & 3: the 16 rows of a fragment
+// read (and every 8 of them) then land on distinct bank groups, and the
+// staging writes stay conflict free too.
+// ---------------------------------------------------------------------------
+constexpr int SBM = 128, SBN = 128, SBK = 32, SNT = 512;
+constexpr int WTI = 4, WTJ = 2;  // 16 x 16 tiles per wavefront (rows, columns)
+
+struct SArgs {
+  const __bf16* a;  // planes of A: [4][K][M][lda]
+  const __bf16* b;  // planes of B^T: [4][K][N][ldb]
+  float *cre, *cim;
+  int64_t M, N, Kd;  // Kd: padded contraction length (multiple of 32)
+  int64_t lda, ldb, ldc;
+  int64_t pa, pb;  // plane strides (elements)
+  int64_t sa, sb, sc;
+  int64_t K;
+  int real_last;
+};
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int swz(int row, int q) { return row * 4 + (q ^ (((row >> 2) ^ (row & 2)) & 3)); }
+
+template <int TERMS, bool REAL>
+__device__ __forceinline__ void split_body(const SArgs& g, int64_t k, int64_t tm, int64_t tn, u32x4* lds) {
+  constexpr int NPL = REAL ? 2 : 4;  // planes read
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int64_t m0 = tm * SBM, n0 = tn * SBN;
+  // per-slice bases; the row offsets below fit in 32 bits (checked on the host)
+  const __bf16* abase = g.a + k * g.sa;
+  const __bf16* bbase = g.b + k * g.sb;
+  // staging chunk p of this thread: plane p, tile row tid >> 2, 16-byte chunk
+  // tid & 3 of the 64-byte k step; rows beyond M (N) read the last row (their
+  // results are never stored). Offsets are in 16-byte units inside one plane
+  // of one slice.
+  const int srow = tid >> 2, sq = tid & 3;
+  uint32_t aoff, boff;
+  {
+    const int64_t ga = m0 + srow < g.M ? m0 + srow : g.M - 1;
+    const int64_t gb = n0 + srow < g.N ? n0 + srow : g.N - 1;
+    aoff = (uint32_t)(ga * (g.lda / 8)) + (uint32_t)sq;
+    boff = (uint32_t)(gb * (g.ldb / 8)) + (uint32_t)sq;
+  }
+  const u32x4* ap[NPL];
+  const u32x4* bp[NPL];
+#pragma unroll
+  for (int p = 0; p < NPL; ++p) {
+    ap[p] = reinterpret_cast<const u32x4*>(abase + p * g.pa);
+    bp[p] = reinterpret_cast<const u32x4*>(bbase + p * g.pb);
+  }
+  // two register sets of staged operands: a step is loaded two steps
+  // before it is consumed, so a load has a whole step of products to land
+  u32x4 ra0[NPL], rb0[NPL], ra1[NPL], rb1[NPL];
+  auto load = [&](u32x4 (&ra)[NPL], u32x4 (&rb)[NPL], int64_t ks) {
+    const uint32_t kq = (uint32_t)(ks * (SBK / 8));
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) {
+      ra[p] = ap[p][aoff + kq];
+      rb[p] = bp[p][boff + kq];
+    }
+  };
+  // LDS: buffer b holds [A planes][B planes], each plane SBM rows x 4 chunks
+  auto store = [&](const u32x4 (&ra)[NPL], const u32x4 (&rb)[NPL], int buf) {
+    u32x4* sa = lds + buf * (2 * 4 * SBM * 4);
+    u32x4* sb = sa + 4 * SBM * 4;
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) {
+      sa[p * SBM * 4 + swz(srow, sq)] = ra[p];
+      sb[p * SBM * 4 + swz(srow, sq)] = rb[p];
+    }
+  };
+
+  f32x4 cr[WTI][WTJ], ci[WTI][WTJ];
+#pragma unroll
+  for (int i = 0; i < WTI; ++i)
+#pragma unroll
+    for (int j = 0; j < WTJ; ++j) {
+      cr[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ci[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int64_t nsteps = g.Kd / SBK;
+  const int64_t last = nsteps - 1;
+  const int fr = lane & 15, fq = lane >> 4;
+  auto compute = [&](int buf) {
+    const u32x4* sa = lds + buf * (2 * 4 * SBM * 4);
+    const u32x4* sb = sa + 4 * SBM * 4;
+    bf16x8 b[WTJ][NPL];
+#pragma unroll
+    for (int j = 0; j < WTJ; ++j)
+#pragma unroll
+      for (int p = 0; p < NPL; ++p) {
+        const int row = wc * (16 * WTJ) + j * 16 + fr;
+        b[j][p] = __builtin_bit_cast(bf16x8, sb[p * SBM * 4 + swz(row, fq)]);
+      }
+#pragma unroll
+    for (int i = 0; i < WTI; ++i) {
+      bf16x8 a[NPL], an[2];
+      const int row = wr * (16 * WTI) + i * 16 + fr;
+#pragma unroll
+      for (int p = 0; p < NPL; ++p) a[p] = __builtin_bit_cast(bf16x8, sa[p * SBM * 4 + swz(row, fq)]);
+      if constexpr (!REAL) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          u32x4 v = __builtin_bit_cast(u32x4, a[2 + h]);
+          v ^= u32x4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+          an[h] = __builtin_bit_cast(bf16x8, v);
+        }
+      }
+      // term-outer order: consecutive products update different accumulators
+#pragma unroll
+      for (int term = 0; term < TERMS; ++term) {
+        const int ha = term == 2 ? 1 : 0, hb = term == 1 ? 1 : 0;
+#pragma unroll
+        for (int j = 0; j < WTJ; ++j)
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ha], b[j][hb], cr[i][j], 0, 0, 0);
+        if constexpr (!REAL) {
+#pragma unroll
+          for (int j = 0; j < WTJ; ++j)
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ha], b[j][2 + hb], ci[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < WTJ; ++j)
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(an[ha], b[j][2 + hb], cr[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < WTJ; ++j)
+            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2 + ha], b[j][hb], ci[i][j], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  if (nsteps > 0) {
+    // step 0 into buffer 0, step 1 in flight in set 1 (steps past the last
+    // re-read the last one: valid memory, never consumed)
+    load(ra0, rb0, 0);
+    store(ra0, rb0, 0);
+    load(ra1, rb1, 1 <= last ? 1 : last);
+  }
+  __syncthreads();
+  // step ks computes from buffer ks & 1 while set (ks + 1) & 1 (step ks + 1,
+  // loaded a step earlier) goes to the other buffer and set ks & 1 takes
+  // step ks + 2; unrolled by two so that the sets swap statically. The loads
+  // stay ahead of the products (scheduling barrier).
+  for (int64_t ks = 0; ks < nsteps; ks += 2) {
+    load(ra0, rb0, ks + 2 <= last ? ks + 2 : last);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0);
+    store(ra1, rb1, 1);
+    __syncthreads();
+    if (ks + 1 >= nsteps) break;
+    load(ra1, rb1, ks + 3 <= last ? ks + 3 : last);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(1);
+    store(ra0, rb0, 0);
+    __syncthreads();
+  }
+
+  // epilogue: lane holds rows 4 (lane / 16) + e, column lane % 16 of a tile
+  float* cre = g.cre + k * g.sc;
+  float* cim = g.cim + k * g.sc;
+#pragma unroll
+  for (int i = 0; i < WTI; ++i)
+#pragma unroll
+    for (int j = 0; j < WTJ; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gm = m0 + wr * (16 * WTI) + i * 16 + 4 * (lane >> 4) + e;
+        const int64_t gn = n0 + wc * (16 * WTJ) + j * 16 + (lane & 15);
+        if (gm < g.M && gn < g.N) {
+          cre[gm * g.ldc + gn] = cr[i][j][e];
+          cim[gm * g.ldc + gn] = REAL ? 0.f : ci[i][j][e];
+        }
+      }
+}
+
+// Workgroups are dispatched to the eight XCDs round robin (workgroup L on
+// XCD L mod 8, position L / 8 there), each XCD with its own L2. The tile map
+// gives every XCD a contiguous run of complex-slice tiles (so the tiles of
+// one Fourier slice, which share its A row blocks and B column blocks, read
+// them through one L2) followed by a contiguous run of the cheaper
+// real-slice tiles, both dealt as evenly as the round robin allows: XCD x
+// takes one extra complex tile when x < (complex tiles mod 8) and one extra
+// real tile when (x - that remainder) mod 8 < (real tiles mod 8), which
+// reproduces the dispatcher's per-XCD counts.
+constexpr int kXcds = 8;
+
+template <int TERMS>
+__global__ __launch_bounds__(SNT, 1) void cgemm_split_kernel(SArgs g, int64_t gm, int64_t gn) {
+  __shared__ u32x4 lds[2 * 2 * 4 * SBM * 4];  // 2 buffers x (A, B) x 4 planes x 128 rows x 4 chunks: 128 KB
+  const int64_t per = gm * gn;
+  const int64_t nreal = (g.real_last && g.K > 1) ? 2 : 1;
+  const int64_t ncomplex = g.K - nreal;
+  const int64_t Tc = ncomplex * per, Tr = nreal * per;
+  const int64_t cq = Tc / kXcds, crem = Tc % kXcds, rq = Tr / kXcds, rrem = Tr % kXcds;
+  const int64_t L = blockIdx.x;
+  const int x = (int)(L % kXcds);
+  const int64_t pos = L / kXcds;
+  const int64_t cc = cq + (x < crem ? 1 : 0);
+  int64_t id;
+  if (pos < cc) {
+    id = x * cq + (x < crem ? x : crem) + pos;
+  } else {
+    int64_t rs = x * rq;
+    for (int y = 0; y < x; ++y) rs += ((y - crem + kXcds) % kXcds) < rrem ? 1 : 0;
+    id = Tc + rs + (pos - cc);
+  }
+  const int64_t zi = id / per, t = id - zi * per;
+  const int64_t tm = t / gn, tn = t - tm * gn;
+  if (zi < ncomplex)
+    split_body<TERMS, false>(g, zi + 1, tm, tn, lds);
+  else
+    split_body<TERMS, true>(g, zi == ncomplex ? 0 : g.K - 1, tm, tn, lds);
+}
+
 }  // namespace
 
 // Takes the product when it is an as-stored (NN) product of float32 spectra
@@ -287,6 +523,29 @@ int cgemm_mfma(const CGemm& p, int prec, hipStream_t st, bool* handled) {
     hipLaunchKernelGGL(cgemm_bf16_kernel<1>, dim3(gx, gy, (unsigned)p.K), dim3(NT), 0, st, g);
   TP_LAUNCH_CHECK();
   *handled = true;
+  return TP_OK;
+}
+
+int cgemm_split(const SplitGemm& p, hipStream_t st) {
+  if (p.K == 0 || p.M == 0 || p.N == 0) return TP_OK;
+  if (p.Kd % SBK || p.lda % SBK || p.ldb % SBK || p.lda < p.Kd || p.ldb < p.Kd)
+    return fail(TP_EINVAL, "split operands need a contraction stride that is a multiple of 32");
+  if ((reinterpret_cast<uintptr_t>(p.a) | reinterpret_cast<uintptr_t>(p.b)) % 16)
+    return fail(TP_EINVAL, "split operands must be 16-byte aligned");
+  if (p.K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
+  // row offsets inside one plane of one slice are 32-bit in 16-byte units
+  if ((p.M * p.lda) / 8 >= (int64_t(1) << 32) || (p.N * p.ldb) / 8 >= (int64_t(1) << 32))
+    return fail(TP_EUNSUPPORTED, "slice too large for the split product");
+  SArgs g{(const __bf16*)p.a, (const __bf16*)p.b, p.cre, p.cim, p.M, p.N, p.Kd, p.lda, p.ldb, p.ldc, p.pa, p.pb, p.sa, p.sb, p.sc, p.K,
+          p.real_last ? 1 : 0};
+  const int64_t gm = (p.M + SBM - 1) / SBM, gn = (p.N + SBN - 1) / SBN;
+  const int64_t tiles = gm * gn * p.K;
+  if (tiles > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many product tiles");
+  if (p.terms == 3)
+    hipLaunchKernelGGL(cgemm_split_kernel<3>, dim3((unsigned)tiles), dim3(SNT), 0, st, g, gm, gn);
+  else
+    hipLaunchKernelGGL(cgemm_split_kernel<1>, dim3((unsigned)tiles), dim3(SNT), 0, st, g, gm, gn);
+  TP_LAUNCH_CHECK();
   return TP_OK;
 }
 
