@@ -44,6 +44,11 @@ sys.path.insert(0, ROOT)
 
 N1, N2, N4, N3, C_PICK = 512, 2048, 512, 64, 256
 PEAK = {"hbm_GBs": 8000.0, "f32": 157.3, "bf16": 2516.6, "f64": 78.6}
+# HBM bytes per launch of the exact-product stages at this workload (bf16x3),
+# from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors of a plain
+# 512 MiB copy); recorded with profiles/tprod_512x2048x64_bf16x3_hbm_traffic.md.
+# Set an entry to None when its kernel changes.
+TRAFFIC = {"gemm": 758.2e6, "fft_a": 545.5e6, "fft_b": 545.5e6, "ifft": 134.4e6}
 
 
 def tprod_flops(n1, n2, n4, n3):
@@ -77,6 +82,9 @@ def parse():
     p.add_argument("--learned-test", type=int, default=40)
     p.add_argument("--learned-epochs", type=int, default=80)
     p.add_argument("--seeds", type=int, default=10)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="first run one plain 512 MiB device-to-device copy (the reference dispatch for the HBM "
+                        "byte counters)")
     return p.parse_args()
 
 
@@ -334,6 +342,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     A_h, B_h = W.rtprod_pair(N1, N2, N4, N3)
     A = torch.from_numpy(A_h).to(dev)
     B = torch.from_numpy(B_h).to(dev)
@@ -416,7 +430,8 @@ def main():
     if dominant == "gemm":
         ach = kernels["gemm"]["TFLOPs_algorithmic"]
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK[peak_key], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK[peak_key], 4), "traffic": None,
+                "frac": round(ach / PEAK[peak_key], 4),
+                "traffic": TRAFFIC["gemm"] if prec == "bf16x3" else None,
                 "kernel": "per-slice complex product (tprod.gemm)",
                 "note": "achieved = algorithmic flops (135.3 GFLOP) / mean launch time; bf16x3 executes 3 bf16 "
                         "products per algorithmic product, so frac <= 1/3 by construction; executed rate in "
@@ -424,7 +439,8 @@ def main():
     else:
         gbs = kernels[dominant]["GBs"]
         roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
-                "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": None, "kernel": "tprod." + dominant}
+                "frac": round(gbs / PEAK["hbm_GBs"], 4),
+                "traffic": TRAFFIC.get(dominant) if prec == "bf16x3" else None, "kernel": "tprod." + dominant}
 
     out = {
         "metric": "t-product TFLOP/s; t-CUR time-to-1e-3 rel err, BF16+learned vs FP32 plain",

@@ -290,3 +290,37 @@ def test_rtprod_bf16x3_matches_oracle(mode):
     idx, _ = picks.host()
     np.testing.assert_array_equal(idx.numpy(), ridx)
     assert rel(Z, D.rtprod(A, B, ridx, rsc)) < BF_TOL["bf16x3"]
+
+
+@pytest.mark.parametrize("shape", [(20, 33, 17, 1), (16, 40, 24, 2), (8, 70, 9, 10), (130, 31, 129, 8)])
+def test_tprod_split_short_tubes_and_tails(shape):
+    """Split-operand path at tube lengths with one or two real slices only,
+    and tiles whose rows, columns and contraction all have ragged tails."""
+    n1, n2, n4, n3 = shape
+    rs = np.random.default_rng(sum(shape) + 11)
+    A = rs.standard_normal((n1, n2, n3)).astype(np.float32)
+    B = rs.standard_normal((n2, n4, n3)).astype(np.float32)
+    Cg = api.tprod(dev(A), dev(B), prec="bf16x3").cpu().numpy()
+    assert rel(Cg, T.tprod_bcirc(A, B)) < BF_TOL["bf16x3"]
+
+
+def test_trace_records_the_stages_of_a_call():
+    A, B = W.rtprod_pair(n1=64, n2=256, n4=32, n3=16)
+    Ad, Bd = dev(A), dev(B)
+    picks = api.tsample("norm2", 32, mode="iid", seed=1, A=Ad)
+    api.trace_enable(True)
+    for _ in range(3):
+        api.tprod(Ad, Bd, prec="bf16x3")
+    api.tprod(Ad, Bd, picks=picks, prec="bf16x3")
+    api.trace_enable(False)
+    api.tprod(Ad, Bd, prec="bf16x3")  # not recorded
+    tr = api.trace_read()
+    for st in ("fft_a", "fft_b", "gemm", "ifft"):
+        calls, ms = tr["tprod." + st]
+        assert calls == 3 and ms > 0
+        calls, ms = tr["rtprod." + st]
+        assert calls == 1 and ms > 0
+    # a fresh enable clears the records
+    api.trace_enable(True)
+    api.trace_enable(False)
+    assert api.trace_read() == {}
