@@ -86,7 +86,8 @@ struct RangeFinder {
     ure = ar.take<double>(K * s * s);
     uim = ar.take<double>(K * s * s);
     evals = ar.take<double>(K * s);
-    const size_t np = gram_part_doubles(K, std::max(m, n), s);
+    size_t np = gram_part_doubles(K, std::max(m, n), s);
+    if (n <= kMaxS) np = std::max(np, xgram_part_doubles(K, m, (int)n, s));
     if (np) {
       pre = ar.take<double>(np);
       pim = ar.take<double>(np);
@@ -104,6 +105,15 @@ struct RangeFinder {
     return mm(X, 0, rows, s, T, 0, s, s, out, K, real_last, dtype, prec, st);
   }
 
+  // Bh = X^H Q (n x s): a row-split cross product when X is narrow (the
+  // range finder of C and of the t-CUR core), the general product otherwise
+  int project(const Spec& X, int prec, hipStream_t st) const {
+    if (n <= kMaxS)
+      return xgram(X.re, X.im, (int)n, n, m * n, Q.re, Q.im, s, s, m * s, dtype, K, m, real_last, Bh.re, Bh.im, pre,
+                   pim, st);
+    return mm(X, 1, m, n, Q, 0, m, s, Bh, K, real_last, dtype, prec, st);
+  }
+
   int run(const Spec& X, int q, uint64_t seed, uint64_t stream_id, int prec, hipStream_t st,
           const int64_t* ncols_dev = nullptr) {
     if (int rc = randn_spectrum(omega.re, omega.im, dtype, K, n, s, real_last, seed, stream_id, st)) return rc;
@@ -114,14 +124,14 @@ struct RangeFinder {
     std::swap(Q, Y);
     for (int it = 0; it < q; ++it) {
       // Z = orth(X^H Q), Q = orth(orth(X Z))
-      if (int rc = mm(X, 1, m, n, Q, 0, m, s, Bh, K, real_last, dtype, prec, st)) return rc;
+      if (int rc = project(X, prec, st)) return rc;
       if (int rc = orth(Bh, n, Z, prec, st)) return rc;
       if (int rc = mm(X, 0, m, n, Z, 0, n, s, Y, K, real_last, dtype, prec, st, ncols_dev)) return rc;
       if (int rc = orth(Y, m, Q, prec, st)) return rc;
       if (int rc = orth(Q, m, Y, prec, st)) return rc;
       std::swap(Q, Y);
     }
-    if (int rc = mm(X, 1, m, n, Q, 0, m, s, Bh, K, real_last, dtype, prec, st)) return rc;
+    if (int rc = project(X, prec, st)) return rc;
     if (int rc = gram(Bh.re, Bh.im, dtype, K, n, s, s, n * s, real_last, gre, gim, pre, pim, st)) return rc;
     return herm_eig(gre, gim, K, s, evals, ure, uim, st);
   }

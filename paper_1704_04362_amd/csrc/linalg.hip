@@ -66,71 +66,94 @@ __global__ void randn_kernel(T* re, T* im, int64_t K, int64_t per_slice, int rea
   }
 }
 
-// Partial Gram matrices: workgroup (k, y) adds conj(x_i) x_j over the rows
-// [y rch, (y + 1) rch) of slice k (X_k rows x s, planar, row stride ldx) and
-// writes its s x s block to part[(k nch + y) s^2] (float64). With one chunk
-// the block is the Gram matrix itself.
-template <typename T>
-__global__ __launch_bounds__(256) void gram_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int64_t K,
-                                                   int64_t rows, int s, int64_t ldx, int64_t sx, int real_last,
-                                                   int64_t rch, double* __restrict__ gre, double* __restrict__ gim) {
+// Partial cross products: workgroup (k, y) adds conj(x_i) y_j over the rows
+// [y rch, (y + 1) rch) of slice k, X_k rows x a and Y_k rows x b (planar,
+// a, b <= 64), and writes its a x b block to part[(k nch + y) a b] (float64).
+// Rows are staged through LDS 32 at a time; each thread owns a BR x BC block
+// of the output (i in BR (t / 16) .., j in BC (t % 16) ..; the 16 x 16 thread
+// grid covers 16 BR x 16 BC >= a x b), so each row costs it BR + BC complex
+// LDS reads for BR BC complex multiply-adds. The Gram matrix X^H X is the
+// case Y = X.
+template <typename T, int BR, int BC>
+__global__ __launch_bounds__(256) void xgram_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int a,
+                                                    int64_t ldx, int64_t sx, const T* __restrict__ yre,
+                                                    const T* __restrict__ yim, int b, int64_t ldy, int64_t sy,
+                                                    int64_t K, int64_t rows, int real_last, int64_t rch,
+                                                    double* __restrict__ pre, double* __restrict__ pim) {
   constexpr int CH = 32;
-  __shared__ double cr[CH][kMaxS + 1], ci[CH][kMaxS + 1];
+  __shared__ double xr_[CH][kMaxS], xi_[CH][kMaxS], yr_[CH][kMaxS], yi_[CH][kMaxS];
   const int64_t k = blockIdx.x;
   const int64_t nch = gridDim.y;
   const bool real = k == 0 || (real_last && k == K - 1);
   const T* xr = xre + k * sx;
   const T* xi = xim + k * sx;
-  const int ne = s * s;
+  const T* yr = yre + k * sy;
+  const T* yi = yim + k * sy;
+  const int tid = threadIdx.x;
+  const int i0 = BR * (tid >> 4), j0 = BC * (tid & 15);
+  const bool act = i0 < a && j0 < b;
   const int64_t rbeg = (int64_t)blockIdx.y * rch;
   const int64_t rend = (rbeg + rch) < rows ? (rbeg + rch) : rows;
-  constexpr int PER = kMaxS * kMaxS / 256;
-  double ar[PER], ai[PER];
+  double cr[BR][BC], ci[BR][BC];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) ar[q] = ai[q] = 0.0;
+  for (int u = 0; u < BR; ++u)
+#pragma unroll
+    for (int v = 0; v < BC; ++v) cr[u][v] = ci[u][v] = 0.0;
   for (int64_t r0 = rbeg; r0 < rend; r0 += CH) {
-    for (int e = threadIdx.x; e < CH * s; e += 256) {
-      const int rr = e / s, c = e - rr * s;
+    for (int e = tid; e < CH * kMaxS; e += 256) {
+      const int rr = e / kMaxS, c = e - rr * kMaxS;
       const int64_t row = r0 + rr;
-      double vr = 0.0, vi = 0.0;
-      if (row < rend) {
-        vr = (double)xr[row * ldx + c];
-        vi = real ? 0.0 : (double)xi[row * ldx + c];
-      }
-      cr[rr][c] = vr;
-      ci[rr][c] = vi;
+      const bool live = row < rend;
+      xr_[rr][c] = (live && c < a) ? (double)xr[row * ldx + c] : 0.0;
+      xi_[rr][c] = (live && c < a && !real) ? (double)xi[row * ldx + c] : 0.0;
+      yr_[rr][c] = (live && c < b) ? (double)yr[row * ldy + c] : 0.0;
+      yi_[rr][c] = (live && c < b && !real) ? (double)yi[row * ldy + c] : 0.0;
     }
     __syncthreads();
-    const int nr = (int)((rend - r0) < CH ? (rend - r0) : CH);
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      if (e >= ne) continue;
-      const int i = e / s, j = e - i * s;
-      double sr = ar[q], si = ai[q];
+    if (act) {
+      const int nr = (int)((rend - r0) < CH ? (rend - r0) : CH);
       for (int rr = 0; rr < nr; ++rr) {
-        // conj(x_i) * x_j
-        sr += cr[rr][i] * cr[rr][j] + ci[rr][i] * ci[rr][j];
-        si += cr[rr][i] * ci[rr][j] - ci[rr][i] * cr[rr][j];
+        double pr[BR], pi[BR], qr[BC], qi[BC];
+#pragma unroll
+        for (int u = 0; u < BR; ++u) {
+          pr[u] = xr_[rr][i0 + u];
+          pi[u] = xi_[rr][i0 + u];
+        }
+#pragma unroll
+        for (int v = 0; v < BC; ++v) {
+          qr[v] = yr_[rr][j0 + v];
+          qi[v] = yi_[rr][j0 + v];
+        }
+#pragma unroll
+        for (int u = 0; u < BR; ++u)
+#pragma unroll
+          for (int v = 0; v < BC; ++v) {
+            // conj(x_i) * y_j
+            cr[u][v] += pr[u] * qr[v] + pi[u] * qi[v];
+            ci[u][v] += pr[u] * qi[v] - pi[u] * qr[v];
+          }
       }
-      ar[q] = sr;
-      ai[q] = si;
     }
     __syncthreads();
   }
-  const int64_t base = (k * nch + blockIdx.y) * ne;
+  if (!act) return;
+  const int64_t base = (k * nch + blockIdx.y) * (int64_t)a * b;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    if (e >= ne) continue;
-    gre[base + e] = ar[q];
-    gim[base + e] = real ? 0.0 : ai[q];
-  }
+  for (int u = 0; u < BR; ++u)
+#pragma unroll
+    for (int v = 0; v < BC; ++v) {
+      const int i = i0 + u, j = j0 + v;
+      if (i < a && j < b) {
+        pre[base + i * b + j] = cr[u][v];
+        pim[base + i * b + j] = real ? 0.0 : ci[u][v];
+      }
+    }
 }
 
-// G[k][e] = sum over chunks y (in order) of part[k][y][e].
-__global__ void gram_reduce_kernel(const double* __restrict__ pre, const double* __restrict__ pim, int64_t K,
-                                   int64_t nch, int ne, double* __restrict__ gre, double* __restrict__ gim) {
+// out[k][e] = sum over chunks y (in order) of part[k][y][e], as type TO.
+template <typename TO>
+__global__ void xgram_reduce_kernel(const double* __restrict__ pre, const double* __restrict__ pim, int64_t K,
+                                    int64_t nch, int ne, TO* __restrict__ ore, TO* __restrict__ oim) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= K * ne) return;
   const int64_t k = t / ne, e = t - k * ne;
@@ -139,30 +162,30 @@ __global__ void gram_reduce_kernel(const double* __restrict__ pre, const double*
     sr += pre[(k * nch + y) * ne + e];
     si += pim[(k * nch + y) * ne + e];
   }
-  gre[t] = sr;
-  gim[t] = si;
+  ore[t] = (TO)sr;
+  oim[t] = (TO)si;
 }
 
 // Eigen-decomposition of one s x s Hermitian matrix per workgroup with the
 // LDS Jacobi solver; eigenvalues are returned in descending order (ties by
 // index) with the matching eigenvector columns.
-template <int MAXN>
-__global__ __launch_bounds__(256) void herm_eig_kernel(const double* __restrict__ gre,
+template <int MAXN, int NT>
+__global__ __launch_bounds__(NT) void herm_eig_kernel(const double* __restrict__ gre,
                                                        const double* __restrict__ gim, int s, int max_sweeps,
                                                        double* __restrict__ evals, double* __restrict__ vre,
                                                        double* __restrict__ vim) {
-  __shared__ JacobiShared<MAXN, 256> sh;
+  __shared__ JacobiShared<MAXN, NT> sh;
   __shared__ int order[MAXN];
   const int64_t k = blockIdx.x;
   const int ne = s * s;
   const int tid = threadIdx.x;
-  for (int e = tid; e < ne; e += 256) {
+  for (int e = tid; e < ne; e += NT) {
     const int i = e / s, j = e - i * s;
     sh.Hr[i][j] = gre[k * ne + e];
     sh.Hi[i][j] = gim[k * ne + e];
   }
   __syncthreads();
-  jacobi_eig_lds<MAXN, 256>(sh, s, max_sweeps, 1e-15);
+  jacobi_eig_lds<MAXN, NT>(sh, s, max_sweeps, 1e-15);
   if (tid < s) {
     const double lt = sh.Hr[tid][tid];
     int rank = 0;
@@ -173,7 +196,7 @@ __global__ __launch_bounds__(256) void herm_eig_kernel(const double* __restrict_
     order[rank] = tid;
   }
   __syncthreads();
-  for (int e = tid; e < ne; e += 256) {
+  for (int e = tid; e < ne; e += NT) {
     const int i = e / s, j = e - i * s;  // row i, sorted column j
     const int src = order[j];
     vre[k * ne + e] = sh.Vr[i][src];
@@ -238,27 +261,61 @@ __global__ __launch_bounds__(128) void chol_inv_kernel(const double* __restrict_
     }
     __syncthreads();
   }
-  // T = R^{-1} on the kept indices, one column per thread (back substitution
-  // of R T = I): T_mm = 1 / R_mm, T_im = -(sum_{i<l<=m} R_il T_lm) / R_ii
-  for (int m = tid; m < s; m += 128) {
-    for (int i = 0; i < s; ++i) {
-      Tr[i][m] = 0.0;
-      Ti[i][m] = 0.0;
-    }
-    if (rd[m] > 0.0) {
-      Tr[m][m] = 1.0 / rd[m];
-      for (int i = m - 1; i >= 0; --i) {
-        if (rd[i] == 0.0) continue;
-        double ar = 0.0, ai = 0.0;
-        for (int l = i + 1; l <= m; ++l) {
-          const double rr = Gr[i][l], ri = Gi[i][l], xr = Tr[l][m], xi = Ti[l][m];
-          ar += rr * xr - ri * xi;
-          ai += rr * xi + ri * xr;
-        }
-        Tr[i][m] = -ar / rd[i];
-        Ti[i][m] = -ai / rd[i];
+  // T = R^{-1} on the kept indices by recursive doubling over diagonal
+  // blocks of the padded MAXN x MAXN factor (R = 0 past s): with T11, T22 the
+  // inverses of two adjacent b x b diagonal blocks, the block above T22 is
+  // T12 = -T11 (R12 T22). W = R12 T22 is kept in the (unused) lower triangle
+  // of G at the transposed position. A dropped index has R_ii = 0 and a zero
+  // row, and gets a zero row and column of T.
+  for (int e = tid; e < MAXN * MAXN; e += 128) {
+    const int i = e / MAXN, j = e - i * MAXN;
+    Tr[i][j] = (i == j && i < s && rd[i] > 0.0) ? 1.0 / rd[i] : 0.0;
+    Ti[i][j] = 0.0;
+    if (i >= s || j >= s) {
+      if (j > i) {
+        Gr[i][j] = 0.0;
+        Gi[i][j] = 0.0;
       }
+    } else if (j > i && rd[i] == 0.0) {
+      Gr[i][j] = 0.0;
+      Gi[i][j] = 0.0;
     }
+  }
+  __syncthreads();
+  for (int b = 1; b < MAXN; b *= 2) {
+    const int nw = (MAXN / (2 * b)) * b * b;
+    // W = R12 T22 (b x b per pair), stored at G[a1 + x][a0 + y]
+    for (int e = tid; e < nw; e += 128) {
+      const int p = e / (b * b), rem = e - p * b * b;
+      const int x = rem / b, y = rem - x * b;  // W row x (block row a0 + x), column y (a1 + y)
+      const int a0 = 2 * p * b, a1 = a0 + b;
+      double wr = 0.0, wi = 0.0;
+      for (int t = 0; t < b; ++t) {
+        const double rr = Gr[a0 + x][a1 + t], ri = Gi[a0 + x][a1 + t];
+        const double tr = Tr[a1 + t][a1 + y], ti = Ti[a1 + t][a1 + y];
+        wr += rr * tr - ri * ti;
+        wi += rr * ti + ri * tr;
+      }
+      Gr[a1 + y][a0 + x] = wr;
+      Gi[a1 + y][a0 + x] = wi;
+    }
+    __syncthreads();
+    // T12 = -T11 W
+    for (int e = tid; e < nw; e += 128) {
+      const int p = e / (b * b), rem = e - p * b * b;
+      const int x = rem / b, y = rem - x * b;
+      const int a0 = 2 * p * b, a1 = a0 + b;
+      double vr = 0.0, vi = 0.0;
+      for (int t = 0; t < b; ++t) {
+        const double tr = Tr[a0 + x][a0 + t], ti = Ti[a0 + x][a0 + t];
+        const double wr = Gr[a1 + y][a0 + t], wi = Gi[a1 + y][a0 + t];
+        vr += tr * wr - ti * wi;
+        vi += tr * wi + ti * wr;
+      }
+      Tr[a0 + x][a1 + y] = -vr;
+      Ti[a0 + x][a1 + y] = -vi;
+    }
+    __syncthreads();
   }
   __syncthreads();
   for (int e = tid; e < ne; e += 128) {
@@ -400,34 +457,81 @@ int64_t gram_chunks(int64_t rows) {
   return c < 1 ? 1 : (c > 16 ? 16 : c);
 }
 
-size_t gram_part_doubles(int64_t K, int64_t rows, int s) {
+size_t gram_part_doubles(int64_t K, int64_t rows, int s) { return (size_t)(K * gram_chunks(rows) * s * s); }
+
+// launches the blocked cross product with the smallest blocks that cover a x b
+template <typename T>
+void launch_xgram(dim3 grid, hipStream_t st, const T* xre, const T* xim, int a, int64_t ldx, int64_t sx,
+                  const T* yre, const T* yim, int b, int64_t ldy, int64_t sy, int64_t K, int64_t rows, int rl,
+                  int64_t rch, double* pre, double* pim) {
+  if (a <= 32 && b <= 32)
+    hipLaunchKernelGGL((xgram_kernel<T, 2, 2>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+                       rows, rl, rch, pre, pim);
+  else if (b <= 32)
+    hipLaunchKernelGGL((xgram_kernel<T, 4, 2>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+                       rows, rl, rch, pre, pim);
+  else if (a <= 32)
+    hipLaunchKernelGGL((xgram_kernel<T, 2, 4>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+                       rows, rl, rch, pre, pim);
+  else
+    hipLaunchKernelGGL((xgram_kernel<T, 4, 4>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+                       rows, rl, rch, pre, pim);
+}
+
+size_t xgram_part_doubles(int64_t K, int64_t rows, int a, int b) {
+  return (size_t)(K * gram_chunks(rows) * a * b);
+}
+
+int xgram(const void* xre, const void* xim, int a, int64_t ldx, int64_t sx, const void* yre, const void* yim, int b,
+          int64_t ldy, int64_t sy, int dtype, int64_t K, int64_t rows, bool real_last, void* ore, void* oim,
+          double* pre, double* pim, hipStream_t st) {
+  if (a < 1 || a > kMaxS || b < 1 || b > kMaxS) return fail(TP_EUNSUPPORTED, "cross product size outside 1..64");
+  if (K == 0) return TP_OK;
+  if (K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
+  if (!pre || !pim) return fail(TP_EWORKSPACE, "cross product partial buffer missing");
   const int64_t nch = gram_chunks(rows);
-  return nch > 1 ? (size_t)(K * nch * s * s) : 0;
+  const int64_t rch = (rows + nch - 1) / nch;
+  const dim3 grid((unsigned)K, (unsigned)nch);
+  const int rl = real_last ? 1 : 0;
+  if (dtype == TP_F64)
+    launch_xgram<double>(grid, st, (const double*)xre, (const double*)xim, a, ldx, sx, (const double*)yre,
+                         (const double*)yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
+  else
+    launch_xgram<float>(grid, st, (const float*)xre, (const float*)xim, a, ldx, sx, (const float*)yre,
+                        (const float*)yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
+  TP_LAUNCH_CHECK();
+  const int ne = a * b;
+  if (dtype == TP_F64)
+    hipLaunchKernelGGL(xgram_reduce_kernel<double>, dim3(blocks_for(K * ne)), dim3(256), 0, st, pre, pim, K, nch, ne,
+                       (double*)ore, (double*)oim);
+  else
+    hipLaunchKernelGGL(xgram_reduce_kernel<float>, dim3(blocks_for(K * ne)), dim3(256), 0, st, pre, pim, K, nch, ne,
+                       (float*)ore, (float*)oim);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
 }
 
 int gram(const void* xre, const void* xim, int dtype, int64_t K, int64_t rows, int s, int64_t ldx, int64_t sx,
          bool real_last, double* gre, double* gim, double* pre, double* pim, hipStream_t st) {
   if (s < 1 || s > kMaxS) return fail(TP_EUNSUPPORTED, "Gram size outside 1..64");
   if (K == 0) return TP_OK;
+  if (K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
+  if (!pre || !pim) return fail(TP_EWORKSPACE, "Gram partial buffer missing");
   const int64_t nch = gram_chunks(rows);
-  if (nch > 1 && (!pre || !pim)) return fail(TP_EWORKSPACE, "Gram partial buffer missing");
   const int64_t rch = (rows + nch - 1) / nch;
-  double* ore = nch > 1 ? pre : gre;
-  double* oim = nch > 1 ? pim : gim;
   const dim3 grid((unsigned)K, (unsigned)nch);
+  const int rl = real_last ? 1 : 0;
   if (dtype == TP_F64)
-    hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, st, (const double*)xre, (const double*)xim, K,
-                       rows, s, ldx, sx, real_last ? 1 : 0, rch, ore, oim);
+    launch_xgram<double>(grid, st, (const double*)xre, (const double*)xim, s, ldx, sx, (const double*)xre,
+                         (const double*)xim, s, ldx, sx, K, rows, rl, rch, pre, pim);
   else
-    hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, st, (const float*)xre, (const float*)xim, K, rows,
-                       s, ldx, sx, real_last ? 1 : 0, rch, ore, oim);
+    launch_xgram<float>(grid, st, (const float*)xre, (const float*)xim, s, ldx, sx, (const float*)xre,
+                        (const float*)xim, s, ldx, sx, K, rows, rl, rch, pre, pim);
   TP_LAUNCH_CHECK();
-  if (nch > 1) {
-    const int ne = s * s;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(blocks_for(K * ne)), dim3(256), 0, st, pre, pim, K, nch, ne, gre,
-                       gim);
-    TP_LAUNCH_CHECK();
-  }
+  const int ne = s * s;
+  hipLaunchKernelGGL(xgram_reduce_kernel<double>, dim3(blocks_for(K * ne)), dim3(256), 0, st, pre, pim, K, nch, ne,
+                     gre, gim);
+  TP_LAUNCH_CHECK();
   return TP_OK;
 }
 
@@ -436,10 +540,11 @@ int herm_eig(const double* gre, const double* gim, int64_t K, int s, double* eva
   if (s < 1 || s > kMaxS) return fail(TP_EUNSUPPORTED, "eigenproblem size outside 1..64");
   if (K == 0) return TP_OK;
   if (s <= 32)
-    hipLaunchKernelGGL(herm_eig_kernel<32>, dim3((unsigned)K), dim3(256), 0, st, gre, gim, s, 40, evals, vre, vim);
+    hipLaunchKernelGGL((herm_eig_kernel<32, 1024>), dim3((unsigned)K), dim3(1024), 0, st, gre, gim, s, 40, evals,
+                       vre, vim);
   else
-    hipLaunchKernelGGL(herm_eig_kernel<kMaxS>, dim3((unsigned)K), dim3(256), 0, st, gre, gim, s, 40, evals, vre,
-                       vim);
+    hipLaunchKernelGGL((herm_eig_kernel<kMaxS, 256>), dim3((unsigned)K), dim3(256), 0, st, gre, gim, s, 40, evals,
+                       vre, vim);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

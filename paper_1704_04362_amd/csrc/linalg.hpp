@@ -16,6 +16,13 @@ int randn_spectrum(void* re, void* im, int dtype, int64_t K, int64_t rows, int64
 size_t gram_part_doubles(int64_t K, int64_t rows, int s);
 int gram(const void* xre, const void* xim, int dtype, int64_t K, int64_t rows, int s, int64_t ldx, int64_t sx,
          bool real_last, double* gre, double* gim, double* pre, double* pim, hipStream_t st);
+// C_k = X_k^H Y_k (a x b, row-major, in the data dtype) for tall X_k (rows x a)
+// and Y_k (rows x b), a, b <= 64, row-split with partials (pre, pim) of
+// xgram_part_doubles(K, rows, a, b) doubles each, added in a fixed order
+size_t xgram_part_doubles(int64_t K, int64_t rows, int a, int b);
+int xgram(const void* xre, const void* xim, int a, int64_t ldx, int64_t sx, const void* yre, const void* yim, int b,
+          int64_t ldy, int64_t sy, int dtype, int64_t K, int64_t rows, bool real_last, void* ore, void* oim,
+          double* pre, double* pim, hipStream_t st);
 // eigenvalues descending (K x s) and eigenvectors as columns (K x s x s)
 int herm_eig(const double* gre, const double* gim, int64_t K, int s, double* evals, double* vre, double* vim,
              hipStream_t st);
