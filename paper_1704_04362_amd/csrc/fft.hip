@@ -240,12 +240,18 @@ __device__ __forceinline__ void emit(T* ore, T* oim, int64_t K, int64_t ks, int6
   }
 }
 
+// Long tubes are staged through LDS in two halves (HALF): half the LDS per
+// workgroup, so twice as many wavefronts fit on a compute unit to hide the
+// memory latency of this HBM-bound kernel; each lane picks its half tube out
+// of LDS between the two stagings.
 template <typename T, int N, bool SPLIT = false>
 __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, FwdArgs a, T* __restrict__ ore,
                                                      T* __restrict__ oim) {
   constexpr int M = N / 2;
-  constexpr int PAD = N + 1;
   constexpr int VN = Vec16<T>::n;
+  constexpr bool HALF = N >= 32 && N % (2 * VN) == 0;
+  constexpr int SPAN = HALF ? N / 2 : N;  // tube entries staged at once
+  constexpr int PAD = SPAN + 1;
   using V = typename Vec16<T>::type;
   __shared__ T lds[kTile * PAD];
   __shared__ int64_t s_src[kTile];
@@ -262,52 +268,64 @@ __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, Fw
   }
   __syncthreads();
 
-  if constexpr (N % VN == 0) {
-    constexpr int CH = N / VN;
+  // stage tube entries [h SPAN, (h + 1) SPAN) of the 64 tubes
+  auto stage = [&](int h) {
+    if constexpr (N % VN == 0) {
+      constexpr int CH = SPAN / VN;
 #pragma unroll
-    for (int it = 0; it < CH; ++it) {
-      const int f = it * kTile + lane;
-      const int tl = f / CH, part = f - tl * CH;
-      const int64_t src = s_src[tl];
-      const double s = s_scl[tl];
-      T v[VN];
+      for (int it = 0; it < CH; ++it) {
+        const int f = it * kTile + lane;
+        const int tl = f / CH, part = f - tl * CH;
+        const int64_t src = s_src[tl];
+        const double s = s_scl[tl];
+        T v[VN];
 #pragma unroll
-      for (int e = 0; e < VN; ++e) v[e] = T(0);
-      if (src >= 0) {
-        const V w = *reinterpret_cast<const V*>(x + src * N + part * VN);
-        const T* wp = reinterpret_cast<const T*>(&w);
+        for (int e = 0; e < VN; ++e) v[e] = T(0);
+        if (src >= 0) {
+          const V w = *reinterpret_cast<const V*>(x + src * N + h * SPAN + part * VN);
+          const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-        for (int e = 0; e < VN; ++e) v[e] = (s == 1.0) ? wp[e] : (T)((double)wp[e] * s);
+          for (int e = 0; e < VN; ++e) v[e] = (s == 1.0) ? wp[e] : (T)((double)wp[e] * s);
+        }
+#pragma unroll
+        for (int e = 0; e < VN; ++e) lds[tl * PAD + part * VN + e] = v[e];
       }
-#pragma unroll
-      for (int e = 0; e < VN; ++e) lds[tl * PAD + part * VN + e] = v[e];
+    } else {
+      for (int it = 0; it < N; ++it) {
+        const int f = it * kTile + lane;
+        const int tl = f / N, e = f - tl * N;
+        const int64_t src = s_src[tl];
+        const double s = s_scl[tl];
+        T v = T(0);
+        if (src >= 0) v = (s == 1.0) ? x[src * N + e] : (T)((double)x[src * N + e] * s);
+        lds[tl * PAD + e] = v;
+      }
     }
-  } else {
-    for (int it = 0; it < N; ++it) {
-      const int f = it * kTile + lane;
-      const int tl = f / N, e = f - tl * N;
-      const int64_t src = s_src[tl];
-      const double s = s_scl[tl];
-      T v = T(0);
-      if (src >= 0) v = (s == 1.0) ? x[src * N + e] : (T)((double)x[src * N + e] * s);
-      lds[tl * PAD + e] = v;
-    }
-  }
-  __syncthreads();
+  };
 
   const int64_t t = tile0 + lane;
-  if (t >= a.ntubes) return;
   const int64_t ks = a.ntubes;
   constexpr int64_t K = N / 2 + 1;
   if constexpr (N == 1) {
+    stage(0);
+    __syncthreads();
+    if (t >= a.ntubes) return;
     emit<T, SPLIT>(ore, oim, K, ks, 0, t, lds[lane * PAD], T(0));
   } else {
+    // z[m] = x[2m] + i x[2m+1]; a half holds z[h SPAN/2 .. (h+1) SPAN/2)
     T zr[M], zi[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      zr[m] = lds[lane * PAD + 2 * m];
-      zi[m] = lds[lane * PAD + 2 * m + 1];
+    for (int h = 0; h < N / SPAN; ++h) {
+      if (h > 0) __syncthreads();
+      stage(h);
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < SPAN / 2; ++m) {
+        zr[h * (SPAN / 2) + m] = lds[lane * PAD + 2 * m];
+        zi[h * (SPAN / 2) + m] = lds[lane * PAD + 2 * m + 1];
+      }
     }
+    if (t >= a.ntubes) return;
     cfft<T, M>(zr, zi);
     emit<T, SPLIT>(ore, oim, K, ks, 0, t, zr[0] + zi[0], T(0));
     emit<T, SPLIT>(ore, oim, K, ks, M, t, zr[0] - zi[0], T(0));
@@ -338,25 +356,43 @@ __global__ __launch_bounds__(kTile) void irfft_kernel(const T* __restrict__ xre,
     if constexpr (N == 1) {
       lds[lane * PAD] = xre[t];
     } else {
-      T Xr[M + 1], Xi[M + 1];
-#pragma unroll
-      for (int k = 0; k <= M; ++k) {
-        Xr[k] = xre[(int64_t)k * ks + t];
-        Xi[k] = (k == 0 || k == M) ? T(0) : xim[(int64_t)k * ks + t];
-      }
-      // Z[k] = E[k] + i O[k]; build conj(Z) for the forward-FFT-based inverse
+      // the half spectrum is read into zr / zi and turned into conj(Z),
+      // Z[k] = E[k] + i O[k], in place: slot k takes X[k] for k < M and
+      // X[M] is held apart; the pair (k, M - k) is rewritten together
       T zr[M], zi[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const int j = M - k;
-        const T er = (Xr[k] + Xr[j]) * T(0.5), ei = (Xi[k] - Xi[j]) * T(0.5);
-        const T dr = (Xr[k] - Xr[j]) * T(0.5), di = (Xi[k] + Xi[j]) * T(0.5);
-        // O = d * conj(W_N^k)
+        zr[k] = xre[(int64_t)k * ks + t];
+        zi[k] = k == 0 ? T(0) : xim[(int64_t)k * ks + t];
+      }
+      const T xmr = xre[(int64_t)M * ks + t];
+      auto zpart = [&](int k, T xkr, T xki, T xjr, T xji, T& outr, T& outi) {
+        const T er = (xkr + xjr) * T(0.5), ei = (xki - xji) * T(0.5);
+        const T dr = (xkr - xjr) * T(0.5), di = (xki + xji) * T(0.5);
+        // O = d * conj(W_N^k); Z = E + i O; store conj(Z)
         const T wr = tw_re<T>(N, k), wi = -tw_im<T>(N, k);
         const T orr = dr * wr - di * wi, oi = dr * wi + di * wr;
-        // Z = E + i O ; store conj(Z)
-        zr[k] = er - oi;
-        zi[k] = -(ei + orr);
+        outr = er - oi;
+        outi = -(ei + orr);
+      };
+      {
+        // k = 0 pairs with X[M] (imaginary parts of both are dropped)
+        T o0r, o0i;
+        zpart(0, zr[0], T(0), xmr, T(0), o0r, o0i);
+        zr[0] = o0r;
+        zi[0] = o0i;
+      }
+#pragma unroll
+      for (int k = 1; k <= M / 2; ++k) {
+        const int j = M - k;
+        const T xkr = zr[k], xki = zi[k], xjr = zr[j], xji = zi[j];
+        T okr, oki, ojr, oji;
+        zpart(k, xkr, xki, xjr, xji, okr, oki);
+        zpart(j, xjr, xji, xkr, xki, ojr, oji);
+        zr[k] = okr;
+        zi[k] = oki;
+        zr[j] = ojr;
+        zi[j] = oji;
       }
       cfft<T, M>(zr, zi);
       const T inv = T(1) / T(M);
