@@ -52,12 +52,21 @@ __global__ __launch_bounds__(LNT) void lateral_partial_kernel(const T* __restric
     double s = 0.0;
     if (f < npieces) {
       if (vec) {
-#pragma unroll 4
-        for (int64_t r = 0; r < rows; ++r) {
-          const V w = *reinterpret_cast<const V*>(a + ((i0 + r) * n2 + j0) * n3 + f * VN);
-          const T* wp = reinterpret_cast<const T*>(&w);
+        // all LROWS loads in flight at once: rows past the end re-read the
+        // last row and are masked out of the sum
+        V w[LROWS];
 #pragma unroll
-          for (int e = 0; e < VN; ++e) s += (double)wp[e] * (double)wp[e];
+        for (int r = 0; r < LROWS; ++r) {
+          const int64_t rr = r < rows ? r : rows - 1;
+          w[r] = *reinterpret_cast<const V*>(a + ((i0 + rr) * n2 + j0) * n3 + f * VN);
+        }
+#pragma unroll
+        for (int r = 0; r < LROWS; ++r) {
+          const T* wp = reinterpret_cast<const T*>(&w[r]);
+          double q = 0.0;
+#pragma unroll
+          for (int e = 0; e < VN; ++e) q += (double)wp[e] * (double)wp[e];
+          s += r < rows ? q : 0.0;
         }
       } else {
         for (int64_t r = 0; r < rows; ++r) {
