@@ -15,7 +15,7 @@ int cgemm_mfma(const CGemm& p, int prec, hipStream_t st, bool* handled);
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int BK = 16, NT = 256;
 
 struct GemmArgs {
   int64_t M, N, Kd;
@@ -28,12 +28,18 @@ struct GemmArgs {
   const int64_t* kdim_dev;
 };
 
-template <typename T>
+// BM x BN tile per workgroup, 4 x 4 outputs per thread (rows ty + TY i,
+// columns tx + TX j with TY = BM / 4, TX = BN / 4): 64 x 64 in general,
+// 128 x 32 for products with at most 32 columns (the range-finder sketches)
+// so that no thread computes columns past the end.
+template <typename T, int BM, int BN>
 __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
+  constexpr int TY = BM / 4, TX = BN / 4;
+  static_assert(TY * TX == NT, "4 x 4 outputs per thread");
   __shared__ T As_re[BK][BM + 1], As_im[BK][BM + 1];
   __shared__ T Bs_re[BK][BN + 1], Bs_im[BK][BN + 1];
   const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
+  const int tx = tid % TX, ty = tid / TX;
   const int64_t k = blockIdx.z;
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   const bool real = (k == 0) || (g.real_last && k == g.K - 1);
@@ -53,10 +59,13 @@ __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) cr[i][j] = ci[i][j] = T(0);
 
-  for (int64_t k0 = 0; k0 < Kd; k0 += BK) {
-    // op(A) tile: BM x BK
+  // the next k step's tile values are loaded into registers while the
+  // current one is consumed from LDS
+  constexpr int RA = (BM * BK) / NT, RB = (BN * BK) / NT;
+  T ra_r[RA], ra_i[RA], rb_r[RB], rb_i[RB];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < (BM * BK) / NT; ++r) {
+    for (int r = 0; r < RA; ++r) {
       int mm, kk;
       if (g.op_a == 0) {
         kk = tid % BK;
@@ -72,12 +81,11 @@ __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
         vr = are[off];
         if (!real) vi = g.op_a == 0 ? aim[off] : -aim[off];
       }
-      As_re[kk][mm] = vr;
-      As_im[kk][mm] = vi;
+      ra_r[r] = vr;
+      ra_i[r] = vi;
     }
-    // op(B) tile: BK x BN
 #pragma unroll
-    for (int r = 0; r < (BN * BK) / NT; ++r) {
+    for (int r = 0; r < RB; ++r) {
       int nn, kk;
       if (g.op_b == 0) {
         nn = tid % BN;
@@ -93,18 +101,52 @@ __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
         vr = bre[off];
         if (!real) vi = g.op_b == 0 ? bim[off] : -bim[off];
       }
-      Bs_re[kk][nn] = vr;
-      Bs_im[kk][nn] = vi;
+      rb_r[r] = vr;
+      rb_i[r] = vi;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      int mm, kk;
+      if (g.op_a == 0) {
+        kk = tid % BK;
+        mm = tid / BK + r * (NT / BK);
+      } else {
+        mm = tid % BM;
+        kk = tid / BM + r * (NT / BM);
+      }
+      As_re[kk][mm] = ra_r[r];
+      As_im[kk][mm] = ra_i[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int nn, kk;
+      if (g.op_b == 0) {
+        nn = tid % BN;
+        kk = tid / BN + r * (NT / BN);
+      } else {
+        kk = tid % BK;
+        nn = tid / BK + r * (NT / BK);
+      }
+      Bs_re[kk][nn] = rb_r[r];
+      Bs_im[kk][nn] = rb_i[r];
+    }
+  };
+
+  if (Kd > 0) load(0);
+  for (int64_t k0 = 0; k0 < Kd; k0 += BK) {
+    store();
     __syncthreads();
+    if (k0 + BK < Kd) load(k0 + BK);
     if (real) {
 #pragma unroll
       for (int kk = 0; kk < BK; ++kk) {
         T a[4], b[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = As_re[kk][ty + 16 * i];
+        for (int i = 0; i < 4; ++i) a[i] = As_re[kk][ty + TY * i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = Bs_re[kk][tx + 16 * j];
+        for (int j = 0; j < 4; ++j) b[j] = Bs_re[kk][tx + TX * j];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -116,13 +158,13 @@ __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
         T ar[4], ai[4], br[4], bi[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          ar[i] = As_re[kk][ty + 16 * i];
-          ai[i] = As_im[kk][ty + 16 * i];
+          ar[i] = As_re[kk][ty + TY * i];
+          ai[i] = As_im[kk][ty + TY * i];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          br[j] = Bs_re[kk][tx + 16 * j];
-          bi[j] = Bs_im[kk][tx + 16 * j];
+          br[j] = Bs_re[kk][tx + TX * j];
+          bi[j] = Bs_im[kk][tx + TX * j];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -139,11 +181,11 @@ __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
   T* cim = (T*)g.cim + k * g.sc;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t gm = m0 + ty + 16 * i;
+    const int64_t gm = m0 + ty + TY * i;
     if (gm >= g.M) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int64_t gn = n0 + tx + 16 * j;
+      const int64_t gn = n0 + tx + TX * j;
       if (gn >= g.N) continue;
       cre[gm * g.ldc + gn] = cr[i][j];
       cim[gm * g.ldc + gn] = real ? T(0) : ci[i][j];
@@ -163,11 +205,20 @@ int cgemm(const CGemm& p, int dtype, int prec, hipStream_t st) {
   GemmArgs g{p.M, p.N, p.Kd, p.are, p.aim, p.bre, p.bim, p.cre, p.cim, p.lda, p.ldb, p.ldc,
              p.sa, p.sb, p.sc, p.op_a, p.op_b, p.K, p.real_last ? 1 : 0, p.kdim_dev};
   if (p.K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
-  dim3 grid((unsigned)((p.N + BN - 1) / BN), (unsigned)((p.M + BM - 1) / BM), (unsigned)p.K);
-  if (dtype == TP_F64)
-    hipLaunchKernelGGL(cgemm_simt_kernel<double>, grid, dim3(NT), 0, st, g);
-  else
-    hipLaunchKernelGGL(cgemm_simt_kernel<float>, grid, dim3(NT), 0, st, g);
+  const bool narrow = p.N <= 32;
+  const int64_t bm = narrow ? 128 : 64, bn = narrow ? 32 : 64;
+  dim3 grid((unsigned)((p.N + bn - 1) / bn), (unsigned)((p.M + bm - 1) / bm), (unsigned)p.K);
+  if (dtype == TP_F64) {
+    if (narrow)
+      hipLaunchKernelGGL((cgemm_simt_kernel<double, 128, 32>), grid, dim3(NT), 0, st, g);
+    else
+      hipLaunchKernelGGL((cgemm_simt_kernel<double, 64, 64>), grid, dim3(NT), 0, st, g);
+  } else {
+    if (narrow)
+      hipLaunchKernelGGL((cgemm_simt_kernel<float, 128, 32>), grid, dim3(NT), 0, st, g);
+    else
+      hipLaunchKernelGGL((cgemm_simt_kernel<float, 64, 64>), grid, dim3(NT), 0, st, g);
+  }
   TP_LAUNCH_CHECK();
   return TP_OK;
 }
