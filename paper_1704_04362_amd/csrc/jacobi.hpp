@@ -16,6 +16,9 @@
 // [[c, s], [-s, c]] with t = tan(theta) the smaller root of
 // t^2 + 2 tau t - 1 = 0, tau = (H_qq - H_pp) / (2 |h|) (the classical
 // symmetric Schur step of Golub and Van Loan, made Hermitian by the phase).
+// It is evaluated as t = sign(d) 2 |h| / (|d| + sqrt(d^2 + 4 |h|^2)),
+// d = H_qq - H_pp, c = 1 / sqrt(1 + t^2), s = t c, e^{i phi} = h / |h|:
+// two square roots side by side, one division and one reciprocal root.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,20 +31,22 @@ struct JacobiShared {
   double Hr[MAXN][MAXN + 1], Hi[MAXN][MAXN + 1];
   double Vr[MAXN][MAXN + 1], Vi[MAXN][MAXN + 1];
   double rc[MAXN / 2 + 1], rs[MAXN / 2 + 1], rpr[MAXN / 2 + 1], rpi[MAXN / 2 + 1];
-  int pp[MAXN / 2 + 1], qq[MAXN / 2 + 1];
   double red[2][NT / 64];
   int done;
 };
 
-// Pair t of round rho in the tournament over m (even) indices.
+// Pair t of round rho in the tournament over m (even) indices. rho < m - 1
+// and t < m / 2, so the residues mod m - 1 need one conditional subtraction.
 __device__ __forceinline__ void jacobi_pair(int m, int rho, int t, int& p, int& q) {
   int a, b;
   if (t == 0) {
     a = m - 1;
     b = rho;
   } else {
-    a = (rho + t) % (m - 1);
-    b = (rho + m - 1 - t) % (m - 1);
+    a = rho + t;
+    a = a >= m - 1 ? a - (m - 1) : a;
+    b = rho + m - 1 - t;
+    b = b >= m - 1 ? b - (m - 1) : b;
   }
   p = a < b ? a : b;
   q = a < b ? b : a;
@@ -56,9 +61,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Diagonalises the n x n Hermitian matrix in sh.H (n <= MAXN) in place,
 // accumulating the unitary in sh.V (initialised here to the identity).
 // Stops when the off-diagonal mass is below rel_tol^2 of the total or after
-// max_sweeps sweeps. All NT threads of the workgroup must call it.
+// max_sweeps sweeps, and returns the number of sweeps made. All NT threads
+// of the workgroup must call it.
 template <int MAXN, int NT>
-__device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps, double rel_tol) {
+__device__ int jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps, double rel_tol) {
   const int tid = threadIdx.x;
   const int ne = n * n;
   for (int e = tid; e < ne; e += NT) {
@@ -85,7 +91,8 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
   const int npairs = m / 2;
   const int nblk = npairs * npairs;
   const double tol2 = rel_tol * rel_tol;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
     {
       double off = 0.0, tot = 0.0;
       for (int e = tid; e < ne; e += NT) {
@@ -120,19 +127,23 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
         double c = 1.0, sn = 0.0, pr = 1.0, pi = 0.0;
         if (q < n) {
           const double hr = sh.Hr[p][q], hi = sh.Hi[p][q];
-          const double habs = sqrt(hr * hr + hi * hi);
-          const double diag = fabs(sh.Hr[p][p]) + fabs(sh.Hr[q][q]);
-          if (habs > 1e-300 && habs > 1e-18 * diag) {
-            const double tau = (sh.Hr[q][q] - sh.Hr[p][p]) / (2.0 * habs);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-            pr = hr / habs;
-            pi = hi / habs;
+          const double hpp = sh.Hr[p][p], hqq = sh.Hr[q][q];
+          const double h2 = hr * hr + hi * hi;
+          const double d = hqq - hpp;
+          const double ih = rsqrt(h2);
+          const double root = sqrt(d * d + 4.0 * h2);
+          const double habs = h2 * ih;
+          const double t = (d >= 0.0 ? 2.0 : -2.0) * habs / (fabs(d) + root);
+          const double ct = rsqrt(1.0 + t * t);
+          // rotate only entries that are not negligible (also rules out
+          // the infinities of an underflowed h2)
+          if (h2 > 1e-300 && habs > 1e-18 * (fabs(hpp) + fabs(hqq))) {
+            c = ct;
+            sn = t * ct;
+            pr = hr * ih;
+            pi = hi * ih;
           }
         }
-        sh.pp[tid] = p;
-        sh.qq[tid] = q;
         sh.rc[tid] = c;
         sh.rs[tid] = sn;
         sh.rpr[tid] = pr;
@@ -147,7 +158,9 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
       for (int e = tid; e < nblk + n * npairs; e += NT) {
         if (e < nblk) {
           const int u = e / npairs, v = e - u * npairs;
-          const int p0 = sh.pp[u], q0 = sh.qq[u], p1 = sh.pp[v], q1 = sh.qq[v];
+          int p0, q0, p1, q1;
+          jacobi_pair(m, rho, u, p0, q0);
+          jacobi_pair(m, rho, v, p1, q1);
           const bool r2 = q0 < n, c2 = q1 < n;
           if (!r2 && !c2) continue;  // 1 x 1 block of two idle indices
           double ar = sh.Hr[p0][p1], ai = sh.Hi[p0][p1];               // (p0, p1)
@@ -197,7 +210,8 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
         } else {
           const int f = e - nblk;
           const int v = f / n, i = f - v * n;
-          const int p = sh.pp[v], q = sh.qq[v];
+          int p, q;
+          jacobi_pair(m, rho, v, p, q);
           if (q >= n) continue;
           const double c = sh.rc[v], s = sh.rs[v], er = sh.rpr[v], ei = -sh.rpi[v];
           const double xr = sh.Vr[i][p], xi = sh.Vi[i][p], yr = sh.Vr[i][q], yi = sh.Vi[i][q];
@@ -211,6 +225,7 @@ __device__ void jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps
       __syncthreads();
     }
   }
+  return sweep;
 }
 
 }  // namespace tp

@@ -74,14 +74,16 @@ __global__ void randn_kernel(T* re, T* im, int64_t K, int64_t per_slice, int rea
 // grid covers 16 BR x 16 BC >= a x b), so each row costs it BR + BC complex
 // LDS reads for BR BC complex multiply-adds. The Gram matrix X^H X is the
 // case Y = X.
-template <typename T, int BR, int BC>
+template <typename T, int BR, int BC, bool SAME>
 __global__ __launch_bounds__(256) void xgram_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int a,
                                                     int64_t ldx, int64_t sx, const T* __restrict__ yre,
                                                     const T* __restrict__ yim, int b, int64_t ldy, int64_t sy,
                                                     int64_t K, int64_t rows, int real_last, int64_t rch,
                                                     double* __restrict__ pre, double* __restrict__ pim) {
-  constexpr int CH = 32;
-  __shared__ double xr_[CH][kMaxS], xi_[CH][kMaxS], yr_[CH][kMaxS], yi_[CH][kMaxS];
+  // staged widths: 16 BR columns of X and 16 BC of Y; Y is not staged again when it is X
+  static_assert(!SAME || BR == BC, "a Gram matrix is square");
+  constexpr int CH = 32, WA = 16 * BR, WB = SAME ? 1 : 16 * BC;
+  __shared__ double xr_[CH][WA], xi_[CH][WA], yr_[CH][WB], yi_[CH][WB];
   const int64_t k = blockIdx.x;
   const int64_t nch = gridDim.y;
   const bool real = k == 0 || (real_last && k == K - 1);
@@ -100,14 +102,21 @@ __global__ __launch_bounds__(256) void xgram_kernel(const T* __restrict__ xre, c
 #pragma unroll
     for (int v = 0; v < BC; ++v) cr[u][v] = ci[u][v] = 0.0;
   for (int64_t r0 = rbeg; r0 < rend; r0 += CH) {
-    for (int e = tid; e < CH * kMaxS; e += 256) {
-      const int rr = e / kMaxS, c = e - rr * kMaxS;
+    for (int e = tid; e < CH * WA; e += 256) {
+      const int rr = e / WA, c = e - rr * WA;
       const int64_t row = r0 + rr;
       const bool live = row < rend;
       xr_[rr][c] = (live && c < a) ? (double)xr[row * ldx + c] : 0.0;
       xi_[rr][c] = (live && c < a && !real) ? (double)xi[row * ldx + c] : 0.0;
-      yr_[rr][c] = (live && c < b) ? (double)yr[row * ldy + c] : 0.0;
-      yi_[rr][c] = (live && c < b && !real) ? (double)yi[row * ldy + c] : 0.0;
+    }
+    if constexpr (!SAME) {
+      for (int e = tid; e < CH * WB; e += 256) {
+        const int rr = e / WB, c = e - rr * WB;
+        const int64_t row = r0 + rr;
+        const bool live = row < rend;
+        yr_[rr][c] = (live && c < b) ? (double)yr[row * ldy + c] : 0.0;
+        yi_[rr][c] = (live && c < b && !real) ? (double)yi[row * ldy + c] : 0.0;
+      }
     }
     __syncthreads();
     if (act) {
@@ -121,8 +130,8 @@ __global__ __launch_bounds__(256) void xgram_kernel(const T* __restrict__ xre, c
         }
 #pragma unroll
         for (int v = 0; v < BC; ++v) {
-          qr[v] = yr_[rr][j0 + v];
-          qi[v] = yi_[rr][j0 + v];
+          qr[v] = SAME ? xr_[rr][j0 + v] : yr_[rr][j0 + v];
+          qi[v] = SAME ? xi_[rr][j0 + v] : yi_[rr][j0 + v];
         }
 #pragma unroll
         for (int u = 0; u < BR; ++u)
@@ -212,11 +221,21 @@ __global__ __launch_bounds__(NT) void herm_eig_kernel(const double* __restrict__
 // kept indices (zero rows and columns elsewhere), so that X T has
 // orthonormal columns on the kept indices and zero columns on the dropped
 // ones. One workgroup per slice; T is s x s, row-major.
+//
+// Each of the 1024 threads keeps MAXN^2 / 1024 entries of the padded
+// MAXN x MAXN upper triangle in registers. Step j publishes row j (already
+// updated by steps < j) to LDS; after one barrier every thread applies
+// G_lm -= conj(G_jl) G_jm / G_jj to its entries below row j. Row j is
+// never written again, so a step needs no second barrier.
+constexpr int kCholNT = 1024;
+
 template <int MAXN, typename T>
-__global__ __launch_bounds__(128) void chol_inv_kernel(const double* __restrict__ gre,
-                                                       const double* __restrict__ gim, int64_t K, int s,
-                                                       double rtol, int real_last, T* __restrict__ tre,
-                                                       T* __restrict__ tim) {
+__global__ __launch_bounds__(kCholNT) void chol_inv_kernel(const double* __restrict__ gre,
+                                                           const double* __restrict__ gim, int64_t K, int s,
+                                                           double rtol, int real_last, T* __restrict__ tre,
+                                                           T* __restrict__ tim) {
+  constexpr int NT = kCholNT, PER = MAXN * MAXN / NT;
+  static_assert(PER >= 1 && PER * NT == MAXN * MAXN, "one or more whole entries per thread");
   __shared__ double Gr[MAXN][MAXN + 1], Gi[MAXN][MAXN + 1];
   __shared__ double Tr[MAXN][MAXN + 1], Ti[MAXN][MAXN + 1];
   __shared__ double rd[MAXN];
@@ -225,83 +244,92 @@ __global__ __launch_bounds__(128) void chol_inv_kernel(const double* __restrict_
   const bool real = k == 0 || (real_last && k == K - 1);
   const int tid = threadIdx.x;
   const int ne = s * s;
-  for (int e = tid; e < ne; e += 128) {
-    const int i = e / s, j = e - i * s;
-    Gr[i][j] = gre[k * ne + e];
-    Gi[i][j] = real ? 0.0 : gim[k * ne + e];
+  int ri[PER], ci[PER];
+  double gr[PER], gi[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + NT * u;
+    ri[u] = e / MAXN;
+    ci[u] = e % MAXN;
+    const bool in = ri[u] < s && ci[u] < s && ci[u] >= ri[u];
+    gr[u] = in ? gre[k * ne + ri[u] * s + ci[u]] : 0.0;
+    gi[u] = (in && !real && ci[u] > ri[u]) ? gim[k * ne + ri[u] * s + ci[u]] : 0.0;
   }
-  __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < s; ++i) m = fmax(m, Gr[i][i]);
-    dmax = m;
+  if (tid < 64) {
+    double m = tid < s ? gre[k * ne + tid * s + tid] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (tid == 0) dmax = m;
   }
   __syncthreads();
   const double tol = rtol * dmax;
   for (int j = 0; j < s; ++j) {
-    const double d = Gr[j][j];
-    const bool keep = d > tol && d > 0.0;
-    const double inv = keep ? 1.0 / sqrt(d) : 0.0;
-    for (int l = j + 1 + tid; l < s; l += 128) {
-      Gr[j][l] *= inv;
-      Gi[j][l] *= inv;
-    }
-    if (tid == 0) rd[j] = keep ? sqrt(d) : 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (ri[u] == j && ci[u] >= j && ci[u] < s) {
+        Gr[j][ci[u]] = gr[u];
+        Gi[j][ci[u]] = gi[u];
+      }
     __syncthreads();
-    if (keep) {
-      // trailing upper triangle: G_lm -= conj(R_jl) R_jm, j < l <= m
-      const int w = s - j - 1;
-      for (int e = tid; e < w * w; e += 128) {
-        const int l = j + 1 + e / w, m = j + 1 + e % w;
-        if (m < l) continue;
-        const double ar = Gr[j][l], ai = Gi[j][l], br = Gr[j][m], bi = Gi[j][m];
-        Gr[l][m] -= ar * br + ai * bi;
-        Gi[l][m] -= ar * bi - ai * br;
+    const double d = Gr[j][j];
+    if (d > tol && d > 0.0) {
+      const double inv = 1.0 / d;
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int l = ri[u], m = ci[u];
+        if (l > j && m >= l && m < s) {
+          const double ar = Gr[j][l], ai = Gi[j][l], br = Gr[j][m], bi = Gi[j][m];
+          gr[u] -= (ar * br + ai * bi) * inv;
+          gi[u] -= (ar * bi - ai * br) * inv;
+        }
       }
     }
-    __syncthreads();
   }
+  // pivots: the published diagonal is the value each step tested
+  if (tid < MAXN) {
+    const double d = tid < s ? Gr[tid][tid] : 0.0;
+    rd[tid] = (tid < s && d > tol && d > 0.0) ? sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  // R (strict upper triangle, zero on dropped rows and past s) and T = diag(1 / R_ii)
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = ri[u], j = ci[u];
+    if (j > i) {
+      const bool live = i < s && j < s && rd[i] > 0.0;
+      Gr[i][j] = live ? gr[u] / rd[i] : 0.0;
+      Gi[i][j] = live ? gi[u] / rd[i] : 0.0;
+    }
+    Tr[i][j] = (i == j && rd[i] > 0.0) ? 1.0 / rd[i] : 0.0;
+    Ti[i][j] = 0.0;
+  }
+  __syncthreads();
   // T = R^{-1} on the kept indices by recursive doubling over diagonal
-  // blocks of the padded MAXN x MAXN factor (R = 0 past s): with T11, T22 the
-  // inverses of two adjacent b x b diagonal blocks, the block above T22 is
+  // blocks of the padded MAXN x MAXN factor: with T11, T22 the inverses of
+  // two adjacent b x b diagonal blocks, the block above T22 is
   // T12 = -T11 (R12 T22). W = R12 T22 is kept in the (unused) lower triangle
   // of G at the transposed position. A dropped index has R_ii = 0 and a zero
   // row, and gets a zero row and column of T.
-  for (int e = tid; e < MAXN * MAXN; e += 128) {
-    const int i = e / MAXN, j = e - i * MAXN;
-    Tr[i][j] = (i == j && i < s && rd[i] > 0.0) ? 1.0 / rd[i] : 0.0;
-    Ti[i][j] = 0.0;
-    if (i >= s || j >= s) {
-      if (j > i) {
-        Gr[i][j] = 0.0;
-        Gi[i][j] = 0.0;
-      }
-    } else if (j > i && rd[i] == 0.0) {
-      Gr[i][j] = 0.0;
-      Gi[i][j] = 0.0;
-    }
-  }
-  __syncthreads();
   for (int b = 1; b < MAXN; b *= 2) {
     const int nw = (MAXN / (2 * b)) * b * b;
-    // W = R12 T22 (b x b per pair), stored at G[a1 + x][a0 + y]
-    for (int e = tid; e < nw; e += 128) {
+    // W = R12 T22 (b x b per pair), stored at G[a1 + y][a0 + x]
+    for (int e = tid; e < nw; e += NT) {
       const int p = e / (b * b), rem = e - p * b * b;
       const int x = rem / b, y = rem - x * b;  // W row x (block row a0 + x), column y (a1 + y)
       const int a0 = 2 * p * b, a1 = a0 + b;
       double wr = 0.0, wi = 0.0;
       for (int t = 0; t < b; ++t) {
-        const double rr = Gr[a0 + x][a1 + t], ri = Gi[a0 + x][a1 + t];
+        const double rr = Gr[a0 + x][a1 + t], rim = Gi[a0 + x][a1 + t];
         const double tr = Tr[a1 + t][a1 + y], ti = Ti[a1 + t][a1 + y];
-        wr += rr * tr - ri * ti;
-        wi += rr * ti + ri * tr;
+        wr += rr * tr - rim * ti;
+        wi += rr * ti + rim * tr;
       }
       Gr[a1 + y][a0 + x] = wr;
       Gi[a1 + y][a0 + x] = wi;
     }
     __syncthreads();
     // T12 = -T11 W
-    for (int e = tid; e < nw; e += 128) {
+    for (int e = tid; e < nw; e += NT) {
       const int p = e / (b * b), rem = e - p * b * b;
       const int x = rem / b, y = rem - x * b;
       const int a0 = 2 * p * b, a1 = a0 + b;
@@ -317,8 +345,7 @@ __global__ __launch_bounds__(128) void chol_inv_kernel(const double* __restrict_
     }
     __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < ne; e += 128) {
+  for (int e = tid; e < ne; e += NT) {
     const int i = e / s, j = e - i * s;
     tre[k * ne + e] = (T)Tr[i][j];
     tim[k * ne + e] = (T)(real ? 0.0 : Ti[i][j]);
@@ -460,21 +487,30 @@ int64_t gram_chunks(int64_t rows) {
 size_t gram_part_doubles(int64_t K, int64_t rows, int s) { return (size_t)(K * gram_chunks(rows) * s * s); }
 
 // launches the blocked cross product with the smallest blocks that cover a x b
-template <typename T>
+template <typename T, bool SAME>
 void launch_xgram(dim3 grid, hipStream_t st, const T* xre, const T* xim, int a, int64_t ldx, int64_t sx,
                   const T* yre, const T* yim, int b, int64_t ldy, int64_t sy, int64_t K, int64_t rows, int rl,
                   int64_t rch, double* pre, double* pim) {
+  if constexpr (SAME) {
+    if (a <= 32)
+      hipLaunchKernelGGL((xgram_kernel<T, 2, 2, true>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy,
+                         sy, K, rows, rl, rch, pre, pim);
+    else
+      hipLaunchKernelGGL((xgram_kernel<T, 4, 4, true>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy,
+                         sy, K, rows, rl, rch, pre, pim);
+    return;
+  }
   if (a <= 32 && b <= 32)
-    hipLaunchKernelGGL((xgram_kernel<T, 2, 2>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+    hipLaunchKernelGGL((xgram_kernel<T, 2, 2, SAME>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
                        rows, rl, rch, pre, pim);
   else if (b <= 32)
-    hipLaunchKernelGGL((xgram_kernel<T, 4, 2>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+    hipLaunchKernelGGL((xgram_kernel<T, 4, 2, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
                        rows, rl, rch, pre, pim);
   else if (a <= 32)
-    hipLaunchKernelGGL((xgram_kernel<T, 2, 4>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+    hipLaunchKernelGGL((xgram_kernel<T, 2, 4, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
                        rows, rl, rch, pre, pim);
   else
-    hipLaunchKernelGGL((xgram_kernel<T, 4, 4>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
+    hipLaunchKernelGGL((xgram_kernel<T, 4, 4, SAME>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
                        rows, rl, rch, pre, pim);
 }
 
@@ -494,11 +530,11 @@ int xgram(const void* xre, const void* xim, int a, int64_t ldx, int64_t sx, cons
   const dim3 grid((unsigned)K, (unsigned)nch);
   const int rl = real_last ? 1 : 0;
   if (dtype == TP_F64)
-    launch_xgram<double>(grid, st, (const double*)xre, (const double*)xim, a, ldx, sx, (const double*)yre,
-                         (const double*)yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
+    launch_xgram<double, false>(grid, st, (const double*)xre, (const double*)xim, a, ldx, sx, (const double*)yre,
+                                (const double*)yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
   else
-    launch_xgram<float>(grid, st, (const float*)xre, (const float*)xim, a, ldx, sx, (const float*)yre,
-                        (const float*)yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
+    launch_xgram<float, false>(grid, st, (const float*)xre, (const float*)xim, a, ldx, sx, (const float*)yre,
+                               (const float*)yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
   TP_LAUNCH_CHECK();
   const int ne = a * b;
   if (dtype == TP_F64)
@@ -522,11 +558,11 @@ int gram(const void* xre, const void* xim, int dtype, int64_t K, int64_t rows, i
   const dim3 grid((unsigned)K, (unsigned)nch);
   const int rl = real_last ? 1 : 0;
   if (dtype == TP_F64)
-    launch_xgram<double>(grid, st, (const double*)xre, (const double*)xim, s, ldx, sx, (const double*)xre,
-                         (const double*)xim, s, ldx, sx, K, rows, rl, rch, pre, pim);
+    launch_xgram<double, true>(grid, st, (const double*)xre, (const double*)xim, s, ldx, sx, (const double*)xre,
+                               (const double*)xim, s, ldx, sx, K, rows, rl, rch, pre, pim);
   else
-    launch_xgram<float>(grid, st, (const float*)xre, (const float*)xim, s, ldx, sx, (const float*)xre,
-                        (const float*)xim, s, ldx, sx, K, rows, rl, rch, pre, pim);
+    launch_xgram<float, true>(grid, st, (const float*)xre, (const float*)xim, s, ldx, sx, (const float*)xre,
+                              (const float*)xim, s, ldx, sx, K, rows, rl, rch, pre, pim);
   TP_LAUNCH_CHECK();
   const int ne = s * s;
   hipLaunchKernelGGL(xgram_reduce_kernel<double>, dim3(blocks_for(K * ne)), dim3(256), 0, st, pre, pim, K, nch, ne,
@@ -543,7 +579,7 @@ int herm_eig(const double* gre, const double* gim, int64_t K, int s, double* eva
     hipLaunchKernelGGL((herm_eig_kernel<32, 1024>), dim3((unsigned)K), dim3(1024), 0, st, gre, gim, s, 40, evals,
                        vre, vim);
   else
-    hipLaunchKernelGGL((herm_eig_kernel<kMaxS, 256>), dim3((unsigned)K), dim3(256), 0, st, gre, gim, s, 40, evals,
+    hipLaunchKernelGGL((herm_eig_kernel<kMaxS, 1024>), dim3((unsigned)K), dim3(1024), 0, st, gre, gim, s, 40, evals,
                        vre, vim);
   TP_LAUNCH_CHECK();
   return TP_OK;
@@ -554,7 +590,7 @@ int chol_inv(const double* gre, const double* gim, int64_t K, int s, double rtol
   if (s < 1 || s > kMaxS) return fail(TP_EUNSUPPORTED, "Cholesky size outside 1..64");
   if (K == 0) return TP_OK;
   const int rl = real_last ? 1 : 0;
-  const dim3 g((unsigned)K), b(128);
+  const dim3 g((unsigned)K), b(kCholNT);
   if (out_dtype == TP_F64) {
     if (s <= 32)
       hipLaunchKernelGGL((chol_inv_kernel<32, double>), g, b, 0, st, gre, gim, K, s, rtol, rl, (double*)tre,
