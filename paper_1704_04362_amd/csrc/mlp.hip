@@ -109,34 +109,127 @@ __global__ __launch_bounds__(SNT) void sketch_mfma_kernel(const float* __restric
   if (g == 0 && jok) out[j * (DS + 1) + DS] = nrm;
 }
 
-// Per block of SJ lateral slices: the float64 sums over the row chunks
+// The same contraction for tubes of at most 16 NKB entries with every load
+// of a horizontal slice issued at once: lane (g, r) holds the NKB float4
+// pieces 4 g + 16 b (b < NKB) of its tube, and the next slice's pieces and
+// its share of the next Phi_i are fetched into registers before the
+// current slice's matrix-core steps, so that HBM latency overlaps the
+// arithmetic. Phi_i is staged transposed in two LDS buffers (one barrier
+// per slice).
+template <int NKB>
+__global__ __launch_bounds__(SNT) void sketch_mfma_pipe_kernel(const float* __restrict__ a,
+                                                                const float* __restrict__ phi, int64_t n1,
+                                                                int64_t n2, int64_t n3, float* __restrict__ partial) {
+  constexpr int LDK = 16 * NKB + 4;
+  constexpr int PH = 16 * NKB * DS / SNT;  // Phi_i entries per thread (padded tube)
+  static_assert(PH * SNT == 16 * NKB * DS, "whole Phi_i per workgroup");
+  __shared__ __align__(16) float phs[2][DS][LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t j0 = (int64_t)blockIdx.x * SJ;
+  const int64_t i0 = (int64_t)blockIdx.y * SIR;
+  const int64_t rows = (n1 - i0) < SIR ? (n1 - i0) : SIR;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t j = j0 + wave * 16 + r;
+  const bool jok = j < n2;
+  auto load_a = [&](int64_t i, float4 (&x)[NKB]) {
+    const float* arow = a + (i * n2 + (jok ? j : 0)) * n3;
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) {
+      const int64_t k = 16 * b + 4 * g;
+      x[b] = (jok && k < n3) ? *reinterpret_cast<const float4*>(arow + k) : float4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  // thread's Phi entries: e = tid + SNT u of the padded (16 NKB) x DS block
+  auto load_phi = [&](int64_t i, float (&v)[PH]) {
+    const float* src = phi + i * n3 * DS;
+#pragma unroll
+    for (int u = 0; u < PH; ++u) {
+      const int e = tid + SNT * u;
+      v[u] = (e / DS) < n3 ? src[e] : 0.f;
+    }
+  };
+  float4 xc[NKB], xn[NKB];
+  float pv[PH];
+  load_a(i0, xc);
+  load_phi(i0, pv);
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  float nrm = 0.f;
+  for (int64_t ii = 0; ii < rows; ++ii) {
+    float(*buf)[LDK] = phs[ii & 1];
+#pragma unroll
+    for (int u = 0; u < PH; ++u) {
+      const int e = tid + SNT * u;
+      buf[e % DS][e / DS] = pv[u];
+    }
+    if (ii + 1 < rows) {
+      load_a(i0 + ii + 1, xn);
+      load_phi(i0 + ii + 1, pv);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) {
+      const float4 x = xc[b];
+      const float4 p = *reinterpret_cast<const float4*>(&buf[r][16 * b + 4 * g]);
+      nrm += x.x * x.x + x.y * x.y + x.z * x.z + x.w * x.w;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, p.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, p.y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, p.z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, p.w, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) xc[b] = xn[b];
+  }
+  float* out = partial + ((int64_t)blockIdx.y * n2) * (DS + 1);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t jj = j0 + wave * 16 + 4 * g + v;
+    if (jj < n2) out[jj * (DS + 1) + r] = acc[v];
+  }
+  nrm += __shfl_xor(nrm, 16);
+  nrm += __shfl_xor(nrm, 32);
+  if (g == 0 && jok) out[j * (DS + 1) + DS] = nrm;
+}
+
+// Per block of SJS lateral slices: the float64 sums over the row chunks
 // (sk[j][0..DS] = sketch and squared norm), and the block's share of the
 // Gram matrix G = sum_j s_j s_j^T and of sum_j a_j (gpart[blk][0..DS*DS]).
+constexpr int SJS = 16;
 __global__ __launch_bounds__(256) void sketch_sum_kernel(const float* __restrict__ partial, int64_t nch, int64_t n2,
                                                           double* __restrict__ sk, double* __restrict__ gpart) {
-  __shared__ double s[SJ][DS + 1];
+  __shared__ double s[SJS][DS + 1];
   const int tid = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * SJ;
-  for (int e = tid; e < SJ * (DS + 1); e += 256) {
-    const int t = e / (DS + 1), d = e - t * (DS + 1);
-    const int64_t j = j0 + t;
+  const int64_t j0 = (int64_t)blockIdx.x * SJS;
+  const int64_t nj = (n2 - j0) < SJS ? (n2 - j0) : SJS;
+  // entries e of the block's (nj x (DS + 1)) run are contiguous in every chunk
+  for (int e = tid; e < SJS * (DS + 1); e += 256) {
+    const int t = e / (DS + 1);
     double v = 0.0;
-    if (j < n2) {
-      for (int64_t y = 0; y < nch; ++y) v += (double)partial[(y * n2 + j) * (DS + 1) + d];
-      sk[j * (DS + 1) + d] = v;
+    if (t < nj) {
+      const float* src = partial + j0 * (DS + 1) + e;
+      const int64_t stride = n2 * (DS + 1);
+      int64_t y = 0;
+      for (; y + 8 <= nch; y += 8) {
+        float f[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) f[u] = src[(y + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += (double)f[u];
+      }
+      for (; y < nch; ++y) v += (double)src[y * stride];
+      sk[j0 * (DS + 1) + e] = v;
     }
-    s[t][d] = v;
+    s[t][e - t * (DS + 1)] = v;
   }
   __syncthreads();
   {
     const int p = tid / DS, q = tid % DS;
     double gsum = 0.0;
-    for (int t = 0; t < SJ; ++t) gsum += s[t][p] * s[t][q];
+    for (int t = 0; t < SJS; ++t) gsum += s[t][p] * s[t][q];
     gpart[blockIdx.x * (DS * DS + 1) + tid] = gsum;
   }
   if (tid == 0) {
     double at = 0.0;
-    for (int t = 0; t < SJ; ++t) at += s[t][DS];
+    for (int t = 0; t < SJS; ++t) at += s[t][DS];
     gpart[blockIdx.x * (DS * DS + 1) + DS * DS] = at;
   }
 }
@@ -476,9 +569,9 @@ unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 }  // namespace
 
 size_t mlp_features_ws(int64_t n1, int64_t n2) {
-  const int64_t nch = (n1 + SIR - 1) / SIR, nb = (n2 + SJ - 1) / SJ;
+  const int64_t nch = (n1 + SIR - 1) / SIR, nbs = (n2 + SJS - 1) / SJS;
   return align_up(size_t(nch) * n2 * (DS + 1) * 4) + align_up(size_t(n2) * (DS + 1) * 8) +
-         align_up(size_t(nb) * (DS * DS + 1) * 8) + align_up(size_t(DS * DS + 1) * 8) + 1024;
+         align_up(size_t(nbs) * (DS * DS + 1) * 8) + align_up(size_t(DS * DS + 1) * 8) + 1024;
 }
 
 int mlp_features(const float* a, int64_t n1, int64_t n2, int64_t n3, const float* phi, float* feat, void* ws,
@@ -488,20 +581,27 @@ int mlp_features(const float* a, int64_t n1, int64_t n2, int64_t n3, const float
   if (lds > 64 * 1024) return fail(TP_EUNSUPPORTED, "tube length too large for feature extraction");
   if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(phi)) % 16)
     return fail(TP_EINVAL, "A and phi must be 16-byte aligned");
-  const int64_t nch = (n1 + SIR - 1) / SIR, nb = (n2 + SJ - 1) / SJ;
+  const int64_t nch = (n1 + SIR - 1) / SIR, nb = (n2 + SJ - 1) / SJ, nbs = (n2 + SJS - 1) / SJS;
   if (nch > 65535) return fail(TP_EUNSUPPORTED, "too many horizontal slices");
   Arena ar(ws, mlp_features_ws(n1, n2));
   float* part = ar.take<float>(nch * n2 * (DS + 1));
   double* sk = ar.take<double>(n2 * (DS + 1));
-  double* gpart = ar.take<double>(nb * (DS * DS + 1));
+  double* gpart = ar.take<double>(nbs * (DS * DS + 1));
   double* wt = ar.take<double>(DS * DS + 1);
   if (!ar.ok()) return fail(TP_EWORKSPACE, "feature workspace too small");
-  hipLaunchKernelGGL(sketch_mfma_kernel, dim3((unsigned)nb, (unsigned)nch), dim3(SNT), lds, st, a, phi, n1, n2, n3,
-                     part);
+  const dim3 grid((unsigned)nb, (unsigned)nch);
+  if (n3 <= 32)
+    hipLaunchKernelGGL(sketch_mfma_pipe_kernel<2>, grid, dim3(SNT), 0, st, a, phi, n1, n2, n3, part);
+  else if (n3 <= 64)
+    hipLaunchKernelGGL(sketch_mfma_pipe_kernel<4>, grid, dim3(SNT), 0, st, a, phi, n1, n2, n3, part);
+  else if (n3 <= 128)
+    hipLaunchKernelGGL(sketch_mfma_pipe_kernel<8>, grid, dim3(SNT), 0, st, a, phi, n1, n2, n3, part);
+  else
+    hipLaunchKernelGGL(sketch_mfma_kernel, grid, dim3(SNT), lds, st, a, phi, n1, n2, n3, part);
   TP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sketch_sum_kernel, dim3((unsigned)nb), dim3(256), 0, st, part, nch, n2, sk, gpart);
+  hipLaunchKernelGGL(sketch_sum_kernel, dim3((unsigned)nbs), dim3(256), 0, st, part, nch, n2, sk, gpart);
   TP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sketch_whiten_kernel, dim3(1), dim3(256), 0, st, gpart, nb, n2, wt);
+  hipLaunchKernelGGL(sketch_whiten_kernel, dim3(1), dim3(256), 0, st, gpart, nbs, n2, wt);
   TP_LAUNCH_CHECK();
   hipLaunchKernelGGL(sketch_apply_kernel, dim3(nblk(n2 * DIN)), dim3(256), 0, st, sk, wt, n2, feat, norms);
   TP_LAUNCH_CHECK();
