@@ -12,6 +12,8 @@
 
 namespace tp {
 int cgemm_mfma(const CGemm& p, int prec, hipStream_t st, bool* handled);
+int cgemm_short(const CGemm& p, int split, hipStream_t st, bool* handled);
+int cgemm_tall(const CGemm& p, int split, hipStream_t st, bool* handled);
 
 namespace {
 
@@ -197,6 +199,16 @@ __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
 
 int cgemm(const CGemm& p, int dtype, int prec, hipStream_t st) {
   if (p.K == 0 || p.M == 0 || p.N == 0) return TP_OK;
+  if (dtype == TP_F32 && (prec == TP_PREC_F32 || prec == TP_PREC_BF16X3)) {
+    const int split = prec == TP_PREC_BF16X3 ? 1 : 0;
+    bool handled = false;
+    // narrow results with a long contraction (range-finder products)
+    if (int rc = cgemm_tall(p, split, st, &handled)) return rc;
+    if (handled) return TP_OK;
+    // short contractions: output-bound kernel on the matrix cores
+    if (int rc = cgemm_short(p, split, st, &handled)) return rc;
+    if (handled) return TP_OK;
+  }
   if (dtype == TP_F32 && prec != TP_PREC_F64) {
     bool handled = false;
     if (int rc = cgemm_mfma(p, prec, st, &handled)) return rc;

@@ -129,7 +129,8 @@ def test_tprod_exact_workload_f64():
     assert rel(Cg, T.tprod_bcirc(A, B)) < 1e-12
 
 
-@pytest.mark.parametrize("shape", [(96, 130, 70, 64), (65, 64, 63, 128), (40, 50, 30, 100), (30, 20, 10, 9)])
+@pytest.mark.parametrize("shape", [(96, 130, 70, 64), (65, 64, 63, 128), (40, 50, 30, 100), (30, 20, 10, 9),
+                                   (96, 20, 130, 16), (70, 7, 80, 9)])
 def test_tprod_f32_matches_bcirc(shape):
     n1, n2, n4, n3 = shape
     rs = np.random.default_rng(sum(shape) + 1)
@@ -236,6 +237,64 @@ def test_rtprod_bad_weights_give_zero():
     picks = api.tsample("user", 2, mode="iid", w=dev(np.zeros(3)))
     Z = api.tprod(dev(A), dev(B), picks=picks, prec="f64")
     assert not Z.any()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("K,M,N,Kd", [(5, 64, 64, 1), (4, 96, 130, 20), (3, 200, 257, 33), (2, 65, 128, 64),
+                                      (65, 128, 256, 8)])
+@pytest.mark.parametrize("real_last", [True, False])
+def test_spectrum_matmul_short_contraction(prec, K, M, N, Kd, real_last):
+    """Products with a contraction of at most 64 (the t-CUR reconstruction
+    shape) take the output-bound kernel: float32 matrix cores (float32
+    tolerance) or split bf16 (the split tolerance), ragged rows and columns,
+    and exactly real DC / Nyquist slices."""
+    rs = np.random.default_rng(M * N + Kd)
+    a = rs.standard_normal((K, M, Kd)) + 1j * rs.standard_normal((K, M, Kd))
+    b = rs.standard_normal((K, Kd, N)) + 1j * rs.standard_normal((K, Kd, N))
+    a = (a.real.astype(np.float32) + 1j * a.imag.astype(np.float32))
+    b = (b.real.astype(np.float32) + 1j * b.imag.astype(np.float32))
+    cre, cim = api.spectrum_matmul((dev(a.real), dev(a.imag)), (dev(b.real), dev(b.imag)), 0, 0, real_last, prec)
+    got = cre.cpu().numpy() + 1j * cim.cpu().numpy()
+    ref = _ref_matmul(a.astype(np.complex128), b.astype(np.complex128), 0, 0, real_last)
+    assert rel(got, ref) < (1e-6 if prec == "f32" else BF_TOL["bf16x3"])
+    assert not cim[0].any()
+    if real_last and K > 1:
+        assert not cim[-1].any()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("op_a", [0, 1])
+@pytest.mark.parametrize("K,M,N,Kd", [(5, 100, 32, 65), (3, 64, 1, 200), (4, 130, 33, 1000), (2, 32, 64, 97),
+                                      (65, 256, 24, 300)])
+def test_spectrum_matmul_tall(prec, op_a, K, M, N, Kd):
+    """Narrow results with a long contraction (the range-finder products,
+    A Omega and A^H Q): float32 or split matrix cores, ragged rows, columns
+    and 32-deep steps, exactly real DC / Nyquist slices."""
+    rs = np.random.default_rng(M + 7 * N + Kd + op_a)
+    ash = (K, Kd, M) if op_a else (K, M, Kd)
+    a = rs.standard_normal(ash) + 1j * rs.standard_normal(ash)
+    b = rs.standard_normal((K, Kd, N)) + 1j * rs.standard_normal((K, Kd, N))
+    a = (a.real.astype(np.float32) + 1j * a.imag.astype(np.float32))
+    b = (b.real.astype(np.float32) + 1j * b.imag.astype(np.float32))
+    cre, cim = api.spectrum_matmul((dev(a.real), dev(a.imag)), (dev(b.real), dev(b.imag)), op_a, 0, True, prec)
+    got = cre.cpu().numpy() + 1j * cim.cpu().numpy()
+    ref = _ref_matmul(a.astype(np.complex128), b.astype(np.complex128), op_a, 0, True)
+    assert rel(got, ref) < (1e-6 if prec == "f32" else BF_TOL["bf16x3"])
+    assert not cim[0].any()
+    if K > 1:
+        assert not cim[-1].any()
+
+
+def test_rtprod_bernoulli_short_contraction():
+    """Bernoulli picks keep the contraction at n2 with the live count on the
+    device; with n2 <= 64 the product takes the short-contraction kernel."""
+    A, B = W.rtprod_pair(n1=96, n2=48, n4=80, n3=16)
+    picks = api.tsample("norm2", 20, mode="bernoulli", seed=3, A=dev(A))
+    Z = api.tprod(dev(A), dev(B), picks=picks, prec="f32").cpu().numpy()
+    ridx, rsc = S.sample(S.weights_norm2(A), 20, "bernoulli", seed=3)
+    idx, _ = picks.host()
+    np.testing.assert_array_equal(idx.numpy(), ridx)
+    assert rel(Z, D.rtprod(A, B, ridx, rsc)) < 1e-5
 
 
 # Split-precision products: each float32 value is hi + lo in bf16 and the
