@@ -283,9 +283,10 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16_kernel(MArgs g) {
 // 128 rows x 64 bytes each, 64 KB) is staged through registers into one of
 // two LDS buffers while the other is consumed, so each step ends with a
 // single barrier. LDS rows are 64 bytes with the four 16-byte chunks
-// XOR-swizzled by ((row >> 2) ^ (row & 2)) & 3: the 16 rows of a fragment
-// read (and every 8 of them) then land on distinct bank groups, and the
-// staging writes stay conflict free too.
+// XOR-swizzled by (row >> 1) & 3; with that swizzle the fragment reads
+// (16 consecutive rows x 4 chunks per wavefront) and the staging writes
+// (16 rows x 4 chunks) measure free of bank conflicts on gfx950
+// (SQ_LDS_BANK_CONFLICT), which other row swizzles are not.
 // ---------------------------------------------------------------------------
 constexpr int SBM = 128, SBN = 128, SBK = 32, SNT = 512;
 constexpr int WTI = 4, WTJ = 2;  // 16 x 16 tiles per wavefront (rows, columns)
@@ -304,7 +305,7 @@ struct SArgs {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int swz(int row, int q) { return row * 4 + (q ^ (((row >> 2) ^ (row & 2)) & 3)); }
+__device__ __forceinline__ int swz(int row, int q) { return row * 4 + (q ^ ((row >> 1) & 3)); }
 
 template <int TERMS, bool REAL>
 __device__ __forceinline__ void split_body(const SArgs& g, int64_t k, int64_t tm, int64_t tn, u32x4* lds) {

@@ -180,7 +180,7 @@ __device__ __forceinline__ bf16x8 bneg(bf16x8 x) {
 template <int KP>
 __global__ __launch_bounds__(QT) void cgemm_short_split_kernel(QArgs g) {
   static_assert(KP % 32 == 0 && KP <= 64, "contraction padded to a multiple of 32");
-  constexpr int LDK = KP + 8;
+  constexpr int LDK = KP + 16;  // row bytes 2 LDK = 32 mod 64: conflict-free 16-byte fragment reads
   constexpr int NS = KP / 32;
   constexpr int RA = QM * KP / QT;
   __shared__ __align__(16) __bf16 as[2][4][QM][LDK];

@@ -185,7 +185,8 @@ __global__ __launch_bounds__(TT) void cgemm_tall_kernel(TArgs g) {
 // reads its 8 consecutive k values of a 32-deep step with one 16-byte read.
 template <int OPA, int NB>
 __global__ __launch_bounds__(TT) void cgemm_tall_split_kernel(TArgs g) {
-  constexpr int LK = KB + 8, NTL = NB / 16;
+  // 96-byte rows (32 mod 64): the 16-byte fragment reads are free of bank conflicts
+  constexpr int LK = KB + 16, NTL = NB / 16;
   __shared__ __align__(16) __bf16 as[2][4][TM][LK];
   __shared__ __align__(16) __bf16 bs[2][4][NB][LK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
