@@ -444,28 +444,47 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
   if (int rc = gather_rows(lay.Ch.re, lay.Ch.im, dt, K, n1, capc, rows->idx, rows->scale, rows->count, capl,
                            lay.W.re, lay.W.im, TP_F64, st))
     return rc;
-  if (int rc = lay.cf.run(lay.W, kCorePowerIters, seed, kStreamOmegaW, TP_PREC_F64, st)) return rc;
   // keep sigma_i > max(l, c) eps sigma_1 among the leading r
   const double core_rtol = double(std::max(capl, capc)) * 2.220446049250313e-16;
-  if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 2.0, lay.Tp.re,
-                             lay.Tp.im, TP_F64, st))
-    return rc;
-  if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 0.0, lay.Tr.re,
-                             lay.Tr.im, TP_F64, st))
-    return rc;
-  // P = Bh U_B,r diag(sigma^-2) = V_r diag(1/sigma) (c x r); U_r = Q U_B,r (l x r)
-  if (int rc = mm(lay.cf.Bh, 0, capc, sw, lay.Tp, 0, sw, r, lay.P64, K, real_last, TP_F64, TP_PREC_F64, st))
-    return rc;
-  if (int rc = mm(lay.cf.Q, 0, capl, sw, lay.Tr, 0, sw, r, lay.U64, K, real_last, TP_F64, TP_PREC_F64, st))
-    return rc;
   Spec Pw = lay.P64, Uw = lay.U64;
-  if (dt == TP_F32) {
-    if (int rc = convert(lay.P64.re, TP_F64, lay.P.re, TP_F32, K * capc * r, st)) return rc;
-    if (int rc = convert(lay.P64.im, TP_F64, lay.P.im, TP_F32, K * capc * r, st)) return rc;
-    if (int rc = convert(lay.U64.re, TP_F64, lay.Ur.re, TP_F32, K * capl * r, st)) return rc;
-    if (int rc = convert(lay.U64.im, TP_F64, lay.Ur.im, TP_F32, K * capl * r, st)) return rc;
-    Pw = lay.P;
-    Uw = lay.Ur;
+  if (core_pinv_fits(capl, capc, sw, r)) {
+    // small cores: the whole range finder, eigen-decomposition and factors
+    // in one workgroup per Fourier slice
+    if (int rc = randn_spectrum(lay.cf.omega.re, lay.cf.omega.im, TP_F64, K, capc, sw, real_last, seed,
+                                kStreamOmegaW, st))
+      return rc;
+    const bool f32 = dt == TP_F32;
+    if (int rc = core_pinv((const double*)lay.W.re, (const double*)lay.W.im, (const double*)lay.cf.omega.re,
+                           (const double*)lay.cf.omega.im, K, capl, capc, sw, r, real_last, kCorePowerIters,
+                           core_rtol, (double*)lay.P64.re, (double*)lay.P64.im, (double*)lay.U64.re,
+                           (double*)lay.U64.im, f32 ? (float*)lay.P.re : nullptr, f32 ? (float*)lay.P.im : nullptr,
+                           f32 ? (float*)lay.Ur.re : nullptr, f32 ? (float*)lay.Ur.im : nullptr, st))
+      return rc;
+    if (f32) {
+      Pw = lay.P;
+      Uw = lay.Ur;
+    }
+  } else {
+    if (int rc = lay.cf.run(lay.W, kCorePowerIters, seed, kStreamOmegaW, TP_PREC_F64, st)) return rc;
+    if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 2.0, lay.Tp.re,
+                               lay.Tp.im, TP_F64, st))
+      return rc;
+    if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 0.0, lay.Tr.re,
+                               lay.Tr.im, TP_F64, st))
+      return rc;
+    // P = Bh U_B,r diag(sigma^-2) = V_r diag(1/sigma) (c x r); U_r = Q U_B,r (l x r)
+    if (int rc = mm(lay.cf.Bh, 0, capc, sw, lay.Tp, 0, sw, r, lay.P64, K, real_last, TP_F64, TP_PREC_F64, st))
+      return rc;
+    if (int rc = mm(lay.cf.Q, 0, capl, sw, lay.Tr, 0, sw, r, lay.U64, K, real_last, TP_F64, TP_PREC_F64, st))
+      return rc;
+    if (dt == TP_F32) {
+      if (int rc = convert(lay.P64.re, TP_F64, lay.P.re, TP_F32, K * capc * r, st)) return rc;
+      if (int rc = convert(lay.P64.im, TP_F64, lay.P.im, TP_F32, K * capc * r, st)) return rc;
+      if (int rc = convert(lay.U64.re, TP_F64, lay.Ur.re, TP_F32, K * capl * r, st)) return rc;
+      if (int rc = convert(lay.U64.im, TP_F64, lay.Ur.im, TP_F32, K * capl * r, st)) return rc;
+      Pw = lay.P;
+      Uw = lay.Ur;
+    }
   }
   // 6. Zhat_k = Chat_k Uhat_k Rhat_k = (Chat_k P_k) (U_r,k^H Rhat_k), then ifft
   if (int rc = mm(lay.Ch, 0, n1, capc, Pw, 0, capc, r, lay.F, K, real_last, dt, prec, st)) return rc;

@@ -1,0 +1,357 @@
+// Fused t-CUR core for small slices: per Fourier slice k, the truncated
+// pseudo-inverse of W_k = D S^T Chat_k (l x c, l, c <= 64) that the core
+// step of Algorithm 5 needs, pinv_r(W) = V_r diag(1/sigma) U_r^H, returned
+// as the two factors P = V_r diag(1/sigma) (c x r) and U_r (l x r).
+//
+// The steps are those of the randomized range finder of Halko, Martinsson
+// and Tropp used for the larger cores, in float64, inside one 1024-thread
+// workgroup per slice with every small matrix in LDS:
+//   Y = W Omega, Q = orth(orth(Y)); q times: Z = orth(W^H Q),
+//   Q = orth(orth(W Z)); Bh = W^H Q; Bh^H Bh = U_B diag(lambda) U_B^H
+//   (Jacobi); P = Bh U_B,r diag(lambda^-1), U_r = Q U_B,r, keeping the
+//   leading r with sigma_i > rtol sigma_1.
+// orth(X) is CholeskyQR: X^H X = R^H R (pivots at or below 1e-24 of the
+// largest diagonal entry dropped), X <- X R^{-1} by forward substitution
+// along the rows of X. W (l c <= 3600 entries)
+// is read into LDS once and used by every product.
+#include "common.hpp"
+#include "jacobi.hpp"
+#include "linalg.hpp"
+
+namespace tp {
+namespace {
+
+constexpr int CNT = 1024, CM = 64, CS = 32, LDY = CS, CW = 3600;
+
+// The Gram / Cholesky scratch is dead once the eigensolver starts, so it
+// shares its LDS with the solver's state.
+struct CoreFactor {
+  double gr[CS][CS + 1], gi[CS][CS + 1];  // Gram, then the strict upper triangle of R
+};
+
+struct CoreShared {
+  double wr[CW], wi[CW];            // W (m x n, m n <= 3600)
+  double yr[CM][LDY], yi[CM][LDY];  // Y / Q (m x s)
+  double zr[CM][LDY], zi[CM][LDY];  // Omega / Bh / Z (n x s)
+  union {
+    CoreFactor f;
+    JacobiShared<CS, CNT> jac;
+  };
+  double rd[CS];
+  double dmax;
+  int order[CS];
+};
+
+struct CoreArgs {
+  const double *wre, *wim;  // K x m x n
+  const double *ore, *oim;  // K x n x s
+  int64_t K;
+  int m, n, s, r, q;
+  int real_last;
+  double rtol;  // truncation, relative to sigma_1
+  double *p64re, *p64im, *u64re, *u64im;  // K x n x r, K x m x r
+  float *p32re, *p32im, *u32re, *u32im;   // optional float32 copies
+};
+
+// The products give each thread one row (or column) of W and the result
+// columns t = tq, tq + 16 (s <= 32): the W entries are loaded once for both,
+// and the contraction is unrolled four deep so that eight loads are in
+// flight. 64 rows x 16 column groups = 1024 threads.
+
+// Y (m x s) = W Z (Z: n x s in zr / zi)
+__device__ void prod_wz(const CoreArgs& a, CoreShared& sh) {
+  const int tid = threadIdx.x, i = tid >> 4, tq = tid & 15;
+  if (i < a.m) {
+    const bool t1 = tq + 16 < a.s, t0 = tq < a.s;
+    const int u0 = t0 ? tq : 0, u1 = t1 ? tq + 16 : 0;
+    double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
+    const double* pr = sh.wr + i * a.n;
+    const double* pi = sh.wi + i * a.n;
+#pragma unroll 4
+    for (int j = 0; j < a.n; ++j) {
+      const double xr = pr[j], xi = pi[j];
+      ar0 += xr * sh.zr[j][u0] - xi * sh.zi[j][u0];
+      ai0 += xr * sh.zi[j][u0] + xi * sh.zr[j][u0];
+      ar1 += xr * sh.zr[j][u1] - xi * sh.zi[j][u1];
+      ai1 += xr * sh.zi[j][u1] + xi * sh.zr[j][u1];
+    }
+    if (t0) {
+      sh.yr[i][tq] = ar0;
+      sh.yi[i][tq] = ai0;
+    }
+    if (t1) {
+      sh.yr[i][tq + 16] = ar1;
+      sh.yi[i][tq + 16] = ai1;
+    }
+  }
+  __syncthreads();
+}
+
+// Bh (n x s, into zr / zi) = W^H Q (Q: m x s in yr / yi)
+__device__ void prod_whq(const CoreArgs& a, CoreShared& sh) {
+  const int tid = threadIdx.x, j = tid >> 4, tq = tid & 15;
+  if (j < a.n) {
+    const bool t1 = tq + 16 < a.s, t0 = tq < a.s;
+    const int u0 = t0 ? tq : 0, u1 = t1 ? tq + 16 : 0;
+    double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < a.m; ++i) {
+      const double xr = sh.wr[i * a.n + j], xi = sh.wi[i * a.n + j];
+      // conj(x) * q
+      ar0 += xr * sh.yr[i][u0] + xi * sh.yi[i][u0];
+      ai0 += xr * sh.yi[i][u0] - xi * sh.yr[i][u0];
+      ar1 += xr * sh.yr[i][u1] + xi * sh.yi[i][u1];
+      ai1 += xr * sh.yi[i][u1] - xi * sh.yr[i][u1];
+    }
+    if (t0) {
+      sh.zr[j][tq] = ar0;
+      sh.zi[j][tq] = ai0;
+    }
+    if (t1) {
+      sh.zr[j][tq + 16] = ar1;
+      sh.zi[j][tq + 16] = ai1;
+    }
+  }
+  __syncthreads();
+}
+
+// G (s x s) = X^H X, X rows x s
+__device__ void gram_lds(const double (*xr)[LDY], const double (*xi)[LDY], int rows, int s, CoreShared& sh) {
+  const int tid = threadIdx.x;
+  if (tid < s * s) {
+    const int p = tid / s, q = tid - p * s;
+    double vr = 0.0, vi = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < rows; ++i) {
+      vr += xr[i][p] * xr[i][q] + xi[i][p] * xi[i][q];
+      vi += xr[i][p] * xi[i][q] - xi[i][p] * xr[i][q];
+    }
+    sh.f.gr[p][q] = vr;
+    sh.f.gi[p][q] = vi;
+  }
+  __syncthreads();
+}
+
+// R from the Gram matrix in gr / gi: register-resident right-looking
+// Cholesky with pivot dropping (entry (tid / 32, tid % 32) per thread). On
+// return rd[j] = R_jj (0 for a dropped index) and gr / gi hold the strict
+// upper triangle of R (zero rows for dropped indices).
+__device__ void chol_lds(int s, double rtol, CoreShared& sh) {
+  const int tid = threadIdx.x;
+  const int ri = tid / CS, ci = tid % CS;
+  const bool mine = ri < s && ci < s && ci >= ri;
+  double gr = mine ? sh.f.gr[ri][ci] : 0.0, gi = (mine && ci > ri) ? sh.f.gi[ri][ci] : 0.0;
+  if (tid < 64) {
+    double mx = tid < s ? sh.f.gr[tid][tid] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (tid == 0) sh.dmax = mx;
+  }
+  __syncthreads();
+  const double tol = rtol * sh.dmax;
+  for (int j = 0; j < s; ++j) {
+    if (ri == j && ci >= j && ci < s) {
+      sh.f.gr[j][ci] = gr;
+      sh.f.gi[j][ci] = gi;
+    }
+    __syncthreads();
+    const double d = sh.f.gr[j][j];
+    if (d > tol && d > 0.0) {
+      const double inv = 1.0 / d;
+      if (ri > j && ci >= ri && ci < s) {
+        const double ar = sh.f.gr[j][ri], ai = sh.f.gi[j][ri], br = sh.f.gr[j][ci], bi = sh.f.gi[j][ci];
+        gr -= (ar * br + ai * bi) * inv;
+        gi -= (ar * bi - ai * br) * inv;
+      }
+    }
+  }
+  if (tid < CS) {
+    const double d = tid < s ? sh.f.gr[tid][tid] : 0.0;
+    sh.rd[tid] = (tid < s && d > tol && d > 0.0) ? sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  // R: strict upper triangle (zero on dropped rows and past s)
+  if (ci > ri) {
+    const bool live = ri < s && ci < s && sh.rd[ri] > 0.0;
+    sh.f.gr[ri][ci] = live ? gr / sh.rd[ri] : 0.0;
+    sh.f.gi[ri][ci] = live ? gi / sh.rd[ri] : 0.0;
+  }
+  __syncthreads();
+}
+
+// X <- X R^{-1} on the kept indices (dropped columns become zero), in place:
+// forward substitution along every row of X, Q_j = (X_j - sum_{a<j} Q_a R_aj)
+// / R_jj, with 16 lanes per row holding columns tq and tq + 16; the pivot
+// value of step j is broadcast from its lane by a 16-wide shuffle, so the
+// 32 steps need no workgroup barrier.
+__device__ void solve_rows(double (*xr)[LDY], double (*xi)[LDY], int rows, int s, CoreShared& sh) {
+  const int tid = threadIdx.x, i = tid >> 4, tq = tid & 15;
+  const bool live = i < rows;
+  const int ii = live ? i : 0;
+  double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+  if (live && tq < s) {
+    r0 = xr[ii][tq];
+    i0 = xi[ii][tq];
+  }
+  if (live && tq + 16 < s) {
+    r1 = xr[ii][tq + 16];
+    i1 = xi[ii][tq + 16];
+  }
+  for (int j = 0; j < s; ++j) {
+    const bool hi = j >= 16;
+    const double vr = __shfl(hi ? r1 : r0, j & 15, 16), vi = __shfl(hi ? i1 : i0, j & 15, 16);
+    const double inv = sh.rd[j] > 0.0 ? 1.0 / sh.rd[j] : 0.0;
+    const double qr = vr * inv, qi = vi * inv;
+    if (tq == (j & 15)) {
+      if (hi) {
+        r1 = qr;
+        i1 = qi;
+      } else {
+        r0 = qr;
+        i0 = qi;
+      }
+    }
+    // x_t -= q R_jt for the columns t > j this lane holds
+    if (tq > j) {
+      const double rr = sh.f.gr[j][tq], ri = sh.f.gi[j][tq];
+      r0 -= qr * rr - qi * ri;
+      i0 -= qr * ri + qi * rr;
+    }
+    if (tq + 16 > j && tq + 16 < s) {
+      const double rr = sh.f.gr[j][tq + 16], ri = sh.f.gi[j][tq + 16];
+      r1 -= qr * rr - qi * ri;
+      i1 -= qr * ri + qi * rr;
+    }
+  }
+  __syncthreads();
+  if (live && tq < s) {
+    xr[i][tq] = r0;
+    xi[i][tq] = i0;
+  }
+  if (live && tq + 16 < s) {
+    xr[i][tq + 16] = r1;
+    xi[i][tq + 16] = i1;
+  }
+  __syncthreads();
+}
+
+__device__ void orth_lds(double (*xr)[LDY], double (*xi)[LDY], int rows, int s, CoreShared& sh) {
+  gram_lds(xr, xi, rows, s, sh);
+  chol_lds(s, 1e-24, sh);
+  solve_rows(xr, xi, rows, s, sh);
+}
+
+__global__ __launch_bounds__(CNT) void core_pinv_kernel(CoreArgs a) {
+  __shared__ CoreShared sh;
+  const int tid = threadIdx.x;
+  const int64_t k = blockIdx.x;
+  const bool real = k == 0 || (a.real_last && k == a.K - 1);
+  const double* wr = a.wre + k * a.m * a.n;
+  const double* wi = a.wim + k * a.m * a.n;
+  // W and Omega (imaginary parts of the real slices read as zero)
+  for (int e = tid; e < a.m * a.n; e += CNT) {
+    sh.wr[e] = wr[e];
+    sh.wi[e] = real ? 0.0 : wi[e];
+  }
+  for (int e = tid; e < a.n * a.s; e += CNT) {
+    const int j = e / a.s, t = e - j * a.s;
+    sh.zr[j][t] = a.ore[k * a.n * a.s + e];
+    sh.zi[j][t] = real ? 0.0 : a.oim[k * a.n * a.s + e];
+  }
+  __syncthreads();
+  prod_wz(a, sh);
+  orth_lds(sh.yr, sh.yi, a.m, a.s, sh);
+  orth_lds(sh.yr, sh.yi, a.m, a.s, sh);
+  for (int it = 0; it < a.q; ++it) {
+    prod_whq(a, sh);
+    orth_lds(sh.zr, sh.zi, a.n, a.s, sh);
+    prod_wz(a, sh);
+    orth_lds(sh.yr, sh.yi, a.m, a.s, sh);
+    orth_lds(sh.yr, sh.yi, a.m, a.s, sh);
+  }
+  prod_whq(a, sh);
+  // Bh^H Bh into the eigensolver
+  gram_lds(sh.zr, sh.zi, a.n, a.s, sh);
+  for (int e = tid; e < a.s * a.s; e += CNT) {
+    const int p = e / a.s, q = e - p * a.s;
+    sh.jac.Hr[p][q] = sh.f.gr[p][q];
+    sh.jac.Hi[p][q] = sh.f.gi[p][q];
+  }
+  __syncthreads();
+  jacobi_eig_lds<CS, CNT>(sh.jac, a.s, 40, 1e-15);
+  if (tid < a.s) {
+    const double lt = sh.jac.Hr[tid][tid];
+    int rank = 0;
+    for (int j = 0; j < a.s; ++j) {
+      const double lj = sh.jac.Hr[j][j];
+      if (lj > lt || (lj == lt && j < tid)) ++rank;
+    }
+    sh.order[rank] = tid;
+  }
+  __syncthreads();
+  // weights of the kept leading columns: 1/lambda for P, 1 for U
+  if (tid < a.r) {
+    const double l0 = sh.jac.Hr[sh.order[0]][sh.order[0]];
+    const double lj = sh.jac.Hr[sh.order[tid]][sh.order[tid]];
+    const double s0 = l0 > 0.0 ? sqrt(l0) : 0.0;
+    const double sj = lj > 0.0 ? sqrt(lj) : 0.0;
+    const bool keep = sj > 0.0 && sj > a.rtol * s0;
+    sh.rd[tid] = keep ? 1.0 / (sj * sj) : 0.0;  // P weight; U keeps the same columns with weight 1
+  }
+  __syncthreads();
+  // P = Bh U_B,r diag(w_P) (n x r), U = Q U_B,r diag(w_U) (m x r)
+  for (int e = tid; e < (a.n + a.m) * a.r; e += CNT) {
+    const bool isp = e < a.n * a.r;
+    const int f = isp ? e : e - a.n * a.r;
+    const int i = f / a.r, c = f - i * a.r;
+    const int col = sh.order[c];
+    double vr = 0.0, vi = 0.0;
+    for (int t = 0; t < a.s; ++t) {
+      const double xr = isp ? sh.zr[i][t] : sh.yr[i][t], xi = isp ? sh.zi[i][t] : sh.yi[i][t];
+      const double er = sh.jac.Vr[t][col], ei = sh.jac.Vi[t][col];
+      vr += xr * er - xi * ei;
+      vi += xr * ei + xi * er;
+    }
+    const double w = isp ? sh.rd[c] : (sh.rd[c] > 0.0 ? 1.0 : 0.0);
+    vr *= w;
+    vi *= w;
+    if (real) vi = 0.0;
+    if (isp) {
+      a.p64re[k * a.n * a.r + f] = vr;
+      a.p64im[k * a.n * a.r + f] = vi;
+      if (a.p32re) {
+        a.p32re[k * a.n * a.r + f] = (float)vr;
+        a.p32im[k * a.n * a.r + f] = (float)vi;
+      }
+    } else {
+      a.u64re[k * a.m * a.r + f] = vr;
+      a.u64im[k * a.m * a.r + f] = vi;
+      if (a.u32re) {
+        a.u32re[k * a.m * a.r + f] = (float)vr;
+        a.u32im[k * a.m * a.r + f] = (float)vi;
+      }
+    }
+  }
+}
+
+}  // namespace
+
+bool core_pinv_fits(int64_t m, int64_t n, int s, int64_t r) {
+  return m >= 1 && n >= 1 && m <= CM && n <= CM && m * n <= CW && s >= 1 && s <= CS && r >= 1 && r <= s;
+}
+
+int core_pinv(const double* wre, const double* wim, const double* ore, const double* oim, int64_t K, int64_t m,
+              int64_t n, int s, int64_t r, bool real_last, int q, double rtol, double* p64re, double* p64im,
+              double* u64re, double* u64im, float* p32re, float* p32im, float* u32re, float* u32im, hipStream_t st) {
+  if (!core_pinv_fits(m, n, s, r))
+    return fail(TP_EUNSUPPORTED, "fused core needs l, c <= 64, l c <= 3600 and r <= s <= 32");
+  if (K == 0) return TP_OK;
+  if (K > 0x7fffffff) return fail(TP_EUNSUPPORTED, "too many Fourier slices");
+  CoreArgs a{wre, wim, ore, oim, K, (int)m, (int)n, s, (int)r, q, real_last ? 1 : 0, rtol,
+             p64re, p64im, u64re, u64im, p32re, p32im, u32re, u32im};
+  hipLaunchKernelGGL(core_pinv_kernel, dim3((unsigned)K), dim3(CNT), 0, st, a);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+}  // namespace tp

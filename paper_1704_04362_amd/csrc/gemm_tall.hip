@@ -276,11 +276,11 @@ void launch_tall(const TArgs& g, int split, dim3 grid, hipStream_t st) {
 }  // namespace
 
 // Takes float32 products C_k = op(A_k) B_k (op_b = N) with at most 64
-// result columns and a contraction longer than 64, in float32 (split = 0)
+// result columns (any contraction length), in float32 (split = 0)
 // or split bf16 (split = 1); *handled says whether it did.
 int cgemm_tall(const CGemm& p, int split, hipStream_t st, bool* handled) {
   *handled = false;
-  if (p.op_b != 0 || p.N < 1 || p.N > 64 || p.Kd <= 64 || p.M < 32) return TP_OK;
+  if (p.op_b != 0 || p.N < 1 || p.N > 64 || p.Kd < 1 || p.M < 32) return TP_OK;
   if (p.K > 65535 || (p.M + TM - 1) / TM > 65535) return TP_OK;
   TArgs g{p.M, p.N, p.Kd, (const float*)p.are, (const float*)p.aim, (const float*)p.bre, (const float*)p.bim,
           (float*)p.cre, (float*)p.cim, p.lda, p.ldb, p.ldc, p.sa, p.sb, p.sc, p.K, p.real_last ? 1 : 0,

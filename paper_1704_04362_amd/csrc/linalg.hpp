@@ -42,4 +42,15 @@ int gather_rows(const void* xre, const void* xim, int in_dtype, int64_t K, int64
                 void* wim, int out_dtype, hipStream_t st);
 int convert(const void* a, int adt, void* b, int bdt, int64_t n, hipStream_t st);
 
+// Fused truncated pseudo-inverse of small t-CUR cores (core.hip): per slice
+// the range finder (q power iterations) on W (m x n, float64) with the given
+// Gaussian Omega (n x s), the Jacobi eigen-decomposition of Bh^H Bh and the
+// factors P = Bh U_B,r diag(1/lambda) (n x r) and U = Q U_B,r (m x r), keeping
+// sigma_i > rtol sigma_1; float32 copies of P and U when those pointers are
+// set. Needs m, n <= 64 and r <= s <= 32 (core_pinv_fits).
+bool core_pinv_fits(int64_t m, int64_t n, int s, int64_t r);
+int core_pinv(const double* wre, const double* wim, const double* ore, const double* oim, int64_t K, int64_t m,
+              int64_t n, int s, int64_t r, bool real_last, int q, double rtol, double* p64re, double* p64im,
+              double* u64re, double* u64im, float* p32re, float* p32im, float* u32re, float* u32im, hipStream_t st);
+
 }  // namespace tp

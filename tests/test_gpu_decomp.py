@@ -123,6 +123,27 @@ def test_tcur_exact_rank_reproduces_input(dtype, prec, tol):
         assert rel(Z.cpu().numpy(), A) < tol, kinds
 
 
+@pytest.mark.parametrize("dtype,prec,tol", [(np.float64, "f64", 1e-9), (np.float32, "f32", 1e-5),
+                                            (np.float32, "bf16x3", 5e-5)])
+@pytest.mark.parametrize("c,l,n3", [(64, 60, 8), (60, 64, 7), (66, 60, 8), (40, 70, 5)])
+def test_tcur_core_paths_match_oracle(dtype, prec, tol, c, l, n3):
+    """Cores with l, c <= 64 take the fused one-workgroup-per-slice
+    pseudo-inverse, larger ones the multi-kernel range finder; both must give
+    the oracle's t-CUR (odd tube lengths have no real Nyquist slice)."""
+    n1, n2, r = 90, 100, 6
+    A, _ = lowrank(n1, n2, n3, r, noise_var=1e-3, salt=c + l)
+    A = A.astype(dtype)
+    wc, wr = _user_weights(n2, 3), _user_weights(n1, 4)
+    Z, cols, rows = api.tcur(dev(A), c, l, r, col_kind="user", row_kind="user", col_w=dev(wc), row_w=dev(wr),
+                             mode="iid", seed=13, prec=prec)
+    ci, cs = S.sample(wc, c, "iid", seed=13, stream=0)
+    ri, rsc = S.sample(wr, l, "iid", seed=13, stream=1)
+    np.testing.assert_array_equal(cols.host()[0].numpy(), ci)
+    np.testing.assert_array_equal(rows.host()[0].numpy(), ri)
+    Zr, _ = D.tcur(A.astype(np.float64), ci, cs, ri, rsc, r=r)
+    assert rel(Z.cpu().numpy(), Zr) < tol
+
+
 def test_tcur_leverage_picks_follow_oracle_scores():
     # The GPU draws from its range-finder leverage scores; they equal the
     # oracle's exact scores to 1e-9 here (exact rank, float64), so the picks

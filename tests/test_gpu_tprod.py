@@ -265,7 +265,7 @@ def test_spectrum_matmul_short_contraction(prec, K, M, N, Kd, real_last):
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 @pytest.mark.parametrize("op_a", [0, 1])
 @pytest.mark.parametrize("K,M,N,Kd", [(5, 100, 32, 65), (3, 64, 1, 200), (4, 130, 33, 1000), (2, 32, 64, 97),
-                                      (65, 256, 24, 300)])
+                                      (65, 256, 24, 300), (5, 100, 20, 60), (3, 64, 32, 7), (2, 33, 64, 1)])
 def test_spectrum_matmul_tall(prec, op_a, K, M, N, Kd):
     """Narrow results with a long contraction (the range-finder products,
     A Omega and A^H Q): float32 or split matrix cores, ragged rows, columns
