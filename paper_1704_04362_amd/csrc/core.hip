@@ -38,6 +38,7 @@ struct CoreShared {
     JacobiShared<CS, CNT> jac;
   };
   double rd[CS];
+  double rinv[CS];  // 1 / R_jj, 0 for a dropped index
   double dmax;
   int order[CS];
 };
@@ -157,7 +158,10 @@ __device__ void chol_lds(int s, double rtol, CoreShared& sh) {
     __syncthreads();
     const double d = sh.f.gr[j][j];
     if (d > tol && d > 0.0) {
-      const double inv = 1.0 / d;
+      // 1 / d: hardware reciprocal refined by two Newton steps
+      double inv = __builtin_amdgcn_rcp(d);
+      inv = fma(fma(-d, inv, 1.0), inv, inv);
+      inv = fma(fma(-d, inv, 1.0), inv, inv);
       if (ri > j && ci >= ri && ci < s) {
         const double ar = sh.f.gr[j][ri], ai = sh.f.gi[j][ri], br = sh.f.gr[j][ci], bi = sh.f.gi[j][ci];
         gr -= (ar * br + ai * bi) * inv;
@@ -167,7 +171,10 @@ __device__ void chol_lds(int s, double rtol, CoreShared& sh) {
   }
   if (tid < CS) {
     const double d = tid < s ? sh.f.gr[tid][tid] : 0.0;
-    sh.rd[tid] = (tid < s && d > tol && d > 0.0) ? sqrt(d) : 0.0;
+    const bool keep = tid < s && d > tol && d > 0.0;
+    const double rd = keep ? sqrt(d) : 0.0;
+    sh.rd[tid] = rd;
+    sh.rinv[tid] = keep ? 1.0 / rd : 0.0;
   }
   __syncthreads();
   // R: strict upper triangle (zero on dropped rows and past s)
@@ -197,10 +204,12 @@ __device__ void solve_rows(double (*xr)[LDY], double (*xi)[LDY], int rows, int s
     r1 = xr[ii][tq + 16];
     i1 = xi[ii][tq + 16];
   }
-  for (int j = 0; j < s; ++j) {
+#pragma unroll
+  for (int j = 0; j < CS; ++j) {
+    if (j >= s) break;
     const bool hi = j >= 16;
     const double vr = __shfl(hi ? r1 : r0, j & 15, 16), vi = __shfl(hi ? i1 : i0, j & 15, 16);
-    const double inv = sh.rd[j] > 0.0 ? 1.0 / sh.rd[j] : 0.0;
+    const double inv = sh.rinv[j];
     const double qr = vr * inv, qi = vi * inv;
     if (tq == (j & 15)) {
       if (hi) {
