@@ -340,11 +340,24 @@ __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, Fw
   }
 }
 
+// Output staging of the inverse transform: the 64 tubes of a workgroup are
+// transposed through LDS in NH pieces of N / NH entries (two for the longer
+// tubes, which halves the LDS a workgroup holds and doubles the workgroups
+// that fit on a CU).
+template <int N>
+struct InvStage {
+  static constexpr int VN = 4;
+  static constexpr int NH = (N >= 64 && N % (2 * VN) == 0) ? 2 : 1;
+  static constexpr int SPAN = N / NH;
+  static constexpr int PAD = SPAN + 1;
+};
+
 template <typename T, int N>
 __global__ __launch_bounds__(kTile) void irfft_kernel(const T* __restrict__ xre, const T* __restrict__ xim,
                                                       int64_t ntubes, T* __restrict__ y) {
   constexpr int M = N / 2;
-  constexpr int PAD = N + 1;
+  using ST = InvStage<N>;
+  constexpr int NH = ST::NH, SPAN = ST::SPAN, PAD = ST::PAD;
   constexpr int VN = Vec16<T>::n;
   using V = typename Vec16<T>::type;
   __shared__ T lds[kTile * PAD];
@@ -352,14 +365,17 @@ __global__ __launch_bounds__(kTile) void irfft_kernel(const T* __restrict__ xre,
   const int64_t tile0 = (int64_t)blockIdx.x * kTile;
   const int64_t t = tile0 + lane;
   const int64_t ks = ntubes;
+  // the time-domain tube of this lane: y[2 m] = zr[m], y[2 m + 1] = zi[m]
+  // once the transform is done (y[0] = zr[0] for N = 1)
+  constexpr int MZ = M > 0 ? M : 1;
+  T zr[MZ], zi[MZ];
   if (t < ntubes) {
     if constexpr (N == 1) {
-      lds[lane * PAD] = xre[t];
+      zr[0] = xre[t];
     } else {
       // the half spectrum is read into zr / zi and turned into conj(Z),
       // Z[k] = E[k] + i O[k], in place: slot k takes X[k] for k < M and
       // X[M] is held apart; the pair (k, M - k) is rewritten together
-      T zr[M], zi[M];
 #pragma unroll
       for (int k = 0; k < M; ++k) {
         zr[k] = xre[(int64_t)k * ks + t];
@@ -398,33 +414,44 @@ __global__ __launch_bounds__(kTile) void irfft_kernel(const T* __restrict__ xre,
       const T inv = T(1) / T(M);
 #pragma unroll
       for (int m = 0; m < M; ++m) {
-        lds[lane * PAD + 2 * m] = zr[m] * inv;
-        lds[lane * PAD + 2 * m + 1] = -zi[m] * inv;
+        zr[m] = zr[m] * inv;
+        zi[m] = -zi[m] * inv;
       }
     }
   }
-  __syncthreads();
-  if constexpr (N % VN == 0) {
-    constexpr int CH = N / VN;
 #pragma unroll
-    for (int it = 0; it < CH; ++it) {
-      const int f = it * kTile + lane;
-      const int tl = f / CH, part = f - tl * CH;
-      const int64_t tt = tile0 + tl;
-      if (tt < ntubes) {
-        V w;
-        T* wp = reinterpret_cast<T*>(&w);
+  for (int h = 0; h < NH; ++h) {
+    if (h > 0) __syncthreads();
+    if (t < ntubes) {
 #pragma unroll
-        for (int e = 0; e < VN; ++e) wp[e] = lds[tl * PAD + part * VN + e];
-        *reinterpret_cast<V*>(y + tt * N + part * VN) = w;
+      for (int e = 0; e < SPAN; ++e) {
+        const int g = h * SPAN + e;  // entry of the tube
+        lds[lane * PAD + e] = (g & 1) ? zi[g >> 1] : zr[g >> 1];
       }
     }
-  } else {
-    for (int it = 0; it < N; ++it) {
-      const int f = it * kTile + lane;
-      const int tl = f / N, e = f - tl * N;
-      const int64_t tt = tile0 + tl;
-      if (tt < ntubes) y[tt * N + e] = lds[tl * PAD + e];
+    __syncthreads();
+    if constexpr (SPAN % VN == 0) {
+      constexpr int CH = SPAN / VN;
+#pragma unroll
+      for (int it = 0; it < CH; ++it) {
+        const int f = it * kTile + lane;
+        const int tl = f / CH, part = f - tl * CH;
+        const int64_t tt = tile0 + tl;
+        if (tt < ntubes) {
+          V w;
+          T* wp = reinterpret_cast<T*>(&w);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) wp[e] = lds[tl * PAD + part * VN + e];
+          *reinterpret_cast<V*>(y + tt * N + h * SPAN + part * VN) = w;
+        }
+      }
+    } else {
+      for (int it = 0; it < SPAN; ++it) {
+        const int f = it * kTile + lane;
+        const int tl = f / SPAN, e = f - tl * SPAN;
+        const int64_t tt = tile0 + tl;
+        if (tt < ntubes) y[tt * N + h * SPAN + e] = lds[tl * PAD + e];
+      }
     }
   }
 }
