@@ -16,8 +16,9 @@ double precision) and follows the paper's definitions in their own order:
 * ``sampling`` - slice norms, the sampling probabilities of Section 3 and the
                  exact-integer pick procedure.
 * ``decomp``   - rt-product (Algorithm 2), t-project / t-CX (Algorithms 3-4),
-                 t-CUR (Algorithm 5), t-SVT and the ADMM completion loop
-                 (Algorithm 7 and the completion problem of Section 2.3).
+                 t-CUR (Algorithm 5), CUR t-NN (Algorithm 6), t-SVT and the
+                 ADMM of Algorithm 7 for robust tensor PCA (eq. tlow7) and
+                 for the completion problem (eq. tlow6).
 * ``mlp``      - the learned leverage proposal (not in the paper).
 
 Parity status of every function is listed in its module header.

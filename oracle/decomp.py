@@ -8,6 +8,8 @@ infrastructure only).
 * tsvt        singular value thresholding of every Fourier slice, the
               closed-form L-update of Algorithm 7 with the tensor nuclear norm.
 * admm_complete  Algorithm 7 adapted to the completion problem (eq. tlow6).
+* admm_rpca   Algorithm 7 as stated, robust tensor PCA (eq. tlow7).
+* cur_tnn     Algorithm 6 (CUR t-NN) given its picks.
 
 Readings where the paper is silent or garbled:
 * S and D carry their entries in the first frontal slice only and are zero
@@ -23,6 +25,12 @@ Readings where the paper is silent or garbled:
   is the tensor-nuclear-norm prox, i.e. a per-Fourier-slice threshold of
   exactly 1/mu (both the nuclear norm and the squared Frobenius norm carry
   the same 1/n3 factor in the Fourier domain).
+* Algorithm 6 picks C and R by the probabilities of eqs. cur-col-prob and
+  colprob_rows_exact but, unlike Algorithms 2-5, does not rescale them: the
+  picked slices are cleaned by the ADMM as they are, and W is the matching
+  rows of the cleaned C, unscaled.
+* The weight lambda of eq. tlow7 is not given; rpca_lambda returns the usual
+  1 / sqrt(max(n1, n2) n3).
 
 Pins (tests/test_oracle_decomp.py): c = n2 with uniform weights gives the
 exact product; unbiasedness and the exact second moment of the estimator by
@@ -30,7 +38,15 @@ Monte Carlo; exact-rank inputs are reproduced exactly by t-CX and t-CUR;
 t-CX is the least-squares optimum (eq. ell2reg); n3 = 1 reduces to matrix
 CX/CUR; circ(tsvt(M, tau)) equals the matrix SVT of circ(M) with the same
 tau; tau = 0 is the identity; prox optimality under random perturbations;
-ADMM residuals shrink.
+ADMM residuals shrink; every ADMM iterate satisfies the optimality
+condition of its E-update exactly (Y = 0 off the observed entries for
+completion, |Y| <= lambda with Y = -lambda sign(E) on the support of E for
+robust PCA) and the converged robust-PCA iterate satisfies the optimality
+conditions of eq. tlow7 (-Y a subgradient of the tensor nuclear norm at L);
+robust PCA with an unbounded lambda is completion with every entry observed;
+low-rank plus sparse spikes are separated; CUR t-NN reproduces an exact-rank
+tensor observed in full, and with every slice picked equals the ADMM of the
+whole tensor.
 """
 
 import numpy as np
@@ -215,3 +231,89 @@ def tcur_tubes(Csl, Rsl, cscale, ridx, rscale, r, ii, jj):
     for k in range(K, n3):
         Zh[:, k] = Zh[:, n3 - k].conj()
     return T._real_part_checked(np.fft.ifft(Zh, axis=1))
+
+
+def soft_threshold(V, t):
+    """Entrywise shrinkage sign(v) max(|v| - t, 0): the minimiser over E of
+    t ||E||_1 + 1/2 ||E - V||_F^2 (the closed-form E-update of Algorithm 7)."""
+    V = np.asarray(V, dtype=np.float64)
+    return np.sign(V) * np.maximum(np.abs(V) - t, 0.0)
+
+
+def rpca_lambda(shape):
+    """Default weight of the l1 term of eq. tlow7, which the paper leaves
+    open: 1 / sqrt(max(n1, n2) n3), the value used by the tensor robust PCA
+    work that eq. tlow7 is taken from."""
+    n1, n2, n3 = shape
+    return 1.0 / np.sqrt(max(n1, n2) * n3)
+
+
+def admm_rpca(X, lam, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None):
+    """Algorithm 7 as stated, for robust tensor PCA (eq. tlow7): minimise
+    ||L||_TNN + lam ||E||_1 subject to X = L + E. From L = E = Y = 0 and
+    mu = mu0 every iteration does
+        L <- tsvt(X - E - Y/mu, 1/mu)                 (L-update, TNN prox)
+        E <- soft_threshold(X - L - Y/mu, lam/mu)     (E-update, l1 prox)
+        Y <- Y + mu (L + E - X)
+        mu <- min(rho mu, mu_max)
+    for exactly `iters` iterations. Returns (L, E, Y, history) with the same
+    per-iteration records as admm_complete."""
+    X = np.asarray(X, dtype=np.float64)
+    L = np.zeros_like(X)
+    E = np.zeros_like(X)
+    Y = np.zeros_like(X)
+    mu = float(mu0)
+    hist = []
+    for _ in range(int(iters)):
+        Lprev, Eprev = L, E
+        L, ranks = tsvt(X - E - Y / mu, 1.0 / mu)
+        E = soft_threshold(X - L - Y / mu, lam / mu)
+        Y = Y + mu * (L + E - X)
+        rec = {
+            "dL": float(np.max(np.abs(L - Lprev))),
+            "dE": float(np.max(np.abs(E - Eprev))),
+            "res": float(np.max(np.abs(L + E - X))),
+            "ranks": ranks,
+            "mu": mu,
+        }
+        if L_true is not None:
+            rec["rse"] = T.rel_fro(L, L_true)
+        hist.append(rec)
+        mu = min(rho * mu, mu_max)
+    return L, E, Y, hist
+
+
+def cur_tnn(X, cidx, ridx, r=None, mask=None, lam=None, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
+    """Algorithm 6 (CUR t-NN) given its picks. The picked slices are taken
+    as they are, without rescaling:
+        C = X[:, cidx, :],  Ct = ADMM(C)
+        R = X[ridx, :, :],  Rt = ADMM(R)
+        W = Ct[ridx, :, :]  (l x c x n3),  U = W^+  (per Fourier slice)
+        L = Ct * U * Rt
+    ADMM is admm_complete on the matching part of `mask` when a mask is
+    given (eq. tlow6) and admm_rpca with weight `lam` otherwise (eq.
+    tlow7). The pseudo-inverse of every Fourier slice keeps at most r
+    singular values (all when r is None) and drops those at or below
+    max(l, c) eps sigma_1. Returns (L, Ct, Rt)."""
+    X = np.asarray(X, dtype=np.float64)
+    cidx = np.asarray(cidx, dtype=np.int64)
+    ridx = np.asarray(ridx, dtype=np.int64)
+    n3 = X.shape[2]
+
+    def admm(part, part_mask):
+        if part_mask is None:
+            return admm_rpca(part, lam, iters, rho, mu0, mu_max)[0]
+        return admm_complete(part, part_mask, iters, rho, mu0, mu_max)[0]
+
+    Ct = admm(X[:, cidx, :], None if mask is None else np.asarray(mask)[:, cidx, :])
+    Rt = admm(X[ridx, :, :], None if mask is None else np.asarray(mask)[ridx, :, :])
+    K = T.half_spectrum_count(n3)
+    Ch, Rh = T.fft3(Ct), T.fft3(Rt)
+    Lh = np.zeros((X.shape[0], X.shape[1], n3), dtype=complex)
+    for k in range(K):
+        Ck = Ch[:, :, k].real if _is_real_slice(k, n3) else Ch[:, :, k]
+        Rk = Rh[:, :, k].real if _is_real_slice(k, n3) else Rh[:, :, k]
+        Uk = pinv_r(Ck[ridx, :], r)
+        Lh[:, :, k] = Ck @ Uk @ Rk
+    L = T._real_part_checked(T.ifft3(_mirror(Lh, K, n3)))
+    return L, Ct, Rt

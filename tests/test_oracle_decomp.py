@@ -202,3 +202,128 @@ def test_tcur_tubes_match_full_tcur():
     ii, jj = np.array([0, 3, 8, 5]), np.array([10, 0, 4, 5])
     got = D.tcur_tubes(A[:, ci, :], A[ri, :, :], cs, ri, rsc, 2, ii, jj)
     np.testing.assert_allclose(got, Z[ii, jj, :], atol=1e-12)
+
+
+def _spiky(n1, n2, n3, r, frac, seed):
+    """Low tubal rank r plus sparse +-5 spikes on a fraction of the entries."""
+    g = np.random.default_rng(seed)
+    Ls = _lowrank(n1, n2, n3, r, seed=seed)
+    S = np.zeros(Ls.shape)
+    hit = g.random(Ls.shape) < frac
+    S[hit] = 5.0 * g.choice([-1.0, 1.0], int(hit.sum()))
+    return Ls, S
+
+
+def test_completion_e_update_optimality_every_iteration():
+    # E-update of the completion loop: Y vanishes off the observed entries
+    Ls = _lowrank(12, 10, 5, 2, seed=21)
+    mask = (rs.random(Ls.shape) < 0.5).astype(np.uint8)
+    for iters in (1, 4, 15):
+        L, E, Y, _ = D.admm_complete(Ls * mask, mask, iters=iters)
+        assert np.max(np.abs(Y[mask == 0])) <= 1e-12 * max(1.0, np.max(np.abs(Y)))
+
+
+def test_soft_threshold_is_the_l1_prox():
+    V = rs.standard_normal((5, 4, 3))
+    t = 0.4
+    E = D.soft_threshold(V, t)
+
+    def obj(Z):
+        return t * np.sum(np.abs(Z)) + 0.5 * np.sum((Z - V) ** 2)
+
+    base = obj(E)
+    for _ in range(30):
+        assert obj(E + 1e-3 * rs.standard_normal(V.shape)) >= base - 1e-12
+    np.testing.assert_array_equal(D.soft_threshold(V, 0.0), V)
+    assert not np.any(D.soft_threshold(V, 10.0))
+
+
+def test_rpca_e_update_optimality_every_iteration():
+    # 0 in lam d||E||_1 + Y_{k+1}: |Y| <= lam everywhere, Y = -lam sign(E) on supp(E)
+    Ls, S = _spiky(14, 12, 4, 2, 0.1, seed=22)
+    X = Ls + S
+    lam = D.rpca_lambda(X.shape)
+    for iters in (2, 40, 100):
+        L, E, Y, _ = D.admm_rpca(X, lam, iters=iters)
+        assert np.max(np.abs(Y)) <= lam * (1 + 1e-9)
+        on = np.abs(E) > 0
+        assert on.any() or iters < 100
+        np.testing.assert_allclose(Y[on], -lam * np.sign(E[on]), rtol=0, atol=1e-9 * lam)
+
+
+def test_rpca_l_update_optimality_every_iteration():
+    # the L-update is the exact prox of the TNN (eq. tnuc): with
+    # G = -Y_{k+1} - mu_k (E_k - E_{k+1}), G is a subgradient of ||.||_TNN at
+    # L_{k+1}: its tensor spectral norm (the dual norm) is <= 1 and
+    # <G, L_{k+1}> = ||L_{k+1}||_TNN
+    Ls, S = _spiky(20, 16, 5, 2, 0.05, seed=23)
+    X = Ls + S + 0.05 * rs.standard_normal(Ls.shape)
+    lam = D.rpca_lambda(X.shape)
+    for iters in (30, 60, 100):
+        L, E, Y, hist = D.admm_rpca(X, lam, iters=iters)
+        Ep = D.admm_rpca(X, lam, iters=iters - 1)[1]
+        G = -Y - hist[-1]["mu"] * (Ep - E)
+        assert T.tspec(G) <= 1 + 1e-10
+        assert abs(np.sum(G * L) - T.tnn(L)) <= 1e-10 * T.tnn(L)
+        assert T.tnn(L) > 0
+
+
+def test_rpca_converges_to_a_feasible_split():
+    Ls, S = _spiky(20, 16, 5, 2, 0.05, seed=23)
+    X = Ls + S + 0.05 * rs.standard_normal(Ls.shape)
+    L, E, Y, hist = D.admm_rpca(X, D.rpca_lambda(X.shape), iters=250)
+    assert hist[-1]["res"] < 1e-10 and hist[-1]["dL"] < 1e-8
+    assert np.count_nonzero(E) > 0 and np.all(hist[-1]["ranks"] < 16)
+
+
+def test_rpca_unbounded_lambda_is_full_completion():
+    X = rs.standard_normal((9, 7, 4))
+    a = D.admm_rpca(X, 1e300, iters=25)
+    b = D.admm_complete(X, np.ones(X.shape, np.uint8), iters=25)
+    for u, v in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_rpca_separates_low_rank_and_spikes():
+    Ls, S = _spiky(30, 30, 5, 2, 0.05, seed=1)
+    L, E, Y, hist = D.admm_rpca(Ls + S, D.rpca_lambda(Ls.shape), iters=200, L_true=Ls)
+    assert hist[-1]["rse"] < 1e-10
+    assert T.rel_fro(E, S) < 1e-10
+
+
+def test_cur_tnn_reproduces_exact_rank_observed_in_full():
+    Ls = _lowrank(30, 36, 5, 2, seed=3)
+    ci, ri = np.array([0, 3, 7, 11, 20, 35]), np.array([1, 2, 9, 17, 29])
+    L, Ct, Rt = D.cur_tnn(Ls, ci, ri, mask=np.ones(Ls.shape, np.uint8), iters=100)
+    assert T.rel_fro(Ct, Ls[:, ci, :]) < 1e-12
+    assert T.rel_fro(L, Ls) < 1e-12
+
+
+def test_cur_tnn_robust_pca_recovers_low_rank():
+    Ls, S = _spiky(30, 36, 5, 2, 0.05, seed=3)
+    g = np.random.default_rng(2)
+    ci, ri = np.sort(g.choice(36, 18, replace=False)), np.sort(g.choice(30, 16, replace=False))
+    L, Ct, Rt = D.cur_tnn(Ls + S, ci, ri, lam=D.rpca_lambda(Ls.shape), iters=200)
+    assert T.rel_fro(Rt, Ls[ri]) < 1e-10
+    assert T.rel_fro(L, Ls) < 1e-10
+
+
+def test_cur_tnn_structure_on_noisy_data():
+    # L = Ct * W^+ * Rt with W = Ct[ri]: every lateral slice of L lies in the
+    # t-range of Ct, and with l >= c = rank(W) the picked rows of L are the
+    # projection of Rt onto the t-range of W
+    X = _lowrank(16, 18, 4, 2, seed=5) + 0.2 * rs.standard_normal((16, 18, 4))
+    ci, ri = np.array([1, 4, 6, 13]), np.array([0, 2, 3, 8, 10, 15])
+    L, Ct, Rt = D.cur_tnn(X, ci, ri, lam=0.2, iters=30)
+    assert T.rel_fro(D.tproject(L, Ct), L) < 1e-10
+    assert T.rel_fro(L[ri], D.tproject(Rt, Ct[ri])) < 1e-10
+    assert T.rel_fro(L[ri], Rt) > 1e-3
+
+
+def test_cur_tnn_with_every_slice_is_the_admm():
+    X = _lowrank(12, 14, 5, 2, seed=6) + 0.3 * rs.standard_normal((12, 14, 5))
+    lam = D.rpca_lambda(X.shape)
+    L, Ct, _ = D.cur_tnn(X, np.arange(14), np.arange(12), lam=lam, iters=40)
+    La = D.admm_rpca(X, lam, iters=40)[0]
+    np.testing.assert_array_equal(Ct, La)
+    assert T.rel_fro(L, La) < 1e-12
