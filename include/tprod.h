@@ -235,7 +235,8 @@ size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, in
                          int prec);
 
 /* ---------------------------------------------------------------------------
- * Singular value thresholding and completion (Algorithm 7; eqs. tnuc, tlow6).
+ * Singular value thresholding, completion, robust PCA and CUR t-NN
+ * (Algorithms 6-7; eqs. tnuc, tlow6, tlow7).
  * ------------------------------------------------------------------------- */
 
 /* L = t-SVT(M, tau): in every Fourier slice, U max(Sigma - tau, 0) V^H, the
@@ -265,6 +266,44 @@ int tp_tcomplete(const tp_tensor* X, const uint8_t* mask, int32_t iters, double 
                  tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
                  void* stream);
 size_t tp_tcomplete_workspace(const tp_tensor* X);
+
+/* Robust tensor PCA by Algorithm 7 as stated (eq. tlow7: minimise
+ * ||L||_TNN + lambda ||E||_1 subject to X = L + E). From L = E = Y = 0 and
+ * mu = mu0, every iteration does
+ *   L <- t-SVT(X - E - Y/mu, 1/mu);
+ *   E <- sign(V) max(|V| - lambda/mu, 0) with V = X - L - Y/mu;
+ *   Y <- Y + mu (L + E - X);  mu <- min(rho mu, mu_max)
+ * for exactly `iters` iterations. X, L, E, Y: tube-major float32 of one
+ * shape (caller-owned device buffers; L, E, Y are overwritten); lambda > 0
+ * (the paper gives no value; 1/sqrt(max(n1, n2) n3) is the usual choice);
+ * ranks as for tp_tcomplete. Workspace: tp_trpca_workspace(X) bytes. */
+int tp_trpca(const tp_tensor* X, double lambda, int32_t iters, double rho, double mu0, double mu_max, tp_tensor* L,
+             tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes, void* stream);
+size_t tp_trpca_workspace(const tp_tensor* X);
+
+/* CUR t-NN (Algorithm 6): c lateral slices C of X picked by col_kind (as
+ * for tp_tcur: TP_P_USER with col_w, TP_P_UNIFORM, TP_P_NORM2, or TP_P_LEV =
+ * lateral leverage of X, eq. cur-col-prob), cleaned by the ADMM of
+ * Algorithm 7 (Ct); l horizontal slices R of X picked by row_kind
+ * (TP_P_LEV = horizontal leverage of Ct, eq. colprob_rows_exact; TP_P_NORM2
+ * = squared norms of X's horizontal slices), cleaned likewise (Rt); then
+ *     L = Ct * pinv_r(W) * Rt,   W = the picked horizontal slices of Ct,
+ * with the rank-r pseudo-inverse of every Fourier slice computed as in
+ * tp_tcur. The picked slices are used as they are (Algorithm 6 does not
+ * rescale them); cols/rows receive the picks (their scales are written but
+ * not used). mask != NULL: completion (eq. tlow6; X holds the observed
+ * values, mask is tube-major uint8 of X's shape, nonzero where observed) and
+ * lambda is ignored; mask == NULL: robust PCA (eq. tlow7) with weight
+ * lambda > 0, the same for C and R. mode TP_S_IID or TP_S_UNIFORM (exactly
+ * c and l picks); 1 <= r <= min(c, l), r + 10 <= 64; float32 data, prec
+ * TP_PREC_F32. L (float32, X's shape) is overwritten. Workspace:
+ * tp_tcur_nn_workspace(X, c, l, r, col_kind, row_kind, mask != NULL). */
+int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c, int64_t l, int64_t r, int col_kind,
+               const double* col_w, int row_kind, const double* row_w, int mode, uint64_t seed, int32_t iters,
+               double rho, double mu0, double mu_max, tp_sample* cols, tp_sample* rows, tp_tensor* L, int prec,
+               void* ws, size_t ws_bytes, void* stream);
+size_t tp_tcur_nn_workspace(const tp_tensor* X, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind,
+                            int masked);
 
 /* ---------------------------------------------------------------------------
  * Learned lateral-leverage proposal (not in the paper; the exact scores of

@@ -55,6 +55,14 @@ _SIGS = {
     "tp_tcomplete": (C.c_int, [P(Tensor), C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
                                P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tcomplete_workspace": (C.c_size_t, [P(Tensor)]),
+    "tp_trpca": (C.c_int, [P(Tensor), C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
+                           P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_trpca_workspace": (C.c_size_t, [P(Tensor)]),
+    "tp_tcur_nn": (C.c_int, [P(Tensor), C.c_void_p, C.c_double, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                             C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_uint64, C.c_int32, C.c_double,
+                             C.c_double, C.c_double, P(Sample), P(Sample), P(Tensor), C.c_int, C.c_void_p,
+                             C.c_size_t, C.c_void_p]),
+    "tp_tcur_nn_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int]),
     "tp_trace_enable": (C.c_int, [C.c_int]),
     "tp_trace_count": (C.c_int, []),
     "tp_trace_entry": (C.c_int, [C.c_int, C.c_char_p, C.c_size_t, P(C.c_int64), P(C.c_double)]),

@@ -248,6 +248,51 @@ def tcomplete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
     return L_, E, Y, ranks
 
 
+def trpca(X, lam=None, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
+    """Robust tensor PCA by the ADMM of Algorithm 7 (eq. tlow7): returns
+    (L, E, Y, ranks of the last iteration). lam defaults to
+    1/sqrt(max(n1, n2) n3)."""
+    _need_gpu(X)
+    n1, n2, n3 = X.shape
+    if lam is None:
+        lam = 1.0 / (max(n1, n2) * n3) ** 0.5
+    L_, E, Y = torch.empty_like(X), torch.empty_like(X), torch.empty_like(X)
+    ranks = torch.empty(half_count(n3), dtype=torch.int32, device=X.device)
+    lib = L.load()
+    tx = _tensor(X)
+    ws = _ws(lib.tp_trpca_workspace(C.byref(tx)), X.device)
+    L.check(lib.tp_trpca(C.byref(tx), float(lam), int(iters), float(rho), float(mu0), float(mu_max),
+                         C.byref(_tensor(L_)), C.byref(_tensor(E)), C.byref(_tensor(Y)), ranks.data_ptr(),
+                         L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream()))
+    return L_, E, Y, ranks
+
+
+def tcur_nn(X, c, l, r, mask=None, lam=None, col_kind="uniform", row_kind="uniform", col_w=None, row_w=None,
+            mode="uniform", seed=0, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, out=None):
+    """CUR t-NN of Algorithm 6: returns (L, column picks, row picks). With a
+    uint8 mask (nonzero where observed) the ADMM is the completion variant,
+    otherwise robust PCA with weight lam (default 1/sqrt(max(n1, n2) n3))."""
+    _need_gpu(X, mask, col_w, row_w)
+    n1, n2, n3 = X.shape
+    if mask is not None and (mask.dtype != torch.uint8 or mask.shape != X.shape):
+        raise ValueError("mask must be uint8 with X's shape")
+    if lam is None:
+        lam = 1.0 / (max(n1, n2) * n3) ** 0.5
+    cols, rows = Picks(c, X.device), Picks(l, X.device)
+    L_ = out if out is not None else torch.empty_like(X)
+    lib = L.load()
+    tx = _tensor(X)
+    cs, rs_ = cols.struct(), rows.struct()
+    ws = _ws(lib.tp_tcur_nn_workspace(C.byref(tx), int(c), int(l), int(r), L.KIND[col_kind], L.KIND[row_kind],
+                                      1 if mask is not None else 0), X.device)
+    L.check(lib.tp_tcur_nn(C.byref(tx), mask.data_ptr() if mask is not None else None, float(lam), int(c), int(l),
+                           int(r), L.KIND[col_kind], col_w.data_ptr() if col_w is not None else None,
+                           L.KIND[row_kind], row_w.data_ptr() if row_w is not None else None, L.MODE[mode],
+                           int(seed), int(iters), float(rho), float(mu0), float(mu_max), C.byref(cs), C.byref(rs_),
+                           C.byref(_tensor(L_)), L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream()))
+    return L_, cols, rows
+
+
 # ---------------------------------------------------------------------------
 # launch tracing
 # ---------------------------------------------------------------------------

@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "linalg.hpp"
+#include "svt.hpp"
 
 namespace tp {
 namespace {
@@ -239,6 +240,129 @@ struct TcurLayout {
   }
 };
 
+// Lateral leverage of A (eq. cur-col-prob) from the rank-r randomized t-SVD
+// (p = 10, q = 1): lay.wbuf gets n2 unnormalised scores.
+int col_leverage(TcurLayout& lay, const void* A, int dt, int64_t n1, int64_t n2, int64_t n3, int64_t K, int64_t r,
+                 uint64_t seed, int prec, bool real_last, double rtol, hipStream_t st) {
+  TubeGather g;
+  g.rows = n1;
+  g.cols = n2;
+  g.in_cols = n2;
+  const int s = lay.sA;
+  if (int rc = fft_forward(A, dt, n3, g, lay.Ah.re, lay.Ah.im, st)) return rc;
+  if (int rc = lay.rfA.run(lay.Ah, kPowerIters, seed, kStreamOmegaA, prec, st)) return rc;
+  if (int rc = eig_transform(lay.rfA.ure, lay.rfA.uim, lay.rfA.evals, K, s, (int)r, 1, rtol, 0.0, lay.UbA.re,
+                             lay.UbA.im, dt, st))
+    return rc;
+  if (int rc = mm(lay.rfA.Bh, 0, n2, s, lay.UbA, 0, s, r, lay.Vs, K, real_last, dt, prec, st)) return rc;
+  return leverage(lay.Vs.re, lay.Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, lay.rfA.evals, s, rtol, lay.lpart,
+                  lay.wbuf, st);
+}
+
+// Horizontal leverage of C (eq. colprob_rows_exact) from the top-r left
+// singular slices of the spectrum in lay.Ch: lay.wbuf2 gets n1 scores.
+int row_leverage(TcurLayout& lay, int dt, int64_t n1, int64_t K, int64_t r, uint64_t seed, int prec, bool real_last,
+                 double rtol, const int64_t* ccount, hipStream_t st) {
+  const int s = lay.sC;
+  if (int rc = lay.rfC.run(lay.Ch, kPowerIters, seed, kStreamOmegaC, prec, st, ccount)) return rc;
+  if (int rc = eig_transform(lay.rfC.ure, lay.rfC.uim, lay.rfC.evals, K, s, (int)r, 1, rtol, 0.0, lay.UbC.re,
+                             lay.UbC.im, dt, st))
+    return rc;
+  if (int rc = mm(lay.rfC.Q, 0, n1, s, lay.UbC, 0, s, r, lay.Us, K, real_last, dt, prec, st)) return rc;
+  return leverage(lay.Us.re, lay.Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol, lay.lpart,
+                  lay.wbuf2, st);
+}
+
+// The core and the reconstruction shared by t-CUR and CUR t-NN, from the
+// spectra lay.Ch (n1 x capc) and lay.Rh (capl x n2): W_k = D S^T Chat_k (the
+// rows ridx of Chat_k, times rscale when given), Uhat_k = pinv_r(W_k) in
+// float64 through a range finder on W_k (pinv_r(W) = V_r diag(1/sigma)
+// U_r^H with U_r = Q U_B,r and V_r = Bh U_B,r diag(1/sigma)), then
+// Zhat_k = (Chat_k P_k)(U_r,k^H Rhat_k) and Z = ifft(Zhat).
+int cur_core(TcurLayout& lay, int64_t n1, int64_t n2, int64_t n3, int64_t K, int64_t capc, int64_t capl, int64_t r,
+             const int32_t* ridx, const double* rscale, const int64_t* rcount, uint64_t seed, int dt, int prec,
+             bool real_last, void* Z, hipStream_t st) {
+  const int sw = lay.sw;
+  if (int rc = gather_rows(lay.Ch.re, lay.Ch.im, dt, K, n1, capc, ridx, rscale, rcount, capl, lay.W.re, lay.W.im,
+                           TP_F64, st))
+    return rc;
+  // keep sigma_i > max(l, c) eps sigma_1 among the leading r
+  const double core_rtol = double(std::max(capl, capc)) * 2.220446049250313e-16;
+  Spec Pw = lay.P64, Uw = lay.U64;
+  if (core_pinv_fits(capl, capc, sw, r)) {
+    // small cores: the whole range finder, eigen-decomposition and factors
+    // in one workgroup per Fourier slice
+    if (int rc = randn_spectrum(lay.cf.omega.re, lay.cf.omega.im, TP_F64, K, capc, sw, real_last, seed,
+                                kStreamOmegaW, st))
+      return rc;
+    const bool f32 = dt == TP_F32;
+    if (int rc = core_pinv((const double*)lay.W.re, (const double*)lay.W.im, (const double*)lay.cf.omega.re,
+                           (const double*)lay.cf.omega.im, K, capl, capc, sw, r, real_last, kCorePowerIters,
+                           core_rtol, (double*)lay.P64.re, (double*)lay.P64.im, (double*)lay.U64.re,
+                           (double*)lay.U64.im, f32 ? (float*)lay.P.re : nullptr, f32 ? (float*)lay.P.im : nullptr,
+                           f32 ? (float*)lay.Ur.re : nullptr, f32 ? (float*)lay.Ur.im : nullptr, st))
+      return rc;
+    if (f32) {
+      Pw = lay.P;
+      Uw = lay.Ur;
+    }
+  } else {
+    if (int rc = lay.cf.run(lay.W, kCorePowerIters, seed, kStreamOmegaW, TP_PREC_F64, st)) return rc;
+    if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 2.0, lay.Tp.re,
+                               lay.Tp.im, TP_F64, st))
+      return rc;
+    if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 0.0, lay.Tr.re,
+                               lay.Tr.im, TP_F64, st))
+      return rc;
+    // P = Bh U_B,r diag(sigma^-2) = V_r diag(1/sigma) (c x r); U_r = Q U_B,r (l x r)
+    if (int rc = mm(lay.cf.Bh, 0, capc, sw, lay.Tp, 0, sw, r, lay.P64, K, real_last, TP_F64, TP_PREC_F64, st))
+      return rc;
+    if (int rc = mm(lay.cf.Q, 0, capl, sw, lay.Tr, 0, sw, r, lay.U64, K, real_last, TP_F64, TP_PREC_F64, st))
+      return rc;
+    if (dt == TP_F32) {
+      if (int rc = convert(lay.P64.re, TP_F64, lay.P.re, TP_F32, K * capc * r, st)) return rc;
+      if (int rc = convert(lay.P64.im, TP_F64, lay.P.im, TP_F32, K * capc * r, st)) return rc;
+      if (int rc = convert(lay.U64.re, TP_F64, lay.Ur.re, TP_F32, K * capl * r, st)) return rc;
+      if (int rc = convert(lay.U64.im, TP_F64, lay.Ur.im, TP_F32, K * capl * r, st)) return rc;
+      Pw = lay.P;
+      Uw = lay.Ur;
+    }
+  }
+  // Zhat_k = Chat_k Uhat_k Rhat_k = (Chat_k P_k) (U_r,k^H Rhat_k), then ifft
+  if (int rc = mm(lay.Ch, 0, n1, capc, Pw, 0, capc, r, lay.F, K, real_last, dt, prec, st)) return rc;
+  if (int rc = mm(Uw, 1, capl, r, lay.Rh, 0, capl, n2, lay.G, K, real_last, dt, prec, st)) return rc;
+  if (int rc = mm(lay.F, 0, n1, r, lay.G, 0, r, n2, lay.Zh, K, real_last, dt, prec, st)) return rc;
+  return fft_inverse(lay.Zh.re, lay.Zh.im, dt, n3, n1, n2, Z, st);
+}
+
+// Time-domain parts of CUR t-NN: the picked slices C (n1 x c) and R (l x n2)
+// with their masks, and the ADMM iterates of each.
+struct CurNNLayout {
+  float *cx = nullptr, *cl = nullptr, *ce = nullptr, *cy = nullptr;
+  float *rx = nullptr, *rl = nullptr, *re = nullptr, *ry = nullptr;
+  uint8_t *cm = nullptr, *rm = nullptr;
+  void* admm = nullptr;
+  size_t admm_bytes = 0;
+  bool carve(Arena& ar, int64_t n1, int64_t n2, int64_t n3, int64_t c, int64_t l, bool masked) {
+    const int64_t nc = n1 * c * n3, nr = l * n2 * n3;
+    cx = ar.take<float>(nc);
+    cl = ar.take<float>(nc);
+    ce = ar.take<float>(nc);
+    cy = ar.take<float>(nc);
+    rx = ar.take<float>(nr);
+    rl = ar.take<float>(nr);
+    re = ar.take<float>(nr);
+    ry = ar.take<float>(nr);
+    if (masked) {
+      cm = ar.take<uint8_t>(nc);
+      rm = ar.take<uint8_t>(nr);
+    }
+    admm_bytes = std::max(admm_workspace(n1, c, n3), admm_workspace(l, n2, n3));
+    admm = ar.take<char>(admm_bytes);
+    return ar.dry() || ar.ok();
+  }
+};
+
 }  // namespace
 }  // namespace tp
 
@@ -361,20 +485,7 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
   //    from caller weights)
   const double* wcol = col_w;
   if (col_kind == TP_P_LEV) {
-    TubeGather g;
-    g.rows = n1;
-    g.cols = n2;
-    g.in_cols = n2;
-    const int s = lay.sA;
-    if (int rc = fft_forward(A->data, dt, n3, g, lay.Ah.re, lay.Ah.im, st)) return rc;
-    if (int rc = lay.rfA.run(lay.Ah, kPowerIters, seed, kStreamOmegaA, prec, st)) return rc;
-    if (int rc = eig_transform(lay.rfA.ure, lay.rfA.uim, lay.rfA.evals, K, s, (int)r, 1, rtol, 0.0, lay.UbA.re,
-                               lay.UbA.im, dt, st))
-      return rc;
-    if (int rc = mm(lay.rfA.Bh, 0, n2, s, lay.UbA, 0, s, r, lay.Vs, K, real_last, dt, prec, st)) return rc;
-    if (int rc = leverage(lay.Vs.re, lay.Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, lay.rfA.evals, s, rtol,
-                          lay.lpart, lay.wbuf, st))
-      return rc;
+    if (int rc = col_leverage(lay, A->data, dt, n1, n2, n3, K, r, seed, prec, real_last, rtol, st)) return rc;
     wcol = lay.wbuf;
   } else if (col_kind == TP_P_NORM2) {
     if (int rc = lateral_norms(A->data, dt, n1, n2, n3, lay.wbuf, lay.part, st)) return rc;
@@ -403,15 +514,7 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
   //    Frobenius norm) and picks
   const double* wrow = row_w;
   if (row_kind == TP_P_LEV) {
-    const int s = lay.sC;
-    if (int rc = lay.rfC.run(lay.Ch, kPowerIters, seed, kStreamOmegaC, prec, st, cols->count)) return rc;
-    if (int rc = eig_transform(lay.rfC.ure, lay.rfC.uim, lay.rfC.evals, K, s, (int)r, 1, rtol, 0.0, lay.UbC.re,
-                               lay.UbC.im, dt, st))
-      return rc;
-    if (int rc = mm(lay.rfC.Q, 0, n1, s, lay.UbC, 0, s, r, lay.Us, K, real_last, dt, prec, st)) return rc;
-    if (int rc = leverage(lay.Us.re, lay.Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol,
-                          lay.lpart, lay.wbuf2, st))
-      return rc;
+    if (int rc = row_leverage(lay, dt, n1, K, r, seed, prec, real_last, rtol, cols->count, st)) return rc;
     wrow = lay.wbuf2;
   } else if (row_kind == TP_P_NORM2) {
     if (int rc = horizontal_norms(A->data, dt, n1, n2, n3, lay.wbuf2, st)) return rc;
@@ -437,60 +540,131 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
     if (int rc = fft_forward(A->data, dt, n3, g, lay.Rh.re, lay.Rh.im, st)) return rc;
   }
 
-  // 5. core: Uhat_k = pinv_r(D S^T Chat_k), in float64, through a range
-  //    finder on W_k = D S^T Chat_k (l x c): pinv_r(W) = V_r diag(1/sigma) U_r^H
-  //    with U_r = Q U_B,r and V_r = Bh U_B,r diag(1/sigma).
-  const int sw = lay.sw;
-  if (int rc = gather_rows(lay.Ch.re, lay.Ch.im, dt, K, n1, capc, rows->idx, rows->scale, rows->count, capl,
-                           lay.W.re, lay.W.im, TP_F64, st))
-    return rc;
-  // keep sigma_i > max(l, c) eps sigma_1 among the leading r
-  const double core_rtol = double(std::max(capl, capc)) * 2.220446049250313e-16;
-  Spec Pw = lay.P64, Uw = lay.U64;
-  if (core_pinv_fits(capl, capc, sw, r)) {
-    // small cores: the whole range finder, eigen-decomposition and factors
-    // in one workgroup per Fourier slice
-    if (int rc = randn_spectrum(lay.cf.omega.re, lay.cf.omega.im, TP_F64, K, capc, sw, real_last, seed,
-                                kStreamOmegaW, st))
-      return rc;
-    const bool f32 = dt == TP_F32;
-    if (int rc = core_pinv((const double*)lay.W.re, (const double*)lay.W.im, (const double*)lay.cf.omega.re,
-                           (const double*)lay.cf.omega.im, K, capl, capc, sw, r, real_last, kCorePowerIters,
-                           core_rtol, (double*)lay.P64.re, (double*)lay.P64.im, (double*)lay.U64.re,
-                           (double*)lay.U64.im, f32 ? (float*)lay.P.re : nullptr, f32 ? (float*)lay.P.im : nullptr,
-                           f32 ? (float*)lay.Ur.re : nullptr, f32 ? (float*)lay.Ur.im : nullptr, st))
-      return rc;
-    if (f32) {
-      Pw = lay.P;
-      Uw = lay.Ur;
-    }
-  } else {
-    if (int rc = lay.cf.run(lay.W, kCorePowerIters, seed, kStreamOmegaW, TP_PREC_F64, st)) return rc;
-    if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 2.0, lay.Tp.re,
-                               lay.Tp.im, TP_F64, st))
-      return rc;
-    if (int rc = eig_transform(lay.cf.ure, lay.cf.uim, lay.cf.evals, K, sw, (int)r, 1, core_rtol, 0.0, lay.Tr.re,
-                               lay.Tr.im, TP_F64, st))
-      return rc;
-    // P = Bh U_B,r diag(sigma^-2) = V_r diag(1/sigma) (c x r); U_r = Q U_B,r (l x r)
-    if (int rc = mm(lay.cf.Bh, 0, capc, sw, lay.Tp, 0, sw, r, lay.P64, K, real_last, TP_F64, TP_PREC_F64, st))
-      return rc;
-    if (int rc = mm(lay.cf.Q, 0, capl, sw, lay.Tr, 0, sw, r, lay.U64, K, real_last, TP_F64, TP_PREC_F64, st))
-      return rc;
-    if (dt == TP_F32) {
-      if (int rc = convert(lay.P64.re, TP_F64, lay.P.re, TP_F32, K * capc * r, st)) return rc;
-      if (int rc = convert(lay.P64.im, TP_F64, lay.P.im, TP_F32, K * capc * r, st)) return rc;
-      if (int rc = convert(lay.U64.re, TP_F64, lay.Ur.re, TP_F32, K * capl * r, st)) return rc;
-      if (int rc = convert(lay.U64.im, TP_F64, lay.Ur.im, TP_F32, K * capl * r, st)) return rc;
-      Pw = lay.P;
-      Uw = lay.Ur;
-    }
+  // 5-6. core Uhat_k = pinv_r(D S^T Chat_k) and Z = ifft(Chat_k Uhat_k Rhat_k)
+  return cur_core(lay, n1, n2, n3, K, capc, capl, r, rows->idx, rows->scale, rows->count, seed, dt, prec, real_last,
+                  Z->data, st);
+}
+
+size_t tp_tcur_nn_workspace(const tp_tensor* X, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind,
+                            int masked) {
+  if (!X || X->n1 < 1 || X->n2 < 1 || X->n3 < 1 || r < 1 || c < 1 || l < 1) return 0;
+  const int64_t K = half_count(X->n3);
+  Arena dry(nullptr, SIZE_MAX);
+  TcurLayout lay;
+  lay.carve(dry, K, X->n1, X->n2, X->n3, c, l, r, col_kind, row_kind, true, TP_F32, (X->n3 % 2 == 0) && K > 1);
+  CurNNLayout nn;
+  nn.carve(dry, X->n1, X->n2, X->n3, c, l, masked != 0);
+  return dry.used + 256;
+}
+
+int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c, int64_t l, int64_t r, int col_kind,
+               const double* col_w, int row_kind, const double* row_w, int mode, uint64_t seed, int32_t iters,
+               double rho, double mu0, double mu_max, tp_sample* cols, tp_sample* rows, tp_tensor* L, int prec,
+               void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_tensor(X, "X")) return rc;
+  if (int rc = check_tensor(L, "L")) return rc;
+  if (X->dtype != TP_F32 || L->dtype != TP_F32) return fail(TP_EDTYPE, "CUR t-NN runs on float32 data");
+  if (prec != TP_PREC_F32) return fail(TP_EDTYPE, "CUR t-NN supports TP_PREC_F32");
+  const int64_t n1 = X->n1, n2 = X->n2, n3 = X->n3, K = half_count(n3);
+  if (L->n1 != n1 || L->n2 != n2 || L->n3 != n3) return fail(TP_ESHAPE, "L must match X");
+  if (c < 1 || c > n2) return fail(TP_EINVAL, "need 1 <= c <= n2");
+  if (l < 1 || l > n1) return fail(TP_EINVAL, "need 1 <= l <= n1");
+  if (r < 1 || r > std::min(c, l)) return fail(TP_EINVAL, "need 1 <= r <= min(c, l)");
+  if (mode != TP_S_IID && mode != TP_S_UNIFORM)
+    return fail(TP_EINVAL, "CUR t-NN needs exactly c and l picks (TP_S_IID or TP_S_UNIFORM)");
+  auto kind_ok = [](int k) { return k == TP_P_USER || k == TP_P_UNIFORM || k == TP_P_NORM2 || k == TP_P_LEV; };
+  if (!kind_ok(col_kind) || !kind_ok(row_kind)) return fail(TP_EINVAL, "unsupported probability kind");
+  if (col_kind == TP_P_USER && !col_w) return fail(TP_EINVAL, "column weights are null");
+  if (row_kind == TP_P_USER && !row_w) return fail(TP_EINVAL, "row weights are null");
+  if (!mask && (!(lambda > 0.0) || !std::isfinite(lambda))) return fail(TP_EINVAL, "lambda must be finite and > 0");
+  if (iters < 1) return fail(TP_EINVAL, "need at least one iteration");
+  if (!(rho >= 1.0) || !(mu0 > 0.0) || !(mu_max >= mu0) || !std::isfinite(rho) || !std::isfinite(mu_max))
+    return fail(TP_EINVAL, "need rho >= 1 and 0 < mu0 <= mu_max");
+  if (!cols || !rows || !cols->idx || !cols->scale || !cols->count || !rows->idx || !rows->scale || !rows->count)
+    return fail(TP_EINVAL, "pick buffers are null");
+  if (cols->cap < c || rows->cap < l) return fail(TP_EINVAL, "pick capacity must be >= c, l");
+  if (sketch_size(r, kOversample, n1, n2) > kMaxS) return fail(TP_EUNSUPPORTED, "r + 10 above 64");
+  const size_t need = tp_tcur_nn_workspace(X, c, l, r, col_kind, row_kind, mask != nullptr);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "CUR t-NN workspace too small");
+
+  const int dt = TP_F32;
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  TcurLayout lay;
+  CurNNLayout nn;
+  if (!lay.carve(ar, K, n1, n2, n3, c, l, r, col_kind, row_kind, true, dt, real_last) ||
+      !nn.carve(ar, n1, n2, n3, c, l, mask != nullptr))
+    return fail(TP_EWORKSPACE, "CUR t-NN workspace too small");
+  const double rtol = 1e-6;
+
+  // 1. lateral slices C of X by col_kind (eq. cur-col-prob for TP_P_LEV),
+  //    taken without rescaling
+  const double* wcol = col_w;
+  if (col_kind == TP_P_LEV) {
+    if (int rc = col_leverage(lay, X->data, dt, n1, n2, n3, K, r, seed, prec, real_last, rtol, st)) return rc;
+    wcol = lay.wbuf;
+  } else if (col_kind == TP_P_NORM2) {
+    if (int rc = lateral_norms(X->data, dt, n1, n2, n3, lay.wbuf, lay.part, st)) return rc;
+    wcol = lay.wbuf;
+  } else if (col_kind == TP_P_UNIFORM) {
+    if (int rc = fill_f64(lay.wbuf, n2, 1.0, st)) return rc;
+    wcol = lay.wbuf;
   }
-  // 6. Zhat_k = Chat_k Uhat_k Rhat_k = (Chat_k P_k) (U_r,k^H Rhat_k), then ifft
-  if (int rc = mm(lay.Ch, 0, n1, capc, Pw, 0, capc, r, lay.F, K, real_last, dt, prec, st)) return rc;
-  if (int rc = mm(Uw, 1, capl, r, lay.Rh, 0, capl, n2, lay.G, K, real_last, dt, prec, st)) return rc;
-  if (int rc = mm(lay.F, 0, n1, r, lay.G, 0, r, n2, lay.Zh, K, real_last, dt, prec, st)) return rc;
-  return fft_inverse(lay.Zh.re, lay.Zh.im, dt, n3, n1, n2, Z->data, st);
+  if (int rc = sample_slices(wcol, n2, c, mode, seed, kStreamColPick, cols->idx, cols->scale, cols->count, lay.sws,
+                             st))
+    return rc;
+  if (int rc = gather_slices(X->data, 4, n2, n3, nullptr, cols->idx, cols->count, n1, c, nn.cx, st)) return rc;
+  if (mask)
+    if (int rc = gather_slices(mask, 1, n2, n3, nullptr, cols->idx, cols->count, n1, c, nn.cm, st)) return rc;
+
+  // 2. Ct = ADMM(C), and its spectrum
+  if (int rc = admm_run(nn.cx, nn.cm, lambda, n1, c, n3, iters, rho, mu0, mu_max, nn.cl, nn.ce, nn.cy, nullptr,
+                        nn.admm, nn.admm_bytes, st))
+    return rc;
+  {
+    TubeGather g;
+    g.rows = n1;
+    g.cols = c;
+    g.in_cols = c;
+    if (int rc = fft_forward(nn.cl, dt, n3, g, lay.Ch.re, lay.Ch.im, st)) return rc;
+  }
+
+  // 3. horizontal slices R of X by row_kind (eq. colprob_rows_exact, the
+  //    horizontal leverage of the cleaned Ct, for TP_P_LEV)
+  const double* wrow = row_w;
+  if (row_kind == TP_P_LEV) {
+    if (int rc = row_leverage(lay, dt, n1, K, r, seed, prec, real_last, rtol, nullptr, st)) return rc;
+    wrow = lay.wbuf2;
+  } else if (row_kind == TP_P_NORM2) {
+    if (int rc = horizontal_norms(X->data, dt, n1, n2, n3, lay.wbuf2, st)) return rc;
+    wrow = lay.wbuf2;
+  } else if (row_kind == TP_P_UNIFORM) {
+    if (int rc = fill_f64(lay.wbuf2, n1, 1.0, st)) return rc;
+    wrow = lay.wbuf2;
+  }
+  if (int rc = sample_slices(wrow, n1, l, mode, seed, kStreamRowPick, rows->idx, rows->scale, rows->count, lay.sws,
+                             st))
+    return rc;
+  if (int rc = gather_slices(X->data, 4, n2, n3, rows->idx, nullptr, rows->count, l, n2, nn.rx, st)) return rc;
+  if (mask)
+    if (int rc = gather_slices(mask, 1, n2, n3, rows->idx, nullptr, rows->count, l, n2, nn.rm, st)) return rc;
+
+  // 4. Rt = ADMM(R), and its spectrum
+  if (int rc = admm_run(nn.rx, nn.rm, lambda, l, n2, n3, iters, rho, mu0, mu_max, nn.rl, nn.re, nn.ry, nullptr,
+                        nn.admm, nn.admm_bytes, st))
+    return rc;
+  {
+    TubeGather g;
+    g.rows = l;
+    g.cols = n2;
+    g.in_cols = n2;
+    if (int rc = fft_forward(nn.rl, dt, n3, g, lay.Rh.re, lay.Rh.im, st)) return rc;
+  }
+
+  // 5. W = the picked rows of Ct (unscaled), U = pinv_r(W), L = Ct * U * Rt
+  return cur_core(lay, n1, n2, n3, K, c, l, r, rows->idx, nullptr, rows->count, seed, dt, prec, real_last, L->data,
+                  st);
 }
 
 }  // extern "C"

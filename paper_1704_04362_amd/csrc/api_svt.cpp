@@ -1,7 +1,8 @@
 // C ABI of the per-Fourier-slice singular value thresholding (the
 // tensor-nuclear-norm prox, i.e. the L-update of Algorithm 7) and of the
-// ADMM completion loop (Algorithm 7 adapted to the completion problem of
-// eq. tlow6). Validation, workspace layout and kernel order only.
+// ADMM loops: Algorithm 7 as stated for robust tensor PCA (eq. tlow7) and
+// adapted to the completion problem of eq. tlow6. Validation, workspace
+// layout and kernel order only.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -75,7 +76,94 @@ int finish_svt(SvtLayout& lay, int64_t K, int64_t n1, int64_t n2, int64_t n3, do
   return fft_inverse(lay.lre, lay.lim, TP_F32, n3, n1, n2, Lout, st);
 }
 
+int check_admm(const tp_tensor* X, const tp_tensor* L, const tp_tensor* E, const tp_tensor* Y, int32_t iters,
+               double rho, double mu0, double mu_max, int prec) {
+  if (int rc = check_f32_tensor(X, "X")) return rc;
+  if (int rc = check_f32_tensor(L, "L")) return rc;
+  if (int rc = check_f32_tensor(E, "E")) return rc;
+  if (int rc = check_f32_tensor(Y, "Y")) return rc;
+  if (prec != TP_PREC_F32) return fail(TP_EDTYPE, "the ADMM supports TP_PREC_F32");
+  for (const tp_tensor* t : {L, E, Y})
+    if (t->n1 != X->n1 || t->n2 != X->n2 || t->n3 != X->n3) return fail(TP_ESHAPE, "L, E, Y must match X");
+  if (iters < 1) return fail(TP_EINVAL, "need at least one iteration");
+  if (!(rho >= 1.0) || !(mu0 > 0.0) || !(mu_max >= mu0) || !std::isfinite(rho) || !std::isfinite(mu_max))
+    return fail(TP_EINVAL, "need rho >= 1 and 0 < mu0 <= mu_max");
+  return TP_OK;
+}
+
 }  // namespace
+
+size_t admm_workspace(int64_t n1, int64_t n2, int64_t n3) {
+  Arena dry(nullptr, SIZE_MAX);
+  SvtLayout lay;
+  lay.carve(dry, half_count(n3), n1, n2, n3, true);
+  return dry.used + 256;
+}
+
+int admm_run(const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3, int iters,
+             double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks, void* ws,
+             size_t ws_bytes, hipStream_t st) {
+  const size_t need = admm_workspace(n1, n2, n3);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "ADMM workspace too small");
+  const int64_t K = half_count(n3), n = n1 * n2 * n3;
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  Arena ar(ws, ws_bytes);
+  SvtLayout lay;
+  if (!lay.carve(ar, K, n1, n2, n3, true)) return fail(TP_EWORKSPACE, "ADMM workspace too small");
+  // L_0 = E_0 = Y_0 = 0
+  if (int rc = zero_f32(e, n, st)) return rc;
+  if (int rc = zero_f32(y, n, st)) return rc;
+  if (int rc = zero_f32(l, n, st)) return rc;
+  if (int rc = svt_identity(lay.ure, lay.uim, K, n1, st)) return rc;
+  double mu = mu0;
+  TubeGather g;
+  g.rows = n1;
+  g.cols = n2;
+  g.in_cols = n2;
+  for (int it = 0; it < iters; ++it) {
+    const float inv_mu = (float)(1.0 / mu);
+    // M = X - E - Y / mu, then its spectrum
+    if (int rc = admm_pre(x, e, y, inv_mu, n, lay.m, st)) return rc;
+    if (int rc = fft_forward(lay.m, TP_F32, n3, g, lay.lre, lay.lim, st)) return rc;
+    // warm start: rotate the new spectrum by the previous iteration's U^H
+    CGemm p;
+    p.K = K;
+    p.M = n1;
+    p.N = n2;
+    p.Kd = n1;
+    p.are = lay.ure;
+    p.aim = lay.uim;
+    p.bre = lay.lre;
+    p.bim = lay.lim;
+    p.cre = lay.xre;
+    p.cim = lay.xim;
+    p.lda = n1;
+    p.ldb = n2;
+    p.ldc = n2;
+    p.sa = n1 * n1;
+    p.sb = n1 * n2;
+    p.sc = n1 * n2;
+    p.real_last = real_last;
+    if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
+    if (int rc = svt_jacobi(lay.xre, lay.xim, lay.ure, lay.uim, K, n1, n2, real_last,
+                            it == 0 ? kColdSweeps : kWarmSweeps, kSvtTol, lay.ratio, lay.conv, st))
+      return rc;
+    // L = SVT(M, 1/mu); the shrink leaves X scaled, so the next warm start
+    // uses Uh only
+    if (int rc = finish_svt(lay, K, n1, n2, n3, 1.0 / mu, real_last, it == iters - 1 ? ranks : nullptr, l, st))
+      return rc;
+    if (mask) {
+      // E = P_unobs(X - L - Y/mu), Y = Y + mu (L + E - X)
+      if (int rc = admm_post(x, mask, l, (float)mu, inv_mu, n, e, y, st)) return rc;
+    } else {
+      // E = shrink(X - L - Y/mu, lam/mu), Y = Y + mu (L + E - X)
+      if (int rc = admm_post_soft(x, l, (float)mu, inv_mu, (float)(lam / mu), n, e, y, st)) return rc;
+    }
+    mu = std::min(rho * mu, mu_max);
+  }
+  return TP_OK;
+}
+
 }  // namespace tp
 
 using namespace tp;
@@ -119,85 +207,26 @@ int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int pr
 
 size_t tp_tcomplete_workspace(const tp_tensor* X) {
   if (!X || X->n1 < 1 || X->n2 < 1 || X->n3 < 1) return 0;
-  Arena dry(nullptr, SIZE_MAX);
-  SvtLayout lay;
-  lay.carve(dry, half_count(X->n3), X->n1, X->n2, X->n3, true);
-  return dry.used + 256;
+  return admm_workspace(X->n1, X->n2, X->n3);
 }
+
+size_t tp_trpca_workspace(const tp_tensor* X) { return tp_tcomplete_workspace(X); }
 
 int tp_tcomplete(const tp_tensor* X, const uint8_t* mask, int32_t iters, double rho, double mu0, double mu_max,
                  tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
                  void* stream) {
-  if (int rc = check_f32_tensor(X, "X")) return rc;
-  if (int rc = check_f32_tensor(L, "L")) return rc;
-  if (int rc = check_f32_tensor(E, "E")) return rc;
-  if (int rc = check_f32_tensor(Y, "Y")) return rc;
   if (!mask) return fail(TP_EINVAL, "mask is null");
-  if (prec != TP_PREC_F32) return fail(TP_EDTYPE, "completion supports TP_PREC_F32");
-  for (const tp_tensor* t : {L, E, Y})
-    if (t->n1 != X->n1 || t->n2 != X->n2 || t->n3 != X->n3) return fail(TP_ESHAPE, "L, E, Y must match X");
-  if (iters < 1) return fail(TP_EINVAL, "need at least one iteration");
-  if (!(rho >= 1.0) || !(mu0 > 0.0) || !(mu_max >= mu0) || !std::isfinite(rho) || !std::isfinite(mu_max))
-    return fail(TP_EINVAL, "need rho >= 1 and 0 < mu0 <= mu_max");
-  const size_t need = tp_tcomplete_workspace(X);
-  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tcomplete workspace too small");
-  const int64_t n1 = X->n1, n2 = X->n2, n3 = X->n3, K = half_count(n3), n = n1 * n2 * n3;
-  const bool real_last = (n3 % 2 == 0) && K > 1;
-  hipStream_t st = S(stream);
-  Arena ar(ws, ws_bytes);
-  SvtLayout lay;
-  if (!lay.carve(ar, K, n1, n2, n3, true)) return fail(TP_EWORKSPACE, "tcomplete workspace too small");
-  float* x = (float*)X->data;
-  float* l = (float*)L->data;
-  float* e = (float*)E->data;
-  float* y = (float*)Y->data;
-  // L_0 = E_0 = Y_0 = 0
-  if (int rc = zero_f32(e, n, st)) return rc;
-  if (int rc = zero_f32(y, n, st)) return rc;
-  if (int rc = zero_f32(l, n, st)) return rc;
-  if (int rc = svt_identity(lay.ure, lay.uim, K, n1, st)) return rc;
-  double mu = mu0;
-  TubeGather g;
-  g.rows = n1;
-  g.cols = n2;
-  g.in_cols = n2;
-  for (int it = 0; it < iters; ++it) {
-    const float inv_mu = (float)(1.0 / mu);
-    // M = X - E - Y / mu, then its spectrum
-    if (int rc = admm_pre(x, e, y, inv_mu, n, lay.m, st)) return rc;
-    if (int rc = fft_forward(lay.m, TP_F32, n3, g, lay.lre, lay.lim, st)) return rc;
-    // warm start: rotate the new spectrum by the previous iteration's U^H
-    CGemm p;
-    p.K = K;
-    p.M = n1;
-    p.N = n2;
-    p.Kd = n1;
-    p.are = lay.ure;
-    p.aim = lay.uim;
-    p.bre = lay.lre;
-    p.bim = lay.lim;
-    p.cre = lay.xre;
-    p.cim = lay.xim;
-    p.lda = n1;
-    p.ldb = n2;
-    p.ldc = n2;
-    p.sa = n1 * n1;
-    p.sb = n1 * n2;
-    p.sc = n1 * n2;
-    p.real_last = real_last;
-    if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
-    if (int rc = svt_jacobi(lay.xre, lay.xim, lay.ure, lay.uim, K, n1, n2, real_last,
-                            it == 0 ? kColdSweeps : kWarmSweeps, kSvtTol, lay.ratio, lay.conv, st))
-      return rc;
-    // L = SVT(M, 1/mu); the shrink leaves X scaled, so the next warm start
-    // uses Uh only
-    if (int rc = finish_svt(lay, K, n1, n2, n3, 1.0 / mu, real_last, it == iters - 1 ? ranks : nullptr, l, st))
-      return rc;
-    // E = P_unobs(X - L - Y/mu), Y = Y + mu (L + E - X)
-    if (int rc = admm_post(x, mask, l, (float)mu, inv_mu, n, e, y, st)) return rc;
-    mu = std::min(rho * mu, mu_max);
-  }
-  return TP_OK;
+  if (int rc = check_admm(X, L, E, Y, iters, rho, mu0, mu_max, prec)) return rc;
+  return admm_run((const float*)X->data, mask, 0.0, X->n1, X->n2, X->n3, iters, rho, mu0, mu_max, (float*)L->data,
+                  (float*)E->data, (float*)Y->data, ranks, ws, ws_bytes, S(stream));
+}
+
+int tp_trpca(const tp_tensor* X, double lambda, int32_t iters, double rho, double mu0, double mu_max, tp_tensor* L,
+             tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(TP_EINVAL, "lambda must be finite and > 0");
+  if (int rc = check_admm(X, L, E, Y, iters, rho, mu0, mu_max, prec)) return rc;
+  return admm_run((const float*)X->data, nullptr, lambda, X->n1, X->n2, X->n3, iters, rho, mu0, mu_max,
+                  (float*)L->data, (float*)E->data, (float*)Y->data, ranks, ws, ws_bytes, S(stream));
 }
 
 }  // extern "C"

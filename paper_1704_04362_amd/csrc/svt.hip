@@ -1,6 +1,7 @@
 // Singular value thresholding of every Fourier slice (the closed-form
-// L-update of Algorithm 7 with the tensor nuclear norm of eq. tnuc) and the
-// elementwise updates of the ADMM completion loop.
+// L-update of Algorithm 7 with the tensor nuclear norm of eq. tnuc), the
+// elementwise updates of the ADMM loops (completion, eq. tlow6, and robust
+// PCA, eq. tlow7) and the slice gathers that feed CUR t-NN (Algorithm 6).
 //
 // SVD by block one-sided Jacobi on rows: every slice M (n1 x n2) is kept as
 // X = U^H M together with Uh = U^H (both row-major, float32 planar). A step
@@ -270,6 +271,44 @@ __global__ void admm_post_kernel(const float* __restrict__ x, const uint8_t* __r
   y[i] = yv + mu * (lv + ev - xv);
 }
 
+// E = shrink(X - L - Y/mu, lam/mu), the prox of (lam/mu) ||.||_1 (robust
+// PCA, eq. tlow7); Y = Y + mu (L + E - X)
+__global__ void admm_post_soft_kernel(const float* __restrict__ x, const float* __restrict__ l, float mu,
+                                      float inv_mu, float thr, int64_t n, float* __restrict__ e,
+                                      float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float xv = x[i], lv = l[i], yv = y[i];
+  const float v = xv - lv - yv * inv_mu;
+  const float ev = v > thr ? v - thr : (v < -thr ? v + thr : 0.f);
+  e[i] = ev;
+  y[i] = yv + mu * (lv + ev - xv);
+}
+
+// out[a][b][t] = in[ra][cb][t] with ra = ridx ? ridx[a] : a and
+// cb = cidx ? cidx[b] : b: picked lateral or horizontal slices of a
+// tube-major tensor with in_cols lateral slices. Entries past the live pick
+// count (*count, for the listed index) are written as zeros; a negative
+// count (rejected weights) leaves every entry zero.
+template <typename T>
+__global__ void gather_slices_kernel(const T* __restrict__ in, int64_t in_cols, int64_t n3,
+                                     const int32_t* __restrict__ ridx, const int32_t* __restrict__ cidx,
+                                     const int64_t* __restrict__ count, int64_t rows, int64_t cols,
+                                     T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols * n3) return;
+  const int64_t tube = i / n3, t = i - tube * n3;
+  const int64_t a = tube / cols, b = tube - a * cols;
+  const int64_t lim = count ? *count : INT64_MAX;
+  if ((ridx && a >= lim) || (cidx && b >= lim)) {
+    out[i] = T(0);
+    return;
+  }
+  const int64_t ra = ridx ? (int64_t)ridx[a] : a;
+  const int64_t cb = cidx ? (int64_t)cidx[b] : b;
+  out[i] = in[(ra * in_cols + cb) * n3 + t];
+}
+
 unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -336,6 +375,30 @@ int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, flo
               float* y, hipStream_t st) {
   if (n == 0) return TP_OK;
   hipLaunchKernelGGL(admm_post_kernel, dim3(nblk(n)), dim3(256), 0, st, x, mask, l, mu, inv_mu, n, e, y);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int admm_post_soft(const float* x, const float* l, float mu, float inv_mu, float thr, int64_t n, float* e, float* y,
+                   hipStream_t st) {
+  if (n == 0) return TP_OK;
+  hipLaunchKernelGGL(admm_post_soft_kernel, dim3(nblk(n)), dim3(256), 0, st, x, l, mu, inv_mu, thr, n, e, y);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int gather_slices(const void* in, int elem_bytes, int64_t in_cols, int64_t n3, const int32_t* ridx,
+                  const int32_t* cidx, const int64_t* count, int64_t rows, int64_t cols, void* out, hipStream_t st) {
+  const int64_t n = rows * cols * n3;
+  if (n == 0) return TP_OK;
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL(gather_slices_kernel<float>, dim3(nblk(n)), dim3(256), 0, st, (const float*)in, in_cols, n3,
+                       ridx, cidx, count, rows, cols, (float*)out);
+  else if (elem_bytes == 1)
+    hipLaunchKernelGGL(gather_slices_kernel<uint8_t>, dim3(nblk(n)), dim3(256), 0, st, (const uint8_t*)in, in_cols,
+                       n3, ridx, cidx, count, rows, cols, (uint8_t*)out);
+  else
+    return fail(TP_EUNSUPPORTED, "slice gather supports 1- and 4-byte elements");
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

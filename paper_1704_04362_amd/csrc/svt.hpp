@@ -18,5 +18,20 @@ int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double
 int admm_pre(const float* x, const float* e, const float* y, float inv_mu, int64_t n, float* m, hipStream_t st);
 int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, float inv_mu, int64_t n, float* e,
               float* y, hipStream_t st);
+int admm_post_soft(const float* x, const float* l, float mu, float inv_mu, float thr, int64_t n, float* e, float* y,
+                   hipStream_t st);
+// out[a][b][:] = in[ridx[a]][cidx[b]][:] (either index list may be null:
+// identity; entries past *count of the listed index are zero); elements of
+// 1 or 4 bytes.
+int gather_slices(const void* in, int elem_bytes, int64_t in_cols, int64_t n3, const int32_t* ridx,
+                  const int32_t* cidx, const int64_t* count, int64_t rows, int64_t cols, void* out,
+                  hipStream_t st);
+// The ADMM of Algorithm 7 on an n1 x n2 x n3 float32 tensor: completion
+// (E zero on mask != 0) when mask is non-null, robust PCA with weight lam
+// otherwise. Workspace: admm_workspace bytes.
+size_t admm_workspace(int64_t n1, int64_t n2, int64_t n3);
+int admm_run(const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3, int iters,
+             double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks, void* ws,
+             size_t ws_bytes, hipStream_t st);
 
 }  // namespace tp

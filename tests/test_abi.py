@@ -94,3 +94,42 @@ def test_spectrum_and_transform_validation():
     Cs = L.Spectrum(0x1000, 0x2000, L.TP_F32, 3, 4, 2)
     assert lib.tp_spectrum_matmul(C.byref(A), 0, C.byref(B), 0, C.byref(Cs), 1, 1, None) == -2
     assert lib.tp_spectrum_matmul(C.byref(A), 2, C.byref(B), 0, C.byref(Cs), 1, 1, None) == -1
+
+
+@pytest.mark.parametrize("case", ["lambda", "shape", "iters"])
+def test_trpca_validation(case):
+    lib = L.load()
+    X, Lt, E, Y = _t(6, 5, 4), _t(6, 5, 4), _t(6, 5, 4), _t(6, 5, 4)
+    lam, iters, want = 0.1, 10, -1
+    if case == "lambda":
+        lam = 0.0
+    elif case == "shape":
+        E = _t(6, 4, 4)
+        want = -2
+    else:
+        iters = 0
+    rc = lib.tp_trpca(C.byref(X), lam, iters, 1.1, 1e-3, 1e10, C.byref(Lt), C.byref(E), C.byref(Y), None,
+                      L.PREC["f32"], C.c_void_p(0x2000), 1 << 30, None)
+    assert rc == want
+
+
+@pytest.mark.parametrize("case", ["bernoulli", "rank", "dtype", "lambda"])
+def test_tcur_nn_validation(case):
+    lib = L.load()
+    X, Lt = _t(20, 24, 4), _t(20, 24, 4)
+    cols = L.Sample(0x3000, 0x4000, 24, 0x5000)
+    rows = L.Sample(0x6000, 0x7000, 20, 0x8000)
+    mode, r, lam, want = L.MODE["uniform"], 2, 0.1, -1
+    if case == "bernoulli":
+        mode = L.MODE["bernoulli"]
+    elif case == "rank":
+        r = 9
+    elif case == "dtype":
+        X = _t(20, 24, 4, dtype=L.TP_F64)
+        want = -3
+    else:
+        lam = -1.0
+    rc = lib.tp_tcur_nn(C.byref(X), None, lam, 8, 6, r, L.KIND["uniform"], None, L.KIND["uniform"], None, mode, 0,
+                        10, 1.1, 1e-3, 1e10, C.byref(cols), C.byref(rows), C.byref(Lt), L.PREC["f32"],
+                        C.c_void_p(0x2000), 1 << 30, None)
+    assert rc == want

@@ -24,7 +24,7 @@ SEED_BASE = 17040436
 
 __all__ = [
     "SEED_BASE", "rng", "gaussian", "exact_pair", "rtprod_pair",
-    "lowrank_factors", "completion_problem", "learned_factors",
+    "lowrank_factors", "completion_problem", "rpca_problem", "learned_factors",
     "lognormal_weights",
 ]
 
@@ -78,6 +78,18 @@ def completion_problem(n1=256, n2=256, n3=100, r=15, noise_var=0.01, p_obs=0.5, 
     N = (g.standard_normal((n1, n2, n3)) * np.sqrt(noise_var)).astype(dtype)
     mask = (g.random((n1, n2, n3)) < p_obs).astype(np.uint8)
     return G1, G2, N, mask
+
+
+def rpca_problem(n1=48, n2=40, n3=6, r=2, spike_frac=0.05, spike_mag=5.0, salt=0, dtype=np.float64):
+    """(G1, G2, S): L* = G1 * G2 has tubal rank r; S holds +-spike_mag on a
+    spike_frac share of the entries (positions and signs uniform) and zeros
+    elsewhere, so X = L* + S is a low-rank tensor with sparse gross errors."""
+    g = rng(6, salt)
+    G1 = g.standard_normal((n1, r, n3))
+    G2 = g.standard_normal((r, n2, n3))
+    hit = g.random((n1, n2, n3)) < spike_frac
+    S = np.where(hit, spike_mag * np.where(g.random((n1, n2, n3)) < 0.5, -1.0, 1.0), 0.0)
+    return G1.astype(dtype), G2.astype(dtype), S.astype(dtype)
 
 
 def learned_factors(index, n1=512, n2=512, n3=64, rmin=5, rmax=40, salt=0, dtype=np.float32):
