@@ -78,6 +78,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-protocol", action="store_true", help="skip the t-CUR / learned-proposal comparison")
+    p.add_argument("--no-tnn", action="store_true", help="skip the completion / robust PCA / CUR t-NN comparison")
+    p.add_argument("--tnn-iters", type=int, default=100)
     p.add_argument("--learned-train", type=int, default=1800)
     p.add_argument("--learned-test", type=int, default=40)
     p.add_argument("--learned-epochs", type=int, default=80)
@@ -283,6 +285,100 @@ def time_to_target(args, api, torch, trainer):
     return out
 
 
+def timed_once(fn, torch):
+    """(ms, result) of one call of fn, HIP events on the current stream."""
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    res = fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), res
+
+
+def traced(fn, api):
+    """Per-stage milliseconds of one call of fn from the library trace."""
+    api.trace_enable(True)
+    fn()
+    tr = api.trace_read()
+    api.trace_enable(False)
+    return {k: round(v[1], 3) for k, v in tr.items()}
+
+
+def tnn_protocol(args, api, torch):
+    """The ADMM of Algorithm 7 on the whole tensor against CUR t-NN
+    (Algorithm 6), for completion (256x256x100, tubal rank 15, 50% observed)
+    and robust PCA (a 192x1140x168 tensor of tubal rank 10 with 20%
+    salt-and-pepper entries): time, time per iteration, per-stage trace and
+    relative error against the clean low-rank tensor."""
+    import workloads as W
+    it = args.tnn_iters
+    out = {"iters": it}
+
+    def rse(L, Ls):
+        return round(float(torch.linalg.vector_norm(L - Ls) / torch.linalg.vector_norm(Ls)), 6)
+
+    # completion
+    G1, G2, N, mask = W.completion_problem()
+    Ls = api.tprod(torch.from_numpy(G1).cuda(), torch.from_numpy(G2).cuda(), prec="f32")
+    m = torch.from_numpy(mask).cuda()
+    X = ((Ls + torch.from_numpy(N).cuda()) * m.to(torch.float32)).contiguous()
+    del G1, G2, N, mask
+    api.tcomplete(X, m, iters=2)
+    ms, (L, _, _, ranks) = timed_once(lambda: api.tcomplete(X, m, iters=it), torch)
+    comp = {"full_admm": {"ms": round(ms, 2), "ms_per_iter": round(ms / it, 3), "rse": rse(L, Ls),
+                          "max_rank": int(ranks.max()),
+                          "stages_ms": traced(lambda: api.tcomplete(X, m, iters=it), api)}}
+    for c in (64, 128):
+        def run(c=c):
+            return api.tcur_nn(X, c, c, 15, mask=m, col_kind="uniform", row_kind="lev", mode="iid", seed=1,
+                               iters=it)
+        run()
+        ms, (L, _, _) = timed_once(run, torch)
+        comp[f"cur_tnn_c{c}"] = {"ms": round(ms, 2), "rse": rse(L, Ls), "stages_ms": traced(run, api)}
+        log(f"completion CUR t-NN c=l={c}: {comp[f'cur_tnn_c{c}']['ms']} ms, rse {comp[f'cur_tnn_c{c}']['rse']}")
+    out["completion"] = {"workload": "X = (L* + N(0, 0.01)) on a Bernoulli(0.5) mask, L* = G1 * G2 of 256x15x100 "
+                                     "and 15x256x100 N(0,1) factors; rho 1.1, mu0 1e-3; CUR t-NN columns i.i.d. "
+                                     "uniform, rows by leverage of the cleaned C, r = 15",
+                         **comp}
+    log(f"completion full ADMM: {comp['full_admm']['ms']} ms, rse {comp['full_admm']['rse']}")
+    del X, Ls, m, L
+
+    # robust PCA, Yale-B-shaped with salt-and-pepper corruption
+    G1, G2, hit, high = W.salt_pepper_problem()
+    Ls = api.tprod(torch.from_numpy(G1).cuda(), torch.from_numpy(G2).cuda(), prec="f32")
+    lo, hi = Ls.min(), Ls.max()
+    Ls = ((Ls - lo) / (hi - lo)).contiguous()
+    hit_d = torch.from_numpy(hit).cuda()
+    X = torch.where(hit_d, torch.from_numpy(high).cuda().to(torch.float32), Ls).contiguous()
+    del G1, G2, hit, high, hit_d
+    n1, n2, n3 = X.shape
+    lam = 1.0 / (max(n1, n2) * n3) ** 0.5
+    rp = {}
+    api.trpca(X, lam, iters=2)
+    ms, (L, E, _, ranks) = timed_once(lambda: api.trpca(X, lam, iters=it), torch)
+    rp["full_admm"] = {"ms": round(ms, 2), "ms_per_iter": round(ms / it, 3), "rse": rse(L, Ls),
+                       "max_rank": int(ranks.max()), "stages_ms": traced(lambda: api.trpca(X, lam, iters=it), api)}
+    log(f"robust PCA full ADMM: {rp['full_admm']['ms']} ms, rse {rp['full_admm']['rse']}")
+    for c, l in ((300, 96),):
+        def run(c=c, l=l):
+            return api.tcur_nn(X, c, l, 10, lam=lam, col_kind="uniform", row_kind="lev", mode="iid", seed=1,
+                               iters=it)
+        run()
+        ms, (L, _, _) = timed_once(run, torch)
+        rp[f"cur_tnn_c{c}_l{l}"] = {"ms": round(ms, 2), "rse": rse(L, Ls), "stages_ms": traced(run, api)}
+        log(f"robust PCA CUR t-NN c={c} l={l}: {ms:.1f} ms, rse {rp[f'cur_tnn_c{c}_l{l}']['rse']}")
+    out["robust_pca"] = {"workload": "192x1140x168 (the Extended Yale B shape): L* = G1 * G2 of tubal rank 10 "
+                                     "rescaled to [0, 1], 20% of the entries set to 0 or 1 (salt and pepper); "
+                                     "lambda = 1/sqrt(max(n1, n2) n3); CUR t-NN columns i.i.d. uniform, rows by "
+                                     "leverage of the cleaned C, r = 10",
+                         **rp}
+    del X, Ls, L, E
+    return out
+
+
 def time_events(fn, reps, torch):
     """Average duration of fn() over reps launches, HIP events on the
     current stream (the one the library enqueues on)."""
@@ -471,6 +567,9 @@ def main():
         trainer, out["learned_proposal"] = learned_protocol(args, api, torch)
         log("t-CUR time to 1e-3")
         out["tcur_time_to_1e-3"] = time_to_target(args, api, torch, trainer)
+    if not args.no_tnn:
+        log("completion / robust PCA: full ADMM against CUR t-NN")
+        out["tensor_nn"] = tnn_protocol(args, api, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A_h, B_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -245,8 +245,9 @@ size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, in
  * the slice threshold is tau itself). ranks (device, K int32 values, may be
  * NULL) receives the number of singular values above tau in each
  * non-redundant slice. The slice SVDs are computed exactly (block one-sided
- * Jacobi to a largest normalised row inner product of 1e-6). float32 data,
- * prec TP_PREC_F32. */
+ * Jacobi on the shorter side of the slices, until every row inner product
+ * is below 1e-6 of the larger squared row norm). float32 data, prec
+ * TP_PREC_F32. */
 int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
             void* stream);
 size_t tp_tsvt_workspace(const tp_tensor* M);

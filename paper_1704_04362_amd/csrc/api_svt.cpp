@@ -15,7 +15,7 @@ namespace {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-constexpr double kSvtTol = 1e-6;   // largest normalised off-diagonal of a converged pair
+constexpr double kSvtTol = 1e-6;   // largest |G_st| / max(G_ss, G_tt) of a converged pair
 constexpr int kColdSweeps = 30;
 constexpr int kWarmSweeps = 12;
 
@@ -37,6 +37,22 @@ struct SvtLayout {
     sig = ar.take<double>(K * n1);
     if (completion) m = ar.take<float>(n1 * n2 * n3);
     return ar.dry() || ar.ok();
+  }
+};
+
+// The t-SVT of a tall tensor runs on its t-transpose (mt, lt hold the
+// transposed input and result).
+struct TsvtLayout {
+  SvtLayout svt;
+  float *mt = nullptr, *lt = nullptr;
+  bool carve(Arena& ar, int64_t n1, int64_t n2, int64_t n3) {
+    const int64_t K = half_count(n3);
+    if (n1 > n2) {
+      mt = ar.take<float>(n1 * n2 * n3);
+      lt = ar.take<float>(n1 * n2 * n3);
+      return svt.carve(ar, K, n2, n1, n3, false);
+    }
+    return svt.carve(ar, K, n1, n2, n3, false);
   }
 };
 
@@ -93,23 +109,14 @@ int check_admm(const tp_tensor* X, const tp_tensor* L, const tp_tensor* E, const
 
 }  // namespace
 
-size_t admm_workspace(int64_t n1, int64_t n2, int64_t n3) {
-  Arena dry(nullptr, SIZE_MAX);
-  SvtLayout lay;
-  lay.carve(dry, half_count(n3), n1, n2, n3, true);
-  return dry.used + 256;
-}
+namespace {
 
-int admm_run(const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3, int iters,
-             double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks, void* ws,
-             size_t ws_bytes, hipStream_t st) {
-  const size_t need = admm_workspace(n1, n2, n3);
-  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "ADMM workspace too small");
+// The loop of the ADMM on an n1 x n2 x n3 problem with the given layout.
+int admm_loop(SvtLayout& lay, const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3,
+              int iters, double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks,
+              hipStream_t st) {
   const int64_t K = half_count(n3), n = n1 * n2 * n3;
   const bool real_last = (n3 % 2 == 0) && K > 1;
-  Arena ar(ws, ws_bytes);
-  SvtLayout lay;
-  if (!lay.carve(ar, K, n1, n2, n3, true)) return fail(TP_EWORKSPACE, "ADMM workspace too small");
   // L_0 = E_0 = Y_0 = 0
   if (int rc = zero_f32(e, n, st)) return rc;
   if (int rc = zero_f32(y, n, st)) return rc;
@@ -122,44 +129,114 @@ int admm_run(const float* x, const uint8_t* mask, double lam, int64_t n1, int64_
   g.in_cols = n2;
   for (int it = 0; it < iters; ++it) {
     const float inv_mu = (float)(1.0 / mu);
-    // M = X - E - Y / mu, then its spectrum
-    if (int rc = admm_pre(x, e, y, inv_mu, n, lay.m, st)) return rc;
-    if (int rc = fft_forward(lay.m, TP_F32, n3, g, lay.lre, lay.lim, st)) return rc;
-    // warm start: rotate the new spectrum by the previous iteration's U^H
-    CGemm p;
-    p.K = K;
-    p.M = n1;
-    p.N = n2;
-    p.Kd = n1;
-    p.are = lay.ure;
-    p.aim = lay.uim;
-    p.bre = lay.lre;
-    p.bim = lay.lim;
-    p.cre = lay.xre;
-    p.cim = lay.xim;
-    p.lda = n1;
-    p.ldb = n2;
-    p.ldc = n2;
-    p.sa = n1 * n1;
-    p.sb = n1 * n2;
-    p.sc = n1 * n2;
-    p.real_last = real_last;
-    if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
-    if (int rc = svt_jacobi(lay.xre, lay.xim, lay.ure, lay.uim, K, n1, n2, real_last,
-                            it == 0 ? kColdSweeps : kWarmSweeps, kSvtTol, lay.ratio, lay.conv, st))
-      return rc;
-    // L = SVT(M, 1/mu); the shrink leaves X scaled, so the next warm start
-    // uses Uh only
-    if (int rc = finish_svt(lay, K, n1, n2, n3, 1.0 / mu, real_last, it == iters - 1 ? ranks : nullptr, l, st))
-      return rc;
-    if (mask) {
-      // E = P_unobs(X - L - Y/mu), Y = Y + mu (L + E - X)
-      if (int rc = admm_post(x, mask, l, (float)mu, inv_mu, n, e, y, st)) return rc;
-    } else {
-      // E = shrink(X - L - Y/mu, lam/mu), Y = Y + mu (L + E - X)
-      if (int rc = admm_post_soft(x, l, (float)mu, inv_mu, (float)(lam / mu), n, e, y, st)) return rc;
+    {
+      // M = X - E - Y / mu, then its spectrum
+      TraceScope ts("admm.pre_fft", st);
+      if (int rc = admm_pre(x, e, y, inv_mu, n, lay.m, st)) return rc;
+      if (int rc = fft_forward(lay.m, TP_F32, n3, g, lay.lre, lay.lim, st)) return rc;
+    }
+    {
+      // warm start: rotate the new spectrum by the previous iteration's U^H
+      TraceScope ts("admm.rotate", st);
+      CGemm p;
+      p.K = K;
+      p.M = n1;
+      p.N = n2;
+      p.Kd = n1;
+      p.are = lay.ure;
+      p.aim = lay.uim;
+      p.bre = lay.lre;
+      p.bim = lay.lim;
+      p.cre = lay.xre;
+      p.cim = lay.xim;
+      p.lda = n1;
+      p.ldb = n2;
+      p.ldc = n2;
+      p.sa = n1 * n1;
+      p.sb = n1 * n2;
+      p.sc = n1 * n2;
+      p.real_last = real_last;
+      if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
+    }
+    {
+      TraceScope ts("admm.jacobi", st);
+      if (int rc = svt_jacobi(lay.xre, lay.xim, lay.ure, lay.uim, K, n1, n2, real_last,
+                              it == 0 ? kColdSweeps : kWarmSweeps, kSvtTol, lay.ratio, lay.conv, st))
+        return rc;
+    }
+    {
+      // L = SVT(M, 1/mu); the shrink leaves X scaled, so the next warm start
+      // uses Uh only
+      TraceScope ts("admm.shrink_ifft", st);
+      if (int rc = finish_svt(lay, K, n1, n2, n3, 1.0 / mu, real_last, it == iters - 1 ? ranks : nullptr, l, st))
+        return rc;
+    }
+    {
+      TraceScope ts("admm.post", st);
+      if (mask) {
+        // E = P_unobs(X - L - Y/mu), Y = Y + mu (L + E - X)
+        if (int rc = admm_post(x, mask, l, (float)mu, inv_mu, n, e, y, st)) return rc;
+      } else {
+        // E = shrink(X - L - Y/mu, lam/mu), Y = Y + mu (L + E - X)
+        if (int rc = admm_post_soft(x, l, (float)mu, inv_mu, (float)(lam / mu), n, e, y, st)) return rc;
+      }
     }
     mu = std::min(rho * mu, mu_max);
+  }
+  return TP_OK;
+}
+
+// Tall problems (n1 > n2) run on the t-transpose: the t-SVT satisfies
+// SVT(M^T) = SVT(M)^T (the Fourier slices of M^T are the conjugate
+// transposes of those of M), and the l1 term, the mask projection and the
+// multiplier update are elementwise, so the iterates of the transposed
+// problem are the transposes of the iterates; the row Jacobi then
+// orthogonalises min(n1, n2) rows.
+struct AdmmLayout {
+  SvtLayout svt;
+  float *xt = nullptr, *tmp = nullptr;
+  uint8_t* mt = nullptr;
+  bool carve(Arena& ar, int64_t n1, int64_t n2, int64_t n3, bool masked) {
+    const int64_t K = half_count(n3);
+    if (n1 > n2) {
+      xt = ar.take<float>(n1 * n2 * n3);
+      tmp = ar.take<float>(n1 * n2 * n3);
+      if (masked) mt = ar.take<uint8_t>(n1 * n2 * n3);
+      return svt.carve(ar, K, n2, n1, n3, true);
+    }
+    return svt.carve(ar, K, n1, n2, n3, true);
+  }
+};
+
+}  // namespace
+
+size_t admm_workspace(int64_t n1, int64_t n2, int64_t n3) {
+  Arena dry(nullptr, SIZE_MAX);
+  AdmmLayout lay;
+  lay.carve(dry, n1, n2, n3, true);
+  return dry.used + 256;
+}
+
+int admm_run(const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3, int iters,
+             double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks, void* ws,
+             size_t ws_bytes, hipStream_t st) {
+  const size_t need = admm_workspace(n1, n2, n3);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "ADMM workspace too small");
+  Arena ar(ws, ws_bytes);
+  AdmmLayout lay;
+  if (!lay.carve(ar, n1, n2, n3, mask != nullptr)) return fail(TP_EWORKSPACE, "ADMM workspace too small");
+  if (n1 <= n2) return admm_loop(lay.svt, x, mask, lam, n1, n2, n3, iters, rho, mu0, mu_max, l, e, y, ranks, st);
+  // transposed problem (n2 x n1 x n3), iterates kept in l, e, y, then turned back
+  const int64_t n = n1 * n2 * n3;
+  if (int rc = ttranspose(x, 4, n1, n2, n3, lay.xt, st)) return rc;
+  if (mask)
+    if (int rc = ttranspose(mask, 1, n1, n2, n3, lay.mt, st)) return rc;
+  if (int rc = admm_loop(lay.svt, lay.xt, mask ? lay.mt : nullptr, lam, n2, n1, n3, iters, rho, mu0, mu_max, l, e,
+                         y, ranks, st))
+    return rc;
+  for (float* b : {l, e, y}) {
+    if (int rc = ttranspose(b, 4, n2, n1, n3, lay.tmp, st)) return rc;
+    TP_HIP_CHECK(hipMemcpyAsync(b, lay.tmp, n * sizeof(float), hipMemcpyDeviceToDevice, st));
   }
   return TP_OK;
 }
@@ -173,8 +250,8 @@ extern "C" {
 size_t tp_tsvt_workspace(const tp_tensor* M) {
   if (!M || M->n1 < 1 || M->n2 < 1 || M->n3 < 1) return 0;
   Arena dry(nullptr, SIZE_MAX);
-  SvtLayout lay;
-  lay.carve(dry, half_count(M->n3), M->n1, M->n2, M->n3, false);
+  TsvtLayout lay;
+  lay.carve(dry, M->n1, M->n2, M->n3);
   return dry.used + 256;
 }
 
@@ -191,18 +268,28 @@ int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int pr
   const bool real_last = (n3 % 2 == 0) && K > 1;
   hipStream_t st = S(stream);
   Arena ar(ws, ws_bytes);
-  SvtLayout lay;
-  if (!lay.carve(ar, K, n1, n2, n3, false)) return fail(TP_EWORKSPACE, "tsvt workspace too small");
+  TsvtLayout lay;
+  if (!lay.carve(ar, n1, n2, n3)) return fail(TP_EWORKSPACE, "tsvt workspace too small");
+  // a tall problem runs on the t-transpose: SVT(M^T) = SVT(M)^T
+  const bool tall = n1 > n2;
+  const int64_t r = tall ? n2 : n1, c = tall ? n1 : n2;
+  const float* src = (const float*)M->data;
+  if (tall) {
+    if (int rc = ttranspose(M->data, 4, n1, n2, n3, lay.mt, st)) return rc;
+    src = lay.mt;
+  }
   TubeGather g;
-  g.rows = n1;
-  g.cols = n2;
-  g.in_cols = n2;
-  if (int rc = fft_forward(M->data, TP_F32, n3, g, lay.xre, lay.xim, st)) return rc;
-  if (int rc = svt_identity(lay.ure, lay.uim, K, n1, st)) return rc;
-  if (int rc = svt_jacobi(lay.xre, lay.xim, lay.ure, lay.uim, K, n1, n2, real_last, kColdSweeps, kSvtTol, lay.ratio,
-                          lay.conv, st))
+  g.rows = r;
+  g.cols = c;
+  g.in_cols = c;
+  if (int rc = fft_forward(src, TP_F32, n3, g, lay.svt.xre, lay.svt.xim, st)) return rc;
+  if (int rc = svt_identity(lay.svt.ure, lay.svt.uim, K, r, st)) return rc;
+  if (int rc = svt_jacobi(lay.svt.xre, lay.svt.xim, lay.svt.ure, lay.svt.uim, K, r, c, real_last, kColdSweeps,
+                          kSvtTol, lay.svt.ratio, lay.svt.conv, st))
     return rc;
-  return finish_svt(lay, K, n1, n2, n3, tau, real_last, ranks, L->data, st);
+  if (!tall) return finish_svt(lay.svt, K, r, c, n3, tau, real_last, ranks, L->data, st);
+  if (int rc = finish_svt(lay.svt, K, r, c, n3, tau, real_last, ranks, lay.lt, st)) return rc;
+  return ttranspose(lay.lt, 4, r, c, n3, L->data, st);
 }
 
 size_t tp_tcomplete_workspace(const tp_tensor* X) {

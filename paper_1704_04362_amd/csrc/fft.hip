@@ -12,8 +12,9 @@
 //      n3 + 1 words so that the transposed read below is conflict free;
 //      gathers of picked slices and their scales are applied here;
 //   2. every lane packs its real tube as z[m] = x[2m] + i x[2m+1] and runs a
-//      length-n3/2 complex FFT in registers (radix 4/2/5/3 Cooley-Tukey,
-//      fully unrolled, twiddles from a per-device constant table);
+//      length-n3/2 complex FFT in registers (radix 4/2/5/3 Cooley-Tukey and
+//      a direct DFT for other prime factors, fully unrolled, twiddles from a
+//      per-device constant table);
 //   3. the half spectrum of the real tube is separated from Z by conjugate
 //      symmetry, X[k] = (Z[k] + conj Z[M-k])/2 + W_n3^k (Z[k] - conj Z[M-k])/2i,
 //      and each slice k is written with one coalesced store per wavefront.
@@ -32,7 +33,7 @@ namespace {
 // Twiddle tables: W_L^e = exp(-2 pi i e / L) for the lengths below, stored
 // back to back (re, im interleaved), computed on the host in long double.
 // --------------------------------------------------------------------------
-constexpr int kTwLens[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 5, 10, 20, 25, 50, 100, 200};
+constexpr int kTwLens[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 5, 10, 20, 25, 50, 100, 200, 7, 21, 84, 168};
 constexpr int kTwCount = sizeof(kTwLens) / sizeof(int);
 
 constexpr int tw_offset(int L) {
@@ -43,7 +44,7 @@ constexpr int tw_offset(int L) {
   }
   return -1;
 }
-constexpr int kTwTotal = tw_offset(200) + 200;
+constexpr int kTwTotal = tw_offset(168) + 168;
 
 __constant__ double g_tw64[2 * kTwTotal];
 __constant__ float g_tw32[2 * kTwTotal];
@@ -106,6 +107,7 @@ constexpr int radix_of(int M) {
 template <typename T, int M>
 __device__ __forceinline__ void cfft(T (&re)[M], T (&im)[M]) {
   if constexpr (M > 1) {
+    static_assert(tw_offset(M) >= 0, "no twiddle table for this transform length");
     constexpr int p = radix_of(M);
     constexpr int Q = M / p;
     T sr[p][Q], si[p][Q];
@@ -248,6 +250,7 @@ template <typename T, int N, bool SPLIT = false>
 __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, FwdArgs a, T* __restrict__ ore,
                                                      T* __restrict__ oim) {
   constexpr int M = N / 2;
+  static_assert(N <= 2 || tw_offset(N) >= 0, "no twiddle table for this tube length");
   constexpr int VN = Vec16<T>::n;
   constexpr bool HALF = N >= 32 && N % (2 * VN) == 0;
   constexpr int SPAN = HALF ? N / 2 : N;  // tube entries staged at once
@@ -356,6 +359,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(kTile) void irfft_kernel(const T* __restrict__ xre, const T* __restrict__ xim,
                                                       int64_t ntubes, T* __restrict__ y) {
   constexpr int M = N / 2;
+  static_assert(N <= 2 || tw_offset(N) >= 0, "no twiddle table for this tube length");
   using ST = InvStage<N>;
   constexpr int NH = ST::NH, SPAN = ST::SPAN, PAD = ST::PAD;
   constexpr int VN = Vec16<T>::n;
@@ -522,6 +526,7 @@ FwdKernel<T> pick_fwd(int64_t n) {
     case 20: return rfft_kernel<T, 20>;
     case 50: return rfft_kernel<T, 50>;
     case 100: return rfft_kernel<T, 100>;
+    case 168: return rfft_kernel<T, 168>;
     default: return nullptr;
   }
 }
@@ -541,6 +546,7 @@ InvKernel<T> pick_inv(int64_t n) {
     case 20: return irfft_kernel<T, 20>;
     case 50: return irfft_kernel<T, 50>;
     case 100: return irfft_kernel<T, 100>;
+    case 168: return irfft_kernel<T, 168>;
     default: return nullptr;
   }
 }

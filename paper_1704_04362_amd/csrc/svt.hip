@@ -144,15 +144,23 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
     sh.Hi[s][t] = gi[q];
   }
   __syncthreads();
-  // largest normalised off-diagonal entry
+  // largest off-diagonal entry relative to the larger squared norm of its
+  // two rows, |G_st| / max(G_ss, G_tt). Rows are stored in float32, so a
+  // rotation leaves rounding of size eps_32 |x_big| in the smaller row and
+  // |G_st| cannot fall below ~eps_32 max(G_ss, G_tt): the usual
+  // |G_st| / sqrt(G_ss G_tt) would never reach the tolerance for pairs whose
+  // norms differ by more than tol / eps_32 and every call would run its
+  // full sweep budget. Scaled by the larger row, the residual rotation
+  // angle is below tol relative to the pair's spectral gap, which bounds
+  // the error of the thresholded result by ~tol ||M||.
   double mr = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + NT * q;
     const int s = e / PR, t = e - s * PR;
     if (s != t) {
-      const double d = sh.Hr[s][s] * sh.Hr[t][t];
-      if (d > 0.0) mr = fmax(mr, sqrt((gr[q] * gr[q] + gi[q] * gi[q]) / d));
+      const double d = fmax(sh.Hr[s][s], sh.Hr[t][t]);
+      if (d > 0.0) mr = fmax(mr, sqrt(gr[q] * gr[q] + gi[q] * gi[q]) / d);
     }
   }
   ratio_red[tid] = mr;
@@ -205,51 +213,72 @@ __global__ void zero_int_kernel(int* p, int64_t n) {
 // and the number of sigma_i > tau per slice. Row norms at or below
 // max(n1, n2) eps_32 sigma_max are rounding residue of rows that the
 // rotations have emptied (a slice has at most min(n1, n2) nonzero singular
-// values) and count as zero. One workgroup per slice; sig is K x n1 scratch.
+// values) and count as zero. One workgroup per slice: a wavefront sums a
+// row with consecutive lanes on consecutive columns, then the scaling pass
+// runs over the slice in storage order; sig (K x n1 scratch) holds the
+// norms and then the factors.
 __global__ __launch_bounds__(NT) void svt_shrink_kernel(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2,
                                                         double tau, int real_last, double* sig, int32_t* ranks) {
   __shared__ double red[NT];
   __shared__ int cnt[NT];
   const int64_t k = blockIdx.x;
   const bool real = k == 0 || (real_last && k == K - 1);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* re = xre + k * n1 * n2;
   float* im = xim + k * n1 * n2;
   double* sg = sig + k * n1;
-  double mx = 0.0;
-  for (int64_t i = threadIdx.x; i < n1; i += NT) {
+  for (int64_t i = wv; i < n1; i += NT / 64) {
     double s2 = 0.0;
-    for (int64_t j = 0; j < n2; ++j) {
+    for (int64_t j = lane; j < n2; j += 64) {
       const double a = re[i * n2 + j], b = real ? 0.0 : im[i * n2 + j];
       s2 += a * a + b * b;
     }
-    sg[i] = sqrt(s2);
-    mx = fmax(mx, sg[i]);
+    s2 = wave_sum(s2);
+    if (lane == 0) sg[i] = sqrt(s2);
   }
-  red[threadIdx.x] = mx;
+  __syncthreads();
+  double mx = 0.0;
+  for (int64_t i = tid; i < n1; i += NT) mx = fmax(mx, sg[i]);
+  red[tid] = mx;
   __syncthreads();
   for (int w = NT / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
     __syncthreads();
   }
   const double floor_ = (double)(n1 > n2 ? n1 : n2) * 1.1920928955078125e-07 * red[0];
   int mine = 0;
-  for (int64_t i = threadIdx.x; i < n1; i += NT) {
+  for (int64_t i = tid; i < n1; i += NT) {
     const double sgi = sg[i];
     const bool kept = sgi > tau && sgi > floor_;
-    const double d = kept ? 1.0 - tau / sgi : 0.0;
     if (kept) ++mine;
-    for (int64_t j = 0; j < n2; ++j) {
-      re[i * n2 + j] = (float)(d * re[i * n2 + j]);
-      if (!real) im[i * n2 + j] = (float)(d * im[i * n2 + j]);
-    }
+    sg[i] = kept ? 1.0 - tau / sgi : 0.0;
   }
-  cnt[threadIdx.x] = mine;
+  cnt[tid] = mine;
   __syncthreads();
+  for (int64_t e = tid; e < n1 * n2; e += NT) {
+    const double d = sg[e / n2];
+    re[e] = (float)(d * re[e]);
+    if (!real) im[e] = (float)(d * im[e]);
+  }
   for (int w = NT / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    if (tid < w) cnt[tid] += cnt[tid + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && ranks) ranks[k] = cnt[0];
+  if (tid == 0 && ranks) ranks[k] = cnt[0];
+}
+
+// t-transpose (Section 2.1): out (n2 x n1 x n3) with out[j][i][t] =
+// in[i][j][(n3 - t) mod n3], i.e. every frontal slice transposed and slices
+// 2..n3 in reverse order; its Fourier slices are the conjugate transposes
+// of those of in.
+template <typename T>
+__global__ void ttranspose_kernel(const T* __restrict__ in, int64_t n1, int64_t n2, int64_t n3, T* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n1 * n2 * n3) return;
+  const int64_t tube = e / n3, t = e - tube * n3;
+  const int64_t j = tube / n1, i = tube - j * n1;
+  const int64_t ts = t == 0 ? 0 : n3 - t;
+  out[e] = in[(i * n2 + j) * n3 + ts];
 }
 
 // M = X - E - Y / mu (tube-major, elementwise)
@@ -383,6 +412,21 @@ int admm_post_soft(const float* x, const float* l, float mu, float inv_mu, float
                    hipStream_t st) {
   if (n == 0) return TP_OK;
   hipLaunchKernelGGL(admm_post_soft_kernel, dim3(nblk(n)), dim3(256), 0, st, x, l, mu, inv_mu, thr, n, e, y);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int ttranspose(const void* in, int elem_bytes, int64_t n1, int64_t n2, int64_t n3, void* out, hipStream_t st) {
+  const int64_t n = n1 * n2 * n3;
+  if (n == 0) return TP_OK;
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL(ttranspose_kernel<float>, dim3(nblk(n)), dim3(256), 0, st, (const float*)in, n1, n2, n3,
+                       (float*)out);
+  else if (elem_bytes == 1)
+    hipLaunchKernelGGL(ttranspose_kernel<uint8_t>, dim3(nblk(n)), dim3(256), 0, st, (const uint8_t*)in, n1, n2, n3,
+                       (uint8_t*)out);
+  else
+    return fail(TP_EUNSUPPORTED, "t-transpose supports 1- and 4-byte elements");
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

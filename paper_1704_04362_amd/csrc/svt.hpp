@@ -20,6 +20,9 @@ int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, flo
               float* y, hipStream_t st);
 int admm_post_soft(const float* x, const float* l, float mu, float inv_mu, float thr, int64_t n, float* e, float* y,
                    hipStream_t st);
+// t-transpose of an n1 x n2 x n3 tube-major tensor into out (n2 x n1 x n3);
+// elements of 1 or 4 bytes.
+int ttranspose(const void* in, int elem_bytes, int64_t n1, int64_t n2, int64_t n3, void* out, hipStream_t st);
 // out[a][b][:] = in[ridx[a]][cidx[b]][:] (either index list may be null:
 // identity; entries past *count of the listed index are zero); elements of
 // 1 or 4 bytes.

@@ -37,7 +37,7 @@ def rel(a, b):
 
 
 TOL = {np.float64: 1e-12, np.float32: 2e-6}
-SIZES_N3 = [1, 2, 3, 4, 5, 7, 8, 10, 16, 20, 50, 64, 100, 128]
+SIZES_N3 = [1, 2, 3, 4, 5, 7, 8, 10, 16, 20, 50, 64, 100, 128, 168]
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])

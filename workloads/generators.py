@@ -24,7 +24,8 @@ SEED_BASE = 17040436
 
 __all__ = [
     "SEED_BASE", "rng", "gaussian", "exact_pair", "rtprod_pair",
-    "lowrank_factors", "completion_problem", "rpca_problem", "learned_factors",
+    "lowrank_factors", "completion_problem", "rpca_problem", "salt_pepper_problem",
+    "learned_factors",
     "lognormal_weights",
 ]
 
@@ -90,6 +91,20 @@ def rpca_problem(n1=48, n2=40, n3=6, r=2, spike_frac=0.05, spike_mag=5.0, salt=0
     hit = g.random((n1, n2, n3)) < spike_frac
     S = np.where(hit, spike_mag * np.where(g.random((n1, n2, n3)) < 0.5, -1.0, 1.0), 0.0)
     return G1.astype(dtype), G2.astype(dtype), S.astype(dtype)
+
+
+def salt_pepper_problem(n1=192, n2=1140, n3=168, r=10, frac=0.2, salt=0):
+    """(G1, G2, hit, high): factors of a tubal-rank-r tensor (float32) and a
+    salt-and-pepper corruption pattern: hit marks a frac share of the entries
+    (uniform positions), high says whether a hit entry is set to the top
+    (True) or the bottom (False) of the value range. The default shape is
+    that of the Extended Yale B face tensor (192 x 1140 x 168)."""
+    g = rng(7, salt)
+    G1 = g.standard_normal((n1, r, n3), dtype=np.float32)
+    G2 = g.standard_normal((r, n2, n3), dtype=np.float32)
+    hit = g.random((n1, n2, n3), dtype=np.float32) < frac
+    high = g.random((n1, n2, n3), dtype=np.float32) < 0.5
+    return G1, G2, hit, high
 
 
 def learned_factors(index, n1=512, n2=512, n3=64, rmin=5, rmax=40, salt=0, dtype=np.float32):
