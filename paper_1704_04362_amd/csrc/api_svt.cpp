@@ -17,7 +17,7 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 constexpr double kSvtTol = 1e-6;   // largest |G_st| / max(G_ss, G_tt) of a converged pair
 constexpr int kColdSweeps = 30;
-constexpr int kWarmSweeps = 12;
+constexpr int kWarmSweeps = 20;
 
 struct SvtLayout {
   float *xre = nullptr, *xim = nullptr, *ure = nullptr, *uim = nullptr, *lre = nullptr, *lim = nullptr;

@@ -28,6 +28,12 @@ constexpr int RB = 16;       // rows per block
 constexpr int PR = 2 * RB;   // rows per pair
 constexpr int CHC = 64;      // columns staged per chunk
 constexpr int NT = 256;
+// Cyclic Jacobi sweeps on the 32 x 32 Gram matrix of a pair step. The outer
+// sweeps revisit every pair until all of them are orthogonal, so a pair step
+// need not diagonalise its Gram matrix exactly: one inner sweep costs about
+// one more outer sweep in total against a full inner solve, at a fraction of
+// the price per step (the inner solve dominates a step).
+constexpr int kInnerSweeps = 1;
 
 struct PairArgs {
   int64_t K, n1, n2;
@@ -373,7 +379,7 @@ int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_
   const int nb = svt_blocks(n1);
   hipLaunchKernelGGL(zero_int_kernel, dim3(nblk(K)), dim3(256), 0, st, conv, K);
   TP_LAUNCH_CHECK();
-  PairArgs a{K, n1, n2, xre, xim, ure, uim, nb, real_last ? 1 : 0, ratio, conv, tol, 12};
+  PairArgs a{K, n1, n2, xre, xim, ure, uim, nb, real_last ? 1 : 0, ratio, conv, tol, kInnerSweeps};
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int round = 0; round < nb - 1; ++round) {
       hipLaunchKernelGGL(svt_pair_kernel, dim3(nb / 2, (unsigned)K), dim3(NT), 0, st, a, round);

@@ -162,11 +162,11 @@ def test_tprod_full_size_sampled_entries():
     assert rel(Cg[ii, jj, kk], ref) < 1e-5
 
 
-@pytest.mark.parametrize("shape", [(64, 300, 16), (33, 1000, 7), (5, 64, 1)])
-def test_slice_norms(shape):
+@pytest.mark.parametrize("shape", [(64, 300, 16), (33, 1000, 7), (5, 64, 1), (10, 700, 64), (7, 3, 128)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_slice_norms(shape, dtype):
     rs = np.random.default_rng(shape[1])
-    A = rs.standard_normal(shape).astype(np.float32) * np.exp(rs.standard_normal(shape[1]))[None, :, None].astype(
-        np.float32)
+    A = rs.standard_normal(shape).astype(dtype) * np.exp(rs.standard_normal(shape[1]))[None, :, None].astype(dtype)
     lat = api.slice_norms(dev(A), "lateral").cpu().numpy()
     hor = api.slice_norms(dev(A), "horizontal").cpu().numpy()
     np.testing.assert_allclose(lat, S.lateral_sq_norms(A), rtol=1e-13)
