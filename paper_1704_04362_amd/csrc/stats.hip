@@ -6,8 +6,6 @@
 // Squares are formed and summed in float64 (a float32 square is exact in
 // float64), always in the same order, so results are reproducible run to
 // run. No floating-point atomics.
-#include <algorithm>
-
 #include "common.hpp"
 
 namespace tp {
@@ -34,8 +32,7 @@ struct V16<double> {
 // In every row those LT tubes are one contiguous run of LT*n3 values; a
 // thread always owns the same 16-byte pieces of that run, so it accumulates
 // its pieces over all rows with independent coalesced loads, and the pieces
-// of a tube are added in a fixed order at the end through LDS. Used for
-// tube lengths whose 16-byte pieces do not fit the streaming kernel below.
+// of a tube are added in a fixed order at the end through LDS.
 template <typename T>
 __global__ __launch_bounds__(LNT) void lateral_partial_kernel(const T* __restrict__ a, int64_t n1, int64_t n2,
                                                                int64_t n3, double* __restrict__ partial) {
@@ -80,63 +77,6 @@ __global__ __launch_bounds__(LNT) void lateral_partial_kernel(const T* __restric
     }
     if (f < LT * CH) piece[f] = s;
   }
-  __syncthreads();
-  if (tid < ntub) {
-    double t = 0.0;
-    for (int64_t p = 0; p < CH; ++p) t += piece[tid * CH + p];
-    partial[(int64_t)blockIdx.y * n2 + j0 + tid] = t;
-  }
-}
-
-// Streaming variant: workgroup (bx, by) owns tubes [bx*tb, +tb), one
-// contiguous run of tb*n3 values (up to SPIECES 16-byte pieces, 64 KB) per
-// horizontal slice, and walks the SROWS slices [by*SROWS, +SROWS) one after
-// the other. At any time a workgroup reads one contiguous 64 KB run, so the
-// concurrent loads spread over all memory channels (reading many slices at
-// once puts runs a power-of-two slice stride apart on the same channels).
-// Each thread owns the pieces tid + LNT*it of the run and sums their squares
-// over the slices; the pieces of a tube are then added in a fixed order
-// through LDS.
-constexpr int SPIECES = 4096;
-constexpr int SPT = SPIECES / LNT;  // pieces per thread
-constexpr int SROWS = 4;
-
-template <typename T>
-__global__ __launch_bounds__(LNT) void lateral_stream_kernel(const T* __restrict__ a, int64_t n1, int64_t n2,
-                                                             int64_t n3, int64_t tb, double* __restrict__ partial) {
-  using V = typename V16<T>::type;
-  constexpr int VN = V16<T>::n;
-  __shared__ double piece[SPIECES];
-  const int tid = threadIdx.x;
-  const int64_t CH = n3 / VN;
-  const int64_t j0 = (int64_t)blockIdx.x * tb;
-  const int64_t i0 = (int64_t)blockIdx.y * SROWS;
-  const int64_t ntub = (n2 - j0) < tb ? (n2 - j0) : tb;
-  const int64_t npieces = ntub * CH;
-  const int64_t rows = (n1 - i0) < SROWS ? (n1 - i0) : SROWS;
-  double s[SPT];
-#pragma unroll
-  for (int it = 0; it < SPT; ++it) s[it] = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const T* run = a + ((i0 + r) * n2 + j0) * n3;
-    V w[SPT];
-#pragma unroll
-    for (int it = 0; it < SPT; ++it) {
-      const int64_t f = tid + LNT * it;
-      const int64_t fc = f < npieces ? f : 0;
-      w[it] = *reinterpret_cast<const V*>(run + fc * VN);
-    }
-#pragma unroll
-    for (int it = 0; it < SPT; ++it) {
-      const T* wp = reinterpret_cast<const T*>(&w[it]);
-      double q = 0.0;
-#pragma unroll
-      for (int e = 0; e < VN; ++e) q += (double)wp[e] * (double)wp[e];
-      s[it] += (tid + LNT * it) < npieces ? q : 0.0;
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < SPT; ++it) piece[tid + LNT * it] = s[it];
   __syncthreads();
   if (tid < ntub) {
     double t = 0.0;
@@ -200,57 +140,30 @@ __global__ void normprod_kernel(const double* a, const double* b, int64_t n, dou
   if (j < n) out[j] = sqrt(a[j] * b[j]);
 }
 
-// Tubes per workgroup of the streaming kernel (0: not applicable): whole
-// tubes whose 16-byte pieces fit one run of SPIECES pieces, at most LNT
-// tubes (one finishing thread each).
-int64_t stream_tubes(int dtype, int64_t n3) {
-  const int vn = dtype == TP_F64 ? 2 : 4;
-  if (n3 % vn != 0) return 0;
-  const int64_t ch = n3 / vn;
-  if (ch > SPIECES) return 0;
-  const int64_t tb = SPIECES / ch;
-  return tb < LNT ? tb : LNT;
-}
-
-int64_t lateral_blocks(int dtype, int64_t n1, int64_t n3) {
-  return stream_tubes(dtype, n3) ? (n1 + SROWS - 1) / SROWS : (n1 + LROWS - 1) / LROWS;
-}
+int64_t lateral_blocks(int64_t n1) { return (n1 + LROWS - 1) / LROWS; }
 
 }  // namespace
 
-size_t lateral_norms_ws(int64_t n1, int64_t n2, int64_t n3) {
-  // the larger of the two kernels' partial counts (the dtype is not known here)
-  const int64_t nb = std::max(lateral_blocks(TP_F32, n1, n3), lateral_blocks(TP_F64, n1, n3));
-  return align_up(size_t(nb) * n2 * 8);
-}
+size_t lateral_norms_ws(int64_t n1, int64_t n2, int64_t) { return align_up(size_t(lateral_blocks(n1)) * n2 * 8); }
 
 int lateral_norms(const void* a, int dtype, int64_t n1, int64_t n2, int64_t n3, double* out, double* ws,
                   hipStream_t st) {
   if (n2 == 0) return TP_OK;
+  const int64_t nb = lateral_blocks(n1);
+  const int vn = dtype == TP_F64 ? 2 : 4;
+  const int64_t CH = (n3 % vn == 0) ? n3 / vn : n3;
+  const size_t lds = size_t(LT) * CH * sizeof(double);
+  if (lds > 64 * 1024) return fail(TP_EUNSUPPORTED, "tube length too large for the slice-norm kernel");
   if (n1 == 0) {
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, out, n2);
     TP_LAUNCH_CHECK();
     return TP_OK;
   }
-  const int64_t nb = lateral_blocks(dtype, n1, n3);
-  if (const int64_t tb = stream_tubes(dtype, n3)) {
-    dim3 grid((unsigned)((n2 + tb - 1) / tb), (unsigned)nb);
-    if (dtype == TP_F64)
-      hipLaunchKernelGGL(lateral_stream_kernel<double>, grid, dim3(LNT), 0, st, (const double*)a, n1, n2, n3, tb,
-                         ws);
-    else
-      hipLaunchKernelGGL(lateral_stream_kernel<float>, grid, dim3(LNT), 0, st, (const float*)a, n1, n2, n3, tb, ws);
-  } else {
-    const int vn = dtype == TP_F64 ? 2 : 4;
-    const int64_t CH = (n3 % vn == 0) ? n3 / vn : n3;
-    const size_t lds = size_t(LT) * CH * sizeof(double);
-    if (lds > 64 * 1024) return fail(TP_EUNSUPPORTED, "tube length too large for the slice-norm kernel");
-    dim3 grid((unsigned)((n2 + LT - 1) / LT), (unsigned)nb);
-    if (dtype == TP_F64)
-      hipLaunchKernelGGL(lateral_partial_kernel<double>, grid, dim3(LNT), lds, st, (const double*)a, n1, n2, n3, ws);
-    else
-      hipLaunchKernelGGL(lateral_partial_kernel<float>, grid, dim3(LNT), lds, st, (const float*)a, n1, n2, n3, ws);
-  }
+  dim3 grid((unsigned)((n2 + LT - 1) / LT), (unsigned)nb);
+  if (dtype == TP_F64)
+    hipLaunchKernelGGL(lateral_partial_kernel<double>, grid, dim3(LNT), lds, st, (const double*)a, n1, n2, n3, ws);
+  else
+    hipLaunchKernelGGL(lateral_partial_kernel<float>, grid, dim3(LNT), lds, st, (const float*)a, n1, n2, n3, ws);
   TP_LAUNCH_CHECK();
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, ws, nb, n2, out);
   TP_LAUNCH_CHECK();
