@@ -51,40 +51,83 @@ __device__ __forceinline__ int tournament(int pos, int round, int nb) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + round) % (nb - 1));
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Staged rows of a pair step live in LDS as float64 with a row stride chosen
+// per access pattern (in doubles): the Gram products read 16 rows x 4
+// consecutive columns per instruction (stride = 4 mod 32 keeps that 2-way,
+// the minimum for 64 eight-byte lanes), the rotations 4 rows x 16 columns
+// (stride = 16 mod 32).
+constexpr int kGramStride = CHC + 4;
+constexpr int kRotStride = CHC + 16;
+constexpr int kStage = PR * kRotStride;
+
+// Copies columns [c0, c0 + nc) of the rows rows[0..PR) (float32 planar) into
+// the float64 staging arrays with row stride S; missing rows and columns
+// past nc read as zero.
+template <int S>
+__device__ __forceinline__ void stage_rows(double* sr, double* si, const float* re, const float* im, int64_t ncols,
+                                           int64_t c0, int nc, const int* rows, bool real) {
+  for (int e = threadIdx.x; e < PR * CHC; e += NT) {
+    const int r = e / CHC, j = e - r * CHC;
+    double vr = 0.0, vi = 0.0;
+    if (j < nc && rows[r] >= 0) {
+      const int64_t off = (int64_t)rows[r] * ncols + c0 + j;
+      vr = (double)re[off];
+      vi = real ? 0.0 : (double)im[off];
+    }
+    sr[r * S + j] = vr;
+    si[r * S + j] = vi;
+  }
+}
+
 // Rotates rows rows[0..PR) of a row-major K x nrows x ncols planar matrix by
-// V^H: out_s = sum_t conj(V_ts) in_t.
-template <typename Sh>
-__device__ void rotate_rows(Sh& sh, double (*cr)[CHC + 1], double (*ci)[CHC + 1], float* re, float* im,
-                            int64_t ncols, const int* rows, bool real) {
-  const int tid = threadIdx.x;
+// V^H: out_s = sum_t conj(V_ts) in_t, on the float64 matrix cores
+// (v_mfma_f64_16x16x4f64: A lane l = A[l % 16][l / 16], B lane l =
+// B[l / 16][l % 16], D lane l register v = D[4 v + l / 16][l % 16], as
+// measured on gfx950).
+// Wavefront w owns output columns [16 w, 16 w + 16) of each staged chunk and
+// both 16-row halves; the V^H fragments (A[s][t] = conj(V[t][s])) are passed
+// in registers: vfr/vfi[h][kk] for row half h and contraction step kk.
+__device__ void rotate_rows(const double (&vfr)[2][8], const double (&vfi)[2][8], double* sr, double* si,
+                            float* re, float* im, int64_t ncols, const int* rows, bool real) {
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int j0 = 16 * w;
   for (int64_t c0 = 0; c0 < ncols; c0 += CHC) {
     const int nc = (int)((ncols - c0) < CHC ? (ncols - c0) : CHC);
-    for (int e = tid; e < PR * CHC; e += NT) {
-      const int s = e / CHC, j = e - s * CHC;
-      double vr = 0.0, vi = 0.0;
-      if (j < nc && rows[s] >= 0) {
-        const int64_t off = (int64_t)rows[s] * ncols + c0 + j;
-        vr = (double)re[off];
-        vi = real ? 0.0 : (double)im[off];
-      }
-      cr[s][j] = vr;
-      ci[s][j] = vi;
-    }
+    stage_rows<kRotStride>(sr, si, re, im, ncols, c0, nc, rows, real);
     __syncthreads();
-    for (int e = tid; e < PR * CHC; e += NT) {
-      const int s = e / CHC, j = e - s * CHC;
-      if (j >= nc || rows[s] < 0) continue;
-      double ar = 0.0, ai = 0.0;
-#pragma unroll 8
-      for (int t = 0; t < PR; ++t) {
-        // conj(V_ts) * x_tj
-        const double vr = sh.Vr[t][s], vi = -sh.Vi[t][s];
-        ar += vr * cr[t][j] - vi * ci[t][j];
-        ai += vr * ci[t][j] + vi * cr[t][j];
+    d4 orr[2], oi[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      orr[h] = d4{0.0, 0.0, 0.0, 0.0};
+      oi[h] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int kk = 0; kk < PR / 4; ++kk) {
+      const int t = 4 * kk + (l >> 4), j = j0 + (l & 15);
+      const double br = sr[t * kRotStride + j], bi = si[t * kRotStride + j];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // conj(V)^T x: re = Vr xr + Vi xi, im = Vr xi - Vi xr
+        orr[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(vfr[h][kk], br, orr[h], 0, 0, 0);
+        orr[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(vfi[h][kk], bi, orr[h], 0, 0, 0);
+        oi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(vfr[h][kk], bi, oi[h], 0, 0, 0);
+        oi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-vfi[h][kk], br, oi[h], 0, 0, 0);
       }
-      const int64_t off = (int64_t)rows[s] * ncols + c0 + j;
-      re[off] = (float)ar;
-      if (!real) im[off] = (float)ai;
+    }
+    const int j = j0 + (l & 15);
+    if (j < nc) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int sidx = 16 * h + 4 * v + (l >> 4);
+          if (rows[sidx] < 0) continue;
+          const int64_t off = (int64_t)rows[sidx] * ncols + c0 + j;
+          re[off] = (float)orr[h][v];
+          if (!real) im[off] = (float)oi[h][v];
+        }
     }
     __syncthreads();
   }
@@ -92,13 +135,13 @@ __device__ void rotate_rows(Sh& sh, double (*cr)[CHC + 1], double (*ci)[CHC + 1]
 
 __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   __shared__ JacobiShared<PR, NT> sh;
-  __shared__ double cr[PR][CHC + 1], ci[PR][CHC + 1];
+  __shared__ double stage_r[kStage], stage_i[kStage];
   __shared__ int rows[PR];
   __shared__ double ratio_red[NT];
   __shared__ int skip;
   const int64_t k = blockIdx.y;
   const int pair = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   if (a.conv[k]) return;
   const bool real = k == 0 || (a.real_last && k == a.K - 1);
   const int ba = tournament(pair, round, a.nb), bb = tournament(a.nb - 1 - pair, round, a.nb);
@@ -111,43 +154,32 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   float* xim = a.xim + k * a.n1 * a.n2;
   float* ure = a.ure + k * a.n1 * a.n1;
   float* uim = a.uim + k * a.n1 * a.n1;
-  // Gram G_st = sum_j x_s[j] conj(x_t[j]), 4 entries per thread
-  double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
+  // Gram G_st = sum_j x_s[j] conj(x_t[j]) on the matrix cores: wavefront w
+  // owns the 16 x 16 block (s0, t0); re = Xr Xr^T + Xi Xi^T,
+  // im = Xi Xr^T - Xr Xi^T (A = rows s0.., B = rows t0.. transposed)
+  const int s0 = 16 * (w >> 1), t0 = 16 * (w & 1);
+  d4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
   __syncthreads();
   for (int64_t c0 = 0; c0 < a.n2; c0 += CHC) {
     const int nc = (int)((a.n2 - c0) < CHC ? (a.n2 - c0) : CHC);
-    for (int e = tid; e < PR * CHC; e += NT) {
-      const int s = e / CHC, j = e - s * CHC;
-      double vr = 0.0, vi = 0.0;
-      if (j < nc && rows[s] >= 0) {
-        const int64_t off = (int64_t)rows[s] * a.n2 + c0 + j;
-        vr = (double)xre[off];
-        vi = real ? 0.0 : (double)xim[off];
-      }
-      cr[s][j] = vr;
-      ci[s][j] = vi;
-    }
+    stage_rows<kGramStride>(stage_r, stage_i, xre, xim, a.n2, c0, nc, rows, real);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + NT * q;
-      const int s = e / PR, t = e - s * PR;
-      double sr = gr[q], si = gi[q];
-      for (int j = 0; j < nc; ++j) {
-        sr += cr[s][j] * cr[t][j] + ci[s][j] * ci[t][j];
-        si += ci[s][j] * cr[t][j] - cr[s][j] * ci[t][j];
-      }
-      gr[q] = sr;
-      gi[q] = si;
+#pragma unroll 4
+    for (int kk = 0; kk < CHC / 4; ++kk) {
+      const int j = 4 * kk + (l >> 4);
+      const double ar = stage_r[(s0 + (l & 15)) * kGramStride + j], ai = stage_i[(s0 + (l & 15)) * kGramStride + j];
+      const double br = stage_r[(t0 + (l & 15)) * kGramStride + j], bi = stage_i[(t0 + (l & 15)) * kGramStride + j];
+      gre = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, gre, 0, 0, 0);
+      gre = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, gre, 0, 0, 0);
+      gim = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, gim, 0, 0, 0);
+      gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, gim, 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + NT * q;
-    const int s = e / PR, t = e - s * PR;
-    sh.Hr[s][t] = gr[q];
-    sh.Hi[s][t] = gi[q];
+  for (int v = 0; v < 4; ++v) {
+    sh.Hr[s0 + 4 * v + (l >> 4)][t0 + (l & 15)] = gre[v];
+    sh.Hi[s0 + 4 * v + (l >> 4)][t0 + (l & 15)] = gim[v];
   }
   __syncthreads();
   // largest off-diagonal entry relative to the larger squared norm of its
@@ -160,19 +192,18 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   // angle is below tol relative to the pair's spectral gap, which bounds
   // the error of the thresholded result by ~tol ||M||.
   double mr = 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + NT * q;
+  for (int e = tid; e < PR * PR; e += NT) {
     const int s = e / PR, t = e - s * PR;
     if (s != t) {
       const double d = fmax(sh.Hr[s][s], sh.Hr[t][t]);
-      if (d > 0.0) mr = fmax(mr, sqrt(gr[q] * gr[q] + gi[q] * gi[q]) / d);
+      const double gr = sh.Hr[s][t], gi = sh.Hi[s][t];
+      if (d > 0.0) mr = fmax(mr, sqrt(gr * gr + gi * gi) / d);
     }
   }
   ratio_red[tid] = mr;
   __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
-    if (tid < w) ratio_red[tid] = fmax(ratio_red[tid], ratio_red[tid + w]);
+  for (int ww = NT / 2; ww > 0; ww >>= 1) {
+    if (tid < ww) ratio_red[tid] = fmax(ratio_red[tid], ratio_red[tid + ww]);
     __syncthreads();
   }
   if (tid == 0) {
@@ -182,8 +213,19 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   __syncthreads();
   if (skip) return;
   jacobi_eig_lds<PR, NT>(sh, PR, a.inner_sweeps, 1e-14);
-  rotate_rows(sh, cr, ci, xre, xim, a.n2, rows, real);
-  rotate_rows(sh, cr, ci, ure, uim, a.n1, rows, real);
+  // V^H fragments for the rotations: A[s][t] = conj(V[t][s]) with
+  // s = 16 h + (l % 16), t = 4 kk + (l / 16); the minus sign of the
+  // imaginary part is applied in the products
+  double vfr[2][8], vfi[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int kk = 0; kk < PR / 4; ++kk) {
+      vfr[h][kk] = sh.Vr[4 * kk + (l >> 4)][16 * h + (l & 15)];
+      vfi[h][kk] = sh.Vi[4 * kk + (l >> 4)][16 * h + (l & 15)];
+    }
+  rotate_rows(vfr, vfi, stage_r, stage_i, xre, xim, a.n2, rows, real);
+  rotate_rows(vfr, vfi, stage_r, stage_i, ure, uim, a.n1, rows, real);
 }
 
 __global__ void svt_conv_kernel(const float* __restrict__ ratio, int64_t K, int nrounds, int npairs, double tol,
