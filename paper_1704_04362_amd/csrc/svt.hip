@@ -62,22 +62,43 @@ constexpr int kGramStride = CHC + 4;
 constexpr int kRotStride = CHC + 16;
 constexpr int kStage = PR * kRotStride;
 
-// Copies columns [c0, c0 + nc) of the rows rows[0..PR) (float32 planar) into
-// the float64 staging arrays with row stride S; missing rows and columns
-// past nc read as zero.
-template <int S>
-__device__ __forceinline__ void stage_rows(double* sr, double* si, const float* re, const float* im, int64_t ncols,
-                                           int64_t c0, int nc, const int* rows, bool real) {
-  for (int e = threadIdx.x; e < PR * CHC; e += NT) {
+// A chunk of the staged rows (columns [c0, c0 + nc) of rows[0..PR), float32
+// planar) as held by one thread between its global loads and its LDS
+// stores: element e = tid + NT q is row e / CHC, column e % CHC; missing rows
+// and columns past nc read as zero. Loading the next chunk into registers
+// before the current one is consumed keeps the global loads in flight
+// during the products.
+constexpr int kChunkPer = PR * CHC / NT;
+struct ChunkRegs {
+  float r[kChunkPer], i[kChunkPer];
+};
+
+__device__ __forceinline__ void load_chunk(ChunkRegs& g, const float* re, const float* im, int64_t ncols, int64_t c0,
+                                           int nc, const int* rows, bool real) {
+#pragma unroll
+  for (int q = 0; q < kChunkPer; ++q) {
+    const int e = threadIdx.x + NT * q;
     const int r = e / CHC, j = e - r * CHC;
-    double vr = 0.0, vi = 0.0;
+    float vr = 0.f, vi = 0.f;
     if (j < nc && rows[r] >= 0) {
       const int64_t off = (int64_t)rows[r] * ncols + c0 + j;
-      vr = (double)re[off];
-      vi = real ? 0.0 : (double)im[off];
+      vr = re[off];
+      vi = real ? 0.f : im[off];
     }
-    sr[r * S + j] = vr;
-    si[r * S + j] = vi;
+    g.r[q] = vr;
+    g.i[q] = vi;
+  }
+}
+
+// Stores a chunk into the float64 staging arrays with row stride S.
+template <int S>
+__device__ __forceinline__ void store_chunk(const ChunkRegs& g, double* sr, double* si) {
+#pragma unroll
+  for (int q = 0; q < kChunkPer; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int r = e / CHC, j = e - r * CHC;
+    sr[r * S + j] = (double)g.r[q];
+    si[r * S + j] = (double)g.i[q];
   }
 }
 
@@ -93,10 +114,17 @@ __device__ void rotate_rows(const double (&vfr)[2][8], const double (&vfi)[2][8]
                             float* re, float* im, int64_t ncols, const int* rows, bool real) {
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int j0 = 16 * w;
+  ChunkRegs g;
+  load_chunk(g, re, im, ncols, 0, (int)(ncols < CHC ? ncols : CHC), rows, real);
   for (int64_t c0 = 0; c0 < ncols; c0 += CHC) {
     const int nc = (int)((ncols - c0) < CHC ? (ncols - c0) : CHC);
-    stage_rows<kRotStride>(sr, si, re, im, ncols, c0, nc, rows, real);
+    store_chunk<kRotStride>(g, sr, si);
     __syncthreads();
+    // the next chunk's columns are disjoint from the ones written below
+    if (c0 + CHC < ncols) {
+      const int64_t c1 = c0 + CHC;
+      load_chunk(g, re, im, ncols, c1, (int)((ncols - c1) < CHC ? (ncols - c1) : CHC), rows, real);
+    }
     d4 orr[2], oi[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -160,10 +188,15 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   const int s0 = 16 * (w >> 1), t0 = 16 * (w & 1);
   d4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
   __syncthreads();
+  ChunkRegs g;
+  load_chunk(g, xre, xim, a.n2, 0, (int)(a.n2 < CHC ? a.n2 : CHC), rows, real);
   for (int64_t c0 = 0; c0 < a.n2; c0 += CHC) {
-    const int nc = (int)((a.n2 - c0) < CHC ? (a.n2 - c0) : CHC);
-    stage_rows<kGramStride>(stage_r, stage_i, xre, xim, a.n2, c0, nc, rows, real);
+    store_chunk<kGramStride>(g, stage_r, stage_i);
     __syncthreads();
+    if (c0 + CHC < a.n2) {
+      const int64_t c1 = c0 + CHC;
+      load_chunk(g, xre, xim, a.n2, c1, (int)((a.n2 - c1) < CHC ? (a.n2 - c1) : CHC), rows, real);
+    }
 #pragma unroll 4
     for (int kk = 0; kk < CHC / 4; ++kk) {
       const int j = 4 * kk + (l >> 4);
