@@ -4,6 +4,7 @@ infrastructure only).
 * rtprod      Algorithm 2 given the picked slices and their scales.
 * tproject    Algorithm 3, t-CX (Algorithm 4) given picked lateral slices.
 * tpinv_r     per-Fourier-slice rank-r truncated pseudo-inverse.
+* tcx_union   t-CX boosted by repetition (the union of the rounds' picks).
 * tcur        Algorithm 5 given picked lateral and horizontal slices.
 * tsvt        singular value thresholding of every Fourier slice, the
               closed-form L-update of Algorithm 7 with the tensor nuclear norm.
@@ -35,7 +36,8 @@ Readings where the paper is silent or garbled:
 Pins (tests/test_oracle_decomp.py): c = n2 with uniform weights gives the
 exact product; unbiasedness and the exact second moment of the estimator by
 Monte Carlo; exact-rank inputs are reproduced exactly by t-CX and t-CUR;
-t-CX is the least-squares optimum (eq. ell2reg); n3 = 1 reduces to matrix
+t-CX is the least-squares optimum (eq. ell2reg) and its union over rounds
+is never worse than any round; n3 = 1 reduces to matrix
 CX/CUR; circ(tsvt(M, tau)) equals the matrix SVT of circ(M) with the same
 tau; tau = 0 is the identity; prox optimality under random perturbations;
 ADMM residuals shrink; every ADMM iterate satisfies the optimality
@@ -111,6 +113,16 @@ def tcx(A, idx, scale):
     idx = np.asarray(idx, dtype=np.int64)
     C = np.asarray(A, dtype=np.float64)[:, idx, :] * np.asarray(scale)[None, :, None]
     return tproject(A, C)
+
+
+def tcx_union(A, rounds):
+    """t-CX boosted by repetition: Algorithm 4 repeated with independent
+    picks, keeping the projection onto the union of all picked lateral
+    slices, C * C^+ * A with C = A[:, concatenation of the rounds' picks, :].
+    By the least-squares property of eq. ell2reg it is never worse than the
+    best single round (the argument that boosts the success probability)."""
+    idx = np.concatenate([np.asarray(r, dtype=np.int64) for r in rounds])
+    return tproject(A, np.asarray(A, dtype=np.float64)[:, idx, :])
 
 
 def tcur(A, cidx, cscale, ridx, rscale, r=None):

@@ -327,3 +327,15 @@ def test_cur_tnn_with_every_slice_is_the_admm():
     La = D.admm_rpca(X, lam, iters=40)[0]
     np.testing.assert_array_equal(Ct, La)
     assert T.rel_fro(L, La) < 1e-12
+
+
+def test_tcx_union_never_worse_than_a_round():
+    A = _lowrank(16, 30, 5, 4, seed=9) + 0.3 * rs.standard_normal((16, 30, 5))
+    g = np.random.default_rng(3)
+    rounds = [g.choice(30, 5, replace=False) for _ in range(3)]
+    Zu = D.tcx_union(A, rounds)
+    errs = [T.rel_fro(D.tcx(A, r, np.ones(5)), A) for r in rounds]
+    assert T.rel_fro(Zu, A) <= min(errs) + 1e-12
+    # a single round is plain t-CX; the union of all slices reproduces A
+    np.testing.assert_allclose(D.tcx_union(A, rounds[:1]), D.tcx(A, rounds[0], np.ones(5)), atol=1e-12)
+    assert T.rel_fro(D.tcx_union(A, [np.arange(30)]), A) < 1e-12
