@@ -55,6 +55,11 @@ _SIGS = {
     "tp_tcomplete": (C.c_int, [P(Tensor), C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
                                P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tcomplete_workspace": (C.c_size_t, [P(Tensor)]),
+    "tp_tproject": (C.c_int, [P(Tensor), P(Tensor), P(Tensor), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_tproject_workspace": (C.c_size_t, [P(Tensor), P(Tensor), C.c_int]),
+    "tp_tcx": (C.c_int, [P(Tensor), C.c_int64, C.c_int32, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_uint64,
+                         P(Sample), P(Tensor), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_tcx_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int32, C.c_int64, C.c_int, C.c_int]),
     "tp_trpca": (C.c_int, [P(Tensor), C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
                            P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_trpca_workspace": (C.c_size_t, [P(Tensor)]),

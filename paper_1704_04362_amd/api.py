@@ -189,6 +189,40 @@ def tsvd_rand(A, r, p=10, q=1, seed=0, prec=None):
     return S, lat, hor
 
 
+def tproject(X, Cs, prec=None, out=None):
+    """t-project of Algorithm 3: Z = C * C^+ * X (C has at most 64 lateral
+    slices)."""
+    _need_gpu(X, Cs)
+    if prec is None:
+        prec = "f64" if X.dtype == torch.float64 else "f32"
+    Z = out if out is not None else torch.empty_like(X)
+    lib = L.load()
+    tx, tc, tz = _tensor(X), _tensor(Cs), _tensor(Z)
+    ws = _ws(lib.tp_tproject_workspace(C.byref(tx), C.byref(tc), L.PREC[prec]), X.device)
+    L.check(lib.tp_tproject(C.byref(tx), C.byref(tc), C.byref(tz), L.PREC[prec], ws.data_ptr(), ws.numel(),
+                            _stream()))
+    return Z
+
+
+def tcx(A, c, rounds=1, r=1, col_kind="norm2", col_w=None, mode="iid", seed=0, prec=None, out=None):
+    """t-CX of Algorithm 4 boosted by repetition (the projection onto the
+    union of `rounds` independent draws of c slices): returns (Z, picks)."""
+    _need_gpu(A, col_w)
+    if prec is None:
+        prec = "f64" if A.dtype == torch.float64 else "f32"
+    cols = Picks(c * rounds, A.device)
+    Z = out if out is not None else torch.empty_like(A)
+    lib = L.load()
+    ta, tz = _tensor(A), _tensor(Z)
+    cs = cols.struct()
+    ws = _ws(lib.tp_tcx_workspace(C.byref(ta), int(c), int(rounds), int(r), L.KIND[col_kind], L.PREC[prec]),
+             A.device)
+    L.check(lib.tp_tcx(C.byref(ta), int(c), int(rounds), int(r), L.KIND[col_kind],
+                       col_w.data_ptr() if col_w is not None else None, L.MODE[mode], int(seed), C.byref(cs),
+                       C.byref(tz), L.PREC[prec], ws.data_ptr(), ws.numel(), _stream()))
+    return Z, cols
+
+
 def tcur(A, c, l, r, col_kind="lev", row_kind="lev", col_w=None, row_w=None, mode="iid", seed=0, prec=None,
          want_z=True, out=None):
     """t-CUR of Algorithm 5: returns (Z, column picks, row picks); Z is None

@@ -99,8 +99,8 @@ struct RangeFinder {
   // out = orthonormal basis of the columns of X (rows x s) by CholeskyQR:
   // X^H X = R^H R, out = X R^{-1}, with pivots at or below rtol times the
   // largest diagonal entry dropped (zero columns).
-  int orth(const Spec& X, int64_t rows, const Spec& out, int prec, hipStream_t st) const {
-    const double rtol = dtype == TP_F64 ? 1e-24 : 1e-11;
+  int orth(const Spec& X, int64_t rows, const Spec& out, int prec, hipStream_t st, double rtol_pivot = 0.0) const {
+    const double rtol = rtol_pivot > 0.0 ? rtol_pivot : (dtype == TP_F64 ? 1e-24 : 1e-11);
     if (int rc = gram(X.re, X.im, dtype, K, rows, s, s, rows * s, real_last, gre, gim, pre, pim, st)) return rc;
     if (int rc = chol_inv(gre, gim, K, s, rtol, real_last, T.re, T.im, dtype, st)) return rc;
     return mm(X, 0, rows, s, T, 0, s, s, out, K, real_last, dtype, prec, st);
@@ -360,6 +360,43 @@ struct CurNNLayout {
     admm_bytes = std::max(admm_workspace(n1, c, n3), admm_workspace(l, n2, n3));
     admm = ar.take<char>(admm_bytes);
     return ar.dry() || ar.ok();
+  }
+};
+
+// Orthogonal projection of every Fourier slice of X onto the range of the
+// matching slice of C (Algorithm 3): Q_k = an orthonormal basis of the
+// columns of Chat_k (CholeskyQR applied twice), then
+// Zhat_k = Q_k (Q_k^H Xhat_k). Xh: K x n1 x n2, Ch: K x n1 x c (c <= 64).
+// A column whose Cholesky pivot falls to kProjPivot of the largest is
+// dropped (zero column), so repeated or dependent slices project onto the
+// numerical range: the Gram matrix is float64 in both cases, so dependent
+// columns leave pivots of ~1e-16 of the largest, and 1e-13 drops them; with
+// float32 columns, Q = C R^-1 is formed in float32 and CholeskyQR2 restores
+// orthogonality only up to a condition number of ~1/sqrt(eps_32), so
+// columns below ~3e-4 of the largest singular value (pivot 1e-7) are
+// dropped. (The range finder keeps its own, smaller thresholds: a spurious
+// direction in a sketch basis is harmless, in a projector it is not.)
+constexpr double kProjPivot64 = 1e-13, kProjPivot32 = 1e-7;
+struct ProjLayout {
+  RangeFinder rf;  // orthonormalisation workspace (m = n1, n = s = c)
+  Spec G, Zh;
+  bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int64_t c, int dt, bool real_last) {
+    rf = RangeFinder{K, n1, c, (int)c, dt, real_last};
+    rf.carve(ar);
+    G = take(ar, K * c * n2, dt);
+    Zh = take(ar, K * n1 * n2, dt);
+    return ar.dry() || ar.ok();
+  }
+  int run(const Spec& Xh, const Spec& Ch, int64_t n1, int64_t n2, int64_t n3, int prec, void* Z,
+          hipStream_t st) {
+    const int64_t K = rf.K, c = rf.s;
+    const int dt = rf.dtype;
+    const double piv = dt == TP_F64 ? kProjPivot64 : kProjPivot32;
+    if (int rc = rf.orth(Ch, n1, rf.Q, prec, st, piv)) return rc;
+    if (int rc = rf.orth(rf.Q, n1, rf.Y, prec, st, piv)) return rc;
+    if (int rc = mm(rf.Y, 1, n1, c, Xh, 0, n1, n2, G, K, rf.real_last, dt, prec, st)) return rc;
+    if (int rc = mm(rf.Y, 0, n1, c, G, 0, c, n2, Zh, K, rf.real_last, dt, prec, st)) return rc;
+    return fft_inverse(Zh.re, Zh.im, dt, n3, n1, n2, Z, st);
   }
 };
 
@@ -665,6 +702,148 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
   // 5. W = the picked rows of Ct (unscaled), U = pinv_r(W), L = Ct * U * Rt
   return cur_core(lay, n1, n2, n3, K, c, l, r, rows->idx, nullptr, rows->count, seed, dt, prec, real_last, L->data,
                   st);
+}
+
+size_t tp_tproject_workspace(const tp_tensor* X, const tp_tensor* C, int prec) {
+  (void)prec;
+  if (!X || !C || X->n1 < 1 || X->n2 < 1 || X->n3 < 1 || C->n2 < 1) return 0;
+  const int64_t K = half_count(X->n3);
+  const bool real_last = (X->n3 % 2 == 0) && K > 1;
+  Arena dry(nullptr, SIZE_MAX);
+  Spec Xh = take(dry, K * X->n1 * X->n2, X->dtype), Ch = take(dry, K * X->n1 * C->n2, X->dtype);
+  (void)Xh;
+  (void)Ch;
+  ProjLayout lay;
+  lay.carve(dry, K, X->n1, X->n2, C->n2, X->dtype, real_last);
+  return dry.used + 256;
+}
+
+int tp_tproject(const tp_tensor* X, const tp_tensor* C, tp_tensor* Z, int prec, void* ws, size_t ws_bytes,
+                void* stream) {
+  if (int rc = check_tensor(X, "X")) return rc;
+  if (int rc = check_tensor(C, "C")) return rc;
+  if (int rc = check_tensor(Z, "Z")) return rc;
+  if (int rc = check_prec(X->dtype, prec)) return rc;
+  if (C->dtype != X->dtype || Z->dtype != X->dtype) return fail(TP_EDTYPE, "X, C and Z must share a dtype");
+  if (C->n1 != X->n1 || C->n3 != X->n3) return fail(TP_ESHAPE, "C must be n1 x c x n3 like X");
+  if (Z->n1 != X->n1 || Z->n2 != X->n2 || Z->n3 != X->n3) return fail(TP_ESHAPE, "Z must match X");
+  if (C->n2 > kMaxS) return fail(TP_EUNSUPPORTED, "more than 64 lateral slices in C");
+  const size_t need = tp_tproject_workspace(X, C, prec);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tproject workspace too small");
+  const int64_t n1 = X->n1, n2 = X->n2, n3 = X->n3, c = C->n2, K = half_count(n3);
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  const int dt = X->dtype;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  Spec Xh = take(ar, K * n1 * n2, dt), Ch = take(ar, K * n1 * c, dt);
+  ProjLayout lay;
+  if (!lay.carve(ar, K, n1, n2, c, dt, real_last)) return fail(TP_EWORKSPACE, "tproject workspace too small");
+  TubeGather gx;
+  gx.rows = n1;
+  gx.cols = n2;
+  gx.in_cols = n2;
+  if (int rc = fft_forward(X->data, dt, n3, gx, Xh.re, Xh.im, st)) return rc;
+  TubeGather gc;
+  gc.rows = n1;
+  gc.cols = c;
+  gc.in_cols = c;
+  if (int rc = fft_forward(C->data, dt, n3, gc, Ch.re, Ch.im, st)) return rc;
+  return lay.run(Xh, Ch, n1, n2, n3, prec, Z->data, st);
+}
+
+size_t tp_tcx_workspace(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r, int col_kind, int prec) {
+  (void)prec;
+  if (!A || A->n1 < 1 || A->n2 < 1 || A->n3 < 1 || c < 1 || rounds < 1) return 0;
+  if (r < 1) r = 1;
+  const int64_t K = half_count(A->n3), cT = c * rounds;
+  const bool real_last = (A->n3 % 2 == 0) && K > 1;
+  Arena dry(nullptr, SIZE_MAX);
+  TcurLayout cur;
+  cur.carve(dry, K, A->n1, A->n2, A->n3, cT, 1, r, col_kind, TP_P_UNIFORM, false, A->dtype, real_last);
+  if (col_kind != TP_P_LEV) (void)take(dry, K * A->n1 * A->n2, A->dtype);
+  (void)dry.take<int64_t>(rounds);
+  ProjLayout lay;
+  lay.carve(dry, K, A->n1, A->n2, cT, A->dtype, real_last);
+  return dry.used + 256;
+}
+
+int tp_tcx(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r, int col_kind, const double* col_w, int mode,
+           uint64_t seed, tp_sample* cols, tp_tensor* Z, int prec, void* ws, size_t ws_bytes, void* stream) {
+  if (int rc = check_tensor(A, "A")) return rc;
+  if (int rc = check_tensor(Z, "Z")) return rc;
+  if (int rc = check_prec(A->dtype, prec)) return rc;
+  const int64_t n1 = A->n1, n2 = A->n2, n3 = A->n3, K = half_count(n3);
+  if (Z->dtype != A->dtype || Z->n1 != n1 || Z->n2 != n2 || Z->n3 != n3) return fail(TP_ESHAPE, "Z must match A");
+  if (c < 1 || c > n2) return fail(TP_EINVAL, "need 1 <= c <= n2");
+  if (rounds < 1) return fail(TP_EINVAL, "need at least one round");
+  if (c * rounds > kMaxS) return fail(TP_EUNSUPPORTED, "more than 64 picked slices over all rounds");
+  if (mode != TP_S_IID && mode != TP_S_UNIFORM)
+    return fail(TP_EINVAL, "t-CX rounds need exactly c picks (TP_S_IID or TP_S_UNIFORM)");
+  if (col_kind != TP_P_USER && col_kind != TP_P_UNIFORM && col_kind != TP_P_NORM2 && col_kind != TP_P_LEV)
+    return fail(TP_EINVAL, "unsupported probability kind");
+  if (col_kind == TP_P_USER && !col_w) return fail(TP_EINVAL, "column weights are null");
+  if (col_kind == TP_P_LEV && (r < 1 || r > std::min(n1, n2) || sketch_size(r, kOversample, n1, n2) > kMaxS))
+    return fail(TP_EINVAL, "leverage needs 1 <= r <= min(n1, n2) and r + 10 <= 64");
+  if (!cols || !cols->idx || !cols->scale || !cols->count) return fail(TP_EINVAL, "pick buffers are null");
+  const int64_t cT = c * rounds;
+  if (cols->cap < cT) return fail(TP_EINVAL, "pick capacity must be >= c * rounds");
+  const int64_t rr = r < 1 ? 1 : r;
+  const size_t need = tp_tcx_workspace(A, c, rounds, rr, col_kind, prec);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tcx workspace too small");
+
+  const int dt = A->dtype;
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  TcurLayout cur;
+  if (!cur.carve(ar, K, n1, n2, n3, cT, 1, rr, col_kind, TP_P_UNIFORM, false, dt, real_last))
+    return fail(TP_EWORKSPACE, "tcx workspace too small");
+  Spec Ah = cur.Ah;
+  if (col_kind != TP_P_LEV) Ah = take(ar, K * n1 * n2, dt);
+  int64_t* counts = ar.take<int64_t>(rounds);
+  ProjLayout lay;
+  if (!lay.carve(ar, K, n1, n2, cT, dt, real_last)) return fail(TP_EWORKSPACE, "tcx workspace too small");
+  const double rtol = dt == TP_F64 ? 1e-12 : 1e-6;
+
+  // 1. probabilities (the leverage path transforms A into Ah on the way)
+  const double* wcol = col_w;
+  if (col_kind == TP_P_LEV) {
+    if (int rc = col_leverage(cur, A->data, dt, n1, n2, n3, K, rr, seed, prec, real_last, rtol, st)) return rc;
+    wcol = cur.wbuf;
+  } else {
+    TubeGather g;
+    g.rows = n1;
+    g.cols = n2;
+    g.in_cols = n2;
+    if (int rc = fft_forward(A->data, dt, n3, g, Ah.re, Ah.im, st)) return rc;
+    if (col_kind == TP_P_NORM2) {
+      if (int rc = lateral_norms(A->data, dt, n1, n2, n3, cur.wbuf, cur.part, st)) return rc;
+      wcol = cur.wbuf;
+    } else if (col_kind == TP_P_UNIFORM) {
+      if (int rc = fill_f64(cur.wbuf, n2, 1.0, st)) return rc;
+      wcol = cur.wbuf;
+    }
+  }
+  // 2. independent rounds of c picks (round i draws from stream 16 i of the
+  //    seed), kept side by side: the union of all rounds
+  for (int32_t i = 0; i < rounds; ++i) {
+    if (int rc = sample_slices(wcol, n2, c, mode, seed, kStreamColPick + 16 * (uint64_t)i, cols->idx + i * c,
+                               cols->scale + i * c, counts + i, cur.sws, st))
+      return rc;
+  }
+  if (int rc = join_counts(counts, rounds, cols->count, st)) return rc;
+  // 3. Chat = the picked lateral slices (unscaled: the projector onto their
+  //    span does not depend on the scales), then Z = C * C^+ * A
+  {
+    TubeGather g;
+    g.rows = n1;
+    g.cols = cT;
+    g.in_cols = n2;
+    g.col_idx = cols->idx;
+    g.count = cols->count;
+    if (int rc = fft_forward(A->data, dt, n3, g, cur.Ch.re, cur.Ch.im, st)) return rc;
+  }
+  return lay.run(Ah, cur.Ch, n1, n2, n3, prec, Z->data, st);
 }
 
 }  // extern "C"

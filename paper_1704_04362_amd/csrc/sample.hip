@@ -262,6 +262,29 @@ __global__ __launch_bounds__(SB) void uniform_kernel(int64_t n, int64_t c, uint6
 
 size_t sampler_ws(int64_t n) { return 3 * align_up(size_t(n) * 8) + 256; }
 
+namespace {
+// out = sum of n pick counts, or -1 if any of them is -1 (rejected weights)
+__global__ void join_counts_kernel(const int64_t* __restrict__ counts, int n, int64_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t t = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t c = counts[i];
+    if (c < 0) {
+      t = -1;
+      break;
+    }
+    t += c;
+  }
+  *out = t;
+}
+}  // namespace
+
+int join_counts(const int64_t* counts, int n, int64_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(join_counts_kernel, dim3(1), dim3(64), 0, st, counts, n, out);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
 int sample_slices(const double* w, int64_t n, int64_t c, int mode, uint64_t seed, uint64_t stream_id, int32_t* idx,
                   double* scale, int64_t* count, void* ws, hipStream_t st) {
   Arena ar(ws, sampler_ws(n));

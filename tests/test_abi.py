@@ -133,3 +133,30 @@ def test_tcur_nn_validation(case):
                         10, 1.1, 1e-3, 1e10, C.byref(cols), C.byref(rows), C.byref(Lt), L.PREC["f32"],
                         C.c_void_p(0x2000), 1 << 30, None)
     assert rc == want
+
+
+@pytest.mark.parametrize("case", ["too_many", "bernoulli", "rounds", "lev_rank"])
+def test_tcx_validation(case):
+    lib = L.load()
+    A, Z = _t(20, 100, 4), _t(20, 100, 4)
+    cols = L.Sample(0x3000, 0x4000, 200, 0x5000)
+    c, rounds, r, kind, mode, want = 8, 2, 2, L.KIND["norm2"], L.MODE["iid"], -1
+    if case == "too_many":
+        c, rounds, want = 33, 2, -7
+    elif case == "bernoulli":
+        mode = L.MODE["bernoulli"]
+    elif case == "rounds":
+        rounds = 0
+    else:
+        kind, r = L.KIND["lev"], 60
+    rc = lib.tp_tcx(C.byref(A), c, rounds, r, kind, None, mode, 0, C.byref(cols), C.byref(Z), L.PREC["f32"],
+                    C.c_void_p(0x2000), 1 << 30, None)
+    assert rc == want
+
+
+def test_tproject_validation():
+    lib = L.load()
+    X, Z = _t(20, 30, 4), _t(20, 30, 4)
+    for Cs, want in ((_t(20, 65, 4), -7), (_t(21, 5, 4), -2), (_t(20, 5, 4, dtype=L.TP_F64), -3)):
+        rc = lib.tp_tproject(C.byref(X), C.byref(Cs), C.byref(Z), L.PREC["f32"], C.c_void_p(0x2000), 1 << 30, None)
+        assert rc == want

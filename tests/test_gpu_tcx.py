@@ -1,0 +1,102 @@
+"""GPU parity of t-project (Algorithm 3) and t-CX boosted by repetition
+(Algorithm 4) against the FP64 oracle, through the C ABI.
+
+Tolerances: float64 1e-10 relative Frobenius error (CholeskyQR2 against the
+oracle's pseudo-inverse on well-conditioned slices); float32 1e-5 and split
+bf16 products 5e-5, as for the other float32 paths. Exact-rank inputs are
+reproduced to the same tolerances. t-CX is compared on the picks the GPU
+drew (the oracle takes them as inputs).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import decomp as D
+from oracle import sampling as S
+from oracle import tensor as T
+
+pytestmark = pytest.mark.gpu
+
+api = pytest.importorskip("paper_1704_04362_amd.api")
+
+CASES = [(np.float64, "f64", 1e-10), (np.float32, "f32", 1e-5), (np.float32, "bf16x3", 5e-5)]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def rel(a, b):
+    a = a.cpu().numpy() if torch.is_tensor(a) else a
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+@pytest.mark.parametrize("dtype,prec,tol", CASES)
+@pytest.mark.parametrize("shape", [(40, 70, 8, 12), (65, 33, 7, 30), (70, 90, 1, 64)])
+def test_tproject_matches_oracle(shape, dtype, prec, tol):
+    n1, n2, n3, c = shape
+    g = np.random.default_rng(sum(shape))
+    X = g.standard_normal((n1, n2, n3)).astype(dtype)
+    Cs = g.standard_normal((n1, c, n3)).astype(dtype)
+    if c >= n1:
+        pytest.skip("C of full row rank: the projector is the identity")
+    Z = api.tproject(dev(X), dev(Cs), prec=prec)
+    ref = D.tproject(X.astype(np.float64), Cs.astype(np.float64))
+    assert rel(Z, ref) < tol
+
+
+@pytest.mark.parametrize("dtype,prec,tol", CASES)
+def test_tproject_repeated_and_zero_slices(dtype, prec, tol):
+    # C = [B, B permuted, 0]: 12 lateral slices spanning the 5 of B (exact
+    # duplicates stay exact through the transform); the projector is that
+    # of B
+    g = np.random.default_rng(5)
+    X = g.standard_normal((36, 50, 6)).astype(dtype)
+    B = g.standard_normal((36, 5, 6)).astype(dtype)
+    Cs = np.concatenate([B, B[:, [3, 0, 4, 1, 2], :], B[:, :1, :], np.zeros((36, 1, 6), dtype)], axis=1)
+    Z = api.tproject(dev(X), dev(Cs), prec=prec)
+    ref = D.tproject(X.astype(np.float64), B.astype(np.float64))
+    assert rel(Z, ref) < tol
+
+
+@pytest.mark.parametrize("dtype,prec,tol", CASES)
+@pytest.mark.parametrize("kind,mode,rounds", [("norm2", "iid", 1), ("uniform", "uniform", 3), ("lev", "iid", 2)])
+def test_tcx_matches_oracle_on_same_picks(kind, mode, rounds, dtype, prec, tol):
+    n1, n2, n3, r = 48, 80, 8, 4
+    G1, G2, N = W.lowrank_factors(n1, n2, n3, r, noise_var=1e-2, salt=11, dtype=np.float64)
+    A = (T.tprod_fft(G1, G2) + N).astype(dtype)
+    Z, picks = api.tcx(dev(A), 8, rounds=rounds, r=r, col_kind=kind, mode=mode, seed=4, prec=prec)
+    idx, _ = picks.host()
+    assert len(idx) == 8 * rounds
+    ref = D.tcx_union(A.astype(np.float64), [idx.numpy()[8 * i:8 * (i + 1)] for i in range(rounds)])
+    assert rel(Z, ref) < tol
+
+
+def test_tcx_exact_rank_reproduces_input():
+    n1, n2, n3, r = 40, 60, 6, 3
+    G1, G2, _ = W.lowrank_factors(n1, n2, n3, r, noise_var=1e-30, salt=12, dtype=np.float64)
+    A = T.tprod_fft(G1, G2)
+    Z, _ = api.tcx(dev(A), 6, rounds=2, r=r, col_kind="lev", mode="iid", seed=1, prec="f64")
+    assert rel(Z, A) < 1e-10
+
+
+def test_tcx_rounds_boost_and_picks_follow_weights():
+    # the union of three rounds is never worse than its first round, and the
+    # i.i.d. picks of every round equal the oracle's draws for the same
+    # weights and stream
+    n1, n2, n3, r = 32, 64, 4, 6
+    g = np.random.default_rng(2)
+    A = T.tprod_fft(g.standard_normal((n1, r, n3)), g.standard_normal((r, n2, n3))) + 0.3 * g.standard_normal(
+        (n1, n2, n3))
+    w = W.lognormal_weights(n2, seed=9)
+    Z3, p3 = api.tcx(dev(A), 5, rounds=3, col_kind="user", col_w=dev(w), mode="iid", seed=7, prec="f64")
+    Z1, p1 = api.tcx(dev(A), 5, rounds=1, col_kind="user", col_w=dev(w), mode="iid", seed=7, prec="f64")
+    i3, i1 = p3.host()[0].numpy(), p1.host()[0].numpy()
+    np.testing.assert_array_equal(i3[:5], i1)
+    for i in range(3):
+        ref, _ = S.sample(w, 5, "iid", seed=7, stream=16 * i)
+        np.testing.assert_array_equal(i3[5 * i:5 * (i + 1)], ref)
+    assert rel(Z3, A) <= rel(Z1, A) + 1e-12
