@@ -282,6 +282,24 @@ def time_to_target(args, api, torch, trainer):
     }
     a, b = res.get("f32+lev", {}).get("ms"), res.get("bf16x3+learned", {}).get("ms")
     out["speedup_bf16x3_learned_vs_f32_lev"] = round(a / b, 3) if a and b else None
+    # t-CX boosted by repetition on the same tensor: c = 30 slices per round
+    tcx = {}
+    for prec in ("f32", "bf16x3"):
+        for kind in ("lev", "norm2"):
+            for rounds in (1, 2):
+                def run(kind=kind, rounds=rounds, prec=prec):
+                    return api.tcx(A, 30, rounds=rounds, r=r, col_kind=kind, mode="iid", seed=3, prec=prec, out=Z)
+                run()
+                ts = []
+                for _ in range(10):
+                    ms, _ = timed_once(run, torch)
+                    ts.append(ms)
+                tcx[f"{prec}+{kind}+rounds{rounds}"] = {"ms": round(float(np.median(ts)), 4),
+                                                        "rel_err": round(rel_err(Z, A, torch), 6)}
+    out["tcx_boosted"] = {"workload": "t-CX of the same tensor, c = 30 lateral slices per round, i.i.d. picks, "
+                                      "projection onto the union of 1 or 2 rounds; median of 10 runs",
+                          "variants": tcx}
+    log(f"t-CX: {tcx}")
     return out
 
 
