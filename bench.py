@@ -79,6 +79,7 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--no-protocol", action="store_true", help="skip the t-CUR / learned-proposal comparison")
     p.add_argument("--no-tnn", action="store_true", help="skip the completion / robust PCA / CUR t-NN comparison")
+    p.add_argument("--no-table1", action="store_true", help="skip the replay of the rt-product experiment")
     p.add_argument("--tnn-iters", type=int, default=100)
     p.add_argument("--learned-train", type=int, default=1800)
     p.add_argument("--learned-test", type=int, default=40)
@@ -397,6 +398,77 @@ def tnn_protocol(args, api, torch):
     return out
 
 
+# the paper's Table 1 (times in s on its CPU; RFE, RSE), for context
+PAPER_TABLE1 = {100: (460, 9.09, 8.13, 0.070, 0.0043, 1.03, 0.39, 0.11),
+                200: (1000, 36.36, 14.27, 0.064, 0.0025, 1.08, 0.12, 0.82),
+                300: (1700, 162.99, 34.89, 0.056, 0.0029, 1.39, 0.41, 0.34),
+                400: (2500, 321.43, 41.04, 0.031, 0.013, 1.64, 0.90, 0.038),
+                500: (3100, 684.01, 67.07, 0.071, 0.0012, 3.09, 0.23, 0.043)}
+
+
+def table1_replay(args, api, torch):
+    """Replay of the rt-product experiment at its shapes: U_r (10^5 x r x 5)
+    with orthonormal Fourier slices, U_r^T * U_r (the identity tensor)
+    estimated from l sampled horizontal slices of U_r by the rt-product,
+    with squared-norm (= exact leverage) or uniform i.i.d. picks, against
+    the exact t-product. RFE = ||I - Z||_F / ||U_r||_F^2 and RSE = the same
+    with the tensor spectral norm (largest spectral norm of a Fourier
+    slice), mean over 10 sampling seeds; time = picks + rt-product, median
+    over the seeds (HIP events)."""
+    n1, n3 = 100000, 5
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(17040436 + 101)
+    out = {"workload": "U_r: n1 = 1e5, n3 = 5, r in 100..500; Fourier slices Q_k of a QR of a Gaussian n1 x r "
+                       "matrix (Haar-distributed like the left singular slices of the paper's Gaussian tensor), "
+                       "conjugate-symmetric so U_r is real; float32 data, bf16x3 products; 10 seeds",
+           "rows": {}}
+    idx_t = [0] + list(range(n3 - 1, 0, -1))
+    for r, row in PAPER_TABLE1.items():
+        l = row[0]
+        K = n3 // 2 + 1
+        Uh = torch.empty((n1, r, n3), dtype=torch.complex64, device="cuda")
+        for k in range(K):
+            g = torch.randn((n1, r), generator=gen, device="cuda", dtype=torch.float32)
+            if k > 0:
+                g = torch.complex(g, torch.randn((n1, r), generator=gen, device="cuda", dtype=torch.float32))
+            q = torch.linalg.qr(g)[0].to(torch.complex64)
+            Uh[:, :, k] = q
+            if k > 0:
+                Uh[:, :, n3 - k] = q.conj()
+        # orthonormal Fourier slices: U_r^T * U_r is the identity tensor and
+        # ||U_r||_F^2 = r
+        U = torch.fft.ifft(Uh, dim=2).real.contiguous()
+        del Uh
+        Ut = U.permute(1, 0, 2)[:, :, idx_t].contiguous()
+        eye = torch.zeros((r, r, n3), device="cuda")
+        eye[:, :, 0] = torch.eye(r, device="cuda")
+        Zx = api.tprod(Ut, U, prec="bf16x3")
+        ms_exact, Zx = timed_once(lambda: api.tprod(Ut, U, prec="bf16x3", out=Zx), torch)
+        ent = {"l": l, "exact_ms": round(ms_exact, 3),
+               "exact_rfe": float(torch.linalg.vector_norm(Zx - eye) / r)}
+        for kind in ("norm2", "uniform"):
+            ts, rfe, rse = [], [], []
+            for seed in range(10):
+                def run(seed=seed, kind=kind):
+                    picks = api.tsample(kind, l, mode="iid", seed=seed, A=Ut)
+                    return api.tprod(Ut, U, picks=picks, prec="bf16x3")
+                run()
+                ms, Z = timed_once(run, torch)
+                ts.append(ms)
+                D = torch.fft.fft((Z - eye).to(torch.float64), dim=2)
+                rfe.append(float(torch.linalg.vector_norm(Z - eye, dtype=torch.float64) / r))
+                rse.append(float(max(torch.linalg.matrix_norm(D[:, :, k], ord=2) for k in range(n3))))
+            ent[kind] = {"ms": round(float(np.median(ts)), 3), "rfe": round(float(np.mean(rfe)), 5),
+                         "rse": round(float(np.mean(rse)), 5)}
+        p = PAPER_TABLE1[r]
+        ent["paper_cpu"] = {"t_product_s": p[1], "nonuniform": {"s": p[2], "rfe": p[3], "rse": p[4]},
+                            "uniform": {"s": p[5], "rfe": p[6], "rse": p[7]}}
+        out["rows"][str(r)] = ent
+        log(f"table 1 replay r={r} l={l}: exact {ent['exact_ms']} ms, norm2 {ent['norm2']}, uniform {ent['uniform']}")
+        del U, Ut, Zx
+    return out
+
+
 def time_events(fn, reps, torch):
     """Average duration of fn() over reps launches, HIP events on the
     current stream (the one the library enqueues on)."""
@@ -585,6 +657,9 @@ def main():
         trainer, out["learned_proposal"] = learned_protocol(args, api, torch)
         log("t-CUR time to 1e-3")
         out["tcur_time_to_1e-3"] = time_to_target(args, api, torch, trainer)
+    if not args.no_table1:
+        log("replay of the rt-product experiment (Table 1 shapes)")
+        out["table1_replay"] = table1_replay(args, api, torch)
     if not args.no_tnn:
         log("completion / robust PCA: full ADMM against CUR t-NN")
         out["tensor_nn"] = tnn_protocol(args, api, torch)
