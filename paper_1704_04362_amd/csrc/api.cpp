@@ -259,8 +259,9 @@ size_t tp_tprod_workspace(const tp_tensor* A, const tp_tensor* B, const tp_sampl
     return align_up(size_t(8) * K * A->n1 * ldk) + align_up(size_t(8) * K * B->n2 * ldk) +
            spectrum_bytes(K, A->n1, B->n2, TP_F32) + 1024;
   }
+  const int64_t part = A->dtype == TP_F32 ? cgemm_ksplit_floats(K, A->n1, B->n2, inner) : 0;
   return spectrum_bytes(K, A->n1, inner, A->dtype) + spectrum_bytes(K, inner, B->n2, A->dtype) +
-         spectrum_bytes(K, A->n1, B->n2, A->dtype) + 1024;
+         spectrum_bytes(K, A->n1, B->n2, A->dtype) + 2 * align_up(size_t(4) * part) + 1024;
 }
 
 int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp_tensor* C, int prec, void* ws,
@@ -356,6 +357,10 @@ int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp
   Plane Ah = take_spectrum(ar, K, n1, inner, A->dtype);
   Plane Bh = take_spectrum(ar, K, inner, n4, A->dtype);
   Plane Ch = take_spectrum(ar, K, n1, n4, A->dtype);
+  // scratch for a split contraction of a product with few output tiles
+  const int64_t part = A->dtype == TP_F32 ? cgemm_ksplit_floats(K, n1, n4, inner) : 0;
+  float* part_re = part ? ar.take<float>(part) : nullptr;
+  float* part_im = part ? ar.take<float>(part) : nullptr;
   if (!ar.ok()) return fail(TP_EWORKSPACE, "t-product workspace too small");
   if (inner > 0) {
     TraceScope ts(sample ? "rtprod.fft_ab" : "tprod.fft_ab", st);
@@ -381,6 +386,9 @@ int tp_tprod(const tp_tensor* A, const tp_tensor* B, const tp_sample* sample, tp
   p.sc = n1 * n4;
   p.real_last = real_last;
   p.kdim_dev = sample ? sample->count : nullptr;
+  p.part_re = part_re;
+  p.part_im = part_im;
+  p.part_cap = part;
   {
     TraceScope ts(nm_mm, st);
     if (int rc = cgemm(p, A->dtype, prec, st)) return rc;

@@ -138,9 +138,21 @@ struct CGemm {
   int op_a = 0, op_b = 0;  // 0 = N, 1 = conjugate transpose
   bool real_last = false;
   const int64_t* kdim_dev = nullptr;
+  // optional float32 scratch for a split contraction (products with few
+  // output tiles and a long contraction): part_cap floats per plane
+  float *part_re = nullptr, *part_im = nullptr;
+  int64_t part_cap = 0;
 };
 
 int cgemm(const CGemm& p, int dtype, int prec, hipStream_t st);
+// Number of contraction parts the matrix-core product would use for an
+// M x N x Kd product over K slices (1 = no split), and the scratch floats
+// per plane it needs for them.
+int cgemm_ksplit(int64_t K, int64_t M, int64_t N, int64_t Kd);
+inline int64_t cgemm_ksplit_floats(int64_t K, int64_t M, int64_t N, int64_t Kd) {
+  const int s = cgemm_ksplit(K, M, N, Kd);
+  return s > 1 ? int64_t(s) * K * M * N : 0;
+}
 
 // ---------------------------------------------------------------------------
 // Slice statistics (stats.hip)

@@ -41,6 +41,11 @@ struct MArgs {
   int64_t K;
   int real_last;
   const int64_t* kdim_dev;
+  // split contraction: part p of ksplit takes [p kchunk, (p + 1) kchunk)
+  // and writes its planes to pre / pim [p][k][M][N]
+  int ksplit;
+  int64_t kchunk;
+  float *pre, *pim;
 };
 
 template <int SPLIT>
@@ -60,7 +65,7 @@ __device__ __forceinline__ void split4(const float (&x)[4], bf16x4& hi, bf16x4& 
 }
 
 template <int SPLIT, bool REAL>
-__device__ __forceinline__ void cgemm_bf16_body(const MArgs& g, int64_t k, __bf16* sA, __bf16* sB) {
+__device__ __forceinline__ void cgemm_bf16_body(const MArgs& g, int64_t k, int part, __bf16* sA, __bf16* sB) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -176,13 +181,16 @@ __device__ __forceinline__ void cgemm_bf16_body(const MArgs& g, int64_t k, __bf1
     }
   };
 
-  const int64_t nsteps = (Kd + BK - 1) / BK;
-  if (nsteps > 0) load_tile(0u);
+  // contraction range of this part (kchunk is a multiple of BK)
+  const int64_t kbeg = (int64_t)part * g.kchunk;
+  const int64_t kend = kbeg + g.kchunk < Kd ? kbeg + g.kchunk : Kd;
+  const int64_t nsteps = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nsteps > 0) load_tile((uint32_t)kbeg);
   for (int64_t ks = 0; ks < nsteps; ++ks) {
     __syncthreads();
     store_tile();
     __syncthreads();
-    if (ks + 1 < nsteps) load_tile((uint32_t)((ks + 1) * BK));
+    if (ks + 1 < nsteps) load_tile((uint32_t)(kbeg + (ks + 1) * BK));
     const int fr = lane & 15, fk = 8 * (lane >> 4);
     // one pass per carried value (r, i, s) with a compile-time index, so the
     // accumulators stay in registers
@@ -219,9 +227,12 @@ __device__ __forceinline__ void cgemm_bf16_body(const MArgs& g, int64_t k, __bf1
     }
   }
 
-  // epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each 16x16 tile
-  float* cre = g.cre + k * g.sc;
-  float* cim = g.cim + k * g.sc;
+  // epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each 16x16
+  // tile; a part of a split contraction writes its own planes (row stride N)
+  const bool parted = g.ksplit > 1;
+  float* cre = parted ? g.pre + ((int64_t)part * g.K + k) * g.M * g.N : g.cre + k * g.sc;
+  float* cim = parted ? g.pim + ((int64_t)part * g.K + k) * g.M * g.N : g.cim + k * g.sc;
+  const int64_t ldc = parted ? g.N : g.ldc;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -233,12 +244,12 @@ __device__ __forceinline__ void cgemm_bf16_body(const MArgs& g, int64_t k, __bf1
         if (gm < g.M && gn < g.N) {
           const float p1 = acc[0][i][j][e];
           if (real) {
-            cre[gm * g.ldc + gn] = p1;
-            cim[gm * g.ldc + gn] = 0.f;
+            cre[gm * ldc + gn] = p1;
+            cim[gm * ldc + gn] = 0.f;
           } else {
             const float p2 = acc[1][i][j][e], p3 = acc[2][i][j][e];
-            cre[gm * g.ldc + gn] = p1 - p2;
-            cim[gm * g.ldc + gn] = p3 - p1 - p2;
+            cre[gm * ldc + gn] = p1 - p2;
+            cim[gm * ldc + gn] = p3 - p1 - p2;
           }
         }
       }
@@ -251,14 +262,16 @@ __global__ __launch_bounds__(NT, 1) void cgemm_bf16_kernel(MArgs g) {
   // LDS: [value r/i/s][split][row][LDK]
   __shared__ __attribute__((aligned(16))) __bf16 sA[3 * SPLIT * BM * LDK];
   __shared__ __attribute__((aligned(16))) __bf16 sB[3 * SPLIT * BN * LDK];
-  // complex slices first in launch order, the two cheaper real slices last
-  const int64_t z = blockIdx.z;
+  // complex slices first in launch order, the two cheaper real slices last;
+  // the parts of a split contraction are the fastest-varying index
+  const int part = (int)(blockIdx.z % (unsigned)g.ksplit);
+  const int64_t z = blockIdx.z / (unsigned)g.ksplit;
   const int64_t nreal = (g.real_last && g.K > 1) ? 2 : 1;
   const int64_t ncomplex = g.K - nreal;
   if (z < ncomplex) {
-    cgemm_bf16_body<SPLIT, false>(g, z + 1, sA, sB);
+    cgemm_bf16_body<SPLIT, false>(g, z + 1, part, sA, sB);
   } else {
-    cgemm_bf16_body<SPLIT, true>(g, z == ncomplex ? 0 : g.K - 1, sA, sB);
+    cgemm_bf16_body<SPLIT, true>(g, z == ncomplex ? 0 : g.K - 1, part, sA, sB);
   }
 }
 
@@ -460,6 +473,23 @@ __device__ __forceinline__ void split_body(const SArgs& g, int64_t k, int64_t tm
       }
 }
 
+// C[k] = sum over the parts of a split contraction, in part order.
+__global__ void ksplit_reduce_kernel(const float* __restrict__ pre, const float* __restrict__ pim, int ksplit,
+                                     int64_t K, int64_t M, int64_t N, float* __restrict__ cre, float* __restrict__ cim,
+                                     int64_t ldc, int64_t sc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = M * N;
+  if (e >= K * per) return;
+  const int64_t k = e / per, r = e - k * per, m = r / N, n = r - m * N;
+  float sr = 0.f, si = 0.f;
+  for (int p = 0; p < ksplit; ++p) {
+    sr += pre[(int64_t)p * K * per + e];
+    si += pim[(int64_t)p * K * per + e];
+  }
+  cre[k * sc + m * ldc + n] = sr;
+  cim[k * sc + m * ldc + n] = si;
+}
+
 // Workgroups are dispatched to the eight XCDs round robin (workgroup L on
 // XCD L mod 8, position L / 8 there), each XCD with its own L2. The tile map
 // gives every XCD a contiguous run of complex-slice tiles (so the tiles of
@@ -514,17 +544,42 @@ int cgemm_mfma(const CGemm& p, int prec, hipStream_t st, bool* handled) {
   // per-slice offsets must fit in 32 bits
   const int64_t lim = int64_t(1) << 31;
   if (p.M * p.lda >= lim || p.Kd * p.ldb >= lim || p.M * p.ldc >= lim) return TP_OK;
+  // a long contraction with few output tiles is split into parts that
+  // write float32 partial planes, summed in part order afterwards, when the
+  // caller provides the scratch
+  int ksplit = cgemm_ksplit(p.K, p.M, p.N, p.Kd);
+  if (ksplit > 1 && (!p.part_re || !p.part_im || p.part_cap < int64_t(ksplit) * p.K * p.M * p.N)) ksplit = 1;
+  const int64_t kchunk = ksplit > 1 ? ((p.Kd + ksplit - 1) / ksplit + BK - 1) / BK * BK : p.Kd;
   MArgs g{p.M, p.N, p.Kd, (const float*)p.are, (const float*)p.aim, (const float*)p.bre, (const float*)p.bim,
           (float*)p.cre, (float*)p.cim, p.lda, p.ldb, p.ldc, p.sa, p.sb, p.sc, p.K, p.real_last ? 1 : 0,
-          p.kdim_dev};
+          p.kdim_dev, ksplit, kchunk, p.part_re, p.part_im};
   const unsigned gx = (unsigned)((p.N + BN - 1) / BN), gy = (unsigned)((p.M + BM - 1) / BM);
+  const unsigned gz = (unsigned)(p.K * ksplit);
   if (prec == TP_PREC_BF16X3)
-    hipLaunchKernelGGL(cgemm_bf16_kernel<2>, dim3(gx, gy, (unsigned)p.K), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL(cgemm_bf16_kernel<2>, dim3(gx, gy, gz), dim3(NT), 0, st, g);
   else
-    hipLaunchKernelGGL(cgemm_bf16_kernel<1>, dim3(gx, gy, (unsigned)p.K), dim3(NT), 0, st, g);
+    hipLaunchKernelGGL(cgemm_bf16_kernel<1>, dim3(gx, gy, gz), dim3(NT), 0, st, g);
   TP_LAUNCH_CHECK();
+  if (ksplit > 1) {
+    const int64_t n = p.K * p.M * p.N;
+    hipLaunchKernelGGL(ksplit_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p.part_re,
+                       p.part_im, ksplit, p.K, p.M, p.N, (float*)p.cre, (float*)p.cim, p.ldc, p.sc);
+    TP_LAUNCH_CHECK();
+  }
   *handled = true;
   return TP_OK;
+}
+
+// Parts of a split contraction: enough workgroups to cover the compute
+// units about twice, each part at least 32 steps of the contraction, at
+// most 64 parts.
+int cgemm_ksplit(int64_t K, int64_t M, int64_t N, int64_t Kd) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * K;
+  if (tiles >= 256 || Kd < 64 * BK) return 1;
+  int64_t s = (512 + tiles - 1) / tiles;
+  s = s < Kd / (32 * BK) ? s : Kd / (32 * BK);
+  s = s < 64 ? s : 64;
+  return s > 1 ? (int)s : 1;
 }
 
 int cgemm_split(const SplitGemm& p, hipStream_t st) {
