@@ -18,7 +18,9 @@
 //   3. the half spectrum of the real tube is separated from Z by conjugate
 //      symmetry, X[k] = (Z[k] + conj Z[M-k])/2 + W_n3^k (Z[k] - conj Z[M-k])/2i,
 //      and each slice k is written with one coalesced store per wavefront.
-// The inverse kernel runs these steps backwards. Lengths without a
+// The inverse kernel runs these steps backwards. Long tubes (n3 above 256
+// without a specialised kernel, prime factors up to 13) use a
+// workgroup-per-tube mixed-radix transform in LDS; other lengths without a
 // specialised kernel use a direct O(n3^2) transform per tube.
 #include <cmath>
 #include <mutex>
@@ -506,6 +508,152 @@ __global__ void irdft_direct_kernel(const T* __restrict__ xre, const T* __restri
   }
 }
 
+// --------------------------------------------------------------------------
+// Long tubes (n3 above 256 without a specialised kernel): one workgroup per
+// tube, the whole tube as n3 complex values in LDS, an in-place mixed-radix
+// decimation-in-time FFT. The input is loaded in digit-reversed order for
+// the radix sequence r_0, r_1, ... (4s first, then 2, 3, 5, then primes up
+// to kLongMaxRadix); stage q combines r_q sub-transforms of span m (the
+// product of the earlier radices) into transforms of span m r_q: for the
+// butterfly (group g, offset j < m) the inputs a[g + j + s m] take the
+// twiddle W_{m r_q}^{j s} and go through an r_q-point DFT, written back to
+// the same positions. Twiddles and the small DFTs' roots are evaluated with
+// sincospi in float64.
+// --------------------------------------------------------------------------
+constexpr int kLongMaxStages = 24;
+constexpr int kLongMaxRadix = 13;
+constexpr int kLongNT = 256;
+constexpr int64_t kLongMin = 257;
+
+struct LongPlan {
+  int n, nst;
+  int rad[kLongMaxStages];
+};
+
+// source index of the element that the digit-reversed load puts at pos
+__device__ __forceinline__ int long_src(const LongPlan& pl, int pos) {
+  int out = 0, m = pl.n;
+  for (int q = 0; q < pl.nst; ++q) {
+    const int p = pl.rad[q];
+    m /= p;
+    out += (pos % p) * m;
+    pos /= p;
+  }
+  return out;
+}
+
+template <typename T>
+__device__ void long_stages(const LongPlan& pl, T* ar, T* ai) {
+  const int n = pl.n;
+  int m = 1;
+  for (int q = 0; q < pl.nst; ++q) {
+    const int p = pl.rad[q], span = m * p;
+    // roots of the p-point DFT
+    double cw[kLongMaxRadix], sw[kLongMaxRadix];
+    for (int e = 0; e < p; ++e) sincospi(-2.0 * e / p, &sw[e], &cw[e]);
+    for (int b = threadIdx.x; b < n / p; b += kLongNT) {
+      const int j = b % m, g = (b / m) * span;
+      double vr[kLongMaxRadix], vi[kLongMaxRadix];
+      for (int t = 0; t < p; ++t) {
+        const double xr = (double)ar[g + j + t * m], xi = (double)ai[g + j + t * m];
+        const int e = (j * t) % span;
+        double sn, cs;
+        sincospi(-2.0 * e / span, &sn, &cs);
+        vr[t] = xr * cs - xi * sn;
+        vi[t] = xr * sn + xi * cs;
+      }
+      for (int t = 0; t < p; ++t) {
+        double accr = 0.0, acci = 0.0;
+        for (int u = 0; u < p; ++u) {
+          const int e = (u * t) % p;
+          accr += vr[u] * cw[e] - vi[u] * sw[e];
+          acci += vr[u] * sw[e] + vi[u] * cw[e];
+        }
+        ar[g + j + t * m] = (T)accr;
+        ai[g + j + t * m] = (T)acci;
+      }
+    }
+    __syncthreads();
+    m = span;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kLongNT) void rfft_long_kernel(const T* __restrict__ x, FwdArgs a, LongPlan pl,
+                                                            T* __restrict__ ore, T* __restrict__ oim) {
+  extern __shared__ unsigned char long_lds[];
+  T* ar = reinterpret_cast<T*>(long_lds);
+  T* ai = ar + pl.n;
+  const int64_t t = blockIdx.x;
+  const int n = pl.n, K = n / 2 + 1;
+  const int64_t ks = a.ntubes;
+  int64_t src = -1;
+  double s = 0.0;
+  const bool live = tube_source(a, t, src, s);
+  for (int pos = threadIdx.x; pos < n; pos += kLongNT) {
+    T v = T(0);
+    if (live) {
+      const T xv = x[src * n + long_src(pl, pos)];
+      v = (s == 1.0) ? xv : (T)((double)xv * s);
+    }
+    ar[pos] = v;
+    ai[pos] = T(0);
+  }
+  __syncthreads();
+  long_stages<T>(pl, ar, ai);
+  for (int k = threadIdx.x; k < K; k += kLongNT) {
+    ore[(int64_t)k * ks + t] = ar[k];
+    oim[(int64_t)k * ks + t] = (k == 0 || 2 * k == n) ? T(0) : ai[k];
+  }
+}
+
+// inverse: the Hermitian extension of the half spectrum, conjugated, goes
+// through the forward stages; y = Re(result) / n
+template <typename T>
+__global__ __launch_bounds__(kLongNT) void irfft_long_kernel(const T* __restrict__ xre, const T* __restrict__ xim,
+                                                             int64_t ntubes, LongPlan pl, T* __restrict__ y) {
+  extern __shared__ unsigned char long_lds[];
+  T* ar = reinterpret_cast<T*>(long_lds);
+  T* ai = ar + pl.n;
+  const int64_t t = blockIdx.x;
+  const int n = pl.n, K = n / 2 + 1;
+  for (int pos = threadIdx.x; pos < n; pos += kLongNT) {
+    const int k = long_src(pl, pos);
+    T vr, vi;
+    if (k < K) {
+      vr = xre[(int64_t)k * ntubes + t];
+      vi = (k == 0 || 2 * k == n) ? T(0) : xim[(int64_t)k * ntubes + t];
+    } else {
+      // X[k] = conj(X[n - k])
+      vr = xre[(int64_t)(n - k) * ntubes + t];
+      vi = -xim[(int64_t)(n - k) * ntubes + t];
+    }
+    ar[pos] = vr;
+    ai[pos] = -vi;
+  }
+  __syncthreads();
+  long_stages<T>(pl, ar, ai);
+  const T inv = T(1) / T(n);
+  for (int e = threadIdx.x; e < n; e += kLongNT) y[t * n + e] = ar[e] * inv;
+}
+
+// Radix plan of a long tube; false when n has a prime factor above
+// kLongMaxRadix, too many stages, or does not fit the LDS budget.
+bool long_plan(int64_t n, int elem_bytes, LongPlan& pl) {
+  if (n < kLongMin || 2 * n * elem_bytes > 64 * 1024) return false;
+  pl.n = (int)n;
+  pl.nst = 0;
+  int64_t r = n;
+  for (int p : {4, 2, 3, 5, 7, 11, 13}) {
+    while (r % p == 0) {
+      if (pl.nst == kLongMaxStages) return false;
+      pl.rad[pl.nst++] = p;
+      r /= p;
+    }
+  }
+  return r == 1;
+}
+
 template <typename T>
 using FwdKernel = void (*)(const T*, FwdArgs, T*, T*);
 template <typename T>
@@ -559,6 +707,10 @@ int fwd_impl(const T* x, int64_t n3, const TubeGather& g, T* re, T* im, hipStrea
   if (auto k = pick_fwd<T>(n3)) {
     const int64_t blocks = (a.ntubes + kTile - 1) / kTile;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTile), 0, st, x, a, re, im);
+  } else if (LongPlan pl; long_plan(n3, (int)sizeof(T), pl)) {
+    if (a.ntubes > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+    hipLaunchKernelGGL(rfft_long_kernel<T>, dim3((unsigned)a.ntubes), dim3(kLongNT), 2 * n3 * sizeof(T), st, x, a,
+                       pl, re, im);
   } else {
     const int64_t blocks = (a.ntubes + 127) / 128;
     hipLaunchKernelGGL(rdft_direct_kernel<T>, dim3((unsigned)blocks), dim3(128), 0, st, x, (int)n3, a, re, im);
@@ -573,6 +725,10 @@ int inv_impl(const T* re, const T* im, int64_t n3, int64_t ntubes, T* y, hipStre
   if (auto k = pick_inv<T>(n3)) {
     const int64_t blocks = (ntubes + kTile - 1) / kTile;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTile), 0, st, re, im, ntubes, y);
+  } else if (LongPlan pl; long_plan(n3, (int)sizeof(T), pl)) {
+    if (ntubes > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+    hipLaunchKernelGGL(irfft_long_kernel<T>, dim3((unsigned)ntubes), dim3(kLongNT), 2 * n3 * sizeof(T), st, re, im,
+                       ntubes, pl, y);
   } else {
     const int64_t blocks = (ntubes + 127) / 128;
     hipLaunchKernelGGL(irdft_direct_kernel<T>, dim3((unsigned)blocks), dim3(128), 0, st, re, im, (int)n3, ntubes,

@@ -410,3 +410,36 @@ def test_rtprod_split_contraction_with_device_count():
     idx, sc = picks.host()
     ref = D.rtprod(A, B, idx.numpy(), sc.numpy())
     assert rel(Zg, ref) < 5e-5
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n3", [300, 1001, 2000, 4096, 257, 2003])
+def test_long_tube_transforms(n3, dtype):
+    """Tubes above 256 without a specialised kernel: the workgroup-per-tube
+    mixed-radix transform (300 = 4*3*5*5, 1001 = 7*11*13, 2000 = 4*4*5*5*5,
+    4096), or the direct transform for a prime factor above 13 (257, 2003);
+    both directions and the round trip."""
+    rs = np.random.default_rng(n3)
+    X = rs.standard_normal((9, 13, n3)).astype(dtype)
+    re, im = api.tfft(dev(X))
+    H = T.half_spectrum(X.astype(np.float64))
+    assert rel(re.cpu().numpy() + 1j * im.cpu().numpy(), H) < TOL[dtype]
+    assert not im[0].any()
+    if n3 % 2 == 0:
+        assert not im[-1].any()
+    Y = api.tifft(re, im, n3).cpu().numpy()
+    assert rel(Y, X) < TOL[dtype]
+    K = n3 // 2 + 1
+    G = rs.standard_normal((K, 7, 5)) + 1j * rs.standard_normal((K, 7, 5))
+    Xi = api.tifft(dev(G.real.astype(dtype)), dev(G.imag.astype(dtype)), n3).cpu().numpy()
+    ref = T.from_half_spectrum((G.real.astype(dtype) + 1j * G.imag.astype(dtype)).astype(np.complex128), n3)
+    assert rel(Xi, ref) < TOL[dtype]
+
+
+def test_msi_shaped_tcur():
+    """t-CUR of a 122 x 120 x 2000 tensor (the MSI shape) of tubal rank 3:
+    the exact-rank input is reproduced; long-tube transforms throughout."""
+    g = np.random.default_rng(31)
+    A = T.tprod_fft(g.standard_normal((122, 3, 2000)), g.standard_normal((3, 120, 2000))).astype(np.float32)
+    Z, cols, rows = api.tcur(dev(A), 12, 12, 3, col_kind="lev", row_kind="lev", seed=2, prec="f32")
+    assert rel(Z.cpu().numpy(), A) < 1e-4
