@@ -155,7 +155,14 @@ __device__ int jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps,
       //   H_pj = c x - s e^{i phi} y,  H_qj = s x + c e^{i phi} y;
       // column transform of pair v on a row (x = M_ip, y = M_iq):
       //   M_ip = c x - s e^{-i phi} y,  M_iq = s x + c e^{-i phi} y.
-      for (int e = tid; e < nblk + n * npairs; e += NT) {
+      // fixed trip count (MAXN bounds the item count), so the compiler can
+      // issue the LDS reads of a thread's items together
+      constexpr int kMaxPairs = MAXN / 2 + 1;
+      constexpr int kTrips = (kMaxPairs * kMaxPairs + MAXN * kMaxPairs + NT - 1) / NT;
+#pragma unroll
+      for (int it = 0; it < kTrips; ++it) {
+        const int e = tid + it * NT;
+        if (e >= nblk + n * npairs) continue;
         if (e < nblk) {
           const int u = e / npairs, v = e - u * npairs;
           int p0, q0, p1, q1;
