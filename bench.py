@@ -337,7 +337,7 @@ def tnn_protocol(args, api, torch):
     out = {"iters": it}
 
     def rse(L, Ls):
-        return round(float(torch.linalg.vector_norm(L - Ls) / torch.linalg.vector_norm(Ls)), 6)
+        return float(f"{float(torch.linalg.vector_norm(L - Ls) / torch.linalg.vector_norm(Ls)):.4g}")
 
     # completion
     G1, G2, N, mask = W.completion_problem()

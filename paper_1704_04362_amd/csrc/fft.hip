@@ -204,6 +204,11 @@ struct FwdArgs {
   const int64_t* count;
   int64_t ld;    // slots per major index (>= cols, or >= rows when colmajor)
   int colmajor;  // slot t = col * ld + row instead of row * ld + col
+  // > 0 (column-major spectra with ld a multiple of the tile): workgroup b
+  // takes the tile (b / nmaj) of major index b mod nmaj, so workgroups that
+  // run together read neighbouring tubes of the tube-major input instead of
+  // tubes a whole input row apart
+  int64_t nmaj;
 };
 
 // Input tube offset and scale of output slot t; returns false for a slot
@@ -262,7 +267,8 @@ __global__ __launch_bounds__(kTile) void rfft_kernel(const T* __restrict__ x, Fw
   __shared__ int64_t s_src[kTile];
   __shared__ double s_scl[kTile];
   const int lane = threadIdx.x;
-  const int64_t tile0 = (int64_t)blockIdx.x * kTile;
+  const int64_t b = blockIdx.x;
+  const int64_t tile0 = a.nmaj > 0 ? (b % a.nmaj) * a.ld + (b / a.nmaj) * kTile : b * kTile;
   {
     const int64_t t = tile0 + lane;
     int64_t src = -1;
@@ -702,7 +708,7 @@ InvKernel<T> pick_inv(int64_t n) {
 template <typename T>
 int fwd_impl(const T* x, int64_t n3, const TubeGather& g, T* re, T* im, hipStream_t st) {
   FwdArgs a{g.rows, g.cols, g.in_cols, g.rows * g.cols, g.row_idx, g.col_idx, g.row_scale, g.col_scale, g.count,
-            g.cols, 0};
+            g.cols, 0, 0};
   if (a.ntubes == 0) return TP_OK;
   if (auto k = pick_fwd<T>(n3)) {
     const int64_t blocks = (a.ntubes + kTile - 1) / kTile;
@@ -770,7 +776,7 @@ int fft_forward_split(const float* x, int64_t n3, const TubeGather& g, bool colm
   if (!k) return fail(TP_EUNSUPPORTED, "no split-output transform for this tube length");
   if (ld < (colmajor ? g.rows : g.cols)) return fail(TP_EINVAL, "split spectrum stride below its extent");
   FwdArgs a{g.rows, g.cols, g.in_cols, (colmajor ? g.cols : g.rows) * ld, g.row_idx, g.col_idx, g.row_scale,
-            g.col_scale, g.count, ld, colmajor ? 1 : 0};
+            g.col_scale, g.count, ld, colmajor ? 1 : 0, (colmajor && ld % kTile == 0) ? g.cols : 0};
   if (a.ntubes == 0) return TP_OK;
   const int64_t blocks = (a.ntubes + kTile - 1) / kTile;
   if (blocks > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
