@@ -47,7 +47,9 @@ typedef enum {
   TP_EDTYPE = -3,      /* unsupported dtype / precision combination    */
   TP_EWORKSPACE = -4,  /* workspace missing or too small               */
   TP_EHIP = -5,        /* a HIP runtime call or kernel launch failed    */
-  TP_ENOCONV = -6,     /* iteration cap reached (result still written) */
+  TP_ENOCONV = -6,     /* reserved: no entry point returns it (the
+                          ADMM calls run a fixed iteration count and the
+                          Jacobi solvers decide convergence on the device) */
   TP_EUNSUPPORTED = -7 /* size outside what the kernels implement      */
 } tp_status;
 
