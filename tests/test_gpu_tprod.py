@@ -322,7 +322,7 @@ def test_spectrum_matmul_split_bf16(prec, K, M, N, Kd):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("shape", [(96, 130, 70, 64), (128, 256, 128, 16), (40, 52, 30, 100)])
+@pytest.mark.parametrize("shape", [(96, 130, 70, 64), (128, 256, 128, 16), (40, 52, 30, 100), (40, 192, 70, 8)])
 def test_tprod_split_bf16_matches_bcirc(prec, shape):
     n1, n2, n4, n3 = shape
     rs = np.random.default_rng(sum(shape) + 3)
@@ -346,6 +346,21 @@ def test_rtprod_bf16x3_matches_oracle(mode):
     picks = api.tsample("norm2", 128, mode=mode, seed=11, A=dev(A))
     Z = api.tprod(dev(A), dev(B), picks=picks, prec="bf16x3").cpu().numpy()
     ridx, rsc = S.sample(S.weights_norm2(A), 128, mode, seed=11)
+    idx, _ = picks.host()
+    np.testing.assert_array_equal(idx.numpy(), ridx)
+    assert rel(Z, D.rtprod(A, B, ridx, rsc)) < BF_TOL["bf16x3"]
+
+
+@pytest.mark.parametrize("mode", ["iid", "bernoulli"])
+def test_rtprod_bf16x3_odd_column_count(mode):
+    """B's forward transform with a contraction stride that is a multiple of
+    64 (64 picks) and an odd number of output columns (70), the case where
+    its workgroups are numbered column-fastest; Bernoulli picks leave the
+    live count below the capacity."""
+    A, B = W.rtprod_pair(n1=96, n2=600, n4=70, n3=16)
+    picks = api.tsample("norm2", 64, mode=mode, seed=3, A=dev(A))
+    Z = api.tprod(dev(A), dev(B), picks=picks, prec="bf16x3").cpu().numpy()
+    ridx, rsc = S.sample(S.weights_norm2(A), 64, mode, seed=3)
     idx, _ = picks.host()
     np.testing.assert_array_equal(idx.numpy(), ridx)
     assert rel(Z, D.rtprod(A, B, ridx, rsc)) < BF_TOL["bf16x3"]
