@@ -18,7 +18,10 @@
  * per-device table of transform twiddles set up on first use.
  *
  * Asynchrony: every call enqueues its work on `stream` (a hipStream_t;
- * NULL is the default stream) and returns without synchronising. Values a
+ * NULL is the default stream) and returns without synchronising (the one
+ * exception is the first call on a device that runs a tube transform,
+ * which uploads the twiddle table synchronously; tp_trace_count also waits
+ * for its recorded events). Values a
  * call writes to device memory (sample counts, ranks) are valid once the
  * stream has reached that point.
  *
