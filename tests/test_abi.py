@@ -113,6 +113,59 @@ def test_trpca_validation(case):
     assert rc == want
 
 
+@pytest.mark.parametrize("case", ["empty", "tau", "nan_tau", "prec", "dtype", "shape", "ws"])
+def test_tsvt_validation(case):
+    lib = L.load()
+    M, Lt = _t(6, 5, 4), _t(6, 5, 4)
+    tau, prec, wsb, want = 0.5, L.PREC["f32"], 1 << 30, -1
+    if case == "empty":
+        M, Lt = _t(0, 5, 4), _t(0, 5, 4)
+        want = -2
+    elif case == "tau":
+        tau = -1.0
+    elif case == "nan_tau":
+        tau = float("nan")
+    elif case == "prec":
+        prec = L.PREC["bf16x3"]
+        want = -3
+    elif case == "dtype":
+        M = _t(6, 5, 4, dtype=L.TP_F64)
+        want = -3
+    elif case == "shape":
+        Lt = _t(6, 5, 5)
+        want = -2
+    else:
+        wsb = 16
+        want = -4
+    rc = lib.tp_tsvt(C.byref(M), tau, C.byref(Lt), None, prec, C.c_void_p(0x2000), wsb, None)
+    assert rc == want, lib.tp_last_error()
+    assert lib.tp_last_error()
+
+
+@pytest.mark.parametrize("case", ["mask", "empty", "rho", "mu", "ws"])
+def test_tcomplete_validation(case):
+    lib = L.load()
+    X, Lt, E, Y = _t(6, 5, 4), _t(6, 5, 4), _t(6, 5, 4), _t(6, 5, 4)
+    mask, rho, mu0, wsb, want = C.c_void_p(0x3000), 1.1, 1e-3, 1 << 30, -1
+    if case == "mask":
+        mask = None
+    elif case == "empty":
+        X, Lt, E, Y = _t(6, 0, 4), _t(6, 0, 4), _t(6, 0, 4), _t(6, 0, 4)
+        want = -2
+    elif case == "rho":
+        rho = 0.5
+    elif case == "mu":
+        mu0 = 0.0
+    else:
+        wsb = 16
+        want = -4
+    rc = lib.tp_tcomplete(C.byref(X), mask, 10, rho, mu0, 1e10, C.byref(Lt), C.byref(E), C.byref(Y), None,
+                          L.PREC["f32"], C.c_void_p(0x2000), wsb, None)
+    assert rc == want, lib.tp_last_error()
+    # the workspace query of an empty tensor is 0
+    assert lib.tp_tcomplete_workspace(C.byref(_t(6, 0, 4))) == 0
+
+
 @pytest.mark.parametrize("case", ["bernoulli", "rank", "dtype", "lambda"])
 def test_tcur_nn_validation(case):
     lib = L.load()

@@ -86,6 +86,42 @@ def test_tsvt_zero_and_huge_threshold():
     assert not L2.any() and not r2.any()
 
 
+def test_tsvt_zero_tensor():
+    M = np.zeros((24, 20, 6), np.float32)
+    L, ranks = api.tsvt(dev(M), 0.5)
+    assert not L.any() and not ranks.any()
+
+
+@pytest.mark.parametrize("shape", [(1, 40, 6), (40, 1, 6), (1, 1, 5), (2, 3, 1)])
+def test_tsvt_thin_slices(shape):
+    # one-row (or one-column) Fourier slices: a single singular value each,
+    # a pair step with one live row
+    M = np.random.default_rng(sum(shape) + 5).standard_normal(shape).astype(np.float32)
+    Md = M.astype(np.float64)
+    Mh = T.fft3(Md)
+    sv = np.sort(np.concatenate([np.linalg.svd(Mh[:, :, k], compute_uv=False)
+                                 for k in range(shape[2] // 2 + 1)]))
+    tau = float(np.sqrt(sv[len(sv) // 2] * sv[len(sv) // 2 - 1])) if len(sv) > 1 else 0.5 * float(sv[0])
+    L, ranks = api.tsvt(dev(M), tau)
+    Lr, rr = D.tsvt(Md, tau)
+    assert rel(L.cpu().numpy(), Lr) < 1e-5
+    np.testing.assert_array_equal(ranks.cpu().numpy(), rr)
+
+
+def test_tcomplete_fully_observed_matches_oracle():
+    # every entry observed: E stays zero and the loop is the plain
+    # t-SVT iteration of Algorithm 7
+    G1, G2, N, _ = W.completion_problem(n1=36, n2=30, n3=6, r=3, salt=4, dtype=np.float64)
+    X = (T.tprod_fft(G1, G2) + N).astype(np.float32)
+    mask = np.ones(X.shape, np.uint8)
+    L, E, Y, ranks = api.tcomplete(dev(X), dev(mask), iters=30)
+    Lr, Er, Yr, hist = D.admm_complete(X.astype(np.float64), mask, iters=30)
+    assert not E.any() and not np.any(Er)
+    assert rel(L.cpu().numpy(), Lr) < 1e-4
+    assert rel(Y.cpu().numpy(), Yr) < 1e-4
+    np.testing.assert_array_equal(ranks.cpu().numpy(), hist[-1]["ranks"])
+
+
 def test_tsvt_full_completion_shape():
     # one t-SVT at the 256x256x100 shape of the completion workload
     G1, G2, N, _ = W.completion_problem(dtype=np.float64)
