@@ -346,7 +346,7 @@ size_t tp_tcur_nn_workspace(const tp_tensor* X, int64_t c, int64_t l, int64_t r,
 
 /* ---------------------------------------------------------------------------
  * Learned lateral-leverage proposal (not in the paper; the exact scores of
- * eq. cur-col-prob stay its judge and fallback).
+ * eq. cur-col-prob stay its reference and fallback).
  * ------------------------------------------------------------------------- */
 
 /* Launch tracing. tp_trace_enable(1) clears earlier records and starts

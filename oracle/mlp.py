@@ -3,7 +3,7 @@
 Not in the paper: the paper estimates leverage scores with a randomized
 routine it cites but does not describe. This proposal predicts the lateral
 leverage distribution of a tensor from cheap per-slice features, and the
-exact scores of eq. cur-col-prob remain its judge and fallback.
+exact scores of eq. cur-col-prob remain its reference and fallback.
 
 Definitions (float64):
 * features(A, Phi): for lateral slice j, s_j = Phi^T vec(A_{:j:}) (Phi is

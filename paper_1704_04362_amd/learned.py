@@ -7,7 +7,7 @@ the leverage scores of the randomized t-SVD of the same tensors. All
 arithmetic runs in libtprod's kernels (features, forward, backward, Adam,
 t-SVD); this module orders the calls, batches the data and keeps the state.
 
-The proposal never replaces the exact scores as the judge: it is mixed with
+The proposal never replaces the exact scores as the reference: it is mixed with
 the uniform distribution (alpha) so that no slice becomes unreachable, and
 callers can always fall back to the exact leverage kind of tp_tcur.
 """
