@@ -162,6 +162,34 @@ def test_tprod_full_size_sampled_entries():
     assert rel(Cg[ii, jj, kk], ref) < 1e-5
 
 
+@pytest.fixture(scope="module")
+def full_rtprod_case():
+    """The rt-product of the benchmark (512x2048x64 x 2048x512x64, c = 256
+    i.i.d. squared-norm picks, seed 7): inputs, the oracle's own picks of the
+    oracle's norms and 256 entries of C * R from eq. tprod on the oracle's
+    gathered and scaled slices."""
+    A, B = W.rtprod_pair()
+    ridx, rsc = S.sample(S.weights_norm2(A), 256, "iid", seed=7)
+    Cs = A[:, ridx, :].astype(np.float64) * rsc[None, :, None]
+    Rs = B[ridx, :, :].astype(np.float64) * rsc[:, None, None]
+    rs = np.random.default_rng(13)
+    ii, jj, kk = rs.integers(0, 512, 256), rs.integers(0, 512, 256), rs.integers(0, 64, 256)
+    return A, B, ridx, rsc, (ii, jj, kk), T.tprod_entries(Cs, Rs, ii, jj, kk)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16x3", 5e-5)])
+def test_rtprod_full_size_sampled_entries(full_rtprod_case, prec, tol):
+    A, B, ridx, rsc, (ii, jj, kk), ref = full_rtprod_case
+    Ad = dev(A)
+    picks = api.tsample("norm2", 256, mode="iid", seed=7, A=Ad)
+    Z = api.tprod(Ad, dev(B), picks=picks, prec=prec).cpu().numpy()
+    idx, sc = picks.host()
+    # norms equal up to summation order: identical picks, scales to a few ulps
+    np.testing.assert_array_equal(idx.numpy(), ridx)
+    np.testing.assert_allclose(sc.numpy(), rsc, rtol=1e-13)
+    assert rel(Z[ii, jj, kk], ref) < tol
+
+
 @pytest.mark.parametrize("shape", [(64, 300, 16), (33, 1000, 7), (5, 64, 1), (10, 700, 64), (7, 3, 128)])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_slice_norms(shape, dtype):
