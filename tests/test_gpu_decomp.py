@@ -61,6 +61,22 @@ def test_tsvd_rand_exact_rank_f64(shape):
     assert abs(lat.sum().item() - r * n3) < 1e-8 * r * n3
 
 
+def test_tsvd_full_rank_of_the_exact_workload():
+    """The full t-SVD of the float64 exact-product workload's A (64x48x16,
+    N(0,1)): r = min(n1, n2) = 48 and no power iteration, so the range
+    finder spans every Fourier slice and the randomized t-SVD is exact.
+    Every lateral slice then has leverage n3 (each Fourier slice of V is
+    square unitary)."""
+    A, _ = W.exact_pair()
+    S_, lat, hor = api.tsvd_rand(dev(A), 48, p=0, q=0, seed=5)
+    _, _, _, sv = T.tsvd(A)
+    np.testing.assert_allclose(S_.cpu().numpy(), sv[:, :48], rtol=1e-10, atol=1e-12 * sv.max())
+    np.testing.assert_allclose(lat.cpu().numpy(), S.weights_lateral_leverage(A, 48), rtol=1e-9)
+    np.testing.assert_allclose(lat.cpu().numpy(), np.full(48, 16.0), rtol=1e-9)
+    ref_h = S.weights_lateral_leverage(T.ttranspose(A), 48)
+    np.testing.assert_allclose(hor.cpu().numpy(), ref_h, rtol=1e-9, atol=1e-9)
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 def test_tsvd_rand_noisy_f32(prec):
     n1, n2, n3, r = 160, 192, 16, 6
