@@ -213,3 +213,22 @@ def test_tproject_validation():
     for Cs, want in ((_t(20, 65, 4), -7), (_t(21, 5, 4), -2), (_t(20, 5, 4, dtype=L.TP_F64), -3)):
         rc = lib.tp_tproject(C.byref(X), C.byref(Cs), C.byref(Z), L.PREC["f32"], C.c_void_p(0x2000), 1 << 30, None)
         assert rc == want
+
+
+def test_missing_library_raises(tmp_path, monkeypatch):
+    # no fallback: without the built library every call fails loudly
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "libtprod.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        L.load()
+
+
+def test_cpu_tensors_are_rejected():
+    # the binding has no CPU path
+    import torch
+    from paper_1704_04362_amd import api
+    A = torch.zeros(4, 5, 6)
+    with pytest.raises(ValueError, match="GPU"):
+        api.tprod(A, torch.zeros(5, 3, 6))
+    with pytest.raises(ValueError, match="GPU"):
+        api.tsvt(A, 0.5)
