@@ -250,6 +250,21 @@ def tcur(A, c, l, r, col_kind="lev", row_kind="lev", col_w=None, row_w=None, mod
     return Z, cols, rows
 
 
+def tsvd_full(A, r, out=None):
+    """Dense leading-r t-SVD (see tp_tsvd_full): returns (U, S) with U the
+    n1 x r x n3 first left singular slices of A (float32) and S the K x r
+    singular values of the Fourier slices (float64, descending)."""
+    _need_gpu(A)
+    n1, n2, n3 = A.shape
+    U = out if out is not None else torch.empty((n1, r, n3), dtype=torch.float32, device=A.device)
+    S = torch.empty((half_count(n3), r), dtype=torch.float64, device=A.device)
+    lib = L.load()
+    t, tu = _tensor(A), _tensor(U)
+    ws = _ws(lib.tp_tsvd_full_workspace(C.byref(t), int(r)), A.device)
+    L.check(lib.tp_tsvd_full(C.byref(t), int(r), C.byref(tu), S.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return U, S
+
+
 def tsvt(M, tau, out=None):
     """Per-Fourier-slice singular value thresholding with threshold tau:
     returns (L, ranks)."""

@@ -56,6 +56,34 @@ struct TsvtLayout {
   }
 };
 
+// Dense leading-r t-SVD: the spectrum of A, the Gram matrix of the shorter
+// side of every Fourier slice (then Q G), the accumulated rotations Q, the
+// picked eigenvector columns and, for a tall A, the left singular planes.
+struct FullSvdLayout {
+  float *are = nullptr, *aim = nullptr, *xre = nullptr, *xim = nullptr, *qre = nullptr, *qim = nullptr;
+  float *vre = nullptr, *vim = nullptr, *ure = nullptr, *uim = nullptr;
+  float* ratio = nullptr;
+  int* conv = nullptr;
+  bool carve(Arena& ar, int64_t n1, int64_t n2, int64_t n3, int64_t r) {
+    const int64_t K = half_count(n3), m = std::min(n1, n2);
+    are = ar.take<float>(K * n1 * n2);
+    aim = ar.take<float>(K * n1 * n2);
+    xre = ar.take<float>(K * m * m);
+    xim = ar.take<float>(K * m * m);
+    qre = ar.take<float>(K * m * m);
+    qim = ar.take<float>(K * m * m);
+    vre = ar.take<float>(K * m * r);
+    vim = ar.take<float>(K * m * r);
+    if (n1 > n2) {
+      ure = ar.take<float>(K * n1 * r);
+      uim = ar.take<float>(K * n1 * r);
+    }
+    ratio = ar.take<float>(svt_ratio_count(K, m));
+    conv = ar.take<int>(K);
+    return ar.dry() || ar.ok();
+  }
+};
+
 int check_f32_tensor(const tp_tensor* t, const char* name) {
   if (!t) return fail(TP_EINVAL, std::string(name) + " is null");
   if (t->dtype != TP_F32) return fail(TP_EDTYPE, std::string(name) + ": thresholding runs on float32 data");
@@ -290,6 +318,91 @@ int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int pr
   if (!tall) return finish_svt(lay.svt, K, r, c, n3, tau, real_last, ranks, L->data, st);
   if (int rc = finish_svt(lay.svt, K, r, c, n3, tau, real_last, ranks, lay.lt, st)) return rc;
   return ttranspose(lay.lt, 4, r, c, n3, L->data, st);
+}
+
+size_t tp_tsvd_full_workspace(const tp_tensor* A, int64_t r) {
+  if (!A || A->n1 < 1 || A->n2 < 1 || A->n3 < 1 || r < 1) return 0;
+  Arena dry(nullptr, SIZE_MAX);
+  FullSvdLayout lay;
+  lay.carve(dry, A->n1, A->n2, A->n3, r);
+  return dry.used + 256;
+}
+
+int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, void* ws, size_t ws_bytes,
+                 void* stream) {
+  if (int rc = check_f32_tensor(A, "A")) return rc;
+  if (int rc = check_f32_tensor(U, "U")) return rc;
+  const int64_t n1 = A->n1, n2 = A->n2, n3 = A->n3, m = std::min(n1, n2);
+  if (r < 1 || r > m) return fail(TP_EINVAL, "need 1 <= r <= min(n1, n2)");
+  if (m > kPickMax) return fail(TP_EUNSUPPORTED, "min(n1, n2) above 4096");
+  if (U->n1 != n1 || U->n2 != r || U->n3 != n3) return fail(TP_ESHAPE, "U must be n1 x r x n3");
+  const size_t need = tp_tsvd_full_workspace(A, r);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tsvd_full workspace too small");
+  const int64_t K = half_count(n3);
+  const bool real_last = (n3 % 2 == 0) && K > 1;
+  const bool tall = n1 > n2;
+  hipStream_t st = S(stream);
+  Arena ar(ws, ws_bytes);
+  FullSvdLayout lay;
+  if (!lay.carve(ar, n1, n2, n3, r)) return fail(TP_EWORKSPACE, "tsvd_full workspace too small");
+  TubeGather g;
+  g.rows = n1;
+  g.cols = n2;
+  g.in_cols = n2;
+  if (int rc = fft_forward(A->data, TP_F32, n3, g, lay.are, lay.aim, st)) return rc;
+  // Gram of the shorter side: A^H A (n2 x n2) for a tall slice, A A^H
+  // (n1 x n1) otherwise
+  CGemm p;
+  p.K = K;
+  p.real_last = real_last;
+  p.are = lay.are;
+  p.aim = lay.aim;
+  p.bre = lay.are;
+  p.bim = lay.aim;
+  p.cre = lay.xre;
+  p.cim = lay.xim;
+  p.lda = n2;
+  p.ldb = n2;
+  p.ldc = m;
+  p.sa = n1 * n2;
+  p.sb = n1 * n2;
+  p.sc = m * m;
+  p.M = m;
+  p.N = m;
+  p.Kd = tall ? n1 : n2;
+  p.op_a = tall ? 1 : 0;
+  p.op_b = tall ? 0 : 1;
+  if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
+  // its eigenvectors by the block Jacobi of the thresholding (rows of Q G
+  // made orthogonal), the r leading ones picked by eigenvalue
+  if (int rc = svt_identity(lay.qre, lay.qim, K, m, st)) return rc;
+  if (int rc = svt_jacobi(lay.xre, lay.xim, lay.qre, lay.qim, K, m, m, real_last, kColdSweeps, kSvtTol, lay.ratio,
+                          lay.conv, st))
+    return rc;
+  if (int rc = tsvd_pick(lay.xre, lay.xim, lay.qre, lay.qim, K, m, r, real_last, tall, lay.vre, lay.vim, S_out, st))
+    return rc;
+  if (!tall) return fft_inverse(lay.vre, lay.vim, TP_F32, n3, n1, r, U->data, st);
+  // U_r = A V_r Sigma_r^-1 (the picked columns already carry 1 / sigma)
+  CGemm u;
+  u.K = K;
+  u.real_last = real_last;
+  u.M = n1;
+  u.N = r;
+  u.Kd = n2;
+  u.are = lay.are;
+  u.aim = lay.aim;
+  u.bre = lay.vre;
+  u.bim = lay.vim;
+  u.cre = lay.ure;
+  u.cim = lay.uim;
+  u.lda = n2;
+  u.ldb = r;
+  u.ldc = r;
+  u.sa = n1 * n2;
+  u.sb = n2 * r;
+  u.sc = n1 * r;
+  if (int rc = cgemm(u, TP_F32, TP_PREC_F32, st)) return rc;
+  return fft_inverse(lay.ure, lay.uim, TP_F32, n3, n1, r, U->data, st);
 }
 
 size_t tp_tcomplete_workspace(const tp_tensor* X) {

@@ -15,6 +15,14 @@ int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_
                int max_sweeps, double tol, float* ratio, int* conv, hipStream_t st);
 int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double tau, bool real_last,
                double* sig, int32_t* ranks, hipStream_t st);
+// Largest m for tsvd_pick (its eigenvalues and picks live in LDS).
+constexpr int64_t kPickMax = 4096;
+// After svt_jacobi on a Gram matrix G (X = Q G, K x m x m): the r leading
+// conjugated eigenvector rows of Q as columns of out (K x m x r planes),
+// scaled by 1 / sqrt(lambda) when inv; sv (K x r float64, may be null)
+// receives sqrt(lambda), descending.
+int tsvd_pick(const float* xre, const float* xim, const float* qre, const float* qim, int64_t K, int64_t m,
+              int64_t r, bool real_last, bool inv, float* ore, float* oim, double* sv, hipStream_t st);
 int admm_pre(const float* x, const float* e, const float* y, float inv_mu, int64_t n, float* m, hipStream_t st);
 int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, float inv_mu, int64_t n, float* e,
               float* y, hipStream_t st);

@@ -232,3 +232,30 @@ def test_cpu_tensors_are_rejected():
         api.tprod(A, torch.zeros(5, 3, 6))
     with pytest.raises(ValueError, match="GPU"):
         api.tsvt(A, 0.5)
+
+
+@pytest.mark.parametrize("case", ["rank", "zero_rank", "ushape", "empty", "dtype", "big", "ws"])
+def test_tsvd_full_validation(case):
+    lib = L.load()
+    A, U, r, wsb, want = _t(30, 20, 4), _t(30, 5, 4), 5, 1 << 30, -1
+    if case == "rank":
+        r, U = 21, _t(30, 21, 4)
+    elif case == "zero_rank":
+        r, U = 0, _t(30, 1, 4)
+    elif case == "ushape":
+        U = _t(30, 6, 4)
+        want = -2
+    elif case == "empty":
+        A = _t(0, 20, 4)
+        want = -2
+    elif case == "dtype":
+        A = _t(30, 20, 4, dtype=L.TP_F64)
+        want = -3
+    elif case == "big":
+        A, U = _t(5000, 5000, 2), _t(5000, 5, 2)
+        want = -7
+    else:
+        wsb = 16
+        want = -4
+    rc = lib.tp_tsvd_full(C.byref(A), r, C.byref(U), None, C.c_void_p(0x2000), wsb, None)
+    assert rc == want, lib.tp_last_error()
