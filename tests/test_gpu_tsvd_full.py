@@ -37,7 +37,7 @@ def _slices(X):
 
 
 @pytest.mark.parametrize("shape,r", [((200, 48, 6), 20), ((40, 90, 5), 12), ((64, 64, 4), 64), ((50, 30, 1), 10),
-                                     ((300, 130, 8), 100), ((33, 70, 7), 33)])
+                                     ((300, 130, 8), 100), ((33, 70, 7), 33), ((60, 40, 300), 10)])
 def test_tsvd_full_matches_oracle(shape, r):
     A = np.random.default_rng(sum(shape) + r).standard_normal(shape).astype(np.float32)
     Ad = A.astype(np.float64)
