@@ -291,18 +291,22 @@ int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int pr
 size_t tp_tsvt_workspace(const tp_tensor* M);
 
 /* Dense leading-r t-SVD (the t-SVD theorem of Section 2.1) without the
- * range finder's 64-column limit: for every Fourier slice A_k the Gram
- * matrix of its shorter side (A_k^H A_k when n1 > n2, A_k A_k^H otherwise,
- * float32) is diagonalised by the block one-sided Jacobi of tp_tsvt, its r
- * leading eigenvectors give V_r (then U_r = A_k V_r Sigma_r^-1) or U_r
- * directly, and U (n1 x r x n3, float32, caller-owned, overwritten) is the
- * inverse transform: the first r left singular slices of A, columns ordered
- * by descending singular value in every Fourier slice. S (device, K x r
- * float64, K = n3/2 + 1; may be NULL) receives the singular values. Because
- * the Gram squares the condition number, singular values below ~1e-3 of the
- * largest lose accuracy in float32 and those below ~3e-4 of it (the square
- * root of float32 rounding) are not resolved; a column whose eigenvalue is
- * exactly zero is zero. A float32; 1 <= r <= min(n1, n2) <= 4096. Workspace:
+ * range finder's 64-column limit. When the longer side of A's slices is at
+ * most four times the shorter, the block one-sided Jacobi of tp_tsvt runs on
+ * every Fourier slice A_k itself (on A_k^H, through the t-transpose, when
+ * n1 > n2) and U_r comes from its accumulated rotations (or from the
+ * orthogonalised rows divided by sigma). Longer slices use the Gram matrix
+ * of the shorter side (A_k^H A_k when n1 > n2, A_k A_k^H otherwise,
+ * float32): the same Jacobi diagonalises it and its r leading eigenvectors
+ * give V_r (then U_r = A_k V_r Sigma_r^-1) or U_r directly. U (n1 x r x n3,
+ * float32, caller-owned, overwritten) is the inverse transform: the first r
+ * left singular slices of A, columns ordered by descending singular value
+ * in every Fourier slice. S (device, K x r float64, K = n3/2 + 1; may be
+ * NULL) receives the singular values. The Gram route squares the condition
+ * number: there singular values below ~1e-3 of the largest lose accuracy in
+ * float32 and those below ~3e-4 of it (the square root of float32 rounding)
+ * are not resolved. A column whose singular value is exactly zero is zero.
+ * A float32; 1 <= r <= min(n1, n2) <= 4096. Workspace:
  * tp_tsvd_full_workspace(A, r) bytes. */
 int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S, void* ws, size_t ws_bytes, void* stream);
 size_t tp_tsvd_full_workspace(const tp_tensor* A, int64_t r);

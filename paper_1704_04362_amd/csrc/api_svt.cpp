@@ -56,28 +56,43 @@ struct TsvtLayout {
   }
 };
 
-// Dense leading-r t-SVD: the spectrum of A, the Gram matrix of the shorter
-// side of every Fourier slice (then Q G), the accumulated rotations Q, the
-// picked eigenvector columns and, for a tall A, the left singular planes.
+// Dense leading-r t-SVD. Near-square slices (longer side at most
+// kDirectRatio times the shorter) run the block Jacobi on the slices
+// themselves (on A^H for a tall A, through the t-transpose); longer ones on
+// the Gram matrix of the shorter side, which is cheaper but squares the
+// condition number.
+constexpr int64_t kDirectRatio = 4;
+
+inline bool tsvd_direct(int64_t n1, int64_t n2) {
+  return std::max(n1, n2) <= kDirectRatio * std::min(n1, n2);
+}
+
+// Buffers: the spectrum of A (of A^T on the direct tall path), the Gram
+// matrix (then Q G) on the Gram path, the accumulated rotations Q, the V
+// columns of the Gram tall path, the left singular planes, and A^T.
 struct FullSvdLayout {
   float *are = nullptr, *aim = nullptr, *xre = nullptr, *xim = nullptr, *qre = nullptr, *qim = nullptr;
-  float *vre = nullptr, *vim = nullptr, *ure = nullptr, *uim = nullptr;
+  float *vre = nullptr, *vim = nullptr, *ure = nullptr, *uim = nullptr, *mt = nullptr;
   float* ratio = nullptr;
   int* conv = nullptr;
   bool carve(Arena& ar, int64_t n1, int64_t n2, int64_t n3, int64_t r) {
     const int64_t K = half_count(n3), m = std::min(n1, n2);
+    const bool direct = tsvd_direct(n1, n2), tall = n1 > n2;
     are = ar.take<float>(K * n1 * n2);
     aim = ar.take<float>(K * n1 * n2);
-    xre = ar.take<float>(K * m * m);
-    xim = ar.take<float>(K * m * m);
+    if (!direct) {
+      xre = ar.take<float>(K * m * m);
+      xim = ar.take<float>(K * m * m);
+    }
     qre = ar.take<float>(K * m * m);
     qim = ar.take<float>(K * m * m);
-    vre = ar.take<float>(K * m * r);
-    vim = ar.take<float>(K * m * r);
-    if (n1 > n2) {
-      ure = ar.take<float>(K * n1 * r);
-      uim = ar.take<float>(K * n1 * r);
+    if (!direct && tall) {
+      vre = ar.take<float>(K * m * r);
+      vim = ar.take<float>(K * m * r);
     }
+    ure = ar.take<float>(K * n1 * r);
+    uim = ar.take<float>(K * n1 * r);
+    if (direct && tall) mt = ar.take<float>(n1 * n2 * n3);
     ratio = ar.take<float>(svt_ratio_count(K, m));
     conv = ar.take<int>(K);
     return ar.dry() || ar.ok();
@@ -340,11 +355,41 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
   if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tsvd_full workspace too small");
   const int64_t K = half_count(n3);
   const bool real_last = (n3 % 2 == 0) && K > 1;
-  const bool tall = n1 > n2;
+  const bool tall = n1 > n2, direct = tsvd_direct(n1, n2);
   hipStream_t st = S(stream);
   Arena ar(ws, ws_bytes);
   FullSvdLayout lay;
   if (!lay.carve(ar, n1, n2, n3, r)) return fail(TP_EWORKSPACE, "tsvd_full workspace too small");
+  if (int rc = svt_identity(lay.qre, lay.qim, K, m, st)) return rc;
+  if (direct) {
+    // the slices themselves (m rows of length n = the longer side): for a
+    // tall A the slices of its t-transpose, A_k^H
+    const int64_t n = std::max(n1, n2);
+    TubeGather g;
+    g.rows = m;
+    g.cols = n;
+    g.in_cols = n;
+    const void* src = A->data;
+    if (tall) {
+      if (int rc = ttranspose(A->data, 4, n1, n2, n3, lay.mt, st)) return rc;
+      src = lay.mt;
+    }
+    if (int rc = fft_forward(src, TP_F32, n3, g, lay.are, lay.aim, st)) return rc;
+    if (int rc = svt_jacobi(lay.are, lay.aim, lay.qre, lay.qim, K, m, n, real_last, kColdSweeps, kSvtTol,
+                            lay.ratio, lay.conv, st))
+      return rc;
+    // rows of X are sigma_i times conjugated singular vectors: U from Q
+    // (wide, X = U^H A) or from X / sigma (tall, X = Sigma U^H)
+    if (tall) {
+      if (int rc = tsvd_pick(lay.are, lay.aim, n, lay.are, lay.aim, n, K, m, r, real_last, 2, false, lay.ure, lay.uim,
+                             S_out, st))
+        return rc;
+    } else if (int rc = tsvd_pick(lay.are, lay.aim, n, lay.qre, lay.qim, m, K, m, r, real_last, 0, false, lay.ure,
+                                  lay.uim, S_out, st)) {
+      return rc;
+    }
+    return fft_inverse(lay.ure, lay.uim, TP_F32, n3, n1, r, U->data, st);
+  }
   TubeGather g;
   g.rows = n1;
   g.cols = n2;
@@ -375,13 +420,18 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
   if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
   // its eigenvectors by the block Jacobi of the thresholding (rows of Q G
   // made orthogonal), the r leading ones picked by eigenvalue
-  if (int rc = svt_identity(lay.qre, lay.qim, K, m, st)) return rc;
   if (int rc = svt_jacobi(lay.xre, lay.xim, lay.qre, lay.qim, K, m, m, real_last, kColdSweeps, kSvtTol, lay.ratio,
                           lay.conv, st))
     return rc;
-  if (int rc = tsvd_pick(lay.xre, lay.xim, lay.qre, lay.qim, K, m, r, real_last, tall, lay.vre, lay.vim, S_out, st))
+  if (!tall) {
+    if (int rc = tsvd_pick(lay.xre, lay.xim, m, lay.qre, lay.qim, m, K, m, r, real_last, 0, true, lay.ure, lay.uim,
+                           S_out, st))
+      return rc;
+    return fft_inverse(lay.ure, lay.uim, TP_F32, n3, n1, r, U->data, st);
+  }
+  if (int rc = tsvd_pick(lay.xre, lay.xim, m, lay.qre, lay.qim, m, K, m, r, real_last, 1, true, lay.vre, lay.vim,
+                         S_out, st))
     return rc;
-  if (!tall) return fft_inverse(lay.vre, lay.vim, TP_F32, n3, n1, r, U->data, st);
   // U_r = A V_r Sigma_r^-1 (the picked columns already carry 1 / sigma)
   CGemm u;
   u.K = K;

@@ -348,38 +348,42 @@ __global__ __launch_bounds__(NT) void svt_shrink_kernel(float* xre, float* xim, 
   if (tid == 0 && ranks) ranks[k] = cnt[0];
 }
 
-// Leading eigenvectors of a Hermitian positive semidefinite Gram matrix G
-// (m x m per slice) after the block Jacobi has made the rows of X = Q G
-// orthogonal: row i of X is lambda_i q_i with q_i (row i of Q) a unit
-// conjugated eigenvector, so lambda_i = ||X_i||. For the r largest lambda
-// (descending, ties by index) column t of out (m x r planes per slice) is
-// conj(q_sel(t)) times 1 / sqrt(lambda) (inv) or 1, and sv[k][t] =
-// sqrt(lambda): with G = A^H A these are V_r / sigma and the singular values
-// of A, with G = A A^H the left singular vectors. One workgroup per slice;
-// a zero eigenvalue gives a zero column when inv is set.
+// Leading singular (or eigen) vectors after the block Jacobi has made the m
+// rows of X (row length ldx) orthogonal, X = Q Y with Q unitary. Row i of X
+// is mu_i times a unit row and so mu_i = ||X_i||. Two uses:
+//  * Y = G, a Hermitian positive semidefinite Gram matrix: q_i (row i of Q)
+//    is a conjugated eigenvector and mu_i its eigenvalue, sigma = sqrt(mu);
+//  * Y = a Fourier slice itself (m <= its row length): mu_i = sigma_i, rows
+//    of Q are the conjugated left singular vectors and rows of X are sigma_i
+//    times the conjugated right ones.
+// For the r largest mu (descending, ties by index) column t of out (len x r
+// planes per slice) is conj(row sel(t) of the source S (row length len))
+// times 1, 1 / sqrt(mu) (mode 1) or 1 / mu (mode 2), and sv[k][t] =
+// sqrt(mu) (sqrt_sv) or mu. One workgroup per slice; a zero mu gives a zero
+// column in modes 1 and 2.
 __global__ __launch_bounds__(NT) void tsvd_pick_kernel(const float* __restrict__ xre, const float* __restrict__ xim,
-                                                       const float* __restrict__ qre, const float* __restrict__ qim,
-                                                       int64_t K, int m, int r, int real_last, int inv,
+                                                       int64_t ldx, const float* __restrict__ sre,
+                                                       const float* __restrict__ sim, int64_t len, int64_t K, int m,
+                                                       int r, int real_last, int mode, int sqrt_sv,
                                                        float* __restrict__ ore, float* __restrict__ oim,
                                                        double* __restrict__ sv) {
-  extern __shared__ double lam[];  // m eigenvalues, then r selected rows (int)
+  extern __shared__ double lam[];  // m row norms, then r selected rows (int)
   int* sel = reinterpret_cast<int*>(lam + m);
   const int64_t k = blockIdx.x;
   const bool real = k == 0 || (real_last && k == K - 1);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t mm = (int64_t)m * m;
-  const float* xr = xre + k * mm;
-  const float* xi = xim + k * mm;
+  const float* xr = xre + k * m * ldx;
+  const float* xi = xim + k * m * ldx;
   for (int i = wv; i < m; i += NT / 64) {
     double s2 = 0.0;
-    for (int j = lane; j < m; j += 64) {
-      const double a = xr[(int64_t)i * m + j], b = real ? 0.0 : xi[(int64_t)i * m + j];
+    for (int64_t j = lane; j < ldx; j += 64) {
+      const double a = xr[(int64_t)i * ldx + j], b = real ? 0.0 : xi[(int64_t)i * ldx + j];
       s2 += a * a + b * b;
     }
     s2 = wave_sum(s2);
     if (lane == 0) lam[i] = sqrt(s2);
   }
-  // every rank below r is taken exactly once for finite lambda; the default
+  // every rank below r is taken exactly once for finite norms; the default
   // keeps a non-finite input in bounds
   for (int t = tid; t < r; t += NT) sel[t] = 0;
   __syncthreads();
@@ -393,20 +397,21 @@ __global__ __launch_bounds__(NT) void tsvd_pick_kernel(const float* __restrict__
     if (rank < r) sel[rank] = i;
   }
   __syncthreads();
-  const float* q_r = qre + k * mm;
-  const float* q_i = qim + k * mm;
-  float* o_r = ore + k * (int64_t)m * r;
-  float* o_i = oim + k * (int64_t)m * r;
-  for (int64_t e = tid; e < (int64_t)m * r; e += NT) {
-    const int j = (int)(e / r), t = (int)(e - (int64_t)j * r);
+  const float* s_r = sre + k * m * len;
+  const float* s_i = sim + k * m * len;
+  float* o_r = ore + k * len * r;
+  float* o_i = oim + k * len * r;
+  for (int64_t e = tid; e < len * r; e += NT) {
+    const int64_t j = e / r;
+    const int t = (int)(e - j * r);
     const int row = sel[t];
     const double l = lam[row];
-    const double sc = inv ? (l > 0.0 ? 1.0 / sqrt(l) : 0.0) : 1.0;
-    o_r[e] = (float)(sc * q_r[(int64_t)row * m + j]);
-    o_i[e] = real ? 0.f : (float)(-sc * q_i[(int64_t)row * m + j]);
+    const double sc = mode == 0 ? 1.0 : (l > 0.0 ? (mode == 1 ? 1.0 / sqrt(l) : 1.0 / l) : 0.0);
+    o_r[e] = (float)(sc * s_r[(int64_t)row * len + j]);
+    o_i[e] = real ? 0.f : (float)(-sc * s_i[(int64_t)row * len + j]);
   }
   if (sv)
-    for (int t = tid; t < r; t += NT) sv[k * r + t] = sqrt(lam[sel[t]]);
+    for (int t = tid; t < r; t += NT) sv[k * r + t] = sqrt_sv ? sqrt(lam[sel[t]]) : lam[sel[t]];
 }
 
 // t-transpose (Section 2.1): out (n2 x n1 x n3) with out[j][i][t] =
@@ -535,13 +540,14 @@ int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double
   return TP_OK;
 }
 
-int tsvd_pick(const float* xre, const float* xim, const float* qre, const float* qim, int64_t K, int64_t m,
-              int64_t r, bool real_last, bool inv, float* ore, float* oim, double* sv, hipStream_t st) {
+int tsvd_pick(const float* xre, const float* xim, int64_t ldx, const float* sre, const float* sim, int64_t len,
+              int64_t K, int64_t m, int64_t r, bool real_last, int mode, bool sqrt_sv, float* ore, float* oim,
+              double* sv, hipStream_t st) {
   if (K == 0 || r == 0) return TP_OK;
-  if (m > kPickMax || r > m) return fail(TP_EUNSUPPORTED, "eigenvector selection needs r <= m <= 4096");
+  if (m > kPickMax || r > m) return fail(TP_EUNSUPPORTED, "vector selection needs r <= m <= 4096");
   const size_t lds = size_t(m) * sizeof(double) + size_t(r) * sizeof(int);
-  hipLaunchKernelGGL(tsvd_pick_kernel, dim3((unsigned)K), dim3(NT), lds, st, xre, xim, qre, qim, K, (int)m, (int)r,
-                     real_last ? 1 : 0, inv ? 1 : 0, ore, oim, sv);
+  hipLaunchKernelGGL(tsvd_pick_kernel, dim3((unsigned)K), dim3(NT), lds, st, xre, xim, ldx, sre, sim, len, K, (int)m,
+                     (int)r, real_last ? 1 : 0, mode, sqrt_sv ? 1 : 0, ore, oim, sv);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

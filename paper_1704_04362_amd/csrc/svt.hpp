@@ -17,12 +17,14 @@ int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double
                double* sig, int32_t* ranks, hipStream_t st);
 // Largest m for tsvd_pick (its eigenvalues and picks live in LDS).
 constexpr int64_t kPickMax = 4096;
-// After svt_jacobi on a Gram matrix G (X = Q G, K x m x m): the r leading
-// conjugated eigenvector rows of Q as columns of out (K x m x r planes),
-// scaled by 1 / sqrt(lambda) when inv; sv (K x r float64, may be null)
-// receives sqrt(lambda), descending.
-int tsvd_pick(const float* xre, const float* xim, const float* qre, const float* qim, int64_t K, int64_t m,
-              int64_t r, bool real_last, bool inv, float* ore, float* oim, double* sv, hipStream_t st);
+// After svt_jacobi (X = Q Y, K x m x ldx, rows orthogonal): the r rows of
+// the source S (K x m x len: Q, or X itself) with the largest row norms mu
+// of X, conjugated, as columns of out (K x len x r planes), scaled by 1
+// (mode 0), 1 / sqrt(mu) (mode 1) or 1 / mu (mode 2); sv (K x r float64,
+// may be null) receives sqrt(mu) (sqrt_sv) or mu, descending.
+int tsvd_pick(const float* xre, const float* xim, int64_t ldx, const float* sre, const float* sim, int64_t len,
+              int64_t K, int64_t m, int64_t r, bool real_last, int mode, bool sqrt_sv, float* ore, float* oim,
+              double* sv, hipStream_t st);
 int admm_pre(const float* x, const float* e, const float* y, float inv_mu, int64_t n, float* m, hipStream_t st);
 int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, float inv_mu, int64_t n, float* e,
               float* y, hipStream_t st);

@@ -8,7 +8,10 @@ leading r columns capture in every Fourier slice, and, where the spectrum
 has a gap after r, the projector U * U^T. Tolerances: the Gram matrix in
 float32 squares the condition number, so a singular value carries 1e-5
 relative plus 8 eps_32 sigma_max^2 / sigma; orthonormality and energy 1e-5,
-projectors 1e-4."""
+projectors 1e-4. Slices whose longer side is more than four times the
+shorter go through the Gram matrix ((200, 48), (30, 150), (400, 80)); the
+others through the block Jacobi on the slices themselves (on A^H through the
+t-transpose when tall)."""
 import numpy as np
 import pytest
 import torch
@@ -37,7 +40,8 @@ def _slices(X):
 
 
 @pytest.mark.parametrize("shape,r", [((200, 48, 6), 20), ((40, 90, 5), 12), ((64, 64, 4), 64), ((50, 30, 1), 10),
-                                     ((300, 130, 8), 100), ((33, 70, 7), 33), ((60, 40, 300), 10)])
+                                     ((300, 130, 8), 100), ((33, 70, 7), 33), ((60, 40, 300), 10),
+                                     ((30, 150, 4), 10)])
 def test_tsvd_full_matches_oracle(shape, r):
     A = np.random.default_rng(sum(shape) + r).standard_normal(shape).astype(np.float32)
     Ad = A.astype(np.float64)
@@ -84,3 +88,23 @@ def test_tsvd_full_rank_deficient_gives_zero_columns():
     assert np.all(s[:, 3:] < 1e-3 * s.max())
     U = U.cpu().numpy().astype(np.float64)
     assert rel(T.tprod_fft(T.ttranspose(U[:, :3]), U[:, :3]), T.teye(3, 4)) < 1e-4
+
+
+@pytest.mark.parametrize("shape", [(72, 40, 6), (40, 90, 5)])
+def test_tsvd_full_direct_path_resolves_a_graded_spectrum(shape):
+    # singular values over four decades: the Jacobi on the slices themselves
+    # keeps an absolute error of a few float32 roundings of sigma_max, which
+    # the Gram route (error ~ eps_32 sigma_max^2 / sigma) could not
+    n1, n2, n3 = shape
+    m = min(n1, n2)
+    g = np.random.default_rng(n1 + n2)
+    G1 = g.standard_normal((n1, m, n3))
+    G2 = g.standard_normal((m, n2, n3)) * (10.0 ** (-4.0 * np.arange(m) / m))[:, None, None]
+    A = T.tprod_fft(G1, G2).astype(np.float32)
+    r = m // 2
+    U, S_ = api.tsvd_full(dev(A), r)
+    _, _, _, sv = T.tsvd(A.astype(np.float64))
+    s_ref = sv[:, :r]
+    assert np.all(np.abs(S_.cpu().numpy() - s_ref) <= 1e-5 * s_ref + 2e-6 * sv.max())
+    U = U.cpu().numpy().astype(np.float64)
+    assert rel(T.tprod_fft(T.ttranspose(U), U), T.teye(r, n3)) < 1e-5
