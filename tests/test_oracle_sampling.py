@@ -151,3 +151,41 @@ def test_horizontal_leverage_of_lateral_subtensor():
     C = rs.standard_normal((10, 4, 5))
     lev = S.weights_horizontal_leverage(C, 2)
     assert abs(lev.sum() - 2 * 5) < 1e-10
+
+
+def test_horizontal_leverage_follows_left_singular_slices():
+    # eq. colprob_rows_exact indexes horizontal slices, so its scores come
+    # from the LEFT singular slices of C (one value per row of C). Build C
+    # (n1 x c x n3, n1 != c) whose column space in every Fourier slice is
+    # spanned by the horizontal basis slices in `rows`: its top-r left
+    # singular slices are supported on exactly those rows, each with
+    # ||Uhat_{i::}||_F^2 = n3, and every other row scores 0.
+    n1, c, n3 = 11, 5, 6
+    rows = [2, 5, 9]
+    r = len(rows)
+    G = rs.standard_normal((r, c, n3))
+    C = np.zeros((n1, c, n3))
+    C[rows] = G
+    lev = S.weights_horizontal_leverage(C, r)
+    assert lev.shape == (n1,)
+    np.testing.assert_allclose(lev[rows], n3, rtol=1e-10)
+    others = [i for i in range(n1) if i not in rows]
+    assert np.all(np.abs(lev[others]) < 1e-20)
+    # the right singular slices of this C are spread over its c columns:
+    # their lateral scores are not an indicator, so a left/right mix-up
+    # fails here as well as on the length
+    lat = S.weights_lateral_leverage(C, r)
+    assert lat.shape == (c,) and np.max(lat) < n3 * (1 - 1e-3)
+
+
+def test_horizontal_leverage_is_lateral_leverage_of_the_t_transpose():
+    # the t-transpose swaps left and right singular slices (Definition
+    # t-transpose with the t-SVD theorem): U of C is V of C^T, so the
+    # horizontal scores of C are the lateral scores of C^T
+    C = rs.standard_normal((9, 4, 7))
+    for r in (1, 2, 3):
+        h = S.weights_horizontal_leverage(C, r)
+        v = S.weights_lateral_leverage(T.ttranspose(C), r)
+        assert h.shape == (9,)
+        np.testing.assert_allclose(h, v, rtol=1e-10, atol=1e-12)
+        assert abs(h.sum() - r * 7) < 1e-9
