@@ -28,6 +28,23 @@ def _need_gpu(*ts):
             raise ValueError("tensors must be contiguous")
 
 
+def _out(out, shape, dtype, device):
+    """The caller's output tensor after checking it can be written by the
+    kernels as a dense array of `shape` and `dtype` on `device`, or a new
+    one."""
+    shape = tuple(int(v) for v in shape)
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    _need_gpu(out)
+    if out.dtype != dtype:
+        raise ValueError(f"out must be {dtype}, got {out.dtype}")
+    if tuple(out.shape) != shape:
+        raise ValueError(f"out must have shape {shape}, got {tuple(out.shape)}")
+    if out.device != torch.device(device):
+        raise ValueError("out must live on the inputs' device")
+    return out
+
+
 def _tensor(x):
     if x.dim() != 3:
         raise ValueError("expected a 3-way tensor")
@@ -157,8 +174,7 @@ def tprod(A, B, picks=None, prec=None, out=None):
     _need_gpu(A, B)
     if prec is None:
         prec = "f64" if A.dtype == torch.float64 else "f32"
-    C_ = out if out is not None else torch.empty((A.shape[0], B.shape[1], A.shape[2]), dtype=A.dtype,
-                                                  device=A.device)
+    C_ = _out(out, (A.shape[0], B.shape[1], A.shape[2]), A.dtype, A.device)
     lib = L.load()
     ta, tb, tc = _tensor(A), _tensor(B), _tensor(C_)
     ps = picks.struct() if picks is not None else None
@@ -195,7 +211,7 @@ def tproject(X, Cs, prec=None, out=None):
     _need_gpu(X, Cs)
     if prec is None:
         prec = "f64" if X.dtype == torch.float64 else "f32"
-    Z = out if out is not None else torch.empty_like(X)
+    Z = _out(out, X.shape, X.dtype, X.device)
     lib = L.load()
     tx, tc, tz = _tensor(X), _tensor(Cs), _tensor(Z)
     ws = _ws(lib.tp_tproject_workspace(C.byref(tx), C.byref(tc), L.PREC[prec]), X.device)
@@ -211,7 +227,7 @@ def tcx(A, c, rounds=1, r=1, col_kind="norm2", col_w=None, mode="iid", seed=0, p
     if prec is None:
         prec = "f64" if A.dtype == torch.float64 else "f32"
     cols = Picks(c * rounds, A.device)
-    Z = out if out is not None else torch.empty_like(A)
+    Z = _out(out, A.shape, A.dtype, A.device)
     lib = L.load()
     ta, tz = _tensor(A), _tensor(Z)
     cs = cols.struct()
@@ -235,7 +251,7 @@ def tcur(A, c, l, r, col_kind="lev", row_kind="lev", col_w=None, row_w=None, mod
     rows = Picks(n1 if mode == "bernoulli" else l, A.device)
     Z = None
     if want_z:
-        Z = out if out is not None else torch.empty_like(A)
+        Z = _out(out, A.shape, A.dtype, A.device)
     lib = L.load()
     t = _tensor(A)
     tz = _tensor(Z) if Z is not None else None
@@ -256,7 +272,7 @@ def tsvd_full(A, r, out=None):
     singular values of the Fourier slices (float64, descending)."""
     _need_gpu(A)
     n1, n2, n3 = A.shape
-    U = out if out is not None else torch.empty((n1, r, n3), dtype=torch.float32, device=A.device)
+    U = _out(out, (n1, r, n3), torch.float32, A.device)
     S = torch.empty((half_count(n3), r), dtype=torch.float64, device=A.device)
     lib = L.load()
     t, tu = _tensor(A), _tensor(U)
@@ -269,7 +285,7 @@ def tsvt(M, tau, out=None):
     """Per-Fourier-slice singular value thresholding with threshold tau:
     returns (L, ranks)."""
     _need_gpu(M)
-    L_ = out if out is not None else torch.empty_like(M)
+    L_ = _out(out, M.shape, M.dtype, M.device)
     ranks = torch.empty(half_count(M.shape[2]), dtype=torch.int32, device=M.device)
     lib = L.load()
     tm, tl = _tensor(M), _tensor(L_)
@@ -328,7 +344,7 @@ def tcur_nn(X, c, l, r, mask=None, lam=None, col_kind="uniform", row_kind="unifo
     if lam is None:
         lam = 1.0 / (max(n1, n2) * n3) ** 0.5
     cols, rows = Picks(c, X.device), Picks(l, X.device)
-    L_ = out if out is not None else torch.empty_like(X)
+    L_ = _out(out, X.shape, X.dtype, X.device)
     lib = L.load()
     tx = _tensor(X)
     cs, rs_ = cols.struct(), rows.struct()

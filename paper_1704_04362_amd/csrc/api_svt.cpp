@@ -361,6 +361,12 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
   FullSvdLayout lay;
   if (!lay.carve(ar, n1, n2, n3, r)) return fail(TP_EWORKSPACE, "tsvd_full workspace too small");
   if (int rc = svt_identity(lay.qre, lay.qim, K, m, st)) return rc;
+  // rounding residue: a row the rotations emptied keeps about
+  // max(n1, n2) eps_32 sigma_max (the thresholding's cutoff); an
+  // eigenvalue of the m x m float32 Gram that is zero keeps about
+  // m eps_32 lambda_max. Values at or below these count as zero.
+  const double eps32 = 1.1920928955078125e-07;
+  const double direct_floor = double(std::max(n1, n2)) * eps32, gram_floor = double(m) * eps32;
   if (direct) {
     // the slices themselves (m rows of length n = the longer side): for a
     // tall A the slices of its t-transpose, A_k^H
@@ -381,11 +387,11 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
     // rows of X are sigma_i times conjugated singular vectors: U from Q
     // (wide, X = U^H A) or from X / sigma (tall, X = Sigma U^H)
     if (tall) {
-      if (int rc = tsvd_pick(lay.are, lay.aim, n, lay.are, lay.aim, n, K, m, r, real_last, 2, false, lay.ure, lay.uim,
-                             S_out, st))
+      if (int rc = tsvd_pick(lay.are, lay.aim, n, lay.are, lay.aim, n, K, m, r, real_last, 2, false, direct_floor,
+                             lay.ure, lay.uim, S_out, st))
         return rc;
-    } else if (int rc = tsvd_pick(lay.are, lay.aim, n, lay.qre, lay.qim, m, K, m, r, real_last, 0, false, lay.ure,
-                                  lay.uim, S_out, st)) {
+    } else if (int rc = tsvd_pick(lay.are, lay.aim, n, lay.qre, lay.qim, m, K, m, r, real_last, 0, false,
+                                  direct_floor, lay.ure, lay.uim, S_out, st)) {
       return rc;
     }
     return fft_inverse(lay.ure, lay.uim, TP_F32, n3, n1, r, U->data, st);
@@ -424,13 +430,13 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
                           lay.conv, st))
     return rc;
   if (!tall) {
-    if (int rc = tsvd_pick(lay.xre, lay.xim, m, lay.qre, lay.qim, m, K, m, r, real_last, 0, true, lay.ure, lay.uim,
-                           S_out, st))
+    if (int rc = tsvd_pick(lay.xre, lay.xim, m, lay.qre, lay.qim, m, K, m, r, real_last, 0, true, gram_floor,
+                           lay.ure, lay.uim, S_out, st))
       return rc;
     return fft_inverse(lay.ure, lay.uim, TP_F32, n3, n1, r, U->data, st);
   }
-  if (int rc = tsvd_pick(lay.xre, lay.xim, m, lay.qre, lay.qim, m, K, m, r, real_last, 1, true, lay.vre, lay.vim,
-                         S_out, st))
+  if (int rc = tsvd_pick(lay.xre, lay.xim, m, lay.qre, lay.qim, m, K, m, r, real_last, 1, true, gram_floor, lay.vre,
+                         lay.vim, S_out, st))
     return rc;
   // U_r = A V_r Sigma_r^-1 (the picked columns already carry 1 / sigma)
   CGemm u;

@@ -11,8 +11,10 @@
 // rows mutually orthogonal. A round-robin tournament over the blocks visits
 // all block pairs in a sweep; the disjoint pairs of a round are independent
 // workgroups. A slice is converged when every pair in a sweep had
-// max |G_st| / sqrt(G_ss G_tt) below the tolerance; later launches for it
-// return at once, so a fixed launch sequence needs no host synchronisation.
+// max |G_st| / max(G_ss, G_tt) below the tolerance (measured against the
+// larger row: rows stored in float32 keep a rounding floor of about
+// eps_32 times the larger row); later launches for it return at once, so a
+// fixed launch sequence needs no host synchronisation.
 // At the end the rows of X are U^H M = Sigma V^H: sigma_i = ||x_i||, and
 //   L = U diag(max(1 - tau / sigma_i, 0)) X = Uh^H (D X).
 #include <cmath>
@@ -359,14 +361,18 @@ __global__ __launch_bounds__(NT) void svt_shrink_kernel(float* xre, float* xim, 
 // For the r largest mu (descending, ties by index) column t of out (len x r
 // planes per slice) is conj(row sel(t) of the source S (row length len))
 // times 1, 1 / sqrt(mu) (mode 1) or 1 / mu (mode 2), and sv[k][t] =
-// sqrt(mu) (sqrt_sv) or mu. One workgroup per slice; a zero mu gives a zero
-// column in modes 1 and 2.
+// sqrt(mu) (sqrt_sv) or mu. One workgroup per slice. A mu at or below
+// floor_rel times the slice's largest mu is rounding residue of a row the
+// rotations have emptied (or of an eigenvalue that is zero): it is reported
+// as 0 and its column is zero in every mode, so a rank-deficient slice gives
+// the same zero columns whichever route produced X.
 __global__ __launch_bounds__(NT) void tsvd_pick_kernel(const float* __restrict__ xre, const float* __restrict__ xim,
                                                        int64_t ldx, const float* __restrict__ sre,
                                                        const float* __restrict__ sim, int64_t len, int64_t K, int m,
-                                                       int r, int real_last, int mode, int sqrt_sv,
+                                                       int r, int real_last, int mode, int sqrt_sv, double floor_rel,
                                                        float* __restrict__ ore, float* __restrict__ oim,
                                                        double* __restrict__ sv) {
+  __shared__ double red[NT];
   extern __shared__ double lam[];  // m row norms, then r selected rows (int)
   int* sel = reinterpret_cast<int*>(lam + m);
   const int64_t k = blockIdx.x;
@@ -396,7 +402,15 @@ __global__ __launch_bounds__(NT) void tsvd_pick_kernel(const float* __restrict__
     }
     if (rank < r) sel[rank] = i;
   }
+  double mx = 0.0;
+  for (int i = tid; i < m; i += NT) mx = fmax(mx, lam[i]);
+  red[tid] = mx;
   __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const double floor_ = floor_rel * red[0];
   const float* s_r = sre + k * m * len;
   const float* s_i = sim + k * m * len;
   float* o_r = ore + k * len * r;
@@ -406,12 +420,15 @@ __global__ __launch_bounds__(NT) void tsvd_pick_kernel(const float* __restrict__
     const int t = (int)(e - j * r);
     const int row = sel[t];
     const double l = lam[row];
-    const double sc = mode == 0 ? 1.0 : (l > 0.0 ? (mode == 1 ? 1.0 / sqrt(l) : 1.0 / l) : 0.0);
+    const double sc = !(l > floor_) ? 0.0 : (mode == 0 ? 1.0 : (mode == 1 ? 1.0 / sqrt(l) : 1.0 / l));
     o_r[e] = (float)(sc * s_r[(int64_t)row * len + j]);
     o_i[e] = real ? 0.f : (float)(-sc * s_i[(int64_t)row * len + j]);
   }
   if (sv)
-    for (int t = tid; t < r; t += NT) sv[k * r + t] = sqrt_sv ? sqrt(lam[sel[t]]) : lam[sel[t]];
+    for (int t = tid; t < r; t += NT) {
+      const double l = lam[sel[t]];
+      sv[k * r + t] = !(l > floor_) ? 0.0 : (sqrt_sv ? sqrt(l) : l);
+    }
 }
 
 // t-transpose (Section 2.1): out (n2 x n1 x n3) with out[j][i][t] =
@@ -541,13 +558,13 @@ int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double
 }
 
 int tsvd_pick(const float* xre, const float* xim, int64_t ldx, const float* sre, const float* sim, int64_t len,
-              int64_t K, int64_t m, int64_t r, bool real_last, int mode, bool sqrt_sv, float* ore, float* oim,
-              double* sv, hipStream_t st) {
+              int64_t K, int64_t m, int64_t r, bool real_last, int mode, bool sqrt_sv, double floor_rel, float* ore,
+              float* oim, double* sv, hipStream_t st) {
   if (K == 0 || r == 0) return TP_OK;
   if (m > kPickMax || r > m) return fail(TP_EUNSUPPORTED, "vector selection needs r <= m <= 4096");
   const size_t lds = size_t(m) * sizeof(double) + size_t(r) * sizeof(int);
   hipLaunchKernelGGL(tsvd_pick_kernel, dim3((unsigned)K), dim3(NT), lds, st, xre, xim, ldx, sre, sim, len, K, (int)m,
-                     (int)r, real_last ? 1 : 0, mode, sqrt_sv ? 1 : 0, ore, oim, sv);
+                     (int)r, real_last ? 1 : 0, mode, sqrt_sv ? 1 : 0, floor_rel, ore, oim, sv);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

@@ -21,10 +21,12 @@ constexpr int64_t kPickMax = 4096;
 // the source S (K x m x len: Q, or X itself) with the largest row norms mu
 // of X, conjugated, as columns of out (K x len x r planes), scaled by 1
 // (mode 0), 1 / sqrt(mu) (mode 1) or 1 / mu (mode 2); sv (K x r float64,
-// may be null) receives sqrt(mu) (sqrt_sv) or mu, descending.
+// may be null) receives sqrt(mu) (sqrt_sv) or mu, descending. A mu at or
+// below floor_rel times the slice's largest counts as zero: value 0, zero
+// column.
 int tsvd_pick(const float* xre, const float* xim, int64_t ldx, const float* sre, const float* sim, int64_t len,
-              int64_t K, int64_t m, int64_t r, bool real_last, int mode, bool sqrt_sv, float* ore, float* oim,
-              double* sv, hipStream_t st);
+              int64_t K, int64_t m, int64_t r, bool real_last, int mode, bool sqrt_sv, double floor_rel, float* ore,
+              float* oim, double* sv, hipStream_t st);
 int admm_pre(const float* x, const float* e, const float* y, float inv_mu, int64_t n, float* m, hipStream_t st);
 int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, float inv_mu, int64_t n, float* e,
               float* y, hipStream_t st);

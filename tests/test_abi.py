@@ -232,6 +232,27 @@ def test_cpu_tensors_are_rejected():
         api.tprod(A, torch.zeros(5, 3, 6))
     with pytest.raises(ValueError, match="GPU"):
         api.tsvt(A, 0.5)
+    # an out= tensor is checked like an input before its pointer is passed:
+    # a host tensor, a strided view, a wrong dtype or a wrong shape is refused
+    with pytest.raises(ValueError, match="GPU"):
+        api._out(torch.zeros(4, 3, 6), (4, 3, 6), torch.float32, "cuda:0")
+    for bad, msg in ((torch.zeros(4, 3, 6, dtype=torch.float64), "float32"), (torch.zeros(4, 4, 6), "shape"),
+                     (torch.zeros(6, 3, 4).permute(2, 1, 0), "contiguous")):
+        with pytest.raises(ValueError, match=msg):
+            api._out(_FakeCuda(bad), (4, 3, 6), torch.float32, "cuda:0")
+
+
+class _FakeCuda:
+    """A CPU tensor that reports itself as a device tensor, so the checks
+    after the device test can run without a GPU."""
+
+    def __init__(self, t):
+        self._t = t
+        self.is_cuda = True
+        self.dtype, self.shape, self.device = t.dtype, t.shape, "cuda:0"
+
+    def is_contiguous(self):
+        return self._t.is_contiguous()
 
 
 @pytest.mark.parametrize("case", ["rank", "zero_rank", "ushape", "empty", "dtype", "big", "ws"])

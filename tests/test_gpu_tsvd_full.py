@@ -78,16 +78,22 @@ def test_tsvd_full_projector_on_low_rank(shape):
     assert rel(P, Pr) < 1e-4
 
 
-def test_tsvd_full_rank_deficient_gives_zero_columns():
+@pytest.mark.parametrize("shape", [(90, 40, 4), (40, 90, 4), (200, 40, 4), (30, 150, 4)])
+def test_tsvd_full_rank_deficient_gives_zero_columns(shape):
     # tubal rank 3 and r = 5: the two extra columns belong to zero singular
-    # values and are zero; the first three are orthonormal
-    G1, G2, _ = W.lowrank_factors(90, 40, 4, 3, noise_var=0.0, salt=5, dtype=np.float64)
+    # values, which every route reports as exactly 0 with a zero column; the
+    # first three are orthonormal. Shapes: tall and wide slices on the direct
+    # route, tall and wide on the Gram route.
+    n1, n2, n3 = shape
+    G1, G2, _ = W.lowrank_factors(n1, n2, n3, 3, noise_var=0.0, salt=5, dtype=np.float64)
     A = T.tprod_fft(G1, G2).astype(np.float32)
     U, S_ = api.tsvd_full(dev(A), 5)
     s = S_.cpu().numpy()
-    assert np.all(s[:, 3:] < 1e-3 * s.max())
+    assert np.all(s[:, 3:] == 0.0)
+    assert np.all(s[:, :3] > 0.0)
     U = U.cpu().numpy().astype(np.float64)
-    assert rel(T.tprod_fft(T.ttranspose(U[:, :3]), U[:, :3]), T.teye(3, 4)) < 1e-4
+    assert np.all(U[:, 3:, :] == 0.0)
+    assert rel(T.tprod_fft(T.ttranspose(U[:, :3]), U[:, :3]), T.teye(3, n3)) < 1e-4
 
 
 @pytest.mark.parametrize("shape", [(72, 40, 6), (40, 90, 5)])
