@@ -15,7 +15,8 @@
  * and the workspace, whose size the *_workspace functions return). Unless a
  * parameter says "host", pointers are device pointers on the current HIP
  * device. The library keeps no per-call state; its only global state is a
- * per-device table of transform twiddles set up on first use.
+ * per-device table of transform twiddles set up on first use and the fixed
+ * scratch array of tp_tsample_noalloc.
  *
  * Asynchrony: every call enqueues its work on `stream` (a hipStream_t;
  * NULL is the default stream) and returns without synchronising (the one
@@ -177,6 +178,20 @@ size_t tp_slice_norms_workspace(const tp_tensor* A, int mode);
 int tp_tsample(int kind, const tp_tensor* A, const tp_tensor* B, const double* w, int64_t n, int64_t c, int mode,
                uint64_t seed, uint64_t stream_id, tp_sample* out, void* ws, size_t ws_bytes, void* stream);
 size_t tp_tsample_workspace(int64_t n);
+
+/* tp_tsample without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid allocation). Same arguments, checks, picks and errors as
+ * tp_tsample; its scratch is a fixed 32 MiB device array inside the library
+ * (tp_tsample_noalloc_max_bytes()), one per GPU, held until the process
+ * ends. Sizes whose tp_tsample workspace (tp_tsample_workspace(n), plus the
+ * slice-norm partials of A for TP_P_NORM2 / TP_P_NORMPROD) exceed it return
+ * TP_EUNSUPPORTED. Calls on one GPU share that array: calls that overlap on
+ * a GPU (other streams, unordered host threads) race; order them. The first
+ * call on a device looks up the array's address there (no allocation). */
+int tp_tsample_noalloc(int kind, const tp_tensor* A, const tp_tensor* B, const double* w, int64_t n, int64_t c,
+                       int mode, uint64_t seed, uint64_t stream_id, tp_sample* out, void* stream);
+size_t tp_tsample_noalloc_max_bytes(void);
 
 /* ---------------------------------------------------------------------------
  * t-product (Algorithm 1) and rt-product (Algorithm 2).

@@ -38,6 +38,9 @@ _SIGS = {
     "tp_tsample": (C.c_int, [C.c_int, P(Tensor), P(Tensor), C.c_void_p, C.c_int64, C.c_int64, C.c_int,
                              C.c_uint64, C.c_uint64, P(Sample), C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tsample_workspace": (C.c_size_t, [C.c_int64]),
+    "tp_tsample_noalloc": (C.c_int, [C.c_int, P(Tensor), P(Tensor), C.c_void_p, C.c_int64, C.c_int64, C.c_int,
+                                     C.c_uint64, C.c_uint64, P(Sample), C.c_void_p]),
+    "tp_tsample_noalloc_max_bytes": (C.c_size_t, []),
     "tp_tprod": (C.c_int, [P(Tensor), P(Tensor), P(Sample), P(Tensor), C.c_int, C.c_void_p, C.c_size_t,
                            C.c_void_p]),
     "tp_tprod_workspace": (C.c_size_t, [P(Tensor), P(Tensor), P(Sample), C.c_int]),

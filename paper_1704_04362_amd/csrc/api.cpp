@@ -192,11 +192,15 @@ size_t tp_tsample_workspace(int64_t n) {
   return sampler_ws(n) + 2 * align_up(size_t(n) * 8);
 }
 
-static size_t tsample_ws_full(int kind, const tp_tensor* A, int64_t n) {
+}  // extern "C"
+
+size_t tp::tsample_ws_full(int kind, const tp_tensor* A, int64_t n) {
   size_t s = tp_tsample_workspace(n);
   if ((kind == TP_P_NORM2 || kind == TP_P_NORMPROD) && A) s += lateral_norms_ws(A->n1, A->n2, A->n3);
   return s;
 }
+
+extern "C" {
 
 int tp_tsample(int kind, const tp_tensor* A, const tp_tensor* B, const double* w, int64_t n, int64_t c, int mode,
                uint64_t seed, uint64_t stream_id, tp_sample* out, void* ws, size_t ws_bytes, void* stream) {

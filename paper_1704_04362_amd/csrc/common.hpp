@@ -172,6 +172,9 @@ size_t sampler_ws(int64_t n);
 // w: device float64 weights (ignored for uniform mode).
 int sample_slices(const double* w, int64_t n, int64_t c, int mode, uint64_t seed, uint64_t stream_id,
                   int32_t* idx, double* scale, int64_t* count, void* ws, hipStream_t st);
+// Workspace bytes tp_tsample needs for these arguments (the n-dependent
+// part plus the lateral-norm partials of A for the norm-based kinds).
+size_t tsample_ws_full(int kind, const tp_tensor* A, int64_t n);
 // *out = sum of the n device counts, or -1 if any is -1.
 int join_counts(const int64_t* counts, int n, int64_t* out, hipStream_t st);
 

@@ -280,3 +280,19 @@ def test_tsvd_full_validation(case):
         want = -4
     rc = lib.tp_tsvd_full(C.byref(A), r, C.byref(U), None, C.c_void_p(0x2000), wsb, None)
     assert rc == want, lib.tp_last_error()
+
+
+def test_tsample_noalloc_rejects_sizes_beyond_its_scratch():
+    # the fixed scratch holds 32 MiB; 2^24 candidate slices need more, which
+    # is refused on the host before anything is enqueued
+    lib = L.load()
+    assert lib.tp_tsample_noalloc_max_bytes() == 32 << 20
+    n = 1 << 24
+    assert lib.tp_tsample_workspace(n) > lib.tp_tsample_noalloc_max_bytes()
+    out = L.Sample(0x1000, 0x2000, 8, 0x3000)
+    rc = lib.tp_tsample_noalloc(L.KIND["uniform"], None, None, None, n, 8, L.MODE["iid"], 0, 0, C.byref(out), None)
+    assert rc == -7
+    assert b"scratch" in lib.tp_last_error()
+    # bad arguments get tp_tsample's own errors
+    assert lib.tp_tsample_noalloc(L.KIND["uniform"], None, None, None, 10, 11, L.MODE["iid"], 0, 0, C.byref(out),
+                                  None) == -1
