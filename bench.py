@@ -57,18 +57,6 @@ def tprod_flops(n1, n2, n4, n3):
     return (8 * (K - 1 - e) + 2 * (1 + e)) * n1 * n2 * n4
 
 
-def gemm_executed_flops(n1, n2, n4, n3, prec):
-    """Flops the matrix cores execute for the per-slice products: complex
-    slices as three real products (3M), each as three bf16 products for
-    bf16x3 (hi*hi + hi*lo + lo*hi) or one for f32; real slices as one real
-    product."""
-    K = n3 // 2 + 1
-    e = 1 if n3 % 2 == 0 else 0
-    split = 3 if prec == "bf16x3" else 1
-    real_products = 3 * (K - 1 - e) + (1 + e)
-    return 2 * n1 * n2 * n4 * real_products * split
-
-
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -481,6 +469,36 @@ def time_events(fn, reps, torch):
     return e0.elapsed_time(e1) / reps  # ms
 
 
+def f32_exact_tprod(api, A, B, C, reps, torch):
+    """The same exact t-product in plain float32 arithmetic (TP_PREC_F32:
+    float32 transforms and per-slice products on the float32 matrix cores),
+    timed with HIP events, with its stages from the library trace and the
+    product's rate against the float32 matrix-core peak."""
+    F = tprod_flops(N1, N2, N4, N3)
+
+    def run():
+        api.tprod(A, B, prec="f32", out=C)
+
+    run()
+    torch.cuda.synchronize()
+    api.trace_enable(True)
+    ms = time_events(run, reps, torch)
+    api.trace_enable(False)
+    trace = api.trace_read()
+    stages = {}
+    for name in ("fft_ab", "gemm", "ifft"):
+        calls, tot = trace.get("tprod." + name, (0, 0.0))
+        if calls:
+            stages[name] = round(tot / calls, 4)
+    out = {"ms": round(ms, 4), "TFLOPs": round(F / (ms * 1e-3) / 1e12, 3), "stages_ms": stages}
+    if "gemm" in stages:
+        ach = F / (stages["gemm"] * 1e-3) / 1e12
+        out["gemm_roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["f32"], "unit": "TFLOP/s",
+                                "frac": round(ach / PEAK["f32"], 4),
+                                "kernel": "cgemm_f32_kernel (v_mfma_f32_16x16x4f32, 4M complex)"}
+    return out
+
+
 def cpu_baseline(A, B, budget_s):
     """The float64 oracle's t-product by its definition (block-row sums of
     eq. tprod), timed on a bounded sample: the first s frontal slices of C,
@@ -576,6 +594,7 @@ def main():
     reps = max(5, args.steps)
     ms_exact = time_events(exact, reps, torch)
     ms_rand = time_events(randomized, reps, torch)
+    f32_plain = f32_exact_tprod(api, A, B, C, reps, torch) if prec != "f32" else None
 
     F = tprod_flops(N1, N2, N4, N3)
     K = N3 // 2 + 1
@@ -645,6 +664,7 @@ def main():
         "exact_tprod_TFLOPs": round(F / (ms_exact * 1e-3) / 1e12, 3),
         "rtprod_ms": round(ms_rand, 4),
         "kernels_ms": kernels,
+        "f32_exact_tprod": f32_plain,
         "wall_s_timed": round(wall, 3),
     }
     del C, Z

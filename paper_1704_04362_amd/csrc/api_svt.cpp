@@ -75,6 +75,9 @@ struct FullSvdLayout {
   float *vre = nullptr, *vim = nullptr, *ure = nullptr, *uim = nullptr, *mt = nullptr;
   float* ratio = nullptr;
   int* conv = nullptr;
+  // partial planes of a split contraction of the Gram product
+  float *part_re = nullptr, *part_im = nullptr;
+  int64_t part = 0;
   bool carve(Arena& ar, int64_t n1, int64_t n2, int64_t n3, int64_t r) {
     const int64_t K = half_count(n3), m = std::min(n1, n2);
     const bool direct = tsvd_direct(n1, n2), tall = n1 > n2;
@@ -83,6 +86,11 @@ struct FullSvdLayout {
     if (!direct) {
       xre = ar.take<float>(K * m * m);
       xim = ar.take<float>(K * m * m);
+      part = cgemm_ksplit_floats(K, m, m, std::max(n1, n2));
+      if (part) {
+        part_re = ar.take<float>(part);
+        part_im = ar.take<float>(part);
+      }
     }
     qre = ar.take<float>(K * m * m);
     qim = ar.take<float>(K * m * m);
@@ -423,6 +431,9 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
   p.Kd = tall ? n1 : n2;
   p.op_a = tall ? 1 : 0;
   p.op_b = tall ? 0 : 1;
+  p.part_re = lay.part_re;
+  p.part_im = lay.part_im;
+  p.part_cap = lay.part;
   if (int rc = cgemm(p, TP_F32, TP_PREC_F32, st)) return rc;
   // its eigenvectors by the block Jacobi of the thresholding (rows of Q G
   // made orthogonal), the r leading ones picked by eigenvalue

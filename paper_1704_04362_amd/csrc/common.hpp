@@ -149,9 +149,12 @@ int cgemm(const CGemm& p, int dtype, int prec, hipStream_t st);
 // M x N x Kd product over K slices (1 = no split), and the scratch floats
 // per plane it needs for them.
 int cgemm_ksplit(int64_t K, int64_t M, int64_t N, int64_t Kd);
+// The same for the float32 matrix-core product (gemm_f32.hip).
+int cgemm_f32_ksplit(int64_t K, int64_t M, int64_t N, int64_t Kd);
 inline int64_t cgemm_ksplit_floats(int64_t K, int64_t M, int64_t N, int64_t Kd) {
-  const int s = cgemm_ksplit(K, M, N, Kd);
-  return s > 1 ? int64_t(s) * K * M * N : 0;
+  const int s = cgemm_ksplit(K, M, N, Kd), s2 = cgemm_f32_ksplit(K, M, N, Kd);
+  const int m = s > s2 ? s : s2;
+  return m > 1 ? int64_t(m) * K * M * N : 0;
 }
 
 // ---------------------------------------------------------------------------

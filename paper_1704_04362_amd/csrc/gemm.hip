@@ -6,14 +6,16 @@
 // tube length, the Nyquist slice are real and skip the imaginary work.
 //
 // This file holds the general kernel (any op, any size, float or double,
-// LDS-tiled on the vector ALUs). The matrix-core kernels for the large
-// float32 products live in gemm_mfma.hip.
+// LDS-tiled on the vector ALUs) and the dispatch. The matrix-core kernels
+// live in gemm_f32.hip (float32 arithmetic), gemm_mfma.hip (split bf16),
+// gemm_short.hip (short contractions) and gemm_tall.hip (narrow results).
 #include "common.hpp"
 
 namespace tp {
 int cgemm_mfma(const CGemm& p, int prec, hipStream_t st, bool* handled);
 int cgemm_short(const CGemm& p, int split, hipStream_t st, bool* handled);
 int cgemm_tall(const CGemm& p, int split, hipStream_t st, bool* handled);
+int cgemm_f32mfma(const CGemm& p, hipStream_t st, bool* handled);
 
 namespace {
 
@@ -207,6 +209,12 @@ int cgemm(const CGemm& p, int dtype, int prec, hipStream_t st) {
     if (handled) return TP_OK;
     // short contractions: output-bound kernel on the matrix cores
     if (int rc = cgemm_short(p, split, st, &handled)) return rc;
+    if (handled) return TP_OK;
+  }
+  if (dtype == TP_F32 && prec == TP_PREC_F32) {
+    // large float32 products on the float32 matrix cores
+    bool handled = false;
+    if (int rc = cgemm_f32mfma(p, st, &handled)) return rc;
     if (handled) return TP_OK;
   }
   if (dtype == TP_F32 && prec != TP_PREC_F64) {

@@ -9,9 +9,10 @@ has a gap after r, the projector U * U^T. Tolerances: the Gram matrix in
 float32 squares the condition number, so a singular value carries 1e-5
 relative plus 8 eps_32 sigma_max^2 / sigma; orthonormality and energy 1e-5,
 projectors 1e-4. Slices whose longer side is more than four times the
-shorter go through the Gram matrix ((200, 48), (30, 150), (400, 80)); the
-others through the block Jacobi on the slices themselves (on A^H through the
-t-transpose when tall)."""
+shorter go through the Gram matrix ((200, 48), (30, 150), (400, 80), and
+(4100, 40) and (9000, 100), the latter's Gram product on the float32
+matrix cores with its long contraction split into parts); the others through the block Jacobi on the slices themselves
+(on A^H through the t-transpose when tall)."""
 import numpy as np
 import pytest
 import torch
@@ -41,7 +42,7 @@ def _slices(X):
 
 @pytest.mark.parametrize("shape,r", [((200, 48, 6), 20), ((40, 90, 5), 12), ((64, 64, 4), 64), ((50, 30, 1), 10),
                                      ((300, 130, 8), 100), ((33, 70, 7), 33), ((60, 40, 300), 10),
-                                     ((30, 150, 4), 10)])
+                                     ((30, 150, 4), 10), ((4100, 40, 4), 12), ((9000, 100, 2), 10)])
 def test_tsvd_full_matches_oracle(shape, r):
     A = np.random.default_rng(sum(shape) + r).standard_normal(shape).astype(np.float32)
     Ad = A.astype(np.float64)
