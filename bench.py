@@ -495,7 +495,7 @@ def f32_exact_tprod(api, A, B, C, reps, torch):
         ach = F / (stages["gemm"] * 1e-3) / 1e12
         out["gemm_roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["f32"], "unit": "TFLOP/s",
                                 "frac": round(ach / PEAK["f32"], 4),
-                                "kernel": "cgemm_f32_kernel (v_mfma_f32_16x16x4f32, 4M complex)"}
+                                "kernel": "cgemm_f32_kernel (v_mfma_f32_16x16x4f32, complex slices as 3 real products)"}
     return out
 
 

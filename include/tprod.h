@@ -61,13 +61,23 @@ typedef enum { TP_F32 = 0, TP_F64 = 1 } tp_dtype;
 
 /* Arithmetic of the per-slice contractions.
  *  TP_PREC_F64    float64 operands and accumulation (TP_F64 storage).
- *  TP_PREC_F32    float32 operands and accumulation.
+ *  TP_PREC_F32    float32 operands and accumulation; products with at least
+ *                 16 rows and columns and a contraction of at least 64 run
+ *                 on the float32 matrix cores with complex products as
+ *                 three real products (Re = P1 - P2, Im = P3 - P1 - P2 with
+ *                 P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi)); smaller
+ *                 ones as four (Re = Ar Br - Ai Bi, Im = Ar Bi + Ai Br).
  *  TP_PREC_BF16X3 float32 operands split as x = hi + lo, hi = bf16(x),
  *                 lo = bf16(x - hi) (round to nearest even), products
  *                 hi*hi + hi*lo + lo*hi on the bf16 matrix cores with
- *                 float32 accumulation; complex products as three real
- *                 products (Re = P1 - P2, Im = P3 - P1 - P2 with
- *                 P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi)).
+ *                 float32 accumulation. Complex products of float32
+ *                 spectra (inside the decompositions) use three real
+ *                 products, with Ar + Ai and Br + Bi formed and split while
+ *                 staging; the t-product and rt-product, whose transforms
+ *                 emit the split planes directly, use four (Re = Ar Br -
+ *                 Ai Bi, Im = Ar Bi + Ai Br): the staging of those planes,
+ *                 not the matrix cores, bounds that product, and three
+ *                 products would need two more planes per operand.
  *  TP_PREC_BF16   single bf16 product (hi*hi only), float32 accumulation. */
 typedef enum { TP_PREC_F64 = 0, TP_PREC_F32 = 1, TP_PREC_BF16X3 = 2, TP_PREC_BF16 = 3 } tp_prec;
 

@@ -3,22 +3,25 @@
 // Fourier-domain products of the dense t-SVD (Gram matrices A^H A, A A^H
 // and U = A V) when the arithmetic is plain float32 (TP_PREC_F32).
 //
-// Complex products use four real products per 4-deep step:
-//   Re C += Ar Br - Ai Bi,   Im C += Ar Bi + Ai Br,
-// and the real slices (DC, Nyquist) take Ar Br alone. Conjugate transposes
-// (op = 1) are applied while staging: the operand is read transposed and its
-// imaginary part negated.
+// Complex slices use three real products (3M):
+//   P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi),
+//   Re C = P1 - P2, Im C = P3 - P1 - P2,
+// with the sums Ar + Ai and Br + Bi formed once per staged element, so the
+// matrix cores do three quarters of the four-product work (this kernel is
+// bound by them); the real slices (DC, Nyquist) take P1 alone. Conjugate
+// transposes (op = 1) are applied while staging: the operand is read
+// transposed and its imaginary part negated before the sum is formed.
 //
 // Tiling: a 256-thread workgroup owns a 128 x 128 tile of one Fourier
 // slice; each of its four wavefronts owns 64 x 64 (4 x 4 matrix-core tiles
-// of 16 x 16, real and imaginary accumulators). A 16-deep step of both
-// operands is staged through registers (loaded one step ahead) into one of
-// two LDS buffers, stored per row with the contraction index permuted so
-// that a lane's four values for the four 4-deep sub-steps are one 16-byte
-// chunk: position 4 (k mod 4) + k / 4 of the row, chunk c of row r stored
-// at chunk c ^ (r mod 4). A fragment read (16 rows x 4 chunks per
-// wavefront) then covers 1 KB of LDS once. The kernel is bound by the
-// matrix cores: each 16-deep step moves 32 KB into LDS for 2.1 MFLOP.
+// of 16 x 16, three accumulators each). A 16-deep step of both operands is
+// staged through registers (loaded one step ahead, never predicated off)
+// into one of two LDS buffers as three planes (re, im, re + im), stored per
+// row with the contraction index permuted so that a lane's four values for
+// the four 4-deep sub-steps are one 16-byte chunk: position 4 (k mod 4) +
+// k / 4 of the row, chunk c of row r stored at chunk c ^ (r mod 4). A
+// fragment read (16 rows x 4 chunks per wavefront) then covers 1 KB of LDS
+// once.
 //
 // Products with few output tiles and a long contraction split the
 // contraction into parts that write float32 partial planes, summed in part
@@ -55,53 +58,59 @@ __device__ __forceinline__ int lds_pos(int row, int k) {
 // Stages one 16-deep step of an operand (rows of op(X): 128 x 16) from
 // global memory into registers. along_k: the stored operand is contiguous
 // along the contraction index (op_a = 0 for A, op_b = 1 for B); otherwise
-// along the rows. Thread t covers 8 elements; out-of-range elements are 0.
+// along the rows. Thread t covers 8 elements. Loads are never predicated
+// off: an element outside the operand reads the slice origin instead (always
+// valid) and is cleared when it is stored to LDS, so all eight loads stay in
+// flight together behind the products of the current step.
 struct Stage {
   float re[8], im[8];
+  uint32_t keep;  // bit p: element p lies inside the operand
 };
 
-template <bool REAL>
-__device__ __forceinline__ void load_stage(Stage& s, const float* xr, const float* xi, int64_t ld, bool along_k,
-                                           bool conj, int64_t r0, int64_t rows, int64_t k0, int64_t kend) {
+__device__ __forceinline__ void stage_coords(bool along_k, int p, int& row, int& kk) {
   const int t = threadIdx.x;
-#pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    int row, kk;
-    if (along_k) {
-      row = (t >> 4) + 16 * p;
-      kk = t & 15;
-    } else {
-      row = (t & 127);
-      kk = (t >> 7) + 2 * p;
-    }
-    const int64_t gr = r0 + row, gk = k0 + kk;
-    float vr = 0.f, vi = 0.f;
-    if (gr < rows && gk < kend) {
-      const int64_t off = along_k ? gr * ld + gk : gk * ld + gr;
-      vr = xr[off];
-      if (!REAL) vi = conj ? -xi[off] : xi[off];
-    }
-    s.re[p] = vr;
-    s.im[p] = vi;
+  if (along_k) {
+    row = (t >> 4) + 16 * p;
+    kk = t & 15;
+  } else {
+    row = (t & 127);
+    kk = (t >> 7) + 2 * p;
   }
 }
 
 template <bool REAL>
-__device__ __forceinline__ void store_stage(const Stage& s, bool along_k, float* lre, float* lim) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ void load_stage(Stage& s, const float* xr, const float* xi, int64_t ld, bool along_k,
+                                           int64_t r0, int64_t rows, int64_t k0, int64_t kend) {
+  s.keep = 0;
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     int row, kk;
-    if (along_k) {
-      row = (t >> 4) + 16 * p;
-      kk = t & 15;
-    } else {
-      row = (t & 127);
-      kk = (t >> 7) + 2 * p;
-    }
+    stage_coords(along_k, p, row, kk);
+    const int64_t gr = r0 + row, gk = k0 + kk;
+    const bool ok = gr < rows && gk < kend;
+    const int64_t off = ok ? (along_k ? gr * ld + gk : gk * ld + gr) : 0;
+    s.re[p] = xr[off];
+    if (!REAL) s.im[p] = xi[off];
+    s.keep |= ok ? (1u << p) : 0u;
+  }
+}
+
+template <bool REAL>
+__device__ __forceinline__ void store_stage(const Stage& s, bool along_k, bool conj, float* lre, float* lim,
+                                            float* lsum) {
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    int row, kk;
+    stage_coords(along_k, p, row, kk);
+    const bool ok = (s.keep >> p) & 1u;
     const int o = lds_pos(row, kk);
-    lre[o] = s.re[p];
-    if (!REAL) lim[o] = s.im[p];
+    const float vr = ok ? s.re[p] : 0.f;
+    lre[o] = vr;
+    if (!REAL) {
+      const float vi = ok ? (conj ? -s.im[p] : s.im[p]) : 0.f;
+      lim[o] = vi;
+      lsum[o] = vr + vi;
+    }
   }
 }
 
@@ -124,65 +133,77 @@ __device__ __forceinline__ void f32_body(const FArgs& g, int64_t k, int part, fl
   const bool a_along_k = g.op_a == 0, b_along_k = g.op_b != 0;
   const bool a_conj = g.op_a != 0, b_conj = g.op_b != 0;
 
-  // LDS: 2 buffers x [A re, A im, B re, B im] x 128 rows x 16 floats
+  // LDS: 2 buffers x [A re, A im, A sum, B re, B im, B sum] x 128 rows x 16
   constexpr int PL = FM * FK;
-  auto buf = [&](int b, int which) { return lds + (b * 4 + which) * PL; };
+  auto buf = [&](int b, int which) { return lds + (b * 6 + which) * PL; };
 
-  f32x4 cr[4][4], ci[4][4];
+  // p1 = Ar Br, p2 = Ai Bi, p3 = (Ar + Ai)(Br + Bi)
+  f32x4 p1[4][4], p2[4][4], p3[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      cr[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-      ci[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      p1[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      p2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      p3[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
 
   Stage sa, sb;
   const int64_t nsteps = kend > kbeg ? (kend - kbeg + FK - 1) / FK : 0;
   if (nsteps > 0) {
-    load_stage<REAL>(sa, are, aim, g.lda, a_along_k, a_conj, m0, g.M, kbeg, kend);
-    load_stage<REAL>(sb, bre, bim, g.ldb, b_along_k, b_conj, n0, g.N, kbeg, kend);
+    load_stage<REAL>(sa, are, aim, g.lda, a_along_k, m0, g.M, kbeg, kend);
+    load_stage<REAL>(sb, bre, bim, g.ldb, b_along_k, n0, g.N, kbeg, kend);
   }
   const int fr = lane & 15, fq = lane >> 4;
   for (int64_t st = 0; st < nsteps; ++st) {
     const int b = (int)(st & 1);
-    store_stage<REAL>(sa, a_along_k, buf(b, 0), buf(b, 1));
-    store_stage<REAL>(sb, b_along_k, buf(b, 2), buf(b, 3));
+    store_stage<REAL>(sa, a_along_k, a_conj, buf(b, 0), buf(b, 1), buf(b, 2));
+    store_stage<REAL>(sb, b_along_k, b_conj, buf(b, 3), buf(b, 4), buf(b, 5));
     __syncthreads();
     if (st + 1 < nsteps) {
       const int64_t k0 = kbeg + (st + 1) * FK;
-      load_stage<REAL>(sa, are, aim, g.lda, a_along_k, a_conj, m0, g.M, k0, kend);
-      load_stage<REAL>(sb, bre, bim, g.ldb, b_along_k, b_conj, n0, g.N, k0, kend);
+      load_stage<REAL>(sa, are, aim, g.lda, a_along_k, m0, g.M, k0, kend);
+      load_stage<REAL>(sb, bre, bim, g.ldb, b_along_k, n0, g.N, k0, kend);
     }
     // fragments: lane (fq, fr) reads row fr of a 16-row tile, chunk fq:
     // the values for k = fq + 4 s, s = 0..3 (sub-step s of the 16-deep step)
-    f32x4 bfr[4], bfi[4];
+    f32x4 br_[4], bi_[4], bs_[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = wc * 64 + j * 16 + fr;
       const int o = row * 16 + 4 * (fq ^ (row & 3));
-      bfr[j] = *reinterpret_cast<const f32x4*>(buf(b, 2) + o);
-      if (!REAL) bfi[j] = *reinterpret_cast<const f32x4*>(buf(b, 3) + o);
+      br_[j] = *reinterpret_cast<const f32x4*>(buf(b, 3) + o);
+      if (!REAL) {
+        bi_[j] = *reinterpret_cast<const f32x4*>(buf(b, 4) + o);
+        bs_[j] = *reinterpret_cast<const f32x4*>(buf(b, 5) + o);
+      }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = wr * 64 + i * 16 + fr;
       const int o = row * 16 + 4 * (fq ^ (row & 3));
       const f32x4 ar = *reinterpret_cast<const f32x4*>(buf(b, 0) + o);
-      f32x4 ai = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (!REAL) ai = *reinterpret_cast<const f32x4*>(buf(b, 1) + o);
-      const f32x4 an = -ai;
+      f32x4 ai = f32x4{0.f, 0.f, 0.f, 0.f}, as = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (!REAL) {
+        ai = *reinterpret_cast<const f32x4*>(buf(b, 1) + o);
+        as = *reinterpret_cast<const f32x4*>(buf(b, 2) + o);
+      }
+      // product-outer order: consecutive matrix-core operations update
+      // different accumulators, so none waits for the one before it
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], bfr[j][s], cr[i][j], 0, 0, 0);
-          if (!REAL) {
-            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[s], bfi[j][s], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], bfi[j][s], ci[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], bfr[j][s], ci[i][j], 0, 0, 0);
-          }
+        for (int j = 0; j < 4; ++j)
+          p1[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], br_[j][s], p1[i][j], 0, 0, 0);
+        if (!REAL) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            p2[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], bi_[j][s], p2[i][j], 0, 0, 0);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            p3[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[s], bs_[j][s], p3[i][j], 0, 0, 0);
         }
+      }
     }
     __syncthreads();
   }
@@ -209,14 +230,15 @@ __device__ __forceinline__ void f32_body(const FArgs& g, int64_t k, int part, fl
         const int64_t gm = m0 + wr * 64 + i * 16 + 4 * fq + v;
         const int64_t gn = n0 + wc * 64 + j * 16 + fr;
         if (gm < g.M && gn < g.N) {
-          cre[gm * ldc + gn] = cr[i][j][v];
-          cim[gm * ldc + gn] = REAL ? 0.f : ci[i][j][v];
+          const float a = p1[i][j][v], c = p2[i][j][v];
+          cre[gm * ldc + gn] = REAL ? a : a - c;
+          cim[gm * ldc + gn] = REAL ? 0.f : p3[i][j][v] - a - c;
         }
       }
 }
 
 __global__ __launch_bounds__(FT, 1) void cgemm_f32_kernel(FArgs g) {
-  __shared__ __attribute__((aligned(16))) float lds[2 * 4 * FM * FK];  // 64 KB
+  __shared__ __attribute__((aligned(16))) float lds[2 * 6 * FM * FK];  // 96 KB
   const int part = (int)(blockIdx.z % (unsigned)g.ksplit);
   const int64_t k = blockIdx.z / (unsigned)g.ksplit;
   const bool real = k == 0 || (g.real_last && k == g.K - 1);
