@@ -51,9 +51,8 @@ typedef enum {
   TP_EDTYPE = -3,      /* unsupported dtype / precision combination    */
   TP_EWORKSPACE = -4,  /* workspace missing or too small               */
   TP_EHIP = -5,        /* a HIP runtime call or kernel launch failed    */
-  TP_ENOCONV = -6,     /* reserved: no entry point returns it (the
-                          ADMM calls run a fixed iteration count and the
-                          Jacobi solvers decide convergence on the device) */
+  TP_ENOCONV = -6,     /* an ADMM call with a stop tolerance reached its
+                          iteration cap first (results still written)   */
   TP_EUNSUPPORTED = -7 /* size outside what the kernels implement      */
 } tp_status;
 
@@ -342,14 +341,22 @@ size_t tp_tsvd_full_workspace(const tp_tensor* A, int64_t r);
  * every iteration does
  *   L <- t-SVT(X - E - Y/mu, 1/mu); E <- P_unobserved(X - L - Y/mu);
  *   Y <- Y + mu (L + E - X);        mu <- min(rho mu, mu_max)
- * for exactly `iters` iterations (the paper's values are rho = 1.1,
- * mu0 = 1e-3, mu_max = 1e10). L, E, Y are outputs (tube-major float32, the
- * shape of X); ranks (may be NULL) gets the last iteration's per-slice
- * ranks. Each iteration's slice SVDs start from the previous iteration's
- * left singular vectors. */
+ * (the paper's values are rho = 1.1, mu0 = 1e-3, mu_max = 1e10), then
+ * Algorithm 7's stop test when tol > 0: the loop ends after the first
+ * iteration with max|L_{k+1} - L_k|, max|E_{k+1} - E_k| and
+ * max|L_{k+1} + E_{k+1} - X| all <= tol (the paper uses 1e-8 in float64;
+ * float32 iterates stall near 1e-7 of their scale). The three quantities
+ * are formed on the device and read back after every iteration, so tol > 0
+ * synchronises the stream once per iteration; reaching `iters` iterations
+ * first returns TP_ENOCONV with the iterates written. tol <= 0 runs exactly
+ * `iters` iterations without synchronising. L, E, Y are outputs (tube-major
+ * float32, the shape of X); ranks (device, may be NULL) gets the last
+ * iteration's per-slice ranks; iters_done (host, may be NULL) the number of
+ * iterations run. Each iteration's slice SVDs start from the previous
+ * iteration's left singular vectors. Workspace: tp_tcomplete_workspace(X). */
 int tp_tcomplete(const tp_tensor* X, const uint8_t* mask, int32_t iters, double rho, double mu0, double mu_max,
-                 tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
-                 void* stream);
+                 double tol, tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int32_t* iters_done, int prec,
+                 void* ws, size_t ws_bytes, void* stream);
 size_t tp_tcomplete_workspace(const tp_tensor* X);
 
 /* Robust tensor PCA by Algorithm 7 as stated (eq. tlow7: minimise
@@ -358,12 +365,15 @@ size_t tp_tcomplete_workspace(const tp_tensor* X);
  *   L <- t-SVT(X - E - Y/mu, 1/mu);
  *   E <- sign(V) max(|V| - lambda/mu, 0) with V = X - L - Y/mu;
  *   Y <- Y + mu (L + E - X);  mu <- min(rho mu, mu_max)
- * for exactly `iters` iterations. X, L, E, Y: tube-major float32 of one
- * shape (caller-owned device buffers; L, E, Y are overwritten); lambda > 0
- * (the paper gives no value; 1/sqrt(max(n1, n2) n3) is the usual choice);
- * ranks as for tp_tcomplete. Workspace: tp_trpca_workspace(X) bytes. */
-int tp_trpca(const tp_tensor* X, double lambda, int32_t iters, double rho, double mu0, double mu_max, tp_tensor* L,
-             tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes, void* stream);
+ * with the stop test, tol, iters_done and TP_ENOCONV as for tp_tcomplete.
+ * X, L, E, Y: tube-major float32 of one shape (caller-owned device buffers;
+ * L, E, Y are overwritten); lambda > 0, or 0 for the default
+ * 1/sqrt(max(n1, n2) n3) (the paper gives no value; this is the one of the
+ * tensor robust PCA work eq. tlow7 comes from); ranks as for tp_tcomplete.
+ * Workspace: tp_trpca_workspace(X) bytes. */
+int tp_trpca(const tp_tensor* X, double lambda, int32_t iters, double rho, double mu0, double mu_max, double tol,
+             tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int32_t* iters_done, int prec, void* ws,
+             size_t ws_bytes, void* stream);
 size_t tp_trpca_workspace(const tp_tensor* X);
 
 /* CUR t-NN (Algorithm 6): c lateral slices C of X picked by col_kind (as
@@ -379,7 +389,8 @@ size_t tp_trpca_workspace(const tp_tensor* X);
  * not used). mask != NULL: completion (eq. tlow6; X holds the observed
  * values, mask is tube-major uint8 of X's shape, nonzero where observed) and
  * lambda is ignored; mask == NULL: robust PCA (eq. tlow7) with weight
- * lambda > 0, the same for C and R. mode TP_S_IID or TP_S_UNIFORM (exactly
+ * lambda > 0 (0: 1/sqrt(max(n1, n2) n3) of X), the same for C and R; both
+ * ADMM runs take exactly `iters` iterations. mode TP_S_IID or TP_S_UNIFORM (exactly
  * c and l picks); 1 <= r <= min(c, l), r + 10 <= 64; float32 data, prec
  * TP_PREC_F32. L (float32, X's shape) is overwritten. Workspace:
  * tp_tcur_nn_workspace(X, c, l, r, col_kind, row_kind, mask != NULL). */

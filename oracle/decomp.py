@@ -175,7 +175,13 @@ def tsvt(M, tau):
     return L, ranks
 
 
-def admm_complete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None):
+def _stopped(rec, tol):
+    """Algorithm 7's convergence check: every one of the three
+    infinity-norm quantities is at most tol."""
+    return tol is not None and rec["dL"] <= tol and rec["dE"] <= tol and rec["res"] <= tol
+
+
+def admm_complete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None, tol=None):
     """Algorithm 7 for the completion problem: minimise ||L||_TNN subject to
     X = L + E with E zero on the observed entries.
 
@@ -185,9 +191,12 @@ def admm_complete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=Non
         E <- P_unobserved(X - L - Y/mu)
         Y <- Y + mu (L + E - X)
         mu <- min(rho mu, mu_max)
-    Returns (L, E, Y, history) where history holds, per iteration, the three
-    infinity-norm stop quantities of Algorithm 7, the per-slice ranks, and
-    the relative error against L_true when given.
+    and then Algorithm 7's check: with tol given, the loop ends after the
+    first iteration whose changes ||L_{k+1} - L_k||_inf, ||E_{k+1} - E_k||_inf
+    and residual ||L_{k+1} + E_{k+1} - X||_inf are all at most tol; at most
+    `iters` iterations run either way. Returns (L, E, Y, history) where
+    history holds, per iteration run, the three stop quantities, the
+    per-slice ranks, and the relative error against L_true when given.
     """
     X = np.asarray(X, dtype=np.float64)
     W = np.asarray(mask, dtype=np.float64)
@@ -212,6 +221,8 @@ def admm_complete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=Non
             rec["rse"] = T.rel_fro(L, L_true)
         hist.append(rec)
         mu = min(rho * mu, mu_max)
+        if _stopped(rec, tol):
+            break
     return L, E, Y, hist
 
 
@@ -260,7 +271,7 @@ def rpca_lambda(shape):
     return 1.0 / np.sqrt(max(n1, n2) * n3)
 
 
-def admm_rpca(X, lam, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None):
+def admm_rpca(X, lam, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None, tol=None):
     """Algorithm 7 as stated, for robust tensor PCA (eq. tlow7): minimise
     ||L||_TNN + lam ||E||_1 subject to X = L + E. From L = E = Y = 0 and
     mu = mu0 every iteration does
@@ -268,7 +279,8 @@ def admm_rpca(X, lam, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None):
         E <- soft_threshold(X - L - Y/mu, lam/mu)     (E-update, l1 prox)
         Y <- Y + mu (L + E - X)
         mu <- min(rho mu, mu_max)
-    for exactly `iters` iterations. Returns (L, E, Y, history) with the same
+    followed by Algorithm 7's check when tol is given (as in admm_complete),
+    for at most `iters` iterations. Returns (L, E, Y, history) with the same
     per-iteration records as admm_complete."""
     X = np.asarray(X, dtype=np.float64)
     L = np.zeros_like(X)
@@ -292,6 +304,8 @@ def admm_rpca(X, lam, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, L_true=None):
             rec["rse"] = T.rel_fro(L, L_true)
         hist.append(rec)
         mu = min(rho * mu, mu_max)
+        if _stopped(rec, tol):
+            break
     return L, E, Y, hist
 
 

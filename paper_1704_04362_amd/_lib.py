@@ -5,6 +5,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtprod.so")
 
 TP_F32, TP_F64 = 0, 1
+TP_ENOCONV = -6
 PREC = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3}
 KIND = {"user": 0, "uniform": 1, "norm2": 2, "normprod": 3, "lev": 4}
 MODE = {"bernoulli": 0, "iid": 1, "uniform": 2}
@@ -57,16 +58,18 @@ _SIGS = {
     "tp_tsvt_workspace": (C.c_size_t, [P(Tensor)]),
     "tp_tsvd_full": (C.c_int, [P(Tensor), C.c_int64, P(Tensor), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tsvd_full_workspace": (C.c_size_t, [P(Tensor), C.c_int64]),
-    "tp_tcomplete": (C.c_int, [P(Tensor), C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
-                               P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_tcomplete": (C.c_int, [P(Tensor), C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                               P(Tensor), P(Tensor), P(Tensor), C.c_void_p, P(C.c_int32), C.c_int, C.c_void_p,
+                               C.c_size_t, C.c_void_p]),
     "tp_tcomplete_workspace": (C.c_size_t, [P(Tensor)]),
     "tp_tproject": (C.c_int, [P(Tensor), P(Tensor), P(Tensor), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tproject_workspace": (C.c_size_t, [P(Tensor), P(Tensor), C.c_int]),
     "tp_tcx": (C.c_int, [P(Tensor), C.c_int64, C.c_int32, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_uint64,
                          P(Sample), P(Tensor), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tcx_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int32, C.c_int64, C.c_int, C.c_int]),
-    "tp_trpca": (C.c_int, [P(Tensor), C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double, P(Tensor),
-                           P(Tensor), P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_trpca": (C.c_int, [P(Tensor), C.c_double, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
+                           P(Tensor), P(Tensor), P(Tensor), C.c_void_p, P(C.c_int32), C.c_int, C.c_void_p, C.c_size_t,
+                           C.c_void_p]),
     "tp_trpca_workspace": (C.c_size_t, [P(Tensor)]),
     "tp_tcur_nn": (C.c_int, [P(Tensor), C.c_void_p, C.c_double, C.c_int64, C.c_int64, C.c_int64, C.c_int,
                              C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_uint64, C.c_int32, C.c_double,

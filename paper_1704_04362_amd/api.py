@@ -295,10 +295,22 @@ def tsvt(M, tau, out=None):
     return L_, ranks
 
 
-def tcomplete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
+def _admm_status(status, info, done):
+    """TP_ENOCONV (a stop tolerance not met within the cap) is a result, not
+    an error: report it in info; raise for anything else."""
+    if info is not None:
+        info["iters"] = int(done.value)
+        info["converged"] = status == 0
+    if status != L.TP_ENOCONV:
+        L.check(status)
+
+
+def tcomplete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, tol=0.0, info=None):
     """ADMM tensor completion (Algorithm 7, completion variant): returns
     (L, E, Y, ranks of the last iteration). mask is a uint8 tensor of X's
-    shape, nonzero where observed."""
+    shape, nonzero where observed. tol > 0 applies Algorithm 7's stop test
+    after every iteration (one host synchronisation per iteration); a dict
+    passed as info receives "iters" (iterations run) and "converged"."""
     _need_gpu(X, mask)
     if mask.dtype != torch.uint8 or mask.shape != X.shape:
         raise ValueError("mask must be uint8 with X's shape")
@@ -307,28 +319,30 @@ def tcomplete(X, mask, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
     lib = L.load()
     tx = _tensor(X)
     ws = _ws(lib.tp_tcomplete_workspace(C.byref(tx)), X.device)
-    L.check(lib.tp_tcomplete(C.byref(tx), mask.data_ptr(), int(iters), float(rho), float(mu0), float(mu_max),
-                             C.byref(_tensor(L_)), C.byref(_tensor(E)), C.byref(_tensor(Y)), ranks.data_ptr(),
-                             L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream()))
+    done = C.c_int32(0)
+    status = lib.tp_tcomplete(C.byref(tx), mask.data_ptr(), int(iters), float(rho), float(mu0), float(mu_max),
+                              float(tol), C.byref(_tensor(L_)), C.byref(_tensor(E)), C.byref(_tensor(Y)),
+                              ranks.data_ptr(), C.byref(done), L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream())
+    _admm_status(status, info, done)
     return L_, E, Y, ranks
 
 
-def trpca(X, lam=None, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10):
+def trpca(X, lam=None, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, tol=0.0, info=None):
     """Robust tensor PCA by the ADMM of Algorithm 7 (eq. tlow7): returns
-    (L, E, Y, ranks of the last iteration). lam defaults to
-    1/sqrt(max(n1, n2) n3)."""
+    (L, E, Y, ranks of the last iteration). lam = None lets the library use
+    its default 1/sqrt(max(n1, n2) n3); tol and info as for tcomplete."""
     _need_gpu(X)
-    n1, n2, n3 = X.shape
-    if lam is None:
-        lam = 1.0 / (max(n1, n2) * n3) ** 0.5
+    n3 = X.shape[2]
     L_, E, Y = torch.empty_like(X), torch.empty_like(X), torch.empty_like(X)
     ranks = torch.empty(half_count(n3), dtype=torch.int32, device=X.device)
     lib = L.load()
     tx = _tensor(X)
     ws = _ws(lib.tp_trpca_workspace(C.byref(tx)), X.device)
-    L.check(lib.tp_trpca(C.byref(tx), float(lam), int(iters), float(rho), float(mu0), float(mu_max),
-                         C.byref(_tensor(L_)), C.byref(_tensor(E)), C.byref(_tensor(Y)), ranks.data_ptr(),
-                         L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream()))
+    done = C.c_int32(0)
+    status = lib.tp_trpca(C.byref(tx), 0.0 if lam is None else float(lam), int(iters), float(rho), float(mu0),
+                          float(mu_max), float(tol), C.byref(_tensor(L_)), C.byref(_tensor(E)), C.byref(_tensor(Y)),
+                          ranks.data_ptr(), C.byref(done), L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream())
+    _admm_status(status, info, done)
     return L_, E, Y, ranks
 
 
@@ -336,13 +350,14 @@ def tcur_nn(X, c, l, r, mask=None, lam=None, col_kind="uniform", row_kind="unifo
             mode="uniform", seed=0, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, out=None):
     """CUR t-NN of Algorithm 6: returns (L, column picks, row picks). With a
     uint8 mask (nonzero where observed) the ADMM is the completion variant,
-    otherwise robust PCA with weight lam (default 1/sqrt(max(n1, n2) n3))."""
+    otherwise robust PCA with weight lam (None: the library's default
+    1/sqrt(max(n1, n2) n3))."""
     _need_gpu(X, mask, col_w, row_w)
     n1, n2, n3 = X.shape
     if mask is not None and (mask.dtype != torch.uint8 or mask.shape != X.shape):
         raise ValueError("mask must be uint8 with X's shape")
     if lam is None:
-        lam = 1.0 / (max(n1, n2) * n3) ** 0.5
+        lam = 0.0  # the library's default weight
     cols, rows = Picks(c, X.device), Picks(l, X.device)
     L_ = _out(out, X.shape, X.dtype, X.device)
     lib = L.load()

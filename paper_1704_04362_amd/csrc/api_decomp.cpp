@@ -613,7 +613,9 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
   if (!kind_ok(col_kind) || !kind_ok(row_kind)) return fail(TP_EINVAL, "unsupported probability kind");
   if (col_kind == TP_P_USER && !col_w) return fail(TP_EINVAL, "column weights are null");
   if (row_kind == TP_P_USER && !row_w) return fail(TP_EINVAL, "row weights are null");
-  if (!mask && (!(lambda > 0.0) || !std::isfinite(lambda))) return fail(TP_EINVAL, "lambda must be finite and > 0");
+  if (!mask && lambda == 0.0) lambda = rpca_default_lambda(X->n1, X->n2, X->n3);
+  if (!mask && (!(lambda > 0.0) || !std::isfinite(lambda)))
+    return fail(TP_EINVAL, "lambda must be finite and >= 0 (0 selects the default)");
   if (iters < 1) return fail(TP_EINVAL, "need at least one iteration");
   if (!(rho >= 1.0) || !(mu0 > 0.0) || !(mu_max >= mu0) || !std::isfinite(rho) || !std::isfinite(mu_max))
     return fail(TP_EINVAL, "need rho >= 1 and 0 < mu0 <= mu_max");
@@ -656,8 +658,8 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
     if (int rc = gather_slices(mask, 1, n2, n3, nullptr, cols->idx, cols->count, n1, c, nn.cm, st)) return rc;
 
   // 2. Ct = ADMM(C), and its spectrum
-  if (int rc = admm_run(nn.cx, nn.cm, lambda, n1, c, n3, iters, rho, mu0, mu_max, nn.cl, nn.ce, nn.cy, nullptr,
-                        nn.admm, nn.admm_bytes, st))
+  if (int rc = admm_run(nn.cx, nn.cm, lambda, n1, c, n3, iters, rho, mu0, mu_max, 0.0, nn.cl, nn.ce, nn.cy, nullptr,
+                        nullptr, nn.admm, nn.admm_bytes, st))
     return rc;
   {
     TubeGather g;
@@ -688,8 +690,8 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
     if (int rc = gather_slices(mask, 1, n2, n3, rows->idx, nullptr, rows->count, l, n2, nn.rm, st)) return rc;
 
   // 4. Rt = ADMM(R), and its spectrum
-  if (int rc = admm_run(nn.rx, nn.rm, lambda, l, n2, n3, iters, rho, mu0, mu_max, nn.rl, nn.re, nn.ry, nullptr,
-                        nn.admm, nn.admm_bytes, st))
+  if (int rc = admm_run(nn.rx, nn.rm, lambda, l, n2, n3, iters, rho, mu0, mu_max, 0.0, nn.rl, nn.re, nn.ry, nullptr,
+                        nullptr, nn.admm, nn.admm_bytes, st))
     return rc;
   {
     TubeGather g;

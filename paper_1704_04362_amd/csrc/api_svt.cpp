@@ -24,7 +24,10 @@ struct SvtLayout {
   float* ratio = nullptr;
   int* conv = nullptr;
   double* sig = nullptr;
-  float* m = nullptr;  // completion only: M = X - E - Y/mu, tube-major
+  float* m = nullptr;  // ADMM only: M = X - E - Y/mu, tube-major
+  // ADMM only, for the stop test: the previous L and E, per-workgroup
+  // partial maxima and the three stop quantities
+  float *lprev = nullptr, *eprev = nullptr, *stop_part = nullptr, *stop_out = nullptr;
   bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int64_t n3, bool completion) {
     xre = ar.take<float>(K * n1 * n2);
     xim = ar.take<float>(K * n1 * n2);
@@ -35,7 +38,14 @@ struct SvtLayout {
     ratio = ar.take<float>(svt_ratio_count(K, n1));
     conv = ar.take<int>(K);
     sig = ar.take<double>(K * n1);
-    if (completion) m = ar.take<float>(n1 * n2 * n3);
+    if (completion) {
+      const int64_t n = n1 * n2 * n3;
+      m = ar.take<float>(n);
+      lprev = ar.take<float>(n);
+      eprev = ar.take<float>(n);
+      stop_part = ar.take<float>(admm_stop_floats(n));
+      stop_out = ar.take<float>(4);
+    }
     return ar.dry() || ar.ok();
   }
 };
@@ -163,9 +173,18 @@ int check_admm(const tp_tensor* X, const tp_tensor* L, const tp_tensor* E, const
 namespace {
 
 // The loop of the ADMM on an n1 x n2 x n3 problem with the given layout.
+// tol > 0: after every iteration Algorithm 7's check (the infinity norms of
+// the changes of L and E and of the residual L + E - X all at most tol) is
+// evaluated on the device and read back, and the loop ends at the first
+// iteration that meets it; reaching `iters` iterations without it gives
+// TP_ENOCONV (the iterates are still written). tol <= 0: exactly `iters`
+// iterations with no host synchronisation. *iters_done (host, may be null)
+// receives the number of iterations run.
 int admm_loop(SvtLayout& lay, const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3,
-              int iters, double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks,
-              hipStream_t st) {
+              int iters, double rho, double mu0, double mu_max, double tol, float* l, float* e, float* y,
+              int32_t* ranks, int32_t* iters_done, hipStream_t st) {
+  const bool check = tol > 0.0;
+  if (iters_done) *iters_done = 0;
   const int64_t K = half_count(n3), n = n1 * n2 * n3;
   const bool real_last = (n3 % 2 == 0) && K > 1;
   // L_0 = E_0 = Y_0 = 0
@@ -215,12 +234,16 @@ int admm_loop(SvtLayout& lay, const float* x, const uint8_t* mask, double lam, i
                               it == 0 ? kColdSweeps : kWarmSweeps, kSvtTol, lay.ratio, lay.conv, st))
         return rc;
     }
+    if (check) {
+      TP_HIP_CHECK(hipMemcpyAsync(lay.lprev, l, n * sizeof(float), hipMemcpyDeviceToDevice, st));
+      TP_HIP_CHECK(hipMemcpyAsync(lay.eprev, e, n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
     {
       // L = SVT(M, 1/mu); the shrink leaves X scaled, so the next warm start
       // uses Uh only
       TraceScope ts("admm.shrink_ifft", st);
-      if (int rc = finish_svt(lay, K, n1, n2, n3, 1.0 / mu, real_last, it == iters - 1 ? ranks : nullptr, l, st))
-        return rc;
+      int32_t* rk = (check || it == iters - 1) ? ranks : nullptr;
+      if (int rc = finish_svt(lay, K, n1, n2, n3, 1.0 / mu, real_last, rk, l, st)) return rc;
     }
     {
       TraceScope ts("admm.post", st);
@@ -233,8 +256,16 @@ int admm_loop(SvtLayout& lay, const float* x, const uint8_t* mask, double lam, i
       }
     }
     mu = std::min(rho * mu, mu_max);
+    if (iters_done) *iters_done = it + 1;
+    if (check) {
+      float q[3] = {0.f, 0.f, 0.f};
+      if (int rc = admm_stop(x, l, lay.lprev, e, lay.eprev, n, lay.stop_part, lay.stop_out, st)) return rc;
+      TP_HIP_CHECK(hipMemcpyAsync(q, lay.stop_out, sizeof(q), hipMemcpyDeviceToHost, st));
+      TP_HIP_CHECK(hipStreamSynchronize(st));
+      if (q[0] <= tol && q[1] <= tol && q[2] <= tol) return TP_OK;
+    }
   }
-  return TP_OK;
+  return check ? fail(TP_ENOCONV, "ADMM: the iteration cap was reached before the stop test held") : TP_OK;
 }
 
 // Tall problems (n1 > n2) run on the t-transpose: the t-SVT satisfies
@@ -269,27 +300,29 @@ size_t admm_workspace(int64_t n1, int64_t n2, int64_t n3) {
 }
 
 int admm_run(const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3, int iters,
-             double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks, void* ws,
-             size_t ws_bytes, hipStream_t st) {
+             double rho, double mu0, double mu_max, double tol, float* l, float* e, float* y, int32_t* ranks,
+             int32_t* iters_done, void* ws, size_t ws_bytes, hipStream_t st) {
   const size_t need = admm_workspace(n1, n2, n3);
   if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "ADMM workspace too small");
   Arena ar(ws, ws_bytes);
   AdmmLayout lay;
   if (!lay.carve(ar, n1, n2, n3, mask != nullptr)) return fail(TP_EWORKSPACE, "ADMM workspace too small");
-  if (n1 <= n2) return admm_loop(lay.svt, x, mask, lam, n1, n2, n3, iters, rho, mu0, mu_max, l, e, y, ranks, st);
+  if (n1 <= n2)
+    return admm_loop(lay.svt, x, mask, lam, n1, n2, n3, iters, rho, mu0, mu_max, tol, l, e, y, ranks, iters_done,
+                     st);
   // transposed problem (n2 x n1 x n3), iterates kept in l, e, y, then turned back
   const int64_t n = n1 * n2 * n3;
   if (int rc = ttranspose(x, 4, n1, n2, n3, lay.xt, st)) return rc;
   if (mask)
     if (int rc = ttranspose(mask, 1, n1, n2, n3, lay.mt, st)) return rc;
-  if (int rc = admm_loop(lay.svt, lay.xt, mask ? lay.mt : nullptr, lam, n2, n1, n3, iters, rho, mu0, mu_max, l, e,
-                         y, ranks, st))
-    return rc;
+  const int status = admm_loop(lay.svt, lay.xt, mask ? lay.mt : nullptr, lam, n2, n1, n3, iters, rho, mu0, mu_max,
+                               tol, l, e, y, ranks, iters_done, st);
+  if (status != TP_OK && status != TP_ENOCONV) return status;
   for (float* b : {l, e, y}) {
     if (int rc = ttranspose(b, 4, n2, n1, n3, lay.tmp, st)) return rc;
     TP_HIP_CHECK(hipMemcpyAsync(b, lay.tmp, n * sizeof(float), hipMemcpyDeviceToDevice, st));
   }
-  return TP_OK;
+  return status;
 }
 
 }  // namespace tp
@@ -480,20 +513,26 @@ size_t tp_tcomplete_workspace(const tp_tensor* X) {
 size_t tp_trpca_workspace(const tp_tensor* X) { return tp_tcomplete_workspace(X); }
 
 int tp_tcomplete(const tp_tensor* X, const uint8_t* mask, int32_t iters, double rho, double mu0, double mu_max,
-                 tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
-                 void* stream) {
+                 double tol, tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int32_t* iters_done, int prec,
+                 void* ws, size_t ws_bytes, void* stream) {
+  if (iters_done) *iters_done = 0;
   if (!mask) return fail(TP_EINVAL, "mask is null");
   if (int rc = check_admm(X, L, E, Y, iters, rho, mu0, mu_max, prec)) return rc;
-  return admm_run((const float*)X->data, mask, 0.0, X->n1, X->n2, X->n3, iters, rho, mu0, mu_max, (float*)L->data,
-                  (float*)E->data, (float*)Y->data, ranks, ws, ws_bytes, S(stream));
+  if (std::isnan(tol)) return fail(TP_EINVAL, "tol is NaN");
+  return admm_run((const float*)X->data, mask, 0.0, X->n1, X->n2, X->n3, iters, rho, mu0, mu_max, tol,
+                  (float*)L->data, (float*)E->data, (float*)Y->data, ranks, iters_done, ws, ws_bytes, S(stream));
 }
 
-int tp_trpca(const tp_tensor* X, double lambda, int32_t iters, double rho, double mu0, double mu_max, tp_tensor* L,
-             tp_tensor* E, tp_tensor* Y, int32_t* ranks, int prec, void* ws, size_t ws_bytes, void* stream) {
-  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(TP_EINVAL, "lambda must be finite and > 0");
+int tp_trpca(const tp_tensor* X, double lambda, int32_t iters, double rho, double mu0, double mu_max, double tol,
+             tp_tensor* L, tp_tensor* E, tp_tensor* Y, int32_t* ranks, int32_t* iters_done, int prec, void* ws,
+             size_t ws_bytes, void* stream) {
+  if (iters_done) *iters_done = 0;
   if (int rc = check_admm(X, L, E, Y, iters, rho, mu0, mu_max, prec)) return rc;
-  return admm_run((const float*)X->data, nullptr, lambda, X->n1, X->n2, X->n3, iters, rho, mu0, mu_max,
-                  (float*)L->data, (float*)E->data, (float*)Y->data, ranks, ws, ws_bytes, S(stream));
+  if (lambda == 0.0) lambda = rpca_default_lambda(X->n1, X->n2, X->n3);
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(TP_EINVAL, "lambda must be finite and >= 0 (0 selects the default)");
+  if (std::isnan(tol)) return fail(TP_EINVAL, "tol is NaN");
+  return admm_run((const float*)X->data, nullptr, lambda, X->n1, X->n2, X->n3, iters, rho, mu0, mu_max, tol,
+                  (float*)L->data, (float*)E->data, (float*)Y->data, ranks, iters_done, ws, ws_bytes, S(stream));
 }
 
 }  // extern "C"

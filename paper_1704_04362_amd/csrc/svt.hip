@@ -478,6 +478,59 @@ __global__ void admm_post_soft_kernel(const float* __restrict__ x, const float* 
   y[i] = yv + mu * (lv + ev - xv);
 }
 
+// The three quantities of Algorithm 7's convergence check for one
+// iteration, reduced per workgroup: max |L - Lprev|, max |E - Eprev| and
+// max |L + E - X| over the workgroup's elements (E the new iterate, read
+// after the E-update; eprev a copy taken before it). One value triple per
+// workgroup in part[3 * block + q]; the maxima are order independent.
+__global__ __launch_bounds__(256) void admm_stop_partial_kernel(const float* __restrict__ x,
+                                                                const float* __restrict__ l,
+                                                                const float* __restrict__ lprev,
+                                                                const float* __restrict__ e,
+                                                                const float* __restrict__ eprev, int64_t n,
+                                                                float* __restrict__ part) {
+  __shared__ float red[3][256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float dl = 0.f, de = 0.f, rs = 0.f;
+  if (i < n) {
+    const float lv = l[i], ev = e[i];
+    dl = fabsf(lv - lprev[i]);
+    de = fabsf(ev - eprev[i]);
+    rs = fabsf(lv + ev - x[i]);
+  }
+  red[0][threadIdx.x] = dl;
+  red[1][threadIdx.x] = de;
+  red[2][threadIdx.x] = rs;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = fmaxf(red[q][threadIdx.x], red[q][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) part[3 * (int64_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// out[q] = max over the nb partial triples (one workgroup)
+__global__ __launch_bounds__(256) void admm_stop_reduce_kernel(const float* __restrict__ part, int64_t nb,
+                                                               float* __restrict__ out) {
+  __shared__ float red[3][256];
+  float m[3] = {0.f, 0.f, 0.f};
+  for (int64_t b = threadIdx.x; b < nb; b += 256)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) m[q] = fmaxf(m[q], part[3 * b + q]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = m[q];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = fmaxf(red[q][threadIdx.x], red[q][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // out[a][b][t] = in[ra][cb][t] with ra = ridx ? ridx[a] : a and
 // cb = cidx ? cidx[b] : b: picked lateral or horizontal slices of a
 // tube-major tensor with in_cols lateral slices. Entries past the live pick
@@ -580,6 +633,19 @@ int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, flo
               float* y, hipStream_t st) {
   if (n == 0) return TP_OK;
   hipLaunchKernelGGL(admm_post_kernel, dim3(nblk(n)), dim3(256), 0, st, x, mask, l, mu, inv_mu, n, e, y);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+size_t admm_stop_floats(int64_t n) { return 3 * size_t(nblk(n)) + 4; }
+
+int admm_stop(const float* x, const float* l, const float* lprev, const float* e, const float* eprev, int64_t n,
+              float* part, float* out, hipStream_t st) {
+  if (n == 0) return TP_OK;
+  const unsigned nb = nblk(n);
+  hipLaunchKernelGGL(admm_stop_partial_kernel, dim3(nb), dim3(256), 0, st, x, l, lprev, e, eprev, n, part);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(admm_stop_reduce_kernel, dim3(1), dim3(256), 0, st, part, (int64_t)nb, out);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

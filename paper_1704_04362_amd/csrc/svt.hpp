@@ -1,6 +1,8 @@
 // Per-slice singular value thresholding and ADMM elementwise steps (svt.hip).
 #pragma once
 
+#include <cmath>
+
 #include "common.hpp"
 
 namespace tp {
@@ -30,6 +32,12 @@ int tsvd_pick(const float* xre, const float* xim, int64_t ldx, const float* sre,
 int admm_pre(const float* x, const float* e, const float* y, float inv_mu, int64_t n, float* m, hipStream_t st);
 int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, float inv_mu, int64_t n, float* e,
               float* y, hipStream_t st);
+// Algorithm 7's stop quantities max |L - Lprev|, max |E - Eprev|,
+// max |L + E - X| into out[0..2] (device), through admm_stop_floats(n) - 4
+// floats of per-workgroup partials in part.
+size_t admm_stop_floats(int64_t n);
+int admm_stop(const float* x, const float* l, const float* lprev, const float* e, const float* eprev, int64_t n,
+              float* part, float* out, hipStream_t st);
 int admm_post_soft(const float* x, const float* l, float mu, float inv_mu, float thr, int64_t n, float* e, float* y,
                    hipStream_t st);
 // t-transpose of an n1 x n2 x n3 tube-major tensor into out (n2 x n1 x n3);
@@ -45,8 +53,18 @@ int gather_slices(const void* in, int elem_bytes, int64_t in_cols, int64_t n3, c
 // (E zero on mask != 0) when mask is non-null, robust PCA with weight lam
 // otherwise. Workspace: admm_workspace bytes.
 size_t admm_workspace(int64_t n1, int64_t n2, int64_t n3);
+// tol > 0 ends the loop at Algorithm 7's stop test (read back after every
+// iteration) and gives TP_ENOCONV at the cap; tol <= 0 runs exactly `iters`
+// iterations without synchronising. *iters_done (host, may be null): the
+// iterations run.
 int admm_run(const float* x, const uint8_t* mask, double lam, int64_t n1, int64_t n2, int64_t n3, int iters,
-             double rho, double mu0, double mu_max, float* l, float* e, float* y, int32_t* ranks, void* ws,
-             size_t ws_bytes, hipStream_t st);
+             double rho, double mu0, double mu_max, double tol, float* l, float* e, float* y, int32_t* ranks,
+             int32_t* iters_done, void* ws, size_t ws_bytes, hipStream_t st);
+// The l1 weight of eq. tlow7 when the caller passes 0: 1/sqrt(max(n1, n2) n3)
+// (the paper gives none; this is the value of the tensor robust PCA work the
+// problem comes from).
+inline double rpca_default_lambda(int64_t n1, int64_t n2, int64_t n3) {
+  return 1.0 / std::sqrt(double(n1 > n2 ? n1 : n2) * double(n3));
+}
 
 }  // namespace tp

@@ -96,21 +96,31 @@ def test_spectrum_and_transform_validation():
     assert lib.tp_spectrum_matmul(C.byref(A), 2, C.byref(B), 0, C.byref(Cs), 1, 1, None) == -1
 
 
-@pytest.mark.parametrize("case", ["lambda", "shape", "iters"])
+@pytest.mark.parametrize("case", ["lambda", "nan_lambda", "shape", "iters", "nan_tol", "ws"])
 def test_trpca_validation(case):
     lib = L.load()
     X, Lt, E, Y = _t(6, 5, 4), _t(6, 5, 4), _t(6, 5, 4), _t(6, 5, 4)
-    lam, iters, want = 0.1, 10, -1
+    lam, iters, tol, wsb, want = 0.1, 10, 0.0, 1 << 30, -1
     if case == "lambda":
-        lam = 0.0
+        lam = -0.5
+    elif case == "nan_lambda":
+        lam = float("nan")
     elif case == "shape":
         E = _t(6, 4, 4)
         want = -2
-    else:
+    elif case == "iters":
         iters = 0
-    rc = lib.tp_trpca(C.byref(X), lam, iters, 1.1, 1e-3, 1e10, C.byref(Lt), C.byref(E), C.byref(Y), None,
-                      L.PREC["f32"], C.c_void_p(0x2000), 1 << 30, None)
-    assert rc == want
+    elif case == "nan_tol":
+        tol = float("nan")
+    else:
+        # lambda = 0 selects the default weight and passes validation, so
+        # the call reaches the workspace check
+        lam, wsb, want = 0.0, 16, -4
+    done = C.c_int32(-5)
+    rc = lib.tp_trpca(C.byref(X), lam, iters, 1.1, 1e-3, 1e10, tol, C.byref(Lt), C.byref(E), C.byref(Y), None,
+                      C.byref(done), L.PREC["f32"], C.c_void_p(0x2000), wsb, None)
+    assert rc == want, lib.tp_last_error()
+    assert done.value == 0
 
 
 @pytest.mark.parametrize("case", ["empty", "tau", "nan_tau", "prec", "dtype", "shape", "ws"])
@@ -159,8 +169,8 @@ def test_tcomplete_validation(case):
     else:
         wsb = 16
         want = -4
-    rc = lib.tp_tcomplete(C.byref(X), mask, 10, rho, mu0, 1e10, C.byref(Lt), C.byref(E), C.byref(Y), None,
-                          L.PREC["f32"], C.c_void_p(0x2000), wsb, None)
+    rc = lib.tp_tcomplete(C.byref(X), mask, 10, rho, mu0, 1e10, 0.0, C.byref(Lt), C.byref(E), C.byref(Y), None,
+                          None, L.PREC["f32"], C.c_void_p(0x2000), wsb, None)
     assert rc == want, lib.tp_last_error()
     # the workspace query of an empty tensor is 0
     assert lib.tp_tcomplete_workspace(C.byref(_t(6, 0, 4))) == 0

@@ -339,3 +339,36 @@ def test_tcx_union_never_worse_than_a_round():
     # a single round is plain t-CX; the union of all slices reproduces A
     np.testing.assert_allclose(D.tcx_union(A, rounds[:1]), D.tcx(A, rounds[0], np.ones(5)), atol=1e-12)
     assert T.rel_fro(D.tcx_union(A, [np.arange(30)]), A) < 1e-12
+
+
+@pytest.mark.parametrize("variant", ["complete", "rpca"])
+def test_admm_stops_at_the_first_iteration_meeting_the_check(variant):
+    # Algorithm 7 ends the loop once ||L_{k+1} - L_k||_inf, ||E_{k+1} -
+    # E_k||_inf and ||L_{k+1} + E_{k+1} - X||_inf are all at most eps. The
+    # stopped run must equal the unstopped run cut at that first iteration,
+    # and no earlier iteration may meet the check.
+    Ls = _lowrank(10, 9, 4, 2, seed=31)
+    if variant == "complete":
+        mask = (np.random.default_rng(32).random(Ls.shape) < 0.7).astype(np.uint8)
+
+        def run(**kw):
+            return D.admm_complete(Ls * mask, mask, **kw)
+    else:
+        lam = D.rpca_lambda(Ls.shape)
+
+        def run(**kw):
+            return D.admm_rpca(Ls, lam, **kw)
+
+    _, _, _, full = run(iters=300)
+    q = np.array([max(h["dL"], h["dE"], h["res"]) for h in full])
+    tol = float(np.quantile(q[q > 0], 0.2))
+    first = int(np.argmax(q <= tol))
+    assert q[first] <= tol and np.all(q[:first] > tol)
+    L, E, Y, hist = run(iters=300, tol=tol)
+    assert len(hist) == first + 1
+    L2, E2, Y2, _ = run(iters=first + 1)
+    np.testing.assert_array_equal(L, L2)
+    np.testing.assert_array_equal(E, E2)
+    np.testing.assert_array_equal(Y, Y2)
+    # an unreachable tolerance runs the whole budget
+    assert len(run(iters=7, tol=0.0)[3]) == 7
