@@ -105,10 +105,25 @@ typedef struct {
  *  TP_P_LEV       tubal leverage scores: lateral ||Vhat_{j::}||_F^2 from the
  *                 top-r right singular slices (eq. cur-col-prob); horizontal
  *                 ||Uhat_{i::}||_F^2 from the top-r left singular slices of C
- *                 (eq. colprob_rows_exact, read with the squared norm). */
+ *                 (eq. colprob_rows_exact, read with the squared norm).
+ *  TP_P_LEARNED   lateral slices only: the learned proposal of
+ *                 tp_mlp_proposal (a network's estimate of the lateral
+ *                 leverage scores, mixed with the uniform distribution), given
+ *                 as a tp_mlp. Not in the paper; TP_P_LEV stays the
+ *                 reference. */
 typedef enum {
-  TP_P_USER = 0, TP_P_UNIFORM = 1, TP_P_NORM2 = 2, TP_P_NORMPROD = 3, TP_P_LEV = 4
+  TP_P_USER = 0, TP_P_UNIFORM = 1, TP_P_NORM2 = 2, TP_P_NORMPROD = 3, TP_P_LEV = 4, TP_P_LEARNED = 5
 } tp_prob_kind;
+
+/* The learned proposal's inputs (TP_P_LEARNED): params, the
+ * tp_mlp_param_count() float32 network parameters; phi, the (n1 n3) x 16
+ * float32 sketch matrix; alpha, the weight of the uniform distribution in
+ * the mixture (see tp_mlp_proposal). Device pointers. */
+typedef struct {
+  const float* params;
+  const float* phi;
+  double alpha;
+} tp_mlp;
 
 /* How slices are picked.
  *  TP_S_BERNOULLI  Algorithm 2: slice i kept with probability min(1, c p_i),
@@ -118,7 +133,8 @@ typedef enum {
  *                  1/sqrt(c p_j); draw order.
  *  TP_S_UNIFORM    c distinct slices uniformly without replacement
  *                  (Corollaries cor:proj-main, cor:gnys-main), scale
- *                  sqrt(n/c); ascending order.
+ *                  sqrt(n/c); ascending order. It uses no weights, so the
+ *                  decompositions accept it with TP_P_UNIFORM only.
  * Decisions are exact integer comparisons on weights quantised to
  * q_i = floor(w_i 2^(B-e)) (e the binary exponent of max w, B = 62 -
  * ceil(log2 n)) against Philox4x64-10 draws keyed by (seed, stream_id) at
@@ -221,22 +237,41 @@ size_t tp_tprod_workspace(const tp_tensor* A, const tp_tensor* B, const tp_sampl
  * eqs. cur-col-prob and colprob_rows_exact).
  * ------------------------------------------------------------------------- */
 
-/* Leading-r t-SVD of A by a Gaussian range finder applied to every
- * non-redundant Fourier slice (s = r + p sketch columns, q power
- * iterations; Halko, Martinsson, Tropp 2011), with an orthonormalisation
- * through the float64 eigen-decomposition of the s x s Gram matrix.
- * Outputs (device float64 arrays, each may be NULL):
- *   S              K x r singular values of the Fourier slices, descending;
- *   lev_lateral    n2 values ||Vhat_{j::}||_F^2 summed over all n3 Fourier
- *                  slices (the lateral leverage scores before normalisation;
- *                  they sum to r n3 when every slice has rank >= r);
- *   lev_horizontal n1 values ||Uhat_{i::}||_F^2, likewise.
- * r + p <= 64 (p is capped so that r + p <= min(n1, n2)); prec
+/* Leading-r t-SVD of A by a range finder applied to every non-redundant
+ * Fourier slice (Halko, Martinsson, Tropp 2011), with an
+ * orthonormalisation through the float64 eigen-decomposition of the s x s
+ * Gram matrix. The basis is
+ *   slices == NULL: a Gaussian sketch of s = r + p columns (p rounded up so
+ *                   that s is a multiple of 4 where the slices allow), then
+ *                   q power iterations;
+ *   slices != NULL: the picked lateral slices Chat_k = Ahat_k S D of
+ *                   Definition t-CX / Algorithm 4 (s = slices->cap columns;
+ *                   device picks as from tp_tsample, columns past *count are
+ *                   zero), then q power iterations (q = 0: the rank-r
+ *                   truncation of the t-CX projection C C^+ A). p unused.
+ * Outputs (each may be NULL):
+ *   S              device K x r float64 singular values of the Fourier
+ *                  slices, descending;
+ *   U              n1 x r x n3 (A's dtype): the first r left singular
+ *                  slices;
+ *   V              n2 x r x n3: the first r right singular slices;
+ *   Z              A's shape: the tubal-rank-r approximation U * S * V^T
+ *                  (the t-SVD theorem truncated to r);
+ *   lev_lateral    device n2 float64 values ||Vhat_{j::}||_F^2 summed over
+ *                  all n3 Fourier slices (the lateral leverage scores before
+ *                  normalisation; they sum to r n3 when every slice has rank
+ *                  >= r);
+ *   lev_horizontal device n1 float64 values ||Uhat_{i::}||_F^2, likewise.
+ * Directions whose eigenvalue is below 1e-6 (float32) or 1e-12 (float64)
+ * of the slice's largest give zero columns. s <= 64 and r <= s; prec
  * TP_PREC_F64 (float64 data), TP_PREC_F32 or TP_PREC_BF16X3 (float32 data;
- * the small eigenproblems are float64 in every case). */
-int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, uint64_t seed, int prec, double* S,
-                 double* lev_lateral, double* lev_horizontal, void* ws, size_t ws_bytes, void* stream);
-size_t tp_tsvd_rand_workspace(const tp_tensor* A, int64_t r, int64_t p, int prec);
+ * the small eigenproblems are float64 in every case). Gaussian sketches use
+ * stream 2 of `seed`. Workspace: tp_tsvd_rand_workspace(A, r, p, slices,
+ * prec) bytes. */
+int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, const tp_sample* slices, uint64_t seed,
+                 int prec, double* S, tp_tensor* U, tp_tensor* V, tp_tensor* Z, double* lev_lateral,
+                 double* lev_horizontal, void* ws, size_t ws_bytes, void* stream);
+size_t tp_tsvd_rand_workspace(const tp_tensor* A, int64_t r, int64_t p, const tp_sample* slices, int prec);
 
 /* ---------------------------------------------------------------------------
  * t-project and t-CX (Algorithms 3 and 4; Definition "t-CX", eq. ell2reg).
@@ -275,26 +310,35 @@ size_t tp_tcx_workspace(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r
  * t-CUR (Definition "t-CUR", Algorithm 5).
  * ------------------------------------------------------------------------- */
 
-/* Picks c lateral slices of A by col_kind (TP_P_USER with col_w, a device
- * array of n2 float64 weights; TP_P_UNIFORM; TP_P_NORM2; TP_P_LEV, lateral
- * leverage of the rank-r t-SVD estimated as in tp_tsvd_rand with p = 10,
- * q = 1), forms Chat_k = Ahat_k S D, then picks l horizontal slices by
- * row_kind (TP_P_USER with row_w, n1 weights; TP_P_UNIFORM; TP_P_NORM2 of
- * A's horizontal slices; TP_P_LEV, horizontal leverage of C from its top-r
- * left singular slices) and returns
+/* Picks c lateral slices of A by col_kind and col_mode (TP_P_USER with
+ * col_w, a device array of n2 float64 weights; TP_P_UNIFORM; TP_P_NORM2;
+ * TP_P_LEV, lateral leverage of the rank-r t-SVD estimated as in
+ * tp_tsvd_rand with p = 10, q = 1; TP_P_LEARNED with mlp), forms
+ * Chat_k = Ahat_k S D, then picks l horizontal slices by row_kind and
+ * row_mode (TP_P_USER with row_w, n1 weights; TP_P_UNIFORM; TP_P_NORM2 of A's
+ * horizontal slices; TP_P_LEV, horizontal leverage of C from its top-r left
+ * singular slices) and returns
  *     Z = ifft(Chat_k pinv_r(D S^T Chat_k) D S^T Ahat_k)
  * where pinv_r keeps the r leading singular values of every Fourier slice
  * of the core (and drops those <= max(l, c) eps sigma_1); the core is
  * computed in float64 by a range finder with 10 extra columns and 2 power
- * iterations. Column picks use stream 0, row picks stream 1 of `seed`.
+ * iterations. A TP_S_UNIFORM mode takes TP_P_UNIFORM only. The remark after
+ * Corollary cor:gnys-main (lateral slices uniformly without replacement,
+ * then horizontal leverage of those slices) is col_kind = TP_P_UNIFORM,
+ * col_mode = TP_S_UNIFORM, row_kind = TP_P_LEV with row_mode TP_S_IID or
+ * TP_S_BERNOULLI. Column picks use stream 0, row picks stream 1 of `seed`.
  * cols/rows receive the picks (capacity >= c and l, or n2 and n1 for
- * TP_S_BERNOULLI). Z (same shape and dtype as A) may be NULL to only draw
- * the picks. r <= min(c, l), r + 10 <= 64. */
-int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, const double* col_w, int row_kind,
-            const double* row_w, int mode, uint64_t seed, tp_sample* cols, tp_sample* rows, tp_tensor* Z, int prec,
-            void* ws, size_t ws_bytes, void* stream);
-size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind, int mode,
-                         int prec);
+ * TP_S_BERNOULLI). core (may be NULL): the core Uhat_k = pinv_r(D S^T Chat_k)
+ * of every non-redundant Fourier slice, a float64 spectrum of K x c x l
+ * (n2 or n1 in place of c or l for Bernoulli picks; rows past the live pick
+ * counts are zero). Z (same shape and dtype as A) may be NULL. With both
+ * NULL only the picks are drawn. r <= min(c, l), r + 10 <= 64; mlp is read
+ * for TP_P_LEARNED only (float32 data, n3 divisible by 4). */
+int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, const double* col_w, int col_mode,
+            int row_kind, const double* row_w, int row_mode, const tp_mlp* mlp, uint64_t seed, tp_sample* cols,
+            tp_sample* rows, tp_spectrum* core, tp_tensor* Z, int prec, void* ws, size_t ws_bytes, void* stream);
+size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, int col_mode,
+                         int row_kind, int row_mode, int prec);
 
 /* ---------------------------------------------------------------------------
  * Singular value thresholding, completion, robust PCA and CUR t-NN
@@ -390,14 +434,15 @@ size_t tp_trpca_workspace(const tp_tensor* X);
  * values, mask is tube-major uint8 of X's shape, nonzero where observed) and
  * lambda is ignored; mask == NULL: robust PCA (eq. tlow7) with weight
  * lambda > 0 (0: 1/sqrt(max(n1, n2) n3) of X), the same for C and R; both
- * ADMM runs take exactly `iters` iterations. mode TP_S_IID or TP_S_UNIFORM (exactly
- * c and l picks); 1 <= r <= min(c, l), r + 10 <= 64; float32 data, prec
+ * ADMM runs take exactly `iters` iterations. col_mode and row_mode are
+ * TP_S_IID or TP_S_UNIFORM (exactly c and l picks; TP_S_UNIFORM with
+ * TP_P_UNIFORM); 1 <= r <= min(c, l), r + 10 <= 64; float32 data, prec
  * TP_PREC_F32. L (float32, X's shape) is overwritten. Workspace:
  * tp_tcur_nn_workspace(X, c, l, r, col_kind, row_kind, mask != NULL). */
 int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c, int64_t l, int64_t r, int col_kind,
-               const double* col_w, int row_kind, const double* row_w, int mode, uint64_t seed, int32_t iters,
-               double rho, double mu0, double mu_max, tp_sample* cols, tp_sample* rows, tp_tensor* L, int prec,
-               void* ws, size_t ws_bytes, void* stream);
+               const double* col_w, int col_mode, int row_kind, const double* row_w, int row_mode, uint64_t seed,
+               int32_t iters, double rho, double mu0, double mu_max, tp_sample* cols, tp_sample* rows, tp_tensor* L,
+               int prec, void* ws, size_t ws_bytes, void* stream);
 size_t tp_tcur_nn_workspace(const tp_tensor* X, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind,
                             int masked);
 

@@ -7,7 +7,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtprod.so
 TP_F32, TP_F64 = 0, 1
 TP_ENOCONV = -6
 PREC = {"f64": 0, "f32": 1, "bf16x3": 2, "bf16": 3}
-KIND = {"user": 0, "uniform": 1, "norm2": 2, "normprod": 3, "lev": 4}
+KIND = {"user": 0, "uniform": 1, "norm2": 2, "normprod": 3, "lev": 4, "learned": 5}
 MODE = {"bernoulli": 0, "iid": 1, "uniform": 2}
 
 
@@ -19,6 +19,10 @@ class Tensor(C.Structure):
 class Spectrum(C.Structure):
     _fields_ = [("re", C.c_void_p), ("im", C.c_void_p), ("dtype", C.c_int32), ("K", C.c_int64),
                 ("rows", C.c_int64), ("cols", C.c_int64)]
+
+
+class Mlp(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("phi", C.c_void_p), ("alpha", C.c_double)]
 
 
 class Sample(C.Structure):
@@ -45,14 +49,15 @@ _SIGS = {
     "tp_tprod": (C.c_int, [P(Tensor), P(Tensor), P(Sample), P(Tensor), C.c_int, C.c_void_p, C.c_size_t,
                            C.c_void_p]),
     "tp_tprod_workspace": (C.c_size_t, [P(Tensor), P(Tensor), P(Sample), C.c_int]),
-    "tp_tsvd_rand": (C.c_int, [P(Tensor), C.c_int64, C.c_int64, C.c_int32, C.c_uint64, C.c_int, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
-    "tp_tsvd_rand_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int]),
-    "tp_tcur": (C.c_int, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
-                          C.c_int, C.c_uint64, P(Sample), P(Sample), P(Tensor), C.c_int, C.c_void_p, C.c_size_t,
-                          C.c_void_p]),
+    "tp_tsvd_rand": (C.c_int, [P(Tensor), C.c_int64, C.c_int64, C.c_int32, P(Sample), C.c_uint64, C.c_int,
+                               C.c_void_p, P(Tensor), P(Tensor), P(Tensor), C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_size_t, C.c_void_p]),
+    "tp_tsvd_rand_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, P(Sample), C.c_int]),
+    "tp_tcur": (C.c_int, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int, C.c_int,
+                          C.c_void_p, C.c_int, P(Mlp), C.c_uint64, P(Sample), P(Sample), P(Spectrum), P(Tensor),
+                          C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tcur_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
-                                       C.c_int]),
+                                       C.c_int, C.c_int]),
     "tp_tsvt": (C.c_int, [P(Tensor), C.c_double, P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
                           C.c_void_p]),
     "tp_tsvt_workspace": (C.c_size_t, [P(Tensor)]),
@@ -72,7 +77,7 @@ _SIGS = {
                            C.c_void_p]),
     "tp_trpca_workspace": (C.c_size_t, [P(Tensor)]),
     "tp_tcur_nn": (C.c_int, [P(Tensor), C.c_void_p, C.c_double, C.c_int64, C.c_int64, C.c_int64, C.c_int,
-                             C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_uint64, C.c_int32, C.c_double,
+                             C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_uint64, C.c_int32, C.c_double,
                              C.c_double, C.c_double, P(Sample), P(Sample), P(Tensor), C.c_int, C.c_void_p,
                              C.c_size_t, C.c_void_p]),
     "tp_tcur_nn_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int]),

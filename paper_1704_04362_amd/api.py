@@ -185,24 +185,47 @@ def tprod(A, B, picks=None, prec=None, out=None):
     return C_
 
 
-def tsvd_rand(A, r, p=10, q=1, seed=0, prec=None):
+def tsvd_rand(A, r, p=10, q=1, seed=0, prec=None, picks=None):
     """Leading-r t-SVD summary by the randomized range finder: returns
     (S, lev_lateral, lev_horizontal) with S the K x r singular values of the
-    Fourier slices and the unnormalised tubal leverage scores (float64)."""
+    Fourier slices and the unnormalised tubal leverage scores (float64).
+    picks (lateral slices of A, e.g. from tsample) replace the Gaussian
+    sketch by the t-CX basis."""
+    S, _, _, _, lat, hor = _tsvd_rand(A, r, p, q, seed, prec, picks, scores=True)
+    return S, lat, hor
+
+
+def tsvd_rand_factors(A, r, p=10, q=1, seed=0, prec=None, picks=None):
+    """The randomized tubal-rank-r t-SVD as tensors: returns (U, S, V, Z)
+    with U (n1 x r x n3) and V (n2 x r x n3) the first r left and right
+    singular slices, S their K x r singular values and Z = U * S * V^T the
+    rank-r approximation (see tp_tsvd_rand)."""
+    S, U, V, Z, _, _ = _tsvd_rand(A, r, p, q, seed, prec, picks, factors=True)
+    return U, S, V, Z
+
+
+def _tsvd_rand(A, r, p, q, seed, prec, picks, scores=False, factors=False):
     _need_gpu(A)
     if prec is None:
         prec = "f64" if A.dtype == torch.float64 else "f32"
     n1, n2, n3 = A.shape
     K = half_count(n3)
     S = torch.empty((K, r), dtype=torch.float64, device=A.device)
-    lat = torch.empty(n2, dtype=torch.float64, device=A.device)
-    hor = torch.empty(n1, dtype=torch.float64, device=A.device)
+    lat = torch.empty(n2, dtype=torch.float64, device=A.device) if scores else None
+    hor = torch.empty(n1, dtype=torch.float64, device=A.device) if scores else None
+    U = torch.empty((n1, r, n3), dtype=A.dtype, device=A.device) if factors else None
+    V = torch.empty((n2, r, n3), dtype=A.dtype, device=A.device) if factors else None
+    Z = torch.empty_like(A) if factors else None
     lib = L.load()
     t = _tensor(A)
-    ws = _ws(lib.tp_tsvd_rand_workspace(C.byref(t), r, p, L.PREC[prec]), A.device)
-    L.check(lib.tp_tsvd_rand(C.byref(t), int(r), int(p), int(q), int(seed), L.PREC[prec], S.data_ptr(),
-                             lat.data_ptr(), hor.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
-    return S, lat, hor
+    ps = picks.struct() if picks is not None else None
+    sp = C.byref(ps) if ps is not None else None
+    ws = _ws(lib.tp_tsvd_rand_workspace(C.byref(t), r, p, sp, L.PREC[prec]), A.device)
+    opt = lambda x: C.byref(_tensor(x)) if x is not None else None  # noqa: E731
+    ptr = lambda x: x.data_ptr() if x is not None else None  # noqa: E731
+    L.check(lib.tp_tsvd_rand(C.byref(t), int(r), int(p), int(q), sp, int(seed), L.PREC[prec], S.data_ptr(), opt(U),
+                             opt(V), opt(Z), ptr(lat), ptr(hor), ws.data_ptr(), ws.numel(), _stream()))
+    return S, U, V, Z, lat, hor
 
 
 def tproject(X, Cs, prec=None, out=None):
@@ -240,29 +263,46 @@ def tcx(A, c, rounds=1, r=1, col_kind="norm2", col_w=None, mode="iid", seed=0, p
 
 
 def tcur(A, c, l, r, col_kind="lev", row_kind="lev", col_w=None, row_w=None, mode="iid", seed=0, prec=None,
-         want_z=True, out=None):
-    """t-CUR of Algorithm 5: returns (Z, column picks, row picks); Z is None
-    when want_z is False."""
+         want_z=True, out=None, row_mode=None, mlp=None, want_core=False):
+    """t-CUR of Algorithm 5: returns (Z, column picks, row picks), plus the
+    float64 core (re, im), each K x c x l, when want_core. Z is None when
+    want_z is False. mode picks the columns, row_mode (default: mode) the
+    rows; "uniform" modes take the "uniform" kind. mlp = (params, phi,
+    alpha) for col_kind "learned"."""
     _need_gpu(A, col_w, row_w)
     if prec is None:
         prec = "f64" if A.dtype == torch.float64 else "f32"
+    row_mode = mode if row_mode is None else row_mode
     n1, n2, n3 = A.shape
-    cols = Picks(n2 if mode == "bernoulli" else c, A.device)
-    rows = Picks(n1 if mode == "bernoulli" else l, A.device)
-    Z = None
-    if want_z:
-        Z = _out(out, A.shape, A.dtype, A.device)
+    capc = n2 if mode == "bernoulli" else c
+    capl = n1 if row_mode == "bernoulli" else l
+    cols = Picks(capc, A.device)
+    rows = Picks(capl, A.device)
+    Z = _out(out, A.shape, A.dtype, A.device) if want_z else None
+    core = None
+    if want_core:
+        core = (torch.empty((half_count(n3), capc, capl), dtype=torch.float64, device=A.device),
+                torch.empty((half_count(n3), capc, capl), dtype=torch.float64, device=A.device))
+    m = None
+    if mlp is not None:
+        params, phi, alpha = mlp
+        _need_gpu(params, phi)
+        m = L.Mlp(params.data_ptr(), phi.data_ptr(), float(alpha))
     lib = L.load()
     t = _tensor(A)
     tz = _tensor(Z) if Z is not None else None
+    tc = _spectrum(*core) if core is not None else None
     cs, rs_ = cols.struct(), rows.struct()
-    ws = _ws(lib.tp_tcur_workspace(C.byref(t), c, l, r, L.KIND[col_kind], L.KIND[row_kind], L.MODE[mode],
-                                   L.PREC[prec]), A.device)
+    ws = _ws(lib.tp_tcur_workspace(C.byref(t), c, l, r, L.KIND[col_kind], L.MODE[mode], L.KIND[row_kind],
+                                   L.MODE[row_mode], L.PREC[prec]), A.device)
     L.check(lib.tp_tcur(C.byref(t), int(c), int(l), int(r), L.KIND[col_kind],
-                        col_w.data_ptr() if col_w is not None else None, L.KIND[row_kind],
-                        row_w.data_ptr() if row_w is not None else None, L.MODE[mode], int(seed), C.byref(cs),
-                        C.byref(rs_), C.byref(tz) if tz is not None else None, L.PREC[prec], ws.data_ptr(),
-                        ws.numel(), _stream()))
+                        col_w.data_ptr() if col_w is not None else None, L.MODE[mode], L.KIND[row_kind],
+                        row_w.data_ptr() if row_w is not None else None, L.MODE[row_mode],
+                        C.byref(m) if m is not None else None, int(seed), C.byref(cs), C.byref(rs_),
+                        C.byref(tc) if tc is not None else None, C.byref(tz) if tz is not None else None,
+                        L.PREC[prec], ws.data_ptr(), ws.numel(), _stream()))
+    if want_core:
+        return Z, cols, rows, core
     return Z, cols, rows
 
 
@@ -347,7 +387,7 @@ def trpca(X, lam=None, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, tol=0.0, info=
 
 
 def tcur_nn(X, c, l, r, mask=None, lam=None, col_kind="uniform", row_kind="uniform", col_w=None, row_w=None,
-            mode="uniform", seed=0, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, out=None):
+            mode="uniform", seed=0, iters=100, rho=1.1, mu0=1e-3, mu_max=1e10, out=None, row_mode=None):
     """CUR t-NN of Algorithm 6: returns (L, column picks, row picks). With a
     uint8 mask (nonzero where observed) the ADMM is the completion variant,
     otherwise robust PCA with weight lam (None: the library's default
@@ -365,9 +405,10 @@ def tcur_nn(X, c, l, r, mask=None, lam=None, col_kind="uniform", row_kind="unifo
     cs, rs_ = cols.struct(), rows.struct()
     ws = _ws(lib.tp_tcur_nn_workspace(C.byref(tx), int(c), int(l), int(r), L.KIND[col_kind], L.KIND[row_kind],
                                       1 if mask is not None else 0), X.device)
+    row_mode = mode if row_mode is None else row_mode
     L.check(lib.tp_tcur_nn(C.byref(tx), mask.data_ptr() if mask is not None else None, float(lam), int(c), int(l),
-                           int(r), L.KIND[col_kind], col_w.data_ptr() if col_w is not None else None,
-                           L.KIND[row_kind], row_w.data_ptr() if row_w is not None else None, L.MODE[mode],
+                           int(r), L.KIND[col_kind], col_w.data_ptr() if col_w is not None else None, L.MODE[mode],
+                           L.KIND[row_kind], row_w.data_ptr() if row_w is not None else None, L.MODE[row_mode],
                            int(seed), int(iters), float(rho), float(mu0), float(mu_max), C.byref(cs), C.byref(rs_),
                            C.byref(_tensor(L_)), L.PREC["f32"], ws.data_ptr(), ws.numel(), _stream()))
     return L_, cols, rows

@@ -118,8 +118,15 @@ struct RangeFinder {
   int run(const Spec& X, int q, uint64_t seed, uint64_t stream_id, int prec, hipStream_t st,
           const int64_t* ncols_dev = nullptr) {
     if (int rc = randn_spectrum(omega.re, omega.im, dtype, K, n, s, real_last, seed, stream_id, st)) return rc;
-    // Y = X Omega, Q = orth(orth(Y))
+    // Y = X Omega
     if (int rc = mm(X, 0, m, n, omega, 0, n, s, Y, K, real_last, dtype, prec, st, ncols_dev)) return rc;
+    return finish(X, q, prec, st, ncols_dev);
+  }
+
+  // The rest of the range finder from a sketch already in Y (m x s): the
+  // Gaussian one of run(), or picked columns of X (the t-CX basis).
+  int finish(const Spec& X, int q, int prec, hipStream_t st, const int64_t* ncols_dev = nullptr) {
+    // Q = orth(orth(Y))
     if (int rc = orth(Y, m, Q, prec, st)) return rc;
     if (int rc = orth(Q, m, Y, prec, st)) return rc;
     std::swap(Q, Y);
@@ -170,27 +177,52 @@ int sketch_size(int64_t r, int64_t p, int64_t m, int64_t n) {
   return (int)s;
 }
 
+// A probability kind and a pick mode that go together. Uniform picks
+// without replacement use no weights, so they take TP_P_UNIFORM only
+// (another kind would be computed and then ignored); the learned proposal
+// exists for lateral slices (columns) only.
+int check_pick_rule(int kind, int mode, bool columns) {
+  if (mode != TP_S_BERNOULLI && mode != TP_S_IID && mode != TP_S_UNIFORM) return fail(TP_EINVAL, "unknown mode");
+  const bool known = kind == TP_P_USER || kind == TP_P_UNIFORM || kind == TP_P_NORM2 || kind == TP_P_LEV ||
+                     (columns && kind == TP_P_LEARNED);
+  if (!known) return fail(TP_EINVAL, "unsupported probability kind");
+  if (mode == TP_S_UNIFORM && kind != TP_P_UNIFORM)
+    return fail(TP_EINVAL, "TP_S_UNIFORM picks use no weights: pass TP_P_UNIFORM");
+  return TP_OK;
+}
+
 // Every buffer of one tp_tsvd_rand call, carved in a fixed order so that the
 // workspace query (dry run) and the call agree.
 struct TsvdLayout {
-  Spec Ah, Ub, Vs, Us;
+  Spec Ah, Ub, Vs, Us, Ubs, Vsc;
   RangeFinder rf;
   double* lpart = nullptr;
   bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int s, int64_t r, int dt, bool real_last) {
-    Ah = take(ar, K * n1 * n2, dt);
+    Ah = take(ar, K * n1 * n2, dt);  // the spectrum of A, later that of A_r
     lpart = ar.take<double>(K * std::max(n1, n2));
     rf = RangeFinder{K, n1, n2, s, dt, real_last};
     rf.carve(ar);
     Ub = take(ar, K * s * r, dt);
     Vs = take(ar, K * n2 * r, dt);
     Us = take(ar, K * n1 * r, dt);
+    Ubs = take(ar, K * s * r, dt);
+    Vsc = take(ar, K * n2 * r, dt);
     return ar.dry() || ar.ok();
   }
 };
 
+// Sketch width of tp_tsvd_rand: r + p (rounded as sketch_size does), or the
+// capacity of the picked slices when the basis comes from them.
+int tsvd_sketch(const tp_tensor* A, int64_t r, int64_t p, const tp_sample* slices) {
+  if (slices) return (int)std::min<int64_t>(slices->cap, int64_t(1) << 30);
+  return sketch_size(r, p, A->n1, A->n2);
+}
+
 struct TcurLayout {
   double *wbuf = nullptr, *wbuf2 = nullptr, *part = nullptr, *lpart = nullptr;
   void* sws = nullptr;
+  void* mlpws = nullptr;  // learned column proposal (TP_P_LEARNED)
+  size_t mlp_bytes = 0;
   Spec Ah, UbA, Vs;          // column leverage
   RangeFinder rfA, rfC, cf;  // range finders on A, C and the core
   Spec Ch, UbC, Us;          // C and its row leverage
@@ -204,6 +236,11 @@ struct TcurLayout {
     sws = ar.take<char>(sampler_ws(nmax));
     part = ar.take<double>(lateral_norms_ws(n1, n2, n3) / 8 + 1);
     lpart = ar.take<double>(K * nmax);
+    if (col_kind == TP_P_LEARNED) {
+      tp_tensor a{nullptr, dt, n1, n2, n3};
+      mlp_bytes = tp_mlp_proposal_workspace(&a);
+      mlpws = ar.take<char>(mlp_bytes);
+    }
     if (col_kind == TP_P_LEV) {
       sA = sketch_size(r, kOversample, n1, n2);
       Ah = take(ar, K * n1 * n2, dt);
@@ -281,7 +318,7 @@ int row_leverage(TcurLayout& lay, int dt, int64_t n1, int64_t K, int64_t r, uint
 // Zhat_k = (Chat_k P_k)(U_r,k^H Rhat_k) and Z = ifft(Zhat).
 int cur_core(TcurLayout& lay, int64_t n1, int64_t n2, int64_t n3, int64_t K, int64_t capc, int64_t capl, int64_t r,
              const int32_t* ridx, const double* rscale, const int64_t* rcount, uint64_t seed, int dt, int prec,
-             bool real_last, void* Z, hipStream_t st) {
+             bool real_last, void* Z, const tp_spectrum* core, hipStream_t st) {
   const int sw = lay.sw;
   if (int rc = gather_rows(lay.Ch.re, lay.Ch.im, dt, K, n1, capc, ridx, rscale, rcount, capl, lay.W.re, lay.W.im,
                            TP_F64, st))
@@ -328,6 +365,14 @@ int cur_core(TcurLayout& lay, int64_t n1, int64_t n2, int64_t n3, int64_t K, int
       Uw = lay.Ur;
     }
   }
+  if (core) {
+    // Uhat_k = pinv_r(W_k) = P_k U_r,k^H (c x l, float64)
+    Spec out;
+    out.re = core->re;
+    out.im = core->im;
+    if (int rc = mm(lay.P64, 0, capc, r, lay.U64, 1, capl, r, out, K, real_last, TP_F64, TP_PREC_F64, st)) return rc;
+  }
+  if (!Z) return TP_OK;
   // Zhat_k = Chat_k Uhat_k Rhat_k = (Chat_k P_k) (U_r,k^H Rhat_k), then ifft
   if (int rc = mm(lay.Ch, 0, n1, capc, Pw, 0, capc, r, lay.F, K, real_last, dt, prec, st)) return rc;
   if (int rc = mm(Uw, 1, capl, r, lay.Rh, 0, capl, n2, lay.G, K, real_last, dt, prec, st)) return rc;
@@ -407,27 +452,42 @@ using namespace tp;
 
 extern "C" {
 
-size_t tp_tsvd_rand_workspace(const tp_tensor* A, int64_t r, int64_t p, int prec) {
+size_t tp_tsvd_rand_workspace(const tp_tensor* A, int64_t r, int64_t p, const tp_sample* slices, int prec) {
   (void)prec;
   if (!A || A->n1 < 1 || A->n2 < 1 || A->n3 < 1 || r < 1) return 0;
   const int64_t K = half_count(A->n3);
+  const int s = tsvd_sketch(A, r, p, slices);
+  if (s < 1 || s > kMaxS) return 0;
   Arena dry(nullptr, SIZE_MAX);
   TsvdLayout lay;
-  lay.carve(dry, K, A->n1, A->n2, sketch_size(r, p, A->n1, A->n2), r, A->dtype, (A->n3 % 2 == 0) && K > 1);
+  lay.carve(dry, K, A->n1, A->n2, s, r, A->dtype, (A->n3 % 2 == 0) && K > 1);
   return dry.used + 256;
 }
 
-int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, uint64_t seed, int prec, double* S_out,
-                 double* lev_lateral, double* lev_horizontal, void* ws, size_t ws_bytes, void* stream) {
+int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, const tp_sample* slices, uint64_t seed,
+                 int prec, double* S_out, tp_tensor* U, tp_tensor* V, tp_tensor* Z, double* lev_lateral,
+                 double* lev_horizontal, void* ws, size_t ws_bytes, void* stream) {
   if (int rc = check_tensor(A, "A")) return rc;
   if (int rc = check_prec(A->dtype, prec)) return rc;
-  if (r < 1 || r > std::min(A->n1, A->n2)) return fail(TP_EINVAL, "need 1 <= r <= min(n1, n2)");
-  if (p < 0 || q < 0) return fail(TP_EINVAL, "oversampling and power iterations must be >= 0");
-  const int s = sketch_size(r, p, A->n1, A->n2);
-  if (s > kMaxS) return fail(TP_EUNSUPPORTED, "r + p above 64");
-  const size_t need = tp_tsvd_rand_workspace(A, r, p, prec);
-  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tsvd_rand workspace too small");
   const int64_t n1 = A->n1, n2 = A->n2, n3 = A->n3, K = half_count(n3);
+  if (r < 1 || r > std::min(n1, n2)) return fail(TP_EINVAL, "need 1 <= r <= min(n1, n2)");
+  if (p < 0 || q < 0) return fail(TP_EINVAL, "oversampling and power iterations must be >= 0");
+  if (slices) {
+    if (!slices->idx || !slices->scale || !slices->count) return fail(TP_EINVAL, "slices: null idx/scale/count");
+    if (slices->cap < r || slices->cap > n2) return fail(TP_EINVAL, "slices: need r <= capacity <= n2");
+  }
+  const int s = tsvd_sketch(A, r, p, slices);
+  if (s > kMaxS) return fail(TP_EUNSUPPORTED, slices ? "more than 64 picked slices" : "r + p above 64");
+  struct Out {
+    tp_tensor* t;
+    int64_t a, b;
+    const char* name;
+  } outs[3] = {{U, n1, r, "U must be n1 x r x n3"}, {V, n2, r, "V must be n2 x r x n3"}, {Z, n1, n2, "Z must match A"}};
+  for (const Out& o : outs)
+    if (o.t && (o.t->dtype != A->dtype || o.t->n1 != o.a || o.t->n2 != o.b || o.t->n3 != n3 || !o.t->data))
+      return fail(TP_ESHAPE, o.name);
+  const size_t need = tp_tsvd_rand_workspace(A, r, p, slices, prec);
+  if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tsvd_rand workspace too small");
   const bool real_last = (n3 % 2 == 0) && K > 1;
   const int dt = A->dtype;
   hipStream_t st = S(stream);
@@ -442,37 +502,67 @@ int tp_tsvd_rand(const tp_tensor* A, int64_t r, int64_t p, int32_t q, uint64_t s
   g.cols = n2;
   g.in_cols = n2;
   if (int rc = fft_forward(A->data, dt, n3, g, Ah.re, Ah.im, st)) return rc;
-  if (int rc = rf.run(Ah, q, seed, kStreamOmegaA, prec, st)) return rc;
+  if (slices) {
+    // the basis of the picked lateral slices (t-CX, Definition t-CX and
+    // Algorithm 4): Y_k = Chat_k = Ahat_k S D, transformed from the
+    // picked tubes (zero columns past the live count)
+    TubeGather gc;
+    gc.rows = n1;
+    gc.cols = s;
+    gc.in_cols = n2;
+    gc.col_idx = slices->idx;
+    gc.col_scale = slices->scale;
+    gc.count = slices->count;
+    if (int rc = fft_forward(A->data, dt, n3, gc, rf.Y.re, rf.Y.im, st)) return rc;
+    if (int rc = rf.finish(Ah, q, prec, st)) return rc;
+  } else if (int rc = rf.run(Ah, q, seed, kStreamOmegaA, prec, st)) {
+    return rc;
+  }
   const double rtol = dt == TP_F64 ? 1e-12 : 1e-6;
   if (S_out)
     if (int rc = singular_values(rf.evals, K, s, (int)r, S_out, st)) return rc;
   // U_B restricted to the leading r eigenvectors
   if (int rc = eig_transform(rf.ure, rf.uim, rf.evals, K, s, (int)r, 1, rtol, 0.0, Ub.re, Ub.im, dt, st)) return rc;
-  if (lev_lateral) {
-    // right singular vectors V = Bh U_B diag(sigma)^-1: rows scaled inside the
-    // leverage reduction
+  if (lev_lateral || Z) {
+    // V Sigma = Bh U_B: the right singular vectors up to their scales
     if (int rc = mm(rf.Bh, 0, n2, s, Ub, 0, s, r, Vs, K, real_last, dt, prec, st)) return rc;
+  }
+  if (lev_lateral)
     if (int rc = leverage(Vs.re, Vs.im, dt, K, n2, r, n2 * r, (int)r, real_last, rf.evals, s, rtol, lay.lpart,
                           lev_lateral, st))
       return rc;
-  }
-  if (lev_horizontal) {
+  if (lev_horizontal || U || Z) {
     // left singular vectors U = Q U_B
     if (int rc = mm(rf.Q, 0, n1, s, Ub, 0, s, r, Us, K, real_last, dt, prec, st)) return rc;
+  }
+  if (lev_horizontal)
     if (int rc = leverage(Us.re, Us.im, dt, K, n1, r, n1 * r, (int)r, real_last, nullptr, s, rtol, lay.lpart,
                           lev_horizontal, st))
       return rc;
+  if (U)
+    if (int rc = fft_inverse(Us.re, Us.im, dt, n3, n1, r, U->data, st)) return rc;
+  if (V) {
+    // V = Bh U_B diag(1 / sigma)
+    if (int rc = eig_transform(rf.ure, rf.uim, rf.evals, K, s, (int)r, 1, rtol, 1.0, lay.Ubs.re, lay.Ubs.im, dt, st))
+      return rc;
+    if (int rc = mm(rf.Bh, 0, n2, s, lay.Ubs, 0, s, r, lay.Vsc, K, real_last, dt, prec, st)) return rc;
+    if (int rc = fft_inverse(lay.Vsc.re, lay.Vsc.im, dt, n3, n2, r, V->data, st)) return rc;
+  }
+  if (Z) {
+    // A_r: Zhat_k = U_k (V_k Sigma_k)^H, into the buffer of A's spectrum
+    if (int rc = mm(Us, 0, n1, r, Vs, 1, n2, r, Ah, K, real_last, dt, prec, st)) return rc;
+    if (int rc = fft_inverse(Ah.re, Ah.im, dt, n3, n1, n2, Z->data, st)) return rc;
   }
   return TP_OK;
 }
 
-size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind, int mode,
-                         int prec) {
+size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, int col_mode,
+                         int row_kind, int row_mode, int prec) {
   (void)prec;
   if (!A || A->n1 < 1 || A->n2 < 1 || A->n3 < 1 || r < 1 || c < 1 || l < 1) return 0;
   const int64_t K = half_count(A->n3);
-  const int64_t capc = mode == TP_S_BERNOULLI ? A->n2 : c;
-  const int64_t capl = mode == TP_S_BERNOULLI ? A->n1 : l;
+  const int64_t capc = col_mode == TP_S_BERNOULLI ? A->n2 : c;
+  const int64_t capl = row_mode == TP_S_BERNOULLI ? A->n1 : l;
   Arena dry(nullptr, SIZE_MAX);
   TcurLayout lay;
   lay.carve(dry, K, A->n1, A->n2, A->n3, capc, capl, r, col_kind, row_kind, true, A->dtype,
@@ -480,32 +570,39 @@ size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, in
   return dry.used + 256;
 }
 
-int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, const double* col_w, int row_kind,
-            const double* row_w, int mode, uint64_t seed, tp_sample* cols, tp_sample* rows, tp_tensor* Z, int prec,
-            void* ws, size_t ws_bytes, void* stream) {
+int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, const double* col_w, int col_mode,
+            int row_kind, const double* row_w, int row_mode, const tp_mlp* mlp, uint64_t seed, tp_sample* cols,
+            tp_sample* rows, tp_spectrum* core, tp_tensor* Z, int prec, void* ws, size_t ws_bytes, void* stream) {
   if (int rc = check_tensor(A, "A")) return rc;
   if (int rc = check_prec(A->dtype, prec)) return rc;
   const int64_t n1 = A->n1, n2 = A->n2, n3 = A->n3, K = half_count(n3);
   if (c < 1 || c > n2) return fail(TP_EINVAL, "need 1 <= c <= n2");
   if (l < 1 || l > n1) return fail(TP_EINVAL, "need 1 <= l <= n1");
   if (r < 1 || r > std::min(c, l)) return fail(TP_EINVAL, "need 1 <= r <= min(c, l)");
-  if (mode != TP_S_BERNOULLI && mode != TP_S_IID && mode != TP_S_UNIFORM) return fail(TP_EINVAL, "unknown mode");
-  auto kind_ok = [](int k) { return k == TP_P_USER || k == TP_P_UNIFORM || k == TP_P_NORM2 || k == TP_P_LEV; };
-  if (!kind_ok(col_kind) || !kind_ok(row_kind)) return fail(TP_EINVAL, "unsupported probability kind");
+  if (int rc = check_pick_rule(col_kind, col_mode, true)) return rc;
+  if (int rc = check_pick_rule(row_kind, row_mode, false)) return rc;
   if (col_kind == TP_P_USER && !col_w) return fail(TP_EINVAL, "column weights are null");
   if (row_kind == TP_P_USER && !row_w) return fail(TP_EINVAL, "row weights are null");
+  if (col_kind == TP_P_LEARNED && (!mlp || !mlp->params || !mlp->phi))
+    return fail(TP_EINVAL, "TP_P_LEARNED needs the network parameters and Phi");
+  if (col_kind == TP_P_LEARNED && (A->dtype != TP_F32 || n3 % 4 != 0))
+    return fail(TP_EUNSUPPORTED, "the learned proposal needs float32 data with n3 divisible by 4");
   if (!cols || !rows || !cols->idx || !cols->scale || !cols->count || !rows->idx || !rows->scale || !rows->count)
     return fail(TP_EINVAL, "pick buffers are null");
-  const int64_t capc = mode == TP_S_BERNOULLI ? n2 : c;
-  const int64_t capl = mode == TP_S_BERNOULLI ? n1 : l;
+  const int64_t capc = col_mode == TP_S_BERNOULLI ? n2 : c;
+  const int64_t capl = row_mode == TP_S_BERNOULLI ? n1 : l;
   if (cols->cap < capc || rows->cap < capl)
     return fail(TP_EINVAL, "pick capacity must be >= c, l (or n2, n1 for Bernoulli picks)");
   if (Z) {
     if (Z->dtype != A->dtype || Z->n1 != n1 || Z->n2 != n2 || Z->n3 != n3 || !Z->data)
       return fail(TP_ESHAPE, "Z must match A");
   }
+  if (core) {
+    if (core->dtype != TP_F64 || core->K != K || core->rows != capc || core->cols != capl || !core->re || !core->im)
+      return fail(TP_ESHAPE, "core must be a float64 spectrum of K x c x l (n2, n1 for Bernoulli picks)");
+  }
   if (sketch_size(r, kOversample, n1, n2) > kMaxS) return fail(TP_EUNSUPPORTED, "r + 10 above 64");
-  const size_t need = tp_tcur_workspace(A, c, l, r, col_kind, row_kind, mode, prec);
+  const size_t need = tp_tcur_workspace(A, c, l, r, col_kind, col_mode, row_kind, row_mode, prec);
   if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tcur workspace too small");
 
   const int dt = A->dtype;
@@ -513,13 +610,14 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
   hipStream_t st = S(stream);
   Arena ar(ws, ws_bytes);
   TcurLayout lay;
-  if (!lay.carve(ar, K, n1, n2, n3, capc, capl, r, col_kind, row_kind, Z != nullptr, dt, real_last))
+  if (!lay.carve(ar, K, n1, n2, n3, capc, capl, r, col_kind, row_kind, Z != nullptr || core != nullptr, dt,
+                 real_last))
     return fail(TP_EWORKSPACE, "tcur workspace too small");
   const double rtol = dt == TP_F64 ? 1e-12 : 1e-6;
 
   // 1. column probabilities and picks (Algorithm 5 takes C as an input; it is
-  //    drawn here as in Algorithm 4, by lateral leverage, norms, uniformly or
-  //    from caller weights)
+  //    drawn here as in Algorithm 4, by lateral leverage, norms, the learned
+  //    proposal, uniformly or from caller weights)
   const double* wcol = col_w;
   if (col_kind == TP_P_LEV) {
     if (int rc = col_leverage(lay, A->data, dt, n1, n2, n3, K, r, seed, prec, real_last, rtol, st)) return rc;
@@ -527,12 +625,16 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
   } else if (col_kind == TP_P_NORM2) {
     if (int rc = lateral_norms(A->data, dt, n1, n2, n3, lay.wbuf, lay.part, st)) return rc;
     wcol = lay.wbuf;
+  } else if (col_kind == TP_P_LEARNED) {
+    if (int rc = tp_mlp_proposal(mlp->params, A, mlp->phi, mlp->alpha, lay.wbuf, lay.mlpws, lay.mlp_bytes, stream))
+      return rc;
+    wcol = lay.wbuf;
   } else if (col_kind == TP_P_UNIFORM) {
     if (int rc = fill_f64(lay.wbuf, n2, 1.0, st)) return rc;
     wcol = lay.wbuf;
   }
-  if (int rc = sample_slices(wcol, n2, c, mode, seed, kStreamColPick, cols->idx, cols->scale, cols->count, lay.sws,
-                             st))
+  if (int rc = sample_slices(wcol, n2, c, col_mode, seed, kStreamColPick, cols->idx, cols->scale, cols->count,
+                             lay.sws, st))
     return rc;
 
   // 2. Chat_k = Ahat_k S D: the picked lateral slices, scaled, transformed once
@@ -560,10 +662,10 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
     if (int rc = fill_f64(lay.wbuf2, n1, 1.0, st)) return rc;
     wrow = lay.wbuf2;
   }
-  if (int rc = sample_slices(wrow, n1, l, mode, seed, kStreamRowPick, rows->idx, rows->scale, rows->count, lay.sws,
-                             st))
+  if (int rc = sample_slices(wrow, n1, l, row_mode, seed, kStreamRowPick, rows->idx, rows->scale, rows->count,
+                             lay.sws, st))
     return rc;
-  if (!Z) return TP_OK;
+  if (!Z && !core) return TP_OK;
 
   // 4. Rhat_k = D S^T Ahat_k
   {
@@ -579,7 +681,7 @@ int tp_tcur(const tp_tensor* A, int64_t c, int64_t l, int64_t r, int col_kind, c
 
   // 5-6. core Uhat_k = pinv_r(D S^T Chat_k) and Z = ifft(Chat_k Uhat_k Rhat_k)
   return cur_core(lay, n1, n2, n3, K, capc, capl, r, rows->idx, rows->scale, rows->count, seed, dt, prec, real_last,
-                  Z->data, st);
+                  Z ? Z->data : nullptr, core, st);
 }
 
 size_t tp_tcur_nn_workspace(const tp_tensor* X, int64_t c, int64_t l, int64_t r, int col_kind, int row_kind,
@@ -595,9 +697,9 @@ size_t tp_tcur_nn_workspace(const tp_tensor* X, int64_t c, int64_t l, int64_t r,
 }
 
 int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c, int64_t l, int64_t r, int col_kind,
-               const double* col_w, int row_kind, const double* row_w, int mode, uint64_t seed, int32_t iters,
-               double rho, double mu0, double mu_max, tp_sample* cols, tp_sample* rows, tp_tensor* L, int prec,
-               void* ws, size_t ws_bytes, void* stream) {
+               const double* col_w, int col_mode, int row_kind, const double* row_w, int row_mode, uint64_t seed,
+               int32_t iters, double rho, double mu0, double mu_max, tp_sample* cols, tp_sample* rows, tp_tensor* L,
+               int prec, void* ws, size_t ws_bytes, void* stream) {
   if (int rc = check_tensor(X, "X")) return rc;
   if (int rc = check_tensor(L, "L")) return rc;
   if (X->dtype != TP_F32 || L->dtype != TP_F32) return fail(TP_EDTYPE, "CUR t-NN runs on float32 data");
@@ -607,10 +709,11 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
   if (c < 1 || c > n2) return fail(TP_EINVAL, "need 1 <= c <= n2");
   if (l < 1 || l > n1) return fail(TP_EINVAL, "need 1 <= l <= n1");
   if (r < 1 || r > std::min(c, l)) return fail(TP_EINVAL, "need 1 <= r <= min(c, l)");
-  if (mode != TP_S_IID && mode != TP_S_UNIFORM)
+  if ((col_mode != TP_S_IID && col_mode != TP_S_UNIFORM) || (row_mode != TP_S_IID && row_mode != TP_S_UNIFORM))
     return fail(TP_EINVAL, "CUR t-NN needs exactly c and l picks (TP_S_IID or TP_S_UNIFORM)");
-  auto kind_ok = [](int k) { return k == TP_P_USER || k == TP_P_UNIFORM || k == TP_P_NORM2 || k == TP_P_LEV; };
-  if (!kind_ok(col_kind) || !kind_ok(row_kind)) return fail(TP_EINVAL, "unsupported probability kind");
+  if (col_kind == TP_P_LEARNED) return fail(TP_EINVAL, "CUR t-NN takes learned weights as TP_P_USER");
+  if (int rc = check_pick_rule(col_kind, col_mode, false)) return rc;
+  if (int rc = check_pick_rule(row_kind, row_mode, false)) return rc;
   if (col_kind == TP_P_USER && !col_w) return fail(TP_EINVAL, "column weights are null");
   if (row_kind == TP_P_USER && !row_w) return fail(TP_EINVAL, "row weights are null");
   if (!mask && lambda == 0.0) lambda = rpca_default_lambda(X->n1, X->n2, X->n3);
@@ -650,8 +753,8 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
     if (int rc = fill_f64(lay.wbuf, n2, 1.0, st)) return rc;
     wcol = lay.wbuf;
   }
-  if (int rc = sample_slices(wcol, n2, c, mode, seed, kStreamColPick, cols->idx, cols->scale, cols->count, lay.sws,
-                             st))
+  if (int rc = sample_slices(wcol, n2, c, col_mode, seed, kStreamColPick, cols->idx, cols->scale, cols->count,
+                             lay.sws, st))
     return rc;
   if (int rc = gather_slices(X->data, 4, n2, n3, nullptr, cols->idx, cols->count, n1, c, nn.cx, st)) return rc;
   if (mask)
@@ -682,7 +785,7 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
     if (int rc = fill_f64(lay.wbuf2, n1, 1.0, st)) return rc;
     wrow = lay.wbuf2;
   }
-  if (int rc = sample_slices(wrow, n1, l, mode, seed, kStreamRowPick, rows->idx, rows->scale, rows->count, lay.sws,
+  if (int rc = sample_slices(wrow, n1, l, row_mode, seed, kStreamRowPick, rows->idx, rows->scale, rows->count, lay.sws,
                              st))
     return rc;
   if (int rc = gather_slices(X->data, 4, n2, n3, rows->idx, nullptr, rows->count, l, n2, nn.rx, st)) return rc;
@@ -703,7 +806,7 @@ int tp_tcur_nn(const tp_tensor* X, const uint8_t* mask, double lambda, int64_t c
 
   // 5. W = the picked rows of Ct (unscaled), U = pinv_r(W), L = Ct * U * Rt
   return cur_core(lay, n1, n2, n3, K, c, l, r, rows->idx, nullptr, rows->count, seed, dt, prec, real_last, L->data,
-                  st);
+                  nullptr, st);
 }
 
 size_t tp_tproject_workspace(const tp_tensor* X, const tp_tensor* C, int prec) {
@@ -781,8 +884,7 @@ int tp_tcx(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r, int col_kin
   if (c * rounds > kMaxS) return fail(TP_EUNSUPPORTED, "more than 64 picked slices over all rounds");
   if (mode != TP_S_IID && mode != TP_S_UNIFORM)
     return fail(TP_EINVAL, "t-CX rounds need exactly c picks (TP_S_IID or TP_S_UNIFORM)");
-  if (col_kind != TP_P_USER && col_kind != TP_P_UNIFORM && col_kind != TP_P_NORM2 && col_kind != TP_P_LEV)
-    return fail(TP_EINVAL, "unsupported probability kind");
+  if (int rc = check_pick_rule(col_kind, mode, false)) return rc;
   if (col_kind == TP_P_USER && !col_w) return fail(TP_EINVAL, "column weights are null");
   if (col_kind == TP_P_LEV && (r < 1 || r > std::min(n1, n2) || sketch_size(r, kOversample, n1, n2) > kMaxS))
     return fail(TP_EINVAL, "leverage needs 1 <= r <= min(n1, n2) and r + 10 <= 64");

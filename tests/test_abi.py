@@ -192,8 +192,8 @@ def test_tcur_nn_validation(case):
         want = -3
     else:
         lam = -1.0
-    rc = lib.tp_tcur_nn(C.byref(X), None, lam, 8, 6, r, L.KIND["uniform"], None, L.KIND["uniform"], None, mode, 0,
-                        10, 1.1, 1e-3, 1e10, C.byref(cols), C.byref(rows), C.byref(Lt), L.PREC["f32"],
+    rc = lib.tp_tcur_nn(C.byref(X), None, lam, 8, 6, r, L.KIND["uniform"], None, mode, L.KIND["uniform"], None,
+                        mode, 0, 10, 1.1, 1e-3, 1e10, C.byref(cols), C.byref(rows), C.byref(Lt), L.PREC["f32"],
                         C.c_void_p(0x2000), 1 << 30, None)
     assert rc == want
 
@@ -306,3 +306,68 @@ def test_tsample_noalloc_rejects_sizes_beyond_its_scratch():
     # bad arguments get tp_tsample's own errors
     assert lib.tp_tsample_noalloc(L.KIND["uniform"], None, None, None, 10, 11, L.MODE["iid"], 0, 0, C.byref(out),
                                   None) == -1
+
+
+@pytest.mark.parametrize("case", ["uniform_with_weights", "row_uniform_with_lev", "learned_rows", "learned_no_mlp",
+                                  "core_shape", "core_dtype", "ok_ws"])
+def test_tcur_validation(case):
+    # uniform picks without replacement use no weights: any other kind is
+    # refused instead of computed and ignored; the learned kind is for
+    # columns and needs its network; the core output has the picks' shape
+    lib = L.load()
+    A, Z = _t(40, 50, 8), _t(40, 50, 8)
+    cols = L.Sample(0x3000, 0x4000, 12, 0x5000)
+    rows = L.Sample(0x6000, 0x7000, 10, 0x8000)
+    K = 5
+    ck, cm, rk, rm, mlp, want, wsb = L.KIND["uniform"], L.MODE["uniform"], L.KIND["lev"], L.MODE["iid"], None, -1, 16
+    core = None
+    if case == "uniform_with_weights":
+        ck = L.KIND["norm2"]
+    elif case == "row_uniform_with_lev":
+        rm = L.MODE["uniform"]
+    elif case == "learned_rows":
+        rk = L.KIND["learned"]
+    elif case == "learned_no_mlp":
+        ck, cm = L.KIND["learned"], L.MODE["iid"]
+    elif case == "core_shape":
+        core = L.Spectrum(0x9000, 0xa000, L.TP_F64, K, 12, 11)
+        want = -2
+    elif case == "core_dtype":
+        core = L.Spectrum(0x9000, 0xa000, L.TP_F32, K, 12, 10)
+        want = -2
+    else:
+        # the remark's procedure with a core of the right shape passes
+        # validation and stops at the workspace
+        core = L.Spectrum(0x9000, 0xa000, L.TP_F64, K, 12, 10)
+        want = -4
+    rc = lib.tp_tcur(C.byref(A), 12, 10, 3, ck, None, cm, rk, None, rm, mlp, 0, C.byref(cols), C.byref(rows),
+                     C.byref(core) if core is not None else None, C.byref(Z), L.PREC["f32"], C.c_void_p(0x2000), wsb,
+                     None)
+    assert rc == want, lib.tp_last_error()
+
+
+@pytest.mark.parametrize("case", ["u_shape", "z_shape", "v_dtype", "slices_cap", "slices_big", "ok_ws"])
+def test_tsvd_rand_validation(case):
+    lib = L.load()
+    A = _t(40, 90, 8)
+    U, V, Z = _t(40, 4, 8), _t(90, 4, 8), _t(40, 90, 8)
+    sl = None
+    want, wsb = -2, 16
+    if case == "u_shape":
+        U = _t(40, 5, 8)
+    elif case == "z_shape":
+        Z = _t(40, 90, 7)
+    elif case == "v_dtype":
+        V = _t(90, 4, 8, dtype=L.TP_F64)
+    elif case == "slices_cap":
+        sl = L.Sample(0x3000, 0x4000, 3, 0x5000)
+        want = -1
+    elif case == "slices_big":
+        sl = L.Sample(0x3000, 0x4000, 70, 0x5000)
+        want = -7
+    else:
+        sl = L.Sample(0x3000, 0x4000, 12, 0x5000)
+        want = -4
+    rc = lib.tp_tsvd_rand(C.byref(A), 4, 10, 1, C.byref(sl) if sl is not None else None, 0, L.PREC["f32"], None,
+                          C.byref(U), C.byref(V), C.byref(Z), None, None, C.c_void_p(0x2000), wsb, None)
+    assert rc == want, lib.tp_last_error()

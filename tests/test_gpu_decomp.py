@@ -116,8 +116,13 @@ def test_tcur_with_user_picks_matches_oracle(dtype, prec, tol, mode):
     A, _ = lowrank(n1, n2, n3, r, noise_var=1e-3, salt=3)
     A = A.astype(dtype)
     wc, wr = _user_weights(n2, 1), _user_weights(n1, 2)
-    Z, cols, rows = api.tcur(dev(A), c, l, r, col_kind="user", row_kind="user", col_w=dev(wc), row_w=dev(wr),
-                             mode=mode, seed=9, prec=prec)
+    if mode == "uniform":
+        # uniform picks without replacement use no weights (the uniform kind)
+        Z, cols, rows = api.tcur(dev(A), c, l, r, col_kind="uniform", row_kind="uniform", mode=mode, seed=9,
+                                 prec=prec)
+    else:
+        Z, cols, rows = api.tcur(dev(A), c, l, r, col_kind="user", row_kind="user", col_w=dev(wc), row_w=dev(wr),
+                                 mode=mode, seed=9, prec=prec)
     ci, cs = S.sample(wc, c, mode, seed=9, stream=0)
     ri, rsc = S.sample(wr, l, mode, seed=9, stream=1)
     gi, gs = cols.host()
@@ -216,3 +221,111 @@ def test_tcur_full_size_sampled_tubes():
     ii, jj = rs.integers(0, n1, 64), rs.integers(0, n2, 64)
     ref = D.tcur_tubes(Csl, Rsl, cs, ri, rsc, r, ii, jj)
     assert rel(Zs[ii, jj, :], ref) < 5e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tcur_core_matches_oracle(prec):
+    # the exported core Uhat_k = pinv_r(D S^T Chat_k) of every Fourier slice
+    n1, n2, n3, r, c, l = 60, 70, 7, 4, 18, 16
+    A, _ = lowrank(n1, n2, n3, r, noise_var=1e-3, salt=41)
+    A = A.astype(np.float64 if prec == "f64" else np.float32)
+    wc, wr = _user_weights(n2, 42), _user_weights(n1, 43)
+    Z, cols, rows, (cre, cim) = api.tcur(dev(A), c, l, r, col_kind="user", row_kind="user", col_w=dev(wc),
+                                         row_w=dev(wr), mode="iid", seed=3, prec=prec, want_core=True)
+    ci, cs = S.sample_iid(wc, c, seed=3, stream=0)
+    ri, rsc = S.sample_iid(wr, l, seed=3, stream=1)
+    Zr, core_r = D.tcur(A.astype(np.float64), ci, cs, ri, rsc, r=r)
+    core = cre.cpu().numpy() + 1j * cim.cpu().numpy()
+    assert core.shape == core_r.shape
+    crel = np.linalg.norm((core - core_r).ravel()) / np.linalg.norm(core_r.ravel())
+    assert crel < (1e-7 if prec == "f64" else 1e-4)
+    assert rel(Z.cpu().numpy(), Zr) < (1e-9 if prec == "f64" else 1e-5)
+    # the core alone, without Z
+    Z2, _, _, (cre2, cim2) = api.tcur(dev(A), c, l, r, col_kind="user", row_kind="user", col_w=dev(wc),
+                                      row_w=dev(wr), mode="iid", seed=3, prec=prec, want_z=False, want_core=True)
+    assert Z2 is None
+    np.testing.assert_array_equal(cre2.cpu().numpy(), cre.cpu().numpy())
+
+
+@pytest.mark.parametrize("row_mode", ["iid", "bernoulli"])
+def test_tcur_approximate_leverage_procedure(row_mode):
+    # the remark after Corollary cor:gnys-main: lateral slices uniformly
+    # without replacement, then horizontal leverage computed from them; the
+    # column picks are the oracle's bit for bit, the row picks those of the
+    # oracle's horizontal leverage of the same C (exact rank, float64: the
+    # scores agree to ~1e-10, far from any bin edge)
+    n1, n2, n3, r, c, l = 64, 80, 8, 4, 16, 14
+    A, _ = lowrank(n1, n2, n3, r, salt=44)
+    Z, cols, rows = api.tcur(dev(A), c, l, r, col_kind="uniform", row_kind="lev", mode="uniform", row_mode=row_mode,
+                             seed=17, prec="f64")
+    ci, cs = S.sample_uniform_norepl(n2, c, seed=17, stream=0)
+    gi, gs = cols.host()
+    np.testing.assert_array_equal(gi.numpy(), ci)
+    np.testing.assert_array_equal(gs.numpy(), cs)
+    C = A[:, ci, :] * cs[None, :, None]
+    ri, rsc = S.sample(S.weights_horizontal_leverage(C, r), l, row_mode, seed=17, stream=1)
+    hi, hs = rows.host()
+    np.testing.assert_array_equal(hi.numpy(), ri)
+    np.testing.assert_allclose(hs.numpy(), rsc, rtol=1e-9)
+    Zr, _ = D.tcur(A, ci, cs, ri, rsc, r=r)
+    assert rel(Z.cpu().numpy(), Zr) < 1e-9
+    assert rel(Z.cpu().numpy(), A) < 1e-9
+
+
+def test_tcur_learned_kind_equals_its_weights():
+    # TP_P_LEARNED computes the proposal inside the call: the same picks and
+    # Z as passing tp_mlp_proposal's weights as TP_P_USER
+    from paper_1704_04362_amd import learned as LP
+    n1, n2, n3, r = 48, 64, 8, 3
+    A, _ = lowrank(n1, n2, n3, r, noise_var=1e-4, salt=45)
+    A = dev(A.astype(np.float32))
+    net = LP.Trainer()
+    phi = LP.sketch_matrix(n1, n3, seed=5)
+    w = api.mlp_proposal(net.params, A, phi, alpha=0.1)
+    Z1, c1, r1 = api.tcur(A, 16, 12, r, col_kind="learned", row_kind="lev", mlp=(net.params, phi, 0.1), seed=6,
+                          prec="f32")
+    Z2, c2, r2 = api.tcur(A, 16, 12, r, col_kind="user", col_w=w, row_kind="lev", seed=6, prec="f32")
+    np.testing.assert_array_equal(c1.host()[0].numpy(), c2.host()[0].numpy())
+    np.testing.assert_array_equal(r1.host()[0].numpy(), r2.host()[0].numpy())
+    np.testing.assert_array_equal(Z1.cpu().numpy(), Z2.cpu().numpy())
+
+
+@pytest.mark.parametrize("dtype,prec,tol", [(np.float64, "f64", 1e-7), (np.float32, "f32", 2e-5)])
+def test_tsvd_rand_rank_r_approximation(dtype, prec, tol):
+    # tubal rank 5 plus noise of variance 1e-10: a gap after the 5th singular
+    # value of every Fourier slice, so the leading subspaces, the truncation
+    # A_r = U * S * V^T and the singular values are unique; the range finder
+    # (p = 10, q = 1) captures them to the noise level
+    n1, n2, n3, r = 70, 60, 8, 5
+    G1, G2, N = W.lowrank_factors(n1, n2, n3, r, noise_var=1e-10, salt=46, dtype=np.float64)
+    A = T.tprod_fft(G1, G2) + N
+    U, Sv, V, Z = api.tsvd_rand_factors(dev(A.astype(dtype)), r, prec=prec)
+    Ur, Sr, Vr, svr = T.tsvd(A, r)
+    Ar = T.tprod_fft(T.tprod_fft(Ur, Sr), T.ttranspose(Vr))
+    Z, U, V = (x.cpu().numpy().astype(np.float64) for x in (Z, U, V))
+    assert rel(Z, Ar) < tol
+    np.testing.assert_allclose(Sv.cpu().numpy(), svr[:, :r], rtol=tol)
+    # t-orthonormal factors and the projectors onto the leading subspaces
+    assert rel(T.tprod_fft(T.ttranspose(U), U), T.teye(r, n3)) < tol
+    assert rel(T.tprod_fft(T.ttranspose(V), V), T.teye(r, n3)) < tol
+    P, Pr = T.tprod_fft(U, T.ttranspose(U)), T.tprod_fft(Ur, T.ttranspose(Ur))
+    assert rel(P, Pr) < 10 * tol
+    Q, Qr = T.tprod_fft(V, T.ttranspose(V)), T.tprod_fft(Vr, T.ttranspose(Vr))
+    assert rel(Q, Qr) < 10 * tol
+
+
+@pytest.mark.parametrize("r", [12, 5])
+def test_tsvd_rand_slices_basis_is_tcx(r):
+    # with the picked lateral slices as the basis and no power iteration the
+    # result is the t-CX projection C C^+ A (Algorithm 4), truncated to
+    # tubal rank r
+    n1, n2, n3, c = 50, 66, 6, 12
+    A, _ = lowrank(n1, n2, n3, 7, noise_var=1e-3, salt=47)
+    Ad = dev(A)
+    picks = api.tsample("uniform", c, mode="uniform", seed=8, n=n2)
+    idx, sc = picks.host()
+    U, Sv, V, Z = api.tsvd_rand_factors(Ad, r, q=0, picks=picks, prec="f64")
+    Zx = D.tcx(A, idx.numpy(), sc.numpy())
+    Ux, Sx, Vx, _ = T.tsvd(Zx, r)
+    want = T.tprod_fft(T.tprod_fft(Ux, Sx), T.ttranspose(Vx))
+    assert rel(Z.cpu().numpy(), want) < 1e-9
