@@ -279,13 +279,19 @@ size_t tp_tsvd_rand_workspace(const tp_tensor* A, int64_t r, int64_t p, const tp
 
 /* Z = C * C^+ * X (Algorithm 3): every Fourier slice of X projected onto the
  * range of the matching slice of C, as Q_k (Q_k^H Xhat_k) with Q_k an
- * orthonormal basis of the columns of Chat_k from CholeskyQR applied twice
- * (a Cholesky pivot at or below 1e-7 (float32) or 1e-13 (float64) of the
- * largest drops its column: repeated or dependent slices project onto the
- * numerical range, and float32 columns below ~3e-4 of the largest singular
- * value of their slice are treated as dependent). X n1 x n2 x n3, C n1 x c x n3 with c <= 64, Z like X; one dtype;
- * prec TP_PREC_F64 (float64) or TP_PREC_F32 / TP_PREC_BF16X3 (float32).
- * Workspace: tp_tproject_workspace(X, C, prec) bytes. */
+ * orthonormal basis of the columns of Chat_k:
+ *   c <= 64: CholeskyQR applied twice; a Cholesky pivot at or below 1e-7
+ *            (float32) or 1e-13 (float64) of the largest drops its column,
+ *            so repeated or dependent slices project onto the numerical
+ *            range (float32 columns below ~3e-4 of the largest singular
+ *            value of their slice are treated as dependent);
+ *   c > 64:  float32 data with c <= min(n1, 4096): the left singular
+ *            vectors of Chat_k from the block one-sided Jacobi on the rows of
+ *            Chat_k^H (no squared condition number), keeping singular values
+ *            above max(n1, c) eps_32 of the largest.
+ * X n1 x n2 x n3, C n1 x c x n3, Z like X; one dtype; prec TP_PREC_F64
+ * (float64) or TP_PREC_F32 / TP_PREC_BF16X3 (float32). Workspace:
+ * tp_tproject_workspace(X, C, prec) bytes. */
 int tp_tproject(const tp_tensor* X, const tp_tensor* C, tp_tensor* Z, int prec, void* ws, size_t ws_bytes,
                 void* stream);
 size_t tp_tproject_workspace(const tp_tensor* X, const tp_tensor* C, int prec);
@@ -299,8 +305,10 @@ size_t tp_tproject_workspace(const tp_tensor* X, const tp_tensor* C, int prec);
  * worse than any single round, which is how repetition boosts the success
  * probability of the relative-error bound. cols receives the picks round
  * after round (capacity >= c * rounds; *count = c * rounds, or -1 when the
- * weights are rejected, in which case Z is zero). c * rounds <= 64; r is
- * used by TP_P_LEV only (r + 10 <= 64). Workspace:
+ * weights are rejected, in which case Z is zero). The projection is that of
+ * tp_tproject with c * rounds columns (more than 64: float32 data and
+ * c * rounds <= min(n1, 4096)); r is used by TP_P_LEV only (r + 10 <= 64).
+ * Workspace:
  * tp_tcx_workspace(A, c, rounds, r, col_kind, prec) bytes. */
 int tp_tcx(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r, int col_kind, const double* col_w, int mode,
            uint64_t seed, tp_sample* cols, tp_tensor* Z, int prec, void* ws, size_t ws_bytes, void* stream);

@@ -256,6 +256,32 @@ def tcur_tubes(Csl, Rsl, cscale, ridx, rscale, r, ii, jj):
     return T._real_part_checked(np.fft.ifft(Zh, axis=1))
 
 
+def tproject_tubes(C, Xcols, jcols, ii, jj):
+    """Selected tubes Z[ii[e], jj[e], :] of Algorithm 3's projection
+    Z = C * C^+ * X, from C (n1 x c x n3) and the lateral slices of X that
+    the tubes need: Xcols[:, t, :] = X[:, jcols[t], :], jj[e] in jcols. Per
+    Fourier slice, Zhat_k[i, j] = (Chat_k Chat_k^+)[i, :] Xhat_k[:, j]; the
+    tube is the inverse transform of Zhat[i, j, :]."""
+    C = np.asarray(C, dtype=np.float64)
+    Xcols = np.asarray(Xcols, dtype=np.float64)
+    n3 = C.shape[2]
+    pos = {int(j): t for t, j in enumerate(np.asarray(jcols, dtype=np.int64))}
+    ii = np.asarray(ii, dtype=np.int64)
+    tt = np.array([pos[int(j)] for j in np.asarray(jj, dtype=np.int64)], dtype=np.int64)
+    K = T.half_spectrum_count(n3)
+    Hc = T.half_spectrum(C)  # (K, n1, c)
+    Hx = T.half_spectrum(Xcols)  # (K, n1, t)
+    Zh = np.zeros((len(ii), n3), dtype=complex)
+    for k in range(K):
+        Ck = Hc[k].real if _is_real_slice(k, n3) else Hc[k]
+        Xk = Hx[k].real if _is_real_slice(k, n3) else Hx[k]
+        Pi = Ck[ii, :] @ np.linalg.pinv(Ck)  # rows ii of the projector
+        Zh[:, k] = np.einsum("en,ne->e", Pi, Xk[:, tt])
+    for k in range(K, n3):
+        Zh[:, k] = Zh[:, n3 - k].conj()
+    return T._real_part_checked(np.fft.ifft(Zh, axis=1))
+
+
 def soft_threshold(V, t):
     """Entrywise shrinkage sign(v) max(|v| - t, 0): the minimiser over E of
     t ||E||_1 + 1/2 ||E - V||_F^2 (the closed-form E-update of Algorithm 7)."""

@@ -229,8 +229,8 @@ def _tsvd_rand(A, r, p, q, seed, prec, picks, scores=False, factors=False):
 
 
 def tproject(X, Cs, prec=None, out=None):
-    """t-project of Algorithm 3: Z = C * C^+ * X (C has at most 64 lateral
-    slices)."""
+    """t-project of Algorithm 3: Z = C * C^+ * X (more than 64 lateral
+    slices in C: float32 data, see tp_tproject)."""
     _need_gpu(X, Cs)
     if prec is None:
         prec = "f64" if X.dtype == torch.float64 else "f32"

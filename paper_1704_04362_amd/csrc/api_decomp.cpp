@@ -410,39 +410,92 @@ struct CurNNLayout {
 
 // Orthogonal projection of every Fourier slice of X onto the range of the
 // matching slice of C (Algorithm 3): Q_k = an orthonormal basis of the
-// columns of Chat_k (CholeskyQR applied twice), then
-// Zhat_k = Q_k (Q_k^H Xhat_k). Xh: K x n1 x n2, Ch: K x n1 x c (c <= 64).
-// A column whose Cholesky pivot falls to kProjPivot of the largest is
-// dropped (zero column), so repeated or dependent slices project onto the
-// numerical range: the Gram matrix is float64 in both cases, so dependent
-// columns leave pivots of ~1e-16 of the largest, and 1e-13 drops them; with
-// float32 columns, Q = C R^-1 is formed in float32 and CholeskyQR2 restores
-// orthogonality only up to a condition number of ~1/sqrt(eps_32), so
-// columns below ~3e-4 of the largest singular value (pivot 1e-7) are
-// dropped. (The range finder keeps its own, smaller thresholds: a spurious
-// direction in a sketch basis is harmless, in a projector it is not.)
+// columns of Chat_k, then Zhat_k = Q_k (Q_k^H Xhat_k). Xh: K x n1 x n2, Ch:
+// K x n1 x c.
+//  * c <= 64: CholeskyQR applied twice. A column whose Cholesky pivot falls
+//    to kProjPivot of the largest is dropped (zero column), so repeated or
+//    dependent slices project onto the numerical range: the Gram matrix is
+//    float64 in both cases, so dependent columns leave pivots of ~1e-16 of
+//    the largest, and 1e-13 drops them; with float32 columns, Q = C R^-1 is
+//    formed in float32 and CholeskyQR2 restores orthogonality only up to a
+//    condition number of ~1/sqrt(eps_32), so columns below ~3e-4 of the
+//    largest singular value (pivot 1e-7) are dropped. (The range finder
+//    keeps its own, smaller thresholds: a spurious direction in a sketch
+//    basis is harmless, in a projector it is not.)
+//  * c > 64 (float32, c <= n1): the block one-sided Jacobi of the
+//    thresholding on the rows of Chat_k^H (c rows of length n1) makes them
+//    sigma_i u_i^H, u_i the left singular vectors of Chat_k, without
+//    squaring the condition number; Q_k = [u_i] for sigma_i above the
+//    rounding residue of the rotations, max(n1, c) eps_32 of the largest,
+//    and zero columns for the others (directions closer to the residue are
+//    not resolved in float32 and would make the projector arbitrary there).
 constexpr double kProjPivot64 = 1e-13, kProjPivot32 = 1e-7;
+constexpr int64_t kProjJacobiMax = 4096;
+
+// Widths of C the projection handles: any up to 64; beyond, float32 data
+// with c <= n1 (more columns than rows span every slice they reach) and
+// c <= 4096 (the column selection keeps its norms in LDS).
+int check_proj_width(int64_t c, int64_t n1, int dtype) {
+  if (c <= kMaxS) return TP_OK;
+  if (dtype != TP_F32) return fail(TP_EUNSUPPORTED, "more than 64 lateral slices need float32 data");
+  if (c > n1) return fail(TP_EUNSUPPORTED, "more than 64 lateral slices need c <= n1");
+  if (c > kProjJacobiMax) return fail(TP_EUNSUPPORTED, "more than 4096 lateral slices");
+  return TP_OK;
+}
 struct ProjLayout {
-  RangeFinder rf;  // orthonormalisation workspace (m = n1, n = s = c)
+  RangeFinder rf;  // orthonormalisation workspace (m = n1, n = s = c), c <= 64
+  bool wide = false;
+  float *xre = nullptr, *xim = nullptr, *qre = nullptr, *qim = nullptr, *ure = nullptr, *uim = nullptr;
+  float* ratio = nullptr;
+  int* conv = nullptr;
   Spec G, Zh;
   bool carve(Arena& ar, int64_t K, int64_t n1, int64_t n2, int64_t c, int dt, bool real_last) {
-    rf = RangeFinder{K, n1, c, (int)c, dt, real_last};
-    rf.carve(ar);
+    wide = c > kMaxS;
+    if (!wide) {
+      rf = RangeFinder{K, n1, c, (int)c, dt, real_last};
+      rf.carve(ar);
+    } else {
+      rf = RangeFinder{K, n1, c, 0, dt, real_last};
+      xre = ar.take<float>(K * c * n1);
+      xim = ar.take<float>(K * c * n1);
+      qre = ar.take<float>(K * c * c);
+      qim = ar.take<float>(K * c * c);
+      ure = ar.take<float>(K * n1 * c);
+      uim = ar.take<float>(K * n1 * c);
+      ratio = ar.take<float>(svt_ratio_count(K, c));
+      conv = ar.take<int>(K);
+    }
     G = take(ar, K * c * n2, dt);
     Zh = take(ar, K * n1 * n2, dt);
     return ar.dry() || ar.ok();
   }
-  int run(const Spec& Xh, const Spec& Ch, int64_t n1, int64_t n2, int64_t n3, int prec, void* Z,
+  int run(const Spec& Xh, const Spec& Ch, int64_t n1, int64_t n2, int64_t n3, int64_t c, int prec, void* Z,
           hipStream_t st) {
-    const int64_t K = rf.K, c = rf.s;
+    const int64_t K = rf.K;
     const int dt = rf.dtype;
-    const double piv = dt == TP_F64 ? kProjPivot64 : kProjPivot32;
-    if (int rc = rf.orth(Ch, n1, rf.Q, prec, st, piv)) return rc;
-    if (int rc = rf.orth(rf.Q, n1, rf.Y, prec, st, piv)) return rc;
-    if (int rc = mm(rf.Y, 1, n1, c, Xh, 0, n1, n2, G, K, rf.real_last, dt, prec, st)) return rc;
-    if (int rc = mm(rf.Y, 0, n1, c, G, 0, c, n2, Zh, K, rf.real_last, dt, prec, st)) return rc;
+    Spec Q;
+    if (!wide) {
+      const double piv = dt == TP_F64 ? kProjPivot64 : kProjPivot32;
+      if (int rc = rf.orth(Ch, n1, rf.Q, prec, st, piv)) return rc;
+      if (int rc = rf.orth(rf.Q, n1, rf.Y, prec, st, piv)) return rc;
+      Q = rf.Y;
+    } else {
+      if (int rc = spec_conj_transpose((const float*)Ch.re, (const float*)Ch.im, K, n1, c, xre, xim, st)) return rc;
+      if (int rc = svt_identity(qre, qim, K, c, st)) return rc;
+      if (int rc = svt_jacobi(xre, xim, qre, qim, K, c, n1, rf.real_last, kProjSweeps, kProjTol, ratio, conv, st))
+        return rc;
+      const double cut = double(std::max(n1, c)) * 1.1920928955078125e-07;
+      if (int rc = tsvd_pick(xre, xim, n1, xre, xim, n1, K, c, c, rf.real_last, 2, false, cut, ure, uim, nullptr, st))
+        return rc;
+      Q.re = ure;
+      Q.im = uim;
+    }
+    if (int rc = mm(Q, 1, n1, c, Xh, 0, n1, n2, G, K, rf.real_last, dt, prec, st)) return rc;
+    if (int rc = mm(Q, 0, n1, c, G, 0, c, n2, Zh, K, rf.real_last, dt, prec, st)) return rc;
     return fft_inverse(Zh.re, Zh.im, dt, n3, n1, n2, Z, st);
   }
+  static constexpr int kProjSweeps = 30;
+  static constexpr double kProjTol = 1e-6;
 };
 
 }  // namespace
@@ -832,7 +885,7 @@ int tp_tproject(const tp_tensor* X, const tp_tensor* C, tp_tensor* Z, int prec, 
   if (C->dtype != X->dtype || Z->dtype != X->dtype) return fail(TP_EDTYPE, "X, C and Z must share a dtype");
   if (C->n1 != X->n1 || C->n3 != X->n3) return fail(TP_ESHAPE, "C must be n1 x c x n3 like X");
   if (Z->n1 != X->n1 || Z->n2 != X->n2 || Z->n3 != X->n3) return fail(TP_ESHAPE, "Z must match X");
-  if (C->n2 > kMaxS) return fail(TP_EUNSUPPORTED, "more than 64 lateral slices in C");
+  if (int rc = check_proj_width(C->n2, X->n1, X->dtype)) return rc;
   const size_t need = tp_tproject_workspace(X, C, prec);
   if (!ws || ws_bytes < need) return fail(TP_EWORKSPACE, "tproject workspace too small");
   const int64_t n1 = X->n1, n2 = X->n2, n3 = X->n3, c = C->n2, K = half_count(n3);
@@ -853,7 +906,7 @@ int tp_tproject(const tp_tensor* X, const tp_tensor* C, tp_tensor* Z, int prec, 
   gc.cols = c;
   gc.in_cols = c;
   if (int rc = fft_forward(C->data, dt, n3, gc, Ch.re, Ch.im, st)) return rc;
-  return lay.run(Xh, Ch, n1, n2, n3, prec, Z->data, st);
+  return lay.run(Xh, Ch, n1, n2, n3, c, prec, Z->data, st);
 }
 
 size_t tp_tcx_workspace(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r, int col_kind, int prec) {
@@ -881,7 +934,7 @@ int tp_tcx(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r, int col_kin
   if (Z->dtype != A->dtype || Z->n1 != n1 || Z->n2 != n2 || Z->n3 != n3) return fail(TP_ESHAPE, "Z must match A");
   if (c < 1 || c > n2) return fail(TP_EINVAL, "need 1 <= c <= n2");
   if (rounds < 1) return fail(TP_EINVAL, "need at least one round");
-  if (c * rounds > kMaxS) return fail(TP_EUNSUPPORTED, "more than 64 picked slices over all rounds");
+  if (int rc = check_proj_width(c * (int64_t)rounds, n1, A->dtype)) return rc;
   if (mode != TP_S_IID && mode != TP_S_UNIFORM)
     return fail(TP_EINVAL, "t-CX rounds need exactly c picks (TP_S_IID or TP_S_UNIFORM)");
   if (int rc = check_pick_rule(col_kind, mode, false)) return rc;
@@ -947,7 +1000,7 @@ int tp_tcx(const tp_tensor* A, int64_t c, int32_t rounds, int64_t r, int col_kin
     g.count = cols->count;
     if (int rc = fft_forward(A->data, dt, n3, g, cur.Ch.re, cur.Ch.im, st)) return rc;
   }
-  return lay.run(Ah, cur.Ch, n1, n2, n3, prec, Z->data, st);
+  return lay.run(Ah, cur.Ch, n1, n2, n3, cT, prec, Z->data, st);
 }
 
 }  // extern "C"

@@ -478,6 +478,21 @@ __global__ void admm_post_soft_kernel(const float* __restrict__ x, const float* 
   y[i] = yv + mu * (lv + ev - xv);
 }
 
+// out[k][j][i] = conj(in[k][i][j]): the conjugate transpose of every
+// Fourier slice (K x rows x cols planar in, K x cols x rows out). Reads are
+// coalesced along j; the writes are strided.
+__global__ void spec_conj_transpose_kernel(const float* __restrict__ re, const float* __restrict__ im, int64_t K,
+                                           int64_t rows, int64_t cols, float* __restrict__ ore,
+                                           float* __restrict__ oim) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = rows * cols;
+  if (e >= K * per) return;
+  const int64_t k = e / per, r = e - k * per, i = r / cols, j = r - i * cols;
+  const int64_t o = k * per + j * rows + i;
+  ore[o] = re[e];
+  oim[o] = -im[e];
+}
+
 // The three quantities of Algorithm 7's convergence check for one
 // iteration, reduced per workgroup: max |L - Lprev|, max |E - Eprev| and
 // max |L + E - X| over the workgroup's elements (E the new iterate, read
@@ -633,6 +648,15 @@ int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, flo
               float* y, hipStream_t st) {
   if (n == 0) return TP_OK;
   hipLaunchKernelGGL(admm_post_kernel, dim3(nblk(n)), dim3(256), 0, st, x, mask, l, mu, inv_mu, n, e, y);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int spec_conj_transpose(const float* re, const float* im, int64_t K, int64_t rows, int64_t cols, float* ore,
+                        float* oim, hipStream_t st) {
+  const int64_t n = K * rows * cols;
+  if (n == 0) return TP_OK;
+  hipLaunchKernelGGL(spec_conj_transpose_kernel, dim3(nblk(n)), dim3(256), 0, st, re, im, K, rows, cols, ore, oim);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

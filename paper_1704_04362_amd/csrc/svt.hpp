@@ -32,6 +32,10 @@ int tsvd_pick(const float* xre, const float* xim, int64_t ldx, const float* sre,
 int admm_pre(const float* x, const float* e, const float* y, float inv_mu, int64_t n, float* m, hipStream_t st);
 int admm_post(const float* x, const uint8_t* mask, const float* l, float mu, float inv_mu, int64_t n, float* e,
               float* y, hipStream_t st);
+// out_k = conj(in_k)^T for every Fourier slice of a float32 planar spectrum
+// (K x rows x cols in, K x cols x rows out).
+int spec_conj_transpose(const float* re, const float* im, int64_t K, int64_t rows, int64_t cols, float* ore,
+                        float* oim, hipStream_t st);
 // Algorithm 7's stop quantities max |L - Lprev|, max |E - Eprev|,
 // max |L + E - X| into out[0..2] (device), through admm_stop_floats(n) - 4
 // floats of per-workgroup partials in part.

@@ -372,3 +372,13 @@ def test_admm_stops_at_the_first_iteration_meeting_the_check(variant):
     np.testing.assert_array_equal(Y, Y2)
     # an unreachable tolerance runs the whole budget
     assert len(run(iters=7, tol=0.0)[3]) == 7
+
+
+def test_tproject_tubes_match_full_tproject():
+    X = rs.standard_normal((12, 9, 6)) + _lowrank(12, 9, 6, 2, seed=51)
+    C = X[:, [1, 4, 7], :] + 0.1 * rs.standard_normal((12, 3, 6))
+    Z = D.tproject(X, C)
+    jcols = np.array([8, 0, 3])
+    ii, jj = np.array([0, 5, 11, 7]), np.array([3, 8, 0, 3])
+    got = D.tproject_tubes(C, X[:, jcols, :], jcols, ii, jj)
+    np.testing.assert_allclose(got, Z[ii, jj, :], atol=1e-12)
