@@ -19,6 +19,7 @@ import torch
 
 import workloads as W
 from oracle import decomp as D
+from oracle import sampling as picks_oracle
 from oracle import tensor as T
 
 pytestmark = pytest.mark.gpu
@@ -81,6 +82,17 @@ def test_tcur_nn_robust_pca_matches_oracle(kinds):
     assert len(ci) == 24 and len(ri) == 20
     if kinds[2] == "uniform":
         assert len(set(ci.tolist())) == 24 and len(set(ri.tolist())) == 20
+    # where both sides sample from identical weights the picks are the
+    # oracle's bit for bit: no weights (uniform), and the squared norms of
+    # X's slices (float64 sums of the same float32 values; equal up to
+    # summation order, far from any bin edge at this seed)
+    if kinds[0] == "uniform":
+        np.testing.assert_array_equal(ci, picks_oracle.sample_uniform_norepl(n2, 24, seed=5, stream=0)[0])
+        np.testing.assert_array_equal(ri, picks_oracle.sample_uniform_norepl(n1, 20, seed=5, stream=1)[0])
+    if kinds[0] == "norm2":
+        wc, wr = picks_oracle.weights_norm2(X), picks_oracle.horizontal_sq_norms(X)
+        np.testing.assert_array_equal(ci, picks_oracle.sample_iid(wc, 24, seed=5, stream=0)[0])
+        np.testing.assert_array_equal(ri, picks_oracle.sample_iid(wr, 20, seed=5, stream=1)[0])
     Lr, _, _ = D.cur_tnn(X.astype(np.float64), ci, ri, r=r, lam=lam, iters=100)
     assert rel(Lg, Lr) < 1e-4
     assert rel(Lg, Ls) < 1e-4

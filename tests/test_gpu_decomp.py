@@ -11,8 +11,9 @@ Tolerances:
 * float32 inputs with noise: singular values 1e-4 relative, leverage
   1e-4 * max p (the range-finder error decays like
   (sigma_{r+p+1}/sigma_r)^(2q+1) and the float32 products add ~1e-6);
-* t-CUR given the same picks: 1e-9 (float64), 1e-5 (float32), 5e-5
-  (split bf16 products) relative Frobenius error; the core is float64 on
+* t-CUR given the same picks: 1e-9 (float64), 1e-5 (float32), 1.1e-5
+  (split bf16 products: twice the largest measured error, 5.2e-6, which is
+  the split product's own) relative Frobenius error; the core is float64 on
   both sides and the randomized top-r subspace equals the exact one up to
   the gap term above.
 """
@@ -109,7 +110,7 @@ def _user_weights(n, seed):
 
 
 @pytest.mark.parametrize("dtype,prec,tol", [(np.float64, "f64", 1e-9), (np.float32, "f32", 1e-5),
-                                            (np.float32, "bf16x3", 5e-5)])
+                                            (np.float32, "bf16x3", 1.1e-5)])
 @pytest.mark.parametrize("mode", ["iid", "bernoulli", "uniform"])
 def test_tcur_with_user_picks_matches_oracle(dtype, prec, tol, mode):
     n1, n2, n3, r, c, l = 72, 90, 8, 4, 24, 20
@@ -145,7 +146,7 @@ def test_tcur_exact_rank_reproduces_input(dtype, prec, tol):
 
 
 @pytest.mark.parametrize("dtype,prec,tol", [(np.float64, "f64", 1e-9), (np.float32, "f32", 1e-5),
-                                            (np.float32, "bf16x3", 5e-5)])
+                                            (np.float32, "bf16x3", 1.1e-5)])
 @pytest.mark.parametrize("c,l,n3", [(64, 60, 8), (60, 64, 7), (66, 60, 8), (40, 70, 5)])
 def test_tcur_core_paths_match_oracle(dtype, prec, tol, c, l, n3):
     """Cores with l, c <= 64 take the fused one-workgroup-per-slice
@@ -220,7 +221,7 @@ def test_tcur_full_size_sampled_tubes():
     rs = np.random.default_rng(0)
     ii, jj = rs.integers(0, n1, 64), rs.integers(0, n2, 64)
     ref = D.tcur_tubes(Csl, Rsl, cs, ri, rsc, r, ii, jj)
-    assert rel(Zs[ii, jj, :], ref) < 5e-5
+    assert rel(Zs[ii, jj, :], ref) < 1.1e-5
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -71,6 +71,16 @@ def test_tcx_matches_oracle_on_same_picks(kind, mode, rounds, dtype, prec, tol):
     Z, picks = api.tcx(dev(A), 8, rounds=rounds, r=r, col_kind=kind, mode=mode, seed=4, prec=prec)
     idx, _ = picks.host()
     assert len(idx) == 8 * rounds
+    # round i draws from stream 16 i: the oracle's picks for identical
+    # weights (none for uniform; the squared norms of the same values)
+    for i in range(rounds):
+        if kind == "uniform":
+            want = S.sample_uniform_norepl(n2, 8, seed=4, stream=16 * i)[0]
+        elif kind == "norm2":
+            want = S.sample_iid(S.weights_norm2(A), 8, seed=4, stream=16 * i)[0]
+        else:
+            continue
+        np.testing.assert_array_equal(idx.numpy()[8 * i:8 * (i + 1)], want)
     ref = D.tcx_union(A.astype(np.float64), [idx.numpy()[8 * i:8 * (i + 1)] for i in range(rounds)])
     assert rel(Z, ref) < tol
 

@@ -7,7 +7,10 @@ Tolerances (relative Frobenius error unless stated):
   sums).
 * float32 paths: transforms 2e-6 (eps_32 = 6e-8 times log2 n3 <= 7 times a
   safety factor of ~5); products 1e-5, the stated float32 bound for the
-  t-product.
+  t-product, and at the benchmark's full size twice the measured error:
+  3e-6 for the exact product (measured 1.3e-6 over a 2048-long
+  contraction), 2e-6 for the rt-product and the split contractions
+  (measured 7.6e-7 to 9.1e-7).
 * picks: bit-exact indices and scales given identical weights.
 """
 import numpy as np
@@ -159,7 +162,7 @@ def test_tprod_full_size_sampled_entries():
     rs = np.random.default_rng(11)
     ii, jj, kk = rs.integers(0, 512, 256), rs.integers(0, 512, 256), rs.integers(0, 64, 256)
     ref = T.tprod_entries(A, B, ii, jj, kk)
-    assert rel(Cg[ii, jj, kk], ref) < 1e-5
+    assert rel(Cg[ii, jj, kk], ref) < 3e-6
 
 
 @pytest.fixture(scope="module")
@@ -177,7 +180,7 @@ def full_rtprod_case():
     return A, B, ridx, rsc, (ii, jj, kk), T.tprod_entries(Cs, Rs, ii, jj, kk)
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("bf16x3", 1.3e-5)])
 def test_rtprod_full_size_sampled_entries(full_rtprod_case, prec, tol):
     A, B, ridx, rsc, (ii, jj, kk), ref = full_rtprod_case
     Ad = dev(A)
@@ -328,9 +331,11 @@ def test_rtprod_bernoulli_short_contraction():
 # Split-precision products: each float32 value is hi + lo in bf16 and the
 # lo*lo term is dropped, a relative error of at most ~2^-16 per product
 # (2^-8 for each of the two dropped parts); summed over random signs the
-# relative Frobenius error stays near 2^-17 ~ 8e-6. The stated bound is 5e-5.
-# Plain bf16 (hi*hi only) carries ~2^-8 per operand: 1e-2.
-BF_TOL = {"bf16x3": 5e-5, "bf16": 1e-2}
+# relative Frobenius error stays near 2^-17 ~ 8e-6. Measured on every test
+# here (MI355X): 3.8e-6 to 6.2e-6, independent of size; the bar is twice the
+# largest, 1.3e-5. Plain bf16 (hi*hi only) carries ~2^-8 per operand: 1e-2
+# (measured 2.3e-3 to 3.3e-3).
+BF_TOL = {"bf16x3": 1.3e-5, "bf16": 1e-2}
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
@@ -428,7 +433,7 @@ def test_trace_records_the_stages_of_a_call():
     assert api.trace_read() == {}
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x3", 5e-5), ("bf16", 1e-2), ("f32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1.3e-5), ("bf16", 1e-2), ("f32", 2e-6)])
 def test_tprod_split_contraction(prec, tol):
     """A product with three output tiles and a 40,000-long contraction
     (n3 = 5: transforms without the split-operand path) runs as contraction
@@ -443,7 +448,7 @@ def test_tprod_split_contraction(prec, tol):
     assert rel(Cg[ii, jj, kk], ref) < tol
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x3", 5e-5), ("f32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1.3e-5), ("f32", 2e-6)])
 def test_rtprod_split_contraction_with_device_count(prec, tol):
     # 3000 i.i.d. picks of 40,000 (two contraction parts, the pick count read
     # on the device)
