@@ -44,11 +44,34 @@ sys.path.insert(0, ROOT)
 
 N1, N2, N4, N3, C_PICK = 512, 2048, 512, 64, 256
 PEAK = {"hbm_GBs": 8000.0, "f32": 157.3, "bf16": 2516.6, "f64": 78.6}
-# HBM bytes per launch of the exact-product stages at this workload (bf16x3),
-# from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors of a plain
-# 512 MiB copy); recorded with profiles/tprod_512x2048x64_bf16x3_hbm_traffic.md.
-# Set an entry to None when its kernel changes.
-TRAFFIC = {"gemm": 758.2e6, "fft_a": 545.5e6, "fft_b": 545.5e6, "ifft": 134.4e6}
+# HBM bytes per launch of the product stages come from the committed
+# counter summary (rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by what they
+# read for a plain copy); it names the source file each figure was taken on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tprod_512x2048x64_hbm_traffic.md")
+
+
+def profiled_traffic():
+    """{stage: bytes per launch} from the counter summary's machine-readable
+    line, keeping only stages whose kernel source is unchanged since the
+    counters were taken (a changed kernel reads as unmeasured)."""
+    import hashlib
+    import re
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            m = re.search(r"<!-- traffic (\{.*?\}) -->", f.read(), flags=re.S)
+        rec = json.loads(m.group(1)) if m else {}
+    except OSError:
+        return {}
+    out = {}
+    for stage, ent in rec.items():
+        try:
+            with open(os.path.join(ROOT, ent["source"]), "rb") as f:
+                same = hashlib.sha256(f.read()).hexdigest()[:16] == ent["sha256"]
+        except OSError:
+            same = False
+        if same:
+            out[stage] = float(ent["bytes"])
+    return out
 
 
 def tprod_flops(n1, n2, n4, n3):
@@ -469,7 +492,7 @@ def time_events(fn, reps, torch):
     return e0.elapsed_time(e1) / reps  # ms
 
 
-def f32_exact_tprod(api, A, B, C, reps, torch):
+def f32_exact_tprod(api, A, B, C, reps, torch, traffic):
     """The same exact t-product in plain float32 arithmetic (TP_PREC_F32:
     float32 transforms and per-slice products on the float32 matrix cores),
     timed with HIP events, with its stages from the library trace and the
@@ -494,39 +517,110 @@ def f32_exact_tprod(api, A, B, C, reps, torch):
     if "gemm" in stages:
         ach = F / (stages["gemm"] * 1e-3) / 1e12
         out["gemm_roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["f32"], "unit": "TFLOP/s",
-                                "frac": round(ach / PEAK["f32"], 4),
+                                "frac": round(ach / PEAK["f32"], 4), "traffic": traffic.get("f32.gemm"),
                                 "kernel": "cgemm_f32_kernel (v_mfma_f32_16x16x4f32, complex slices as 3 real products)"}
     return out
 
 
-def cpu_baseline(A, B, budget_s):
-    """The float64 oracle's t-product by its definition (block-row sums of
-    eq. tprod), timed on a bounded sample: the first s frontal slices of C,
-    s grown until the budget is used; the rate is scaled to all n3 slices."""
+def _oracle_tprod_rate(A64, B64, budget_s):
+    """Seconds for output frontal slices 0..s-1 of the oracle t-product, s
+    grown until about budget_s is used; returns (s, seconds)."""
     from oracle import tensor as T
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
-    A64 = A.astype(np.float64)
-    B64 = B.astype(np.float64)
     t0 = time.perf_counter()
     T.tprod_slices(A64, B64, [0])
     t1 = time.perf_counter() - t0
     s = int(max(1, min(N3, budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     T.tprod_slices(A64, B64, list(range(s)))
+    return s, time.perf_counter() - t0
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def oracle_tcur_c3(n3_sample=8, c=60, r=20):
+    """The oracle's whole t-CUR pipeline (exact lateral leverage from its
+    t-SVD, i.i.d. column picks, horizontal leverage of C, row picks, then
+    Algorithm 5) on the rank-20 1024x1024 workload generated with n3_sample
+    frontal slices instead of 128; the per-Fourier-slice work dominates, so
+    the time is also scaled by the ratio of non-redundant Fourier slices."""
+    import workloads as W
+    from oracle import decomp as D
+    from oracle import sampling as S
+    from oracle import tensor as T
+    G1, G2, N = W.lowrank_factors(n3=n3_sample)
+    A = T.tprod_fft(G1.astype(np.float64), G2.astype(np.float64)) + N
+    t0 = time.perf_counter()
+    ci, cs = S.sample(S.weights_lateral_leverage(A, r), c, "iid", seed=0)
+    C = A[:, ci, :] * cs[None, :, None]
+    ri, rs = S.sample(S.weights_horizontal_leverage(C, r), c, "iid", seed=0, stream=1)
+    D.tcur(A, ci, cs, ri, rs, r=r)
     ts = time.perf_counter() - t0
+    scale = T.half_spectrum_count(128) / T.half_spectrum_count(n3_sample)
+    return {"s": round(ts, 3), "scaled_to_n3_128_s": round(ts * scale, 2),
+            "sample": f"1024x1024x{n3_sample} tensor of tubal rank {r} plus N(0,1e-3) noise, c=l={c}, whole "
+                      f"pipeline (exact leverage, picks, Algorithm 5); scaled by {scale:.1f} "
+                      f"(non-redundant Fourier slices of n3=128 over n3={n3_sample})"}
+
+
+def oracle_admm_c4(iters=2):
+    """Iterations of the oracle's completion ADMM (Algorithm 7 with the
+    tensor nuclear norm) on the 256x256x100 rank-15 workload, per
+    iteration."""
+    import workloads as W
+    from oracle import decomp as D
+    from oracle import tensor as T
+    G1, G2, N, mask = W.completion_problem()
+    X = (T.tprod_fft(G1.astype(np.float64), G2.astype(np.float64)) + N) * mask
+    t0 = time.perf_counter()
+    D.admm_complete(X, mask.astype(np.float64), iters=iters)
+    ts = time.perf_counter() - t0
+    return {"ms_per_iter": round(1e3 * ts / iters, 1), "scaled_to_100_iters_s": round(100 * ts / iters, 1),
+            "sample": f"{iters} iterations of completion ADMM on 256x256x100, tubal rank 15, N(0,0.01) noise, 50% "
+                      f"observed; scaled to 100 iterations"}
+
+
+def cpu_baseline(A, B, budget_s, extended=True):
+    """The float64 oracle's t-product by its definition (block-row sums of
+    eq. tprod), timed on a bounded sample: the first s frontal slices of C,
+    s grown until the budget is used; the rate is scaled to all n3 slices.
+    Also the same sample on one BLAS thread, and (extended) the oracle's
+    t-CUR and completion ADMM on bounded samples of their workloads."""
+    cores = _blas_threads()
+    A64 = A.astype(np.float64)
+    B64 = B.astype(np.float64)
+    s, ts = _oracle_tprod_rate(A64, B64, budget_s)
     full = ts * N3 / s
-    return {
-        "value": round(tprod_flops(N1, N2, N4, N3) / full / 1e12, 6),
+    F = tprod_flops(N1, N2, N4, N3)
+    out = {
+        "value": round(F / full / 1e12, 6),
         "unit": "TFLOP/s",
         "cores": int(cores),
         "kind": "oracle",
         "sample": f"float64 oracle t-product by definition (block-row sums of eq. tprod), output frontal slices "
                   f"0..{s - 1} of {N3} in {ts:.2f} s, scaled to all {N3} slices ({full:.1f} s)",
     }
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            s1, t1 = _oracle_tprod_rate(A64, B64, budget_s / 2)
+        full1 = t1 * N3 / s1
+        out["single_thread"] = {"value": round(F / full1 / 1e12, 6), "unit": "TFLOP/s", "cores": 1,
+                                "sample": f"output frontal slices 0..{s1 - 1} in {t1:.2f} s, scaled to {N3} "
+                                          f"({full1:.1f} s)"}
+    except ImportError:  # pragma: no cover
+        out["single_thread"] = None
+    if extended:
+        log("oracle timing: t-CUR sample")
+        out["tcur_1024x1024x128"] = oracle_tcur_c3()
+        log("oracle timing: completion ADMM sample")
+        out["admm_completion_256x256x100"] = oracle_admm_c4()
+    return out
 
 
 def main():
@@ -594,7 +688,8 @@ def main():
     reps = max(5, args.steps)
     ms_exact = time_events(exact, reps, torch)
     ms_rand = time_events(randomized, reps, torch)
-    f32_plain = f32_exact_tprod(api, A, B, C, reps, torch) if prec != "f32" else None
+    traffic = profiled_traffic()
+    f32_plain = f32_exact_tprod(api, A, B, C, reps, torch, traffic) if prec != "f32" else None
 
     F = tprod_flops(N1, N2, N4, N3)
     K = N3 // 2 + 1
@@ -632,7 +727,7 @@ def main():
         ach = kernels["gemm"]["TFLOPs_algorithmic"]
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK[peak_key], "unit": "TFLOP/s",
                 "frac": round(ach / PEAK[peak_key], 4),
-                "traffic": TRAFFIC["gemm"] if prec == "bf16x3" else None,
+                "traffic": traffic.get(prec + ".gemm"),
                 "kernel": "per-slice complex product (tprod.gemm)",
                 "note": "achieved = algorithmic flops (135.3 GFLOP) / mean launch time; bf16x3 executes 3 bf16 "
                         "products per algorithmic product, so frac <= 1/3 by construction; executed rate in "
@@ -641,7 +736,7 @@ def main():
         gbs = kernels[dominant]["GBs"]
         roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
                 "frac": round(gbs / PEAK["hbm_GBs"], 4),
-                "traffic": TRAFFIC.get(dominant) if prec == "bf16x3" else None, "kernel": "tprod." + dominant}
+                "traffic": traffic.get(prec + "." + dominant), "kernel": "tprod." + dominant}
 
     out = {
         "metric": "t-product TFLOP/s; t-CUR time-to-1e-3 rel err, BF16+learned vs FP32 plain",
@@ -680,7 +775,8 @@ def main():
         log("completion / robust PCA: full ADMM against CUR t-NN")
         out["tensor_nn"] = tnn_protocol(args, api, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A_h, B_h, args.cpu_seconds)
+        log("oracle timing: t-product sample")
+        out["cpu_baseline"] = cpu_baseline(A_h, B_h, args.cpu_seconds, extended=not args.no_protocol)
     print(json.dumps(out), flush=True)
 
 

@@ -216,9 +216,30 @@ def test_picks_bit_exact_with_user_weights(n, c, mode):
         np.testing.assert_array_equal(sc.numpy(), rsc)
 
 
+@pytest.mark.parametrize("n,c", [(65537, 300), (100000, 2000), (257, 64), (40000, 40000)])
+@pytest.mark.parametrize("mode", ["bernoulli", "iid", "uniform"])
+def test_picks_bit_exact_across_many_workgroups(n, c, mode):
+    # 256 slices per workgroup: 65537 slices make 257 per-workgroup totals,
+    # one more than a single scan pass over them holds; c = n makes the
+    # uniform select's top byte hold the largest key
+    w = W.lognormal_weights(n, seed=n + c + 1, zeros=5)
+    picks = api.tsample("user", c, mode=mode, seed=5, stream_id=2, w=dev(w))
+    idx, sc = picks.host()
+    ridx, rsc = S.sample(w, c, mode, seed=5, stream=2)
+    np.testing.assert_array_equal(idx.numpy(), ridx)
+    np.testing.assert_array_equal(sc.numpy(), rsc)
+
+
 def test_picks_reject_bad_weights_on_device():
     for bad in ([1.0, -1.0, 2.0], [0.0, 0.0, 0.0], [1.0, float("nan"), 1.0], [float("inf"), 1.0, 1.0]):
-        picks = api.tsample("user", 2, mode="iid", w=dev(np.array(bad)))
+        for mode in ("iid", "bernoulli"):
+            picks = api.tsample("user", 2, mode=mode, w=dev(np.array(bad)))
+            assert int(picks.count.item()) == -1
+    # a bad weight in a later workgroup
+    w = np.ones(5000)
+    w[4100] = -0.5
+    for mode in ("iid", "bernoulli"):
+        picks = api.tsample("user", 10, mode=mode, w=dev(w))
         assert int(picks.count.item()) == -1
 
 
