@@ -214,7 +214,9 @@ def test_admm_stop_test_matches_oracle(variant):
 
 def test_admm_cap_before_the_stop_test_reports_no_convergence():
     # an unreachable tolerance: TP_ENOCONV with the iterates of the capped
-    # run written, identical to the run without the test
+    # run written, identical to the run without the test (a problem small
+    # enough that every iteration's Jacobi converges within the sweep budget
+    # of a fixed-count run)
     G1, G2, N, mask = W.completion_problem(n1=30, n2=28, n3=6, r=2, salt=7, dtype=np.float64)
     X = ((T.tprod_fft(G1, G2) + N) * mask).astype(np.float32)
     info = {}
@@ -224,3 +226,24 @@ def test_admm_cap_before_the_stop_test_reports_no_convergence():
     np.testing.assert_array_equal(L.cpu().numpy(), L0.cpu().numpy())
     np.testing.assert_array_equal(Y.cpu().numpy(), Y0.cpu().numpy())
     np.testing.assert_array_equal(ranks.cpu().numpy(), ranks0.cpu().numpy())
+
+
+def test_fixed_count_sweep_budget_at_full_size():
+    """A fixed-count ADMM spends at most three Jacobi sweeps on each
+    warm-started iteration but the last; with the stop test (here an
+    unreachable one) every iteration runs to convergence. On the
+    256x256x100 completion workload the two runs differ by 1.2e-4 in L after
+    100 iterations (bar: twice that) and agree on the error against L*."""
+    G1, G2, N, mask = W.completion_problem()
+    Ls = api.tprod(dev(G1), dev(G2), prec="f32")
+    m = dev(mask)
+    X = ((Ls + dev(N)) * m.to(torch.float32)).contiguous()
+    L, _, _, ranks = api.tcomplete(X, m, iters=100)
+    info = {}
+    Lx, _, _, ranks_x = api.tcomplete(X, m, iters=100, tol=1e-30, info=info)
+    assert info == {"iters": 100, "converged": False}
+    assert rel(L.cpu().numpy(), Lx.cpu().numpy()) < 2.5e-4
+    rse = float(torch.linalg.vector_norm(L - Ls) / torch.linalg.vector_norm(Ls))
+    rse_x = float(torch.linalg.vector_norm(Lx - Ls) / torch.linalg.vector_norm(Ls))
+    assert abs(rse - rse_x) < 2e-4 * rse_x
+    assert abs(int(ranks.max()) - int(ranks_x.max())) <= 1
