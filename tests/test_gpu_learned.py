@@ -78,13 +78,17 @@ def _kl(p, q):
     return float(np.sum(p[m] * (np.log(p[m]) - np.log(q[m]))))
 
 
-def test_held_out_gain_over_norm_sampling(phi):
+def test_held_out_gain_over_norm_and_uniform_sampling(phi):
+    """The trained network's proposal against the two cheap proposals it
+    competes with: closer to the exact leverage distribution (KL) than
+    squared norms and than uniform sampling, and no more slices needed for
+    a 1e-3 t-CUR (median over held-out tensors)."""
     F, Tg = dataset(range(160), phi)
     tr = LP.Trainer()
     hist = tr.fit(F, Tg, epochs=30, batch=16, lr=2e-3, seed=2)
     assert hist[-1] < 0.7 * hist[0]
-    kl_net, kl_nrm = [], []
-    need = {"learned": [], "norm2": []}
+    kl_net, kl_nrm, kl_uni = [], [], []
+    need = {"learned": [], "norm2": [], "uniform": []}
     grid = [16, 24, 32, 48, 64, 96]
     for t in range(1000, 1008):
         A, r, _ = make(t)
@@ -95,13 +99,14 @@ def test_held_out_gain_over_norm_sampling(phi):
         kl_net.append(_kl(p, q / q.sum()))
         nrm = api.slice_norms(A, "lateral").cpu().numpy()
         kl_nrm.append(_kl(p, nrm / nrm.sum()))
+        kl_uni.append(_kl(p, np.full(p.size, 1.0 / p.size)))
         w = tr.proposal(A, phi)
         for kind in need:
             c_ok = None
             for c in grid:
                 errs = []
                 for s in range(5):
-                    Z, _, _ = api.tcur(A, c, c, r, col_kind="user" if kind == "learned" else "norm2",
+                    Z, _, _ = api.tcur(A, c, c, r, col_kind="user" if kind == "learned" else kind,
                                        col_w=w if kind == "learned" else None, seed=s, prec="f32")
                     errs.append(float(torch.linalg.vector_norm(Z - A) / torch.linalg.vector_norm(A)))
                 if np.median(errs) <= 1e-3:
@@ -109,4 +114,6 @@ def test_held_out_gain_over_norm_sampling(phi):
                     break
             need[kind].append(c_ok if c_ok is not None else 10 ** 6)
     assert np.mean(kl_net) < np.mean(kl_nrm)
+    assert np.mean(kl_net) < np.mean(kl_uni)
     assert np.median(need["learned"]) <= np.median(need["norm2"])
+    assert np.median(need["learned"]) <= np.median(need["uniform"])
