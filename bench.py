@@ -21,7 +21,9 @@ Beside the headline it runs the t-CUR comparison the metric names
     scores of generated 512x512x64 tensors (tubal rank 5..40, coherence
     sigma_c in [0, 2], 1e-4 relative noise), then, on held-out tensors, the
     slices needed for 1e-3 error are found for exact leverage, the learned
-    proposal, squared norms and uniform sampling;
+    proposal, squared norms and uniform sampling, and on the coherent ones
+    (sigma_c >= 1, where these differ) the whole pipeline is timed at the
+    c each proposal needs;
   * time to 1e-3: on the 1024x1024x128 tensor of tubal rank 20 plus
     N(0, 1e-3) noise, for float32 and bf16x3 products with each proposal,
     the smallest c = l of {40, 60, ..., 400} whose median relative error
@@ -206,6 +208,7 @@ def learned_protocol(args, api, torch):
     del feats, targets
     need = {k: [] for k in PROPOSALS}
     kl = {k: [] for k in ("learned", "norm2", "uniform")}
+    timed_coh = {}
     for t in range(args.learned_train, args.learned_train + args.learned_test):
         A, r, sigma_c = learned_tensor(t, api, torch)
         lev = LP.leverage_scores(A, r)
@@ -220,6 +223,13 @@ def learned_protocol(args, api, torch):
             run = cur_runner(api, A, r, kind, "bf16x3", w if kind == "learned" else None)
             c, _ = slices_needed(run, A, args.seeds, torch)
             need[kind].append(c)
+            if sigma_c >= 1.0:
+                # coherent tensors, where the proposals need different c: the
+                # whole pipeline (proposal included) at the c it needs
+                ms = None
+                if c is not None:
+                    ms = pipeline_ms(api, torch, A, r, kind, "bf16x3", c, trainer, phi, reps=10)
+                timed_coh.setdefault(t, {})[kind] = {"c": c, "ms": ms}
         log(f"learned test tensor {t - args.learned_train + 1}/{args.learned_test}: r={r} sigma_c={sigma_c:.2f} "
             + " ".join(f"{k}={need[k][-1]}" for k in PROPOSALS))
 
@@ -244,7 +254,59 @@ def learned_protocol(args, api, torch):
         "learned_le_norm2_fraction": round(float(np.mean([
             (a if a is not None else 1e9) <= (b if b is not None else 1e9)
             for a, b in zip(need["learned"], need["norm2"])])), 3),
+        "learned_le_uniform_fraction": round(float(np.mean([
+            (a if a is not None else 1e9) <= (b if b is not None else 1e9)
+            for a, b in zip(need["learned"], need["uniform"])])), 3),
+        "coherent_time_to_1e-3": coherent_summary(timed_coh),
     }
+
+
+def pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, reps=20, Z=None):
+    """Median time (HIP events) of the whole t-CUR pipeline at c = l:
+    proposal (the network's inference for the learned kind, the range finder
+    for exact leverage), picks, gathers, transforms, core and Z."""
+    Z = torch.empty_like(A) if Z is None else Z
+    st = torch.cuda.current_stream()
+
+    def pipeline():
+        if kind == "learned":
+            wl = trainer.proposal(A, phi)
+            api.tcur(A, c, c, r, col_kind="user", row_kind="lev", col_w=wl, seed=0, prec=prec, out=Z)
+        else:
+            api.tcur(A, c, c, r, col_kind=kind, row_kind="lev", seed=0, prec=prec, out=Z)
+    pipeline()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        pipeline()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return round(float(np.median(ts)), 4)
+
+
+def coherent_summary(timed):
+    """Per coherent held-out tensor, the time to 1e-3 of each proposal and
+    the fastest; overall, how often each proposal is fastest and the median
+    time ratio of the learned proposal to uniform and to exact leverage
+    (censored runs count as slower than any finished one)."""
+    if not timed:
+        return None
+    fastest = {k: 0 for k in PROPOSALS}
+    ratio_uni, ratio_lev = [], []
+    for ent in timed.values():
+        ms = {k: (v["ms"] if v["ms"] is not None else float("inf")) for k, v in ent.items()}
+        fastest[min(ms, key=ms.get)] += 1
+        if np.isfinite(ms["learned"]):
+            ratio_uni.append(ms["learned"] / ms["uniform"] if np.isfinite(ms["uniform"]) else 0.0)
+            ratio_lev.append(ms["learned"] / ms["lev"] if np.isfinite(ms["lev"]) else 0.0)
+    return {"tensors": len(timed), "fastest_count": fastest,
+            "median_time_ratio_learned_to_uniform": round(float(np.median(ratio_uni)), 3) if ratio_uni else None,
+            "median_time_ratio_learned_to_lev": round(float(np.median(ratio_lev)), 3) if ratio_lev else None,
+            "per_tensor": {str(t): ent for t, ent in timed.items()}}
 
 
 def time_to_target(args, api, torch, trainer):
@@ -258,7 +320,6 @@ def time_to_target(args, api, torch, trainer):
     phi = LP.sketch_matrix(A.shape[0], A.shape[2], seed=13)
     w = trainer.proposal(A, phi)
     Z = torch.empty_like(A)
-    st = torch.cuda.current_stream()
     res = {}
     for prec in ("f32", "bf16x3"):
         for kind in PROPOSALS:
@@ -266,24 +327,7 @@ def time_to_target(args, api, torch, trainer):
             c, err = slices_needed(run, A, args.seeds, torch)
             entry = {"c": c, "err_median": err}
             if c is not None:
-                def pipeline():
-                    if kind == "learned":
-                        wl = trainer.proposal(A, phi)
-                        api.tcur(A, c, c, r, col_kind="user", row_kind="lev", col_w=wl, seed=0, prec=prec, out=Z)
-                    else:
-                        api.tcur(A, c, c, r, col_kind=kind, row_kind="lev", seed=0, prec=prec, out=Z)
-                pipeline()
-                torch.cuda.synchronize()
-                ts = []
-                for _ in range(20):
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(st)
-                    pipeline()
-                    e1.record(st)
-                    torch.cuda.synchronize()
-                    ts.append(e0.elapsed_time(e1))
-                entry["ms"] = round(float(np.median(ts)), 4)
+                entry["ms"] = pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, Z=Z)
             res[f"{prec}+{kind}"] = entry
             log(f"time-to-1e-3 {prec}+{kind}: {entry}")
     out = {
