@@ -468,10 +468,37 @@ __global__ __launch_bounds__(kTile) void irfft_kernel(const T* __restrict__ xre,
   }
 }
 
-// Direct transforms for lengths without a specialised kernel.
-template <typename T>
+// Direct transforms for lengths without a specialised kernel. Every term
+// uses a root exp(-2 pi i m / N) with m = k n mod N; up to kDirectTable
+// points the N roots are evaluated once per workgroup into LDS (the same
+// sincospi values the direct formula takes), beyond that per term.
+constexpr int kDirectTable = 2048;
+
+template <bool TABLE>
+__device__ __forceinline__ void direct_root(const double* tw, int m, int N, double& sn, double& cs) {
+  if (TABLE) {
+    cs = tw[m];
+    sn = tw[N + m];
+  } else {
+    sincospi(2.0 * (double)m / (double)N, &sn, &cs);
+  }
+}
+
+__device__ __forceinline__ void direct_table(double* tw, int N) {
+  for (int m = threadIdx.x; m < N; m += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)N, &sn, &cs);
+    tw[m] = cs;
+    tw[N + m] = sn;
+  }
+  __syncthreads();
+}
+
+template <typename T, bool TABLE>
 __global__ void rdft_direct_kernel(const T* __restrict__ x, int N, FwdArgs a, T* __restrict__ ore,
                                    T* __restrict__ oim) {
+  extern __shared__ double tw[];  // TABLE: cos, then sin, of 2 pi m / N
+  if (TABLE) direct_table(tw, N);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.ntubes) return;
   const int K = N / 2 + 1;
@@ -481,12 +508,15 @@ __global__ void rdft_direct_kernel(const T* __restrict__ x, int N, FwdArgs a, T*
   for (int k = 0; k < K; ++k) {
     double accr = 0, acci = 0;
     if (live) {
+      int m = 0;  // k n mod N
       for (int n = 0; n < N; ++n) {
         double sn, cs;
-        sincospi(2.0 * (double)((int64_t)k * n % N) / (double)N, &sn, &cs);
+        direct_root<TABLE>(tw, m, N, sn, cs);
         const double v = (double)(T)((double)x[src * N + n] * s);
         accr += v * cs;
         acci -= v * sn;
+        m += k;
+        m = m >= N ? m - N : m;
       }
     }
     ore[(int64_t)k * a.ntubes + t] = (T)accr;
@@ -494,21 +524,26 @@ __global__ void rdft_direct_kernel(const T* __restrict__ x, int N, FwdArgs a, T*
   }
 }
 
-template <typename T>
+template <typename T, bool TABLE>
 __global__ void irdft_direct_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int N, int64_t ntubes,
                                     T* __restrict__ y) {
+  extern __shared__ double tw[];
+  if (TABLE) direct_table(tw, N);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntubes) return;
   const int K = N / 2 + 1;
   for (int n = 0; n < N; ++n) {
     double acc = 0;
+    int m = 0;  // k n mod N
     for (int k = 0; k < K; ++k) {
       const double wk = (k == 0 || 2 * k == N) ? 1.0 : 2.0;
       double sn, cs;
-      sincospi(2.0 * (double)((int64_t)k * n % N) / (double)N, &sn, &cs);
+      direct_root<TABLE>(tw, m, N, sn, cs);
       const double xr = (double)xre[(int64_t)k * ntubes + t];
       const double xi = (k == 0 || 2 * k == N) ? 0.0 : (double)xim[(int64_t)k * ntubes + t];
       acc += wk * (xr * cs - xi * sn);
+      m += n;
+      m = m >= N ? m - N : m;
     }
     y[t * N + n] = (T)(acc / N);
   }
@@ -719,7 +754,12 @@ int fwd_impl(const T* x, int64_t n3, const TubeGather& g, T* re, T* im, hipStrea
                        pl, re, im);
   } else {
     const int64_t blocks = (a.ntubes + 127) / 128;
-    hipLaunchKernelGGL(rdft_direct_kernel<T>, dim3((unsigned)blocks), dim3(128), 0, st, x, (int)n3, a, re, im);
+    if (n3 <= kDirectTable)
+      hipLaunchKernelGGL((rdft_direct_kernel<T, true>), dim3((unsigned)blocks), dim3(128), 2 * n3 * sizeof(double), st,
+                         x, (int)n3, a, re, im);
+    else
+      hipLaunchKernelGGL((rdft_direct_kernel<T, false>), dim3((unsigned)blocks), dim3(128), 0, st, x, (int)n3, a, re,
+                         im);
   }
   TP_LAUNCH_CHECK();
   return TP_OK;
@@ -737,8 +777,12 @@ int inv_impl(const T* re, const T* im, int64_t n3, int64_t ntubes, T* y, hipStre
                        ntubes, pl, y);
   } else {
     const int64_t blocks = (ntubes + 127) / 128;
-    hipLaunchKernelGGL(irdft_direct_kernel<T>, dim3((unsigned)blocks), dim3(128), 0, st, re, im, (int)n3, ntubes,
-                       y);
+    if (n3 <= kDirectTable)
+      hipLaunchKernelGGL((irdft_direct_kernel<T, true>), dim3((unsigned)blocks), dim3(128), 2 * n3 * sizeof(double),
+                         st, re, im, (int)n3, ntubes, y);
+    else
+      hipLaunchKernelGGL((irdft_direct_kernel<T, false>), dim3((unsigned)blocks), dim3(128), 0, st, re, im, (int)n3,
+                         ntubes, y);
   }
   TP_LAUNCH_CHECK();
   return TP_OK;
