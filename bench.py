@@ -536,7 +536,7 @@ def time_events(fn, reps, torch):
     return e0.elapsed_time(e1) / reps  # ms
 
 
-def f32_exact_tprod(api, A, B, C, reps, torch, traffic):
+def f32_exact_tprod(api, A, B, C, reps, torch, traffic, peaks):
     """The same exact t-product in plain float32 arithmetic (TP_PREC_F32:
     float32 transforms and per-slice products on the float32 matrix cores),
     timed with HIP events, with its stages from the library trace and the
@@ -562,7 +562,28 @@ def f32_exact_tprod(api, A, B, C, reps, torch, traffic):
         ach = F / (stages["gemm"] * 1e-3) / 1e12
         out["gemm_roofline"] = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["f32"], "unit": "TFLOP/s",
                                 "frac": round(ach / PEAK["f32"], 4), "traffic": traffic.get("f32.gemm"),
+                                "frac_of_measured_gemm": round(ach / peaks["f32_gemm_TFLOPs"], 4),
                                 "kernel": "cgemm_f32_kernel (v_mfma_f32_16x16x4f32, complex slices as 3 real products)"}
+    return out
+
+
+def measured_peaks(torch):
+    """Achievable rates on this GPU for context beside the nominal peaks: a
+    1 GiB device-to-device copy (torch's copy kernel; bytes read + written)
+    and torch's library GEMM (8192^3 in bf16, 4096^3 in float32). They are
+    library figures, not this repository's kernels."""
+    out = {}
+    src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = time_events(lambda: dst.copy_(src), 10, torch)
+    out["hbm_copy_GBs"] = round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    for name, dt, n in (("bf16_gemm_TFLOPs", torch.bfloat16, 8192), ("f32_gemm_TFLOPs", torch.float32, 4096)):
+        a = torch.randn(n, n, device="cuda").to(dt)
+        b = torch.randn(n, n, device="cuda").to(dt)
+        ms = time_events(lambda: torch.matmul(a, b), 10, torch)
+        out[name] = round(2 * n ** 3 / (ms * 1e-3) / 1e12, 1)
+        del a, b
     return out
 
 
@@ -733,7 +754,8 @@ def main():
     ms_exact = time_events(exact, reps, torch)
     ms_rand = time_events(randomized, reps, torch)
     traffic = profiled_traffic()
-    f32_plain = f32_exact_tprod(api, A, B, C, reps, torch, traffic) if prec != "f32" else None
+    peaks = measured_peaks(torch)
+    f32_plain = f32_exact_tprod(api, A, B, C, reps, torch, traffic, peaks) if prec != "f32" else None
 
     F = tprod_flops(N1, N2, N4, N3)
     K = N3 // 2 + 1
@@ -769,18 +791,22 @@ def main():
     peak_key = "bf16" if split else "f32"
     if dominant == "gemm":
         ach = kernels["gemm"]["TFLOPs_algorithmic"]
+        gemm_ref = peaks["bf16_gemm_TFLOPs"] if split else peaks["f32_gemm_TFLOPs"]
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK[peak_key], "unit": "TFLOP/s",
                 "frac": round(ach / PEAK[peak_key], 4),
                 "traffic": traffic.get(prec + ".gemm"),
                 "kernel": "per-slice complex product (tprod.gemm)",
+                "frac_of_measured_gemm": round((ach * (terms if split else 1)) / gemm_ref, 4),
                 "note": "achieved = algorithmic flops (135.3 GFLOP) / mean launch time; bf16x3 executes 3 bf16 "
                         "products per algorithmic product, so frac <= 1/3 by construction; executed rate in "
-                        "kernels_ms.gemm"}
+                        "kernels_ms.gemm; frac_of_measured_gemm = executed rate / torch's bf16 GEMM rate "
+                        "(measured_peaks)"}
     else:
         gbs = kernels[dominant]["GBs"]
         roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK["hbm_GBs"], "unit": "GB/s",
                 "frac": round(gbs / PEAK["hbm_GBs"], 4),
-                "traffic": traffic.get(prec + "." + dominant), "kernel": "tprod." + dominant}
+                "traffic": traffic.get(prec + "." + dominant), "kernel": "tprod." + dominant,
+                "frac_of_measured_copy": round(gbs / peaks["hbm_copy_GBs"], 4)}
 
     out = {
         "metric": "t-product TFLOP/s; t-CUR time-to-1e-3 rel err, BF16+learned vs FP32 plain",
@@ -799,6 +825,7 @@ def main():
                                "slice scales; rt-product c=256 i.i.d. squared-norm picks",
                    "n1": N1, "n2": N2, "n4": N4, "n3": N3, "c": C_PICK, "parallelism": "single GPU"},
         "roofline": roof,
+        "measured_peaks": peaks,
         "exact_tprod_ms": round(ms_exact, 4),
         "exact_tprod_TFLOPs": round(F / (ms_exact * 1e-3) / 1e12, 3),
         "rtprod_ms": round(ms_rand, 4),
