@@ -548,10 +548,16 @@ def f32_exact_tprod(api, A, B, C, reps, torch, traffic, peaks):
 
     run()
     torch.cuda.synchronize()
-    api.trace_enable(True)
+    api.trace_enable(2)
     ms = time_events(run, reps, torch)
     api.trace_enable(False)
     trace = api.trace_read()
+    api.trace_enable(True)
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    api.trace_enable(False)
+    trace.update({k: v for k, v in api.trace_read().items() if not k.endswith(".gemm")})
     stages = {}
     for name in ("fft_ab", "gemm", "ifft"):
         calls, tot = trace.get("tprod." + name, (0, 0.0))
@@ -732,9 +738,12 @@ def main():
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    # stage timings come from the library's own event pairs recorded on this
-    # stream during the timed steps
-    api.trace_enable(True)
+    # the per-slice product's launch times come from the library's own event
+    # pairs recorded on this stream during the timed steps; only the product
+    # stages are recorded there (every pair costs some device time: recording
+    # every stage lengthened a step by 6-7%), the other stages' times come
+    # from the same steps run once more with every stage recorded
+    api.trace_enable(2)
     w0 = time.perf_counter()
     e0.record(st)
     for _ in range(args.steps):
@@ -745,9 +754,15 @@ def main():
     api.trace_enable(False)
     ms_step = e0.elapsed_time(e1) / args.steps
     trace = api.trace_read()
+    api.trace_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    api.trace_enable(False)
+    trace_all = api.trace_read()
 
     def avg(name):
-        calls, ms = trace.get(name, (0, 0.0))
+        calls, ms = (trace if name.endswith(".gemm") else trace_all).get(name, (0, 0.0))
         return ms / calls if calls else None
 
     reps = max(5, args.steps)

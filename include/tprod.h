@@ -463,7 +463,11 @@ size_t tp_tcur_nn_workspace(const tp_tensor* X, int64_t c, int64_t l, int64_t r,
  * recording: each stage of a call (for the t-product "tprod.fft_a",
  * "tprod.fft_b", "tprod.gemm", "tprod.ifft", with the prefix "rtprod." when
  * picks are given) records a HIP event pair on the
- * caller's stream around its kernels. tp_trace_enable(0) stops recording.
+ * caller's stream around its kernels. tp_trace_enable(2) does the same for
+ * the per-slice product stages only (names ending in ".gemm"): each event
+ * pair costs some device time, so a caller timing a whole step can keep the
+ * pairs to the kernel it wants to see. tp_trace_enable(0) stops recording;
+ * other values give TP_EINVAL.
  * tp_trace_count() waits for the recorded events, folds them into per-stage
  * totals and returns the number of stages; tp_trace_entry(i, ...) reports
  * stage i: its name (copied into name, name_cap bytes with the terminating

@@ -419,8 +419,11 @@ def tcur_nn(X, c, l, r, mask=None, lam=None, col_kind="uniform", row_kind="unifo
 # ---------------------------------------------------------------------------
 
 def trace_enable(on=True):
-    """Start (clearing earlier records) or stop recording stage timings."""
-    L.check(L.load().tp_trace_enable(1 if on else 0))
+    """Start (clearing earlier records) or stop recording stage timings:
+    True / 1 every stage, 2 the per-slice product stages only, False / 0
+    stop."""
+    mode = (1 if on else 0) if isinstance(on, bool) else int(on)
+    L.check(L.load().tp_trace_enable(mode))
 
 
 def trace_read():

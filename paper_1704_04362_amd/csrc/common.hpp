@@ -105,8 +105,9 @@ struct SplitGemm {
 };
 int cgemm_split(const SplitGemm& p, hipStream_t st);
 
-// Launch tracing (trace.cpp): with tp_trace_enable(1), a scope records HIP
-// events on its stream around the work enqueued inside it.
+// Launch tracing (trace.cpp): with tp_trace_enable(1) (2: only scopes named
+// "*.gemm"), a scope records HIP events on its stream around the work
+// enqueued inside it.
 class TraceScope {
  public:
   TraceScope(const char* name, hipStream_t st);

@@ -24,7 +24,7 @@ struct Agg {
 };
 
 std::mutex g_mu;
-bool g_on = false;
+int g_mode = 0;  // 0 off, 1 every stage, 2 the slice-product stages only
 std::vector<Rec> g_recs;
 std::vector<Agg> g_aggs;
 
@@ -38,13 +38,20 @@ void drop_records() {
 
 }  // namespace
 
-bool trace_on() {
-  std::lock_guard<std::mutex> lk(g_mu);
-  return g_on;
+bool trace_on(const char* name) {
+  int mode;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    mode = g_mode;
+  }
+  if (mode == 1) return true;
+  if (mode != 2) return false;
+  const std::string n(name);
+  return n.size() >= 5 && n.compare(n.size() - 5, 5, ".gemm") == 0;
 }
 
 TraceScope::TraceScope(const char* name, hipStream_t st) : name_(name), st_(st) {
-  if (!trace_on()) return;
+  if (!trace_on(name)) return;
   if (hipEventCreate(&e0_) != hipSuccess) return;
   if (hipEventCreate(&e1_) != hipSuccess) {
     (void)hipEventDestroy(e0_);
@@ -76,12 +83,13 @@ using namespace tp;
 extern "C" {
 
 int tp_trace_enable(int on) {
+  if (on < 0 || on > 2) return fail(TP_EINVAL, "trace: mode must be 0, 1 or 2");
   std::lock_guard<std::mutex> lk(g_mu);
   if (on) {
     drop_records();
     g_aggs.clear();
   }
-  g_on = on != 0;
+  g_mode = on;
   return TP_OK;
 }
 

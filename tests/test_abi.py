@@ -19,6 +19,16 @@ def test_library_exports_every_declared_symbol():
         assert f" T {n}" in out, n
 
 
+def test_trace_modes():
+    # host-side bookkeeping only: no device work
+    lib = L.load()
+    for mode in (-1, 3):
+        assert lib.tp_trace_enable(mode) == -1  # TP_EINVAL
+    for mode in (2, 1, 0):
+        assert lib.tp_trace_enable(mode) == 0
+    assert lib.tp_trace_count() == 0
+
+
 def test_status_strings_and_version():
     lib = L.load()
     assert lib.tp_version() >= 100

@@ -452,6 +452,14 @@ def test_trace_records_the_stages_of_a_call():
     api.trace_enable(True)
     api.trace_enable(False)
     assert api.trace_read() == {}
+    # mode 2 records the per-slice product stages only
+    api.trace_enable(2)
+    api.tprod(Ad, Bd, prec="bf16x3")
+    api.tprod(Ad, Bd, picks=picks, prec="bf16x3")
+    api.trace_enable(False)
+    tr = api.trace_read()
+    assert sorted(tr) == ["rtprod.gemm", "tprod.gemm"]
+    assert tr["tprod.gemm"][0] == 1 and tr["rtprod.gemm"][0] == 1
 
 
 @pytest.mark.parametrize("prec,tol", [("bf16x3", 1.3e-5), ("bf16", 1e-2), ("f32", 2e-6)])
