@@ -59,8 +59,6 @@ int check_sample(const tp_sample* s, int64_t n) {
   return TP_OK;
 }
 
-size_t esize(int dtype) { return dtype == TP_F64 ? 8 : 4; }
-
 int64_t round_up32(int64_t n) { return (n + 31) / 32 * 32; }
 
 // the t-product takes the split-operand matrix-core path for float32 data
