@@ -296,30 +296,36 @@ __global__ void zero_int_kernel(int* p, int64_t n) {
 // and the number of sigma_i > tau per slice. Row norms at or below
 // max(n1, n2) eps_32 sigma_max are rounding residue of rows that the
 // rotations have emptied (a slice has at most min(n1, n2) nonzero singular
-// values) and count as zero. One workgroup per slice: a wavefront sums a
-// row with consecutive lanes on consecutive columns, then the scaling pass
-// runs over the slice in storage order; sig (K x n1 scratch) holds the
-// norms and then the factors.
-__global__ __launch_bounds__(NT) void svt_shrink_kernel(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2,
-                                                        double tau, int real_last, double* sig, int32_t* ranks) {
+// values) and count as zero. Three passes over all slices at once: a
+// wavefront per row sums it with consecutive lanes on consecutive columns;
+// one workgroup per slice turns the norms into factors (sig, K x n1, holds
+// the norms and then the factors); the scaling runs over every element.
+__global__ __launch_bounds__(NT) void svt_rownorm_kernel(const float* __restrict__ xre, const float* __restrict__ xim,
+                                                         int64_t K, int64_t n1, int64_t n2, int real_last,
+                                                         double* __restrict__ sig) {
+  const int64_t row = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= K * n1) return;
+  const int64_t k = row / n1;
+  const bool real = k == 0 || (real_last && k == K - 1);
+  const float* re = xre + row * n2;
+  const float* im = xim + row * n2;
+  double s2 = 0.0;
+  for (int64_t j = lane; j < n2; j += 64) {
+    const double a = re[j], b = real ? 0.0 : im[j];
+    s2 += a * a + b * b;
+  }
+  s2 = wave_sum(s2);
+  if (lane == 0) sig[row] = sqrt(s2);
+}
+
+__global__ __launch_bounds__(NT) void svt_factor_kernel(int64_t n1, int64_t n2, double tau, double* sig,
+                                                        int32_t* ranks) {
   __shared__ double red[NT];
   __shared__ int cnt[NT];
   const int64_t k = blockIdx.x;
-  const bool real = k == 0 || (real_last && k == K - 1);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  float* re = xre + k * n1 * n2;
-  float* im = xim + k * n1 * n2;
+  const int tid = threadIdx.x;
   double* sg = sig + k * n1;
-  for (int64_t i = wv; i < n1; i += NT / 64) {
-    double s2 = 0.0;
-    for (int64_t j = lane; j < n2; j += 64) {
-      const double a = re[i * n2 + j], b = real ? 0.0 : im[i * n2 + j];
-      s2 += a * a + b * b;
-    }
-    s2 = wave_sum(s2);
-    if (lane == 0) sg[i] = sqrt(s2);
-  }
-  __syncthreads();
   double mx = 0.0;
   for (int64_t i = tid; i < n1; i += NT) mx = fmax(mx, sg[i]);
   red[tid] = mx;
@@ -338,16 +344,22 @@ __global__ __launch_bounds__(NT) void svt_shrink_kernel(float* xre, float* xim, 
   }
   cnt[tid] = mine;
   __syncthreads();
-  for (int64_t e = tid; e < n1 * n2; e += NT) {
-    const double d = sg[e / n2];
-    re[e] = (float)(d * re[e]);
-    if (!real) im[e] = (float)(d * im[e]);
-  }
   for (int w = NT / 2; w > 0; w >>= 1) {
     if (tid < w) cnt[tid] += cnt[tid + w];
     __syncthreads();
   }
   if (tid == 0 && ranks) ranks[k] = cnt[0];
+}
+
+__global__ void svt_scale_kernel(float* __restrict__ xre, float* __restrict__ xim, int64_t K, int64_t n1, int64_t n2,
+                                 int real_last, const double* __restrict__ sig) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K * n1 * n2) return;
+  const int64_t row = e / n2, k = row / n1;
+  const bool real = k == 0 || (real_last && k == K - 1);
+  const double d = sig[row];
+  xre[e] = (float)(d * xre[e]);
+  if (!real) xim[e] = (float)(d * xim[e]);
 }
 
 // Leading singular (or eigen) vectors after the block Jacobi has made the m
@@ -619,8 +631,13 @@ int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_
 
 int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double tau, bool real_last,
                double* sig, int32_t* ranks, hipStream_t st) {
-  hipLaunchKernelGGL(svt_shrink_kernel, dim3((unsigned)K), dim3(NT), 0, st, xre, xim, K, n1, n2, tau,
-                     real_last ? 1 : 0, sig, ranks);
+  if (K * n1 == 0) return TP_OK;
+  const int rl = real_last ? 1 : 0;
+  const int64_t rows = K * n1;
+  hipLaunchKernelGGL(svt_rownorm_kernel, dim3((unsigned)((rows + NT / 64 - 1) / (NT / 64))), dim3(NT), 0, st, xre,
+                     xim, K, n1, n2, rl, sig);
+  hipLaunchKernelGGL(svt_factor_kernel, dim3((unsigned)K), dim3(NT), 0, st, n1, n2, tau, sig, ranks);
+  hipLaunchKernelGGL(svt_scale_kernel, dim3(nblk(K * n1 * n2)), dim3(256), 0, st, xre, xim, K, n1, n2, rl, sig);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }
