@@ -15,8 +15,15 @@
  * and the workspace, whose size the *_workspace functions return). Unless a
  * parameter says "host", pointers are device pointers on the current HIP
  * device. The library keeps no per-call state; its only global state is a
- * per-device table of transform twiddles set up on first use and the fixed
- * scratch array of tp_tsample_noalloc.
+ * per-device table of transform twiddles set up on first use, the fixed
+ * scratch array of tp_tsample_noalloc, and a per-device side stream with
+ * two events, created on first use, on which the block Jacobi sweeps of
+ * the singular value thresholding (tp_tsvt, the ADMM calls, tp_tsvd_full,
+ * t-project beyond 64 slices) run half of the Fourier slices when a launch
+ * has more pair steps than the GPU has compute units and fewer than 7/8 of
+ * twice that number (the steps that fit at once). That work is forked
+ * from `stream` by an event and joined back to it before the call's later
+ * work, so it stays ordered with `stream` (also under graph capture).
  *
  * Asynchrony: every call enqueues its work on `stream` (a hipStream_t;
  * NULL is the default stream) and returns without synchronising (the one

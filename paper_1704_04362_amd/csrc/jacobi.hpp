@@ -19,18 +19,25 @@
 // It is evaluated as t = sign(d) 2 |h| / (|d| + sqrt(d^2 + 4 |h|^2)),
 // d = H_qq - H_pp, c = 1 / sqrt(1 + t^2), s = t c, e^{i phi} = h / |h|:
 // two square roots side by side, one division and one reciprocal root.
+//
+// For an even n and several update items per thread, a round's update is
+// branch-free and issues all of a thread's LDS reads before its writes.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace tp {
 
+// Rotation of one pair: c, s and the phase e^{i phi} (re, im), read as two
+// 16-byte words.
+typedef double jrot __attribute__((ext_vector_type(4)));
+
 template <int MAXN, int NT>
 struct JacobiShared {
   static_assert(NT % 64 == 0, "whole wavefronts");
   double Hr[MAXN][MAXN + 1], Hi[MAXN][MAXN + 1];
   double Vr[MAXN][MAXN + 1], Vi[MAXN][MAXN + 1];
-  double rc[MAXN / 2 + 1], rs[MAXN / 2 + 1], rpr[MAXN / 2 + 1], rpi[MAXN / 2 + 1];
+  jrot rot[MAXN / 2 + 1];
   double red[2][NT / 64];
   int done;
 };
@@ -56,6 +63,96 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// Row transform of pair (c, s, e) on a column (x = M_p, y = M_q):
+//   M_p = c x - s e y,  M_q = s x + c e y;
+// the column transform is the same with conj(e).
+__device__ __forceinline__ void jrot_apply(double c, double s, double er, double ei, double& xr, double& xi,
+                                           double& yr, double& yi) {
+  const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
+  const double nxr = c * xr - s * eyr, nxi = c * xi - s * eyi;
+  yr = s * xr + c * eyr;
+  yi = s * xi + c * eyi;
+  xr = nxr;
+  xi = nxi;
+}
+
+// One round's update H <- J^H H J, V <- V J for an even n (no idle index):
+// npairs^2 2 x 2 blocks of H and n x npairs row pairs of V, flat-indexed
+// over the workgroup. Every item reads and writes only its own entries, so
+// all of a thread's reads are issued before its first write.
+template <int MAXN, int NT>
+__device__ __forceinline__ void jacobi_update_even(JacobiShared<MAXN, NT>& sh, int n, int rho) {
+  constexpr int kP = MAXN / 2;
+  constexpr int kTrips = (3 * kP * kP + NT - 1) / NT;
+  constexpr int kBatch = 4;  // items held in registers at once (~36 registers each)
+  const int tid = threadIdx.x;
+  const int npairs = n >> 1, nblk = npairs * npairs, nitems = 3 * nblk;
+#pragma unroll
+  for (int g0 = 0; g0 < kTrips; g0 += kBatch) {
+    constexpr int kB = kTrips < kBatch ? kTrips : kBatch;
+    double x[kB][8];
+    jrot ru[kB], rv[kB];
+    int a0[kB], a1[kB], b0[kB], b1[kB];
+#pragma unroll
+    for (int t = 0; t < kB; ++t) {
+      const int e = tid + (g0 + t) * NT;
+      if (g0 + t >= kTrips) break;
+      if (e < nblk) {
+        const int u = e / npairs, v = e - u * npairs;
+        jacobi_pair(n, rho, u, a0[t], a1[t]);
+        jacobi_pair(n, rho, v, b0[t], b1[t]);
+        x[t][0] = sh.Hr[a0[t]][b0[t]];
+        x[t][1] = sh.Hi[a0[t]][b0[t]];
+        x[t][2] = sh.Hr[a0[t]][b1[t]];
+        x[t][3] = sh.Hi[a0[t]][b1[t]];
+        x[t][4] = sh.Hr[a1[t]][b0[t]];
+        x[t][5] = sh.Hi[a1[t]][b0[t]];
+        x[t][6] = sh.Hr[a1[t]][b1[t]];
+        x[t][7] = sh.Hi[a1[t]][b1[t]];
+        ru[t] = sh.rot[u];
+        rv[t] = sh.rot[v];
+      } else if (e < nitems) {
+        const int f = e - nblk;
+        const int v = f / n, i = f - v * n;
+        a0[t] = i;
+        jacobi_pair(n, rho, v, b0[t], b1[t]);
+        x[t][0] = sh.Vr[i][b0[t]];
+        x[t][1] = sh.Vi[i][b0[t]];
+        x[t][2] = sh.Vr[i][b1[t]];
+        x[t][3] = sh.Vi[i][b1[t]];
+        rv[t] = sh.rot[v];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kB; ++t) {
+      const int e = tid + (g0 + t) * NT;
+      if (g0 + t >= kTrips) break;
+      if (e < nblk) {
+        // rows (pair u) on columns b0 and b1, then columns (pair v) on rows a0 and a1
+        jrot_apply(ru[t][0], ru[t][1], ru[t][2], ru[t][3], x[t][0], x[t][1], x[t][4], x[t][5]);
+        jrot_apply(ru[t][0], ru[t][1], ru[t][2], ru[t][3], x[t][2], x[t][3], x[t][6], x[t][7]);
+        jrot_apply(rv[t][0], rv[t][1], rv[t][2], -rv[t][3], x[t][0], x[t][1], x[t][2], x[t][3]);
+        jrot_apply(rv[t][0], rv[t][1], rv[t][2], -rv[t][3], x[t][4], x[t][5], x[t][6], x[t][7]);
+        sh.Hr[a0[t]][b0[t]] = x[t][0];
+        sh.Hi[a0[t]][b0[t]] = x[t][1];
+        sh.Hr[a0[t]][b1[t]] = x[t][2];
+        sh.Hi[a0[t]][b1[t]] = x[t][3];
+        sh.Hr[a1[t]][b0[t]] = x[t][4];
+        sh.Hi[a1[t]][b0[t]] = x[t][5];
+        sh.Hr[a1[t]][b1[t]] = x[t][6];
+        sh.Hi[a1[t]][b1[t]] = x[t][7];
+      } else if (e < nitems) {
+        jrot_apply(rv[t][0], rv[t][1], rv[t][2], -rv[t][3], x[t][0], x[t][1], x[t][2], x[t][3]);
+        const int i = a0[t];
+        sh.Vr[i][b0[t]] = x[t][0];
+        sh.Vi[i][b0[t]] = x[t][1];
+        sh.Vr[i][b1[t]] = x[t][2];
+        sh.Vi[i][b1[t]] = x[t][3];
+      }
+    }
+  }
 }
 
 // Diagonalises the n x n Hermitian matrix in sh.H (n <= MAXN) in place,
@@ -91,6 +188,10 @@ __device__ int jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps,
   const int npairs = m / 2;
   const int nblk = npairs * npairs;
   const double tol2 = rel_tol * rel_tol;
+  // the batched update pays where a thread has several items per round;
+  // with one item each it measured slower than the loop below
+  constexpr int kP = MAXN / 2;
+  constexpr bool kEvenBatched = (3 * kP * kP + NT - 1) / NT > 1 && NT < 1024;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     {
@@ -144,12 +245,16 @@ __device__ int jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps,
             pi = hi * ih;
           }
         }
-        sh.rc[tid] = c;
-        sh.rs[tid] = sn;
-        sh.rpr[tid] = pr;
-        sh.rpi[tid] = pi;
+        sh.rot[tid] = jrot{c, sn, pr, pi};
       }
       __syncthreads();
+      if constexpr (kEvenBatched) {
+        if (!(n & 1)) {
+          jacobi_update_even<MAXN, NT>(sh, n, rho);
+          __syncthreads();
+          continue;
+        }
+      }
       // H <- J^H H J by 2 x 2 blocks, then V <- V J by row pairs. Row
       // transform of pair u on a column (x = H_pj, y = H_qj):
       //   H_pj = c x - s e^{i phi} y,  H_qj = s x + c e^{i phi} y;
@@ -175,7 +280,7 @@ __device__ int jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps,
           double cr = r2 ? sh.Hr[q0][p1] : 0.0, ci = r2 ? sh.Hi[q0][p1] : 0.0;  // (q0, p1)
           double dr = (r2 && c2) ? sh.Hr[q0][q1] : 0.0, di = (r2 && c2) ? sh.Hi[q0][q1] : 0.0;
           if (r2) {
-            const double c = sh.rc[u], s = sh.rs[u], er = sh.rpr[u], ei = sh.rpi[u];
+            const double c = sh.rot[u][0], s = sh.rot[u][1], er = sh.rot[u][2], ei = sh.rot[u][3];
             // column p1: x = a, y = c
             double eyr = er * cr - ei * ci, eyi = er * ci + ei * cr;
             const double nar = c * ar - s * eyr, nai = c * ai - s * eyi;
@@ -188,7 +293,7 @@ __device__ int jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps,
             ar = nar, ai = nai, cr = ncr, ci = nci, br = nbr, bi = nbi, dr = ndr, di = ndi;
           }
           if (c2) {
-            const double c = sh.rc[v], s = sh.rs[v], er = sh.rpr[v], ei = -sh.rpi[v];
+            const double c = sh.rot[v][0], s = sh.rot[v][1], er = sh.rot[v][2], ei = -sh.rot[v][3];
             // row p0: x = a, y = b
             double eyr = er * br - ei * bi, eyi = er * bi + ei * br;
             const double nar = c * ar - s * eyr, nai = c * ai - s * eyi;
@@ -220,7 +325,7 @@ __device__ int jacobi_eig_lds(JacobiShared<MAXN, NT>& sh, int n, int max_sweeps,
           int p, q;
           jacobi_pair(m, rho, v, p, q);
           if (q >= n) continue;
-          const double c = sh.rc[v], s = sh.rs[v], er = sh.rpr[v], ei = -sh.rpi[v];
+          const double c = sh.rot[v][0], s = sh.rot[v][1], er = sh.rot[v][2], ei = -sh.rot[v][3];
           const double xr = sh.Vr[i][p], xi = sh.Vi[i][p], yr = sh.Vr[i][q], yi = sh.Vi[i][q];
           const double eyr = er * yr - ei * yi, eyi = er * yi + ei * yr;
           sh.Vr[i][p] = c * xr - s * eyr;

@@ -18,6 +18,9 @@
 // At the end the rows of X are U^H M = Sigma V^H: sigma_i = ||x_i||, and
 //   L = U diag(max(1 - tau / sigma_i, 0)) X = Uh^H (D X).
 #include <cmath>
+#include <memory>
+#include <mutex>
+#include <vector>
 
 #include "common.hpp"
 #include "jacobi.hpp"
@@ -39,6 +42,7 @@ constexpr int kInnerSweeps = 1;
 
 struct PairArgs {
   int64_t K, n1, n2;
+  int64_t k0;        // first slice of this launch (blockIdx.y counts from it)
   float *xre, *xim;  // K x n1 x n2
   float *ure, *uim;  // K x n1 x n1
   int nb;            // number of blocks (even; the last may be partial or empty)
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   __shared__ int rows[PR];
   __shared__ double ratio_red[NT];
   __shared__ int skip;
-  const int64_t k = blockIdx.y;
+  const int64_t k = a.k0 + blockIdx.y;
   const int pair = blockIdx.x;
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   if (a.conv[k]) return;
@@ -263,10 +267,10 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   rotate_rows(vfr, vfi, stage_r, stage_i, ure, uim, a.n1, rows, real);
 }
 
-__global__ void svt_conv_kernel(const float* __restrict__ ratio, int64_t K, int nrounds, int npairs, double tol,
-                                int* conv) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
+__global__ void svt_conv_kernel(const float* __restrict__ ratio, int64_t K, int64_t k0, int64_t k1, int nrounds,
+                                int npairs, double tol, int* conv) {
+  const int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= k1) return;
   if (conv[k]) return;
   float m = 0.f;
   for (int r = 0; r < nrounds; ++r)
@@ -584,6 +588,37 @@ __global__ void gather_slices_kernel(const T* __restrict__ in, int64_t in_cols, 
 
 unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Stream groups of the Jacobi sweeps: the caller's stream and one side
+// stream per device (three or four streams measured slower than two), with
+// the events that fork the side stream from, and join it to, the caller's
+// stream; mu serialises the enqueue of one call.
+constexpr int kSvtStreams = 2;
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int cus = 0;  // compute units of the device
+  std::mutex mu;
+};
+std::mutex g_side_mu;
+std::vector<std::unique_ptr<SideStream>> g_side;
+
+int side_stream(SideStream** out) {
+  int dev = 0;
+  TP_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  if (dev >= (int)g_side.size()) g_side.resize(dev + 1);
+  if (!g_side[dev]) {
+    auto ss = std::make_unique<SideStream>();
+    TP_HIP_CHECK(hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking));
+    TP_HIP_CHECK(hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming));
+    TP_HIP_CHECK(hipEventCreateWithFlags(&ss->join, hipEventDisableTiming));
+    TP_HIP_CHECK(hipDeviceGetAttribute(&ss->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    g_side[dev] = std::move(ss);
+  }
+  *out = g_side[dev].get();
+  return TP_OK;
+}
+
 }  // namespace
 
 size_t svt_ratio_count(int64_t K, int64_t n1) {
@@ -617,15 +652,41 @@ int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_
   const int nb = svt_blocks(n1);
   hipLaunchKernelGGL(zero_int_kernel, dim3(nblk(K)), dim3(256), 0, st, conv, K);
   TP_LAUNCH_CHECK();
-  PairArgs a{K, n1, n2, xre, xim, ure, uim, nb, real_last ? 1 : 0, ratio, conv, tol, kInnerSweeps};
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int round = 0; round < nb - 1; ++round) {
-      hipLaunchKernelGGL(svt_pair_kernel, dim3(nb / 2, (unsigned)K), dim3(NT), 0, st, a, round);
+  PairArgs a{K, n1, n2, 0, xre, xim, ure, uim, nb, real_last ? 1 : 0, ratio, conv, tol, kInnerSweeps};
+  // slices [k0, k1) on stream s
+  auto sweeps = [&](int64_t k0, int64_t k1, hipStream_t s) -> int {
+    PairArgs g = a;
+    g.k0 = k0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      for (int round = 0; round < nb - 1; ++round) {
+        hipLaunchKernelGGL(svt_pair_kernel, dim3(nb / 2, (unsigned)(k1 - k0)), dim3(NT), 0, s, g, round);
+        TP_LAUNCH_CHECK();
+      }
+      hipLaunchKernelGGL(svt_conv_kernel, dim3(nblk(k1 - k0)), dim3(256), 0, s, ratio, K, k0, k1, nb - 1, nb / 2,
+                         tol, conv);
       TP_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(svt_conv_kernel, dim3(nblk(K)), dim3(256), 0, st, ratio, K, nb - 1, nb / 2, tol, conv);
-    TP_LAUNCH_CHECK();
-  }
+    return TP_OK;
+  };
+  // The slices are independent: when one launch would leave compute units
+  // with a free pair-step slot (two fit per compute unit by LDS) but has more
+  // workgroups than compute units, the second half of the slices runs on
+  // the side stream, so that one half's pair steps fill the units that the
+  // other half's launch leaves idle. Measured on 51 slices of 256 x 256 (408
+  // pair steps per launch on 256 units): 7% faster than one stream; on 85
+  // slices of 192 x 1140 (510 pair steps, every slot taken): 7% slower.
+  SideStream* ss = nullptr;
+  if (int rc = side_stream(&ss)) return rc;
+  const int64_t w = K * (nb / 2);
+  if (K < kSvtStreams || w <= ss->cus || 8 * w > 7 * 2 * ss->cus) return sweeps(0, K, st);
+  std::lock_guard<std::mutex> lk(ss->mu);
+  const int64_t kh = K / 2;
+  TP_HIP_CHECK(hipEventRecord(ss->fork, st));
+  TP_HIP_CHECK(hipStreamWaitEvent(ss->s, ss->fork, 0));
+  if (int rc = sweeps(kh, K, ss->s)) return rc;
+  TP_HIP_CHECK(hipEventRecord(ss->join, ss->s));
+  if (int rc = sweeps(0, kh, st)) return rc;
+  TP_HIP_CHECK(hipStreamWaitEvent(st, ss->join, 0));
   return TP_OK;
 }
 

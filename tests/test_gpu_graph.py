@@ -50,3 +50,34 @@ def test_replays_equal_eager_calls():
         torch.cuda.synchronize()
         for got, want in zip((C1, C2, Z), ref):
             assert torch.equal(got, want), rep
+
+
+def test_svt_sweeps_on_two_streams_replay_equal_eager():
+    # 33 slices of 256 x 256 give 264 pair steps per launch, enough for the
+    # sweeps to split over the caller's stream and the side stream; the
+    # fork and join are captured with the rest of the call
+    g0 = torch.Generator().manual_seed(11)
+    M = torch.randn(256, 256, 64, generator=g0).cuda()
+    L1 = torch.empty_like(M)
+    holder = {}
+
+    def call():
+        holder["L"], holder["ranks"] = api.tsvt(M, 30.0, out=L1)
+
+    call()
+    torch.cuda.synchronize()
+    ref_L, ref_ranks = L1.clone(), holder["ranks"].clone()
+    assert int(ref_ranks.min()) > 0 and int(ref_ranks.max()) < 256
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        L1.fill_(float("nan"))
+        holder["ranks"].fill_(-1)
+        api.tsvt(M[:64, :64, :8].contiguous(), 1.0)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(L1, ref_L), rep
+        assert torch.equal(holder["ranks"], ref_ranks), rep
