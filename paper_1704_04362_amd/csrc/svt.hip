@@ -75,6 +75,7 @@ constexpr int kStage = PR * kRotStride;
 // before the current one is consumed keeps the global loads in flight
 // during the products.
 constexpr int kChunkPer = PR * CHC / NT;
+constexpr int kGramDepth = 2, kRotDepth = 1;
 struct ChunkRegs {
   float r[kChunkPer], i[kChunkPer];
 };
@@ -108,6 +109,33 @@ __device__ __forceinline__ void store_chunk(const ChunkRegs& g, double* sr, doub
   }
 }
 
+// Runs body(c0, nc) over the column chunks [c0, c0 + nc) of the staged rows,
+// each chunk stored to the LDS staging arrays (row stride S) before its
+// body. DEPTH (1 or 2) chunks are kept in flight in registers: chunk
+// c + DEPTH is loaded while chunk c is multiplied. Every thread must call
+// it; body must only read the staging arrays.
+template <int S, int DEPTH, class Body>
+__device__ __forceinline__ void staged_chunks(const float* re, const float* im, int64_t ncols, const int* rows,
+                                              bool real, double* sr, double* si, Body&& body) {
+  static_assert(DEPTH == 1 || DEPTH == 2, "one or two chunks in flight");
+  auto width = [ncols](int64_t c) { return (int)((ncols - c) < CHC ? (ncols - c) : CHC); };
+  ChunkRegs g[DEPTH];
+  load_chunk(g[0], re, im, ncols, 0, width(0), rows, real);
+  if (DEPTH == 2 && CHC < ncols) load_chunk(g[DEPTH - 1], re, im, ncols, CHC, width(CHC), rows, real);
+  for (int64_t c0 = 0; c0 < ncols; c0 += DEPTH * CHC) {
+#pragma unroll
+    for (int b = 0; b < DEPTH; ++b) {
+      const int64_t c = c0 + b * CHC;
+      if (c >= ncols) break;
+      store_chunk<S>(g[b], sr, si);
+      __syncthreads();
+      if (c + DEPTH * CHC < ncols) load_chunk(g[b], re, im, ncols, c + DEPTH * CHC, width(c + DEPTH * CHC), rows, real);
+      body(c, width(c));
+      __syncthreads();
+    }
+  }
+}
+
 // Rotates rows rows[0..PR) of a row-major K x nrows x ncols planar matrix by
 // V^H: out_s = sum_t conj(V_ts) in_t, on the float64 matrix cores
 // (v_mfma_f64_16x16x4f64: A lane l = A[l % 16][l / 16], B lane l =
@@ -120,17 +148,7 @@ __device__ void rotate_rows(const double (&vfr)[2][8], const double (&vfi)[2][8]
                             float* re, float* im, int64_t ncols, const int* rows, bool real) {
   const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
   const int j0 = 16 * w;
-  ChunkRegs g;
-  load_chunk(g, re, im, ncols, 0, (int)(ncols < CHC ? ncols : CHC), rows, real);
-  for (int64_t c0 = 0; c0 < ncols; c0 += CHC) {
-    const int nc = (int)((ncols - c0) < CHC ? (ncols - c0) : CHC);
-    store_chunk<kRotStride>(g, sr, si);
-    __syncthreads();
-    // the next chunk's columns are disjoint from the ones written below
-    if (c0 + CHC < ncols) {
-      const int64_t c1 = c0 + CHC;
-      load_chunk(g, re, im, ncols, c1, (int)((ncols - c1) < CHC ? (ncols - c1) : CHC), rows, real);
-    }
+  staged_chunks<kRotStride, kRotDepth>(re, im, ncols, rows, real, sr, si, [&](int64_t c0, int nc) {
     d4 orr[2], oi[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -150,6 +168,7 @@ __device__ void rotate_rows(const double (&vfr)[2][8], const double (&vfi)[2][8]
         oi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-vfi[h][kk], br, oi[h], 0, 0, 0);
       }
     }
+    // the chunks still in flight cover later columns than the ones written
     const int j = j0 + (l & 15);
     if (j < nc) {
 #pragma unroll
@@ -163,8 +182,7 @@ __device__ void rotate_rows(const double (&vfr)[2][8], const double (&vfi)[2][8]
           if (!real) im[off] = (float)oi[h][v];
         }
     }
-    __syncthreads();
-  }
+  });
 }
 
 __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
@@ -194,15 +212,7 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
   const int s0 = 16 * (w >> 1), t0 = 16 * (w & 1);
   d4 gre = {0.0, 0.0, 0.0, 0.0}, gim = {0.0, 0.0, 0.0, 0.0};
   __syncthreads();
-  ChunkRegs g;
-  load_chunk(g, xre, xim, a.n2, 0, (int)(a.n2 < CHC ? a.n2 : CHC), rows, real);
-  for (int64_t c0 = 0; c0 < a.n2; c0 += CHC) {
-    store_chunk<kGramStride>(g, stage_r, stage_i);
-    __syncthreads();
-    if (c0 + CHC < a.n2) {
-      const int64_t c1 = c0 + CHC;
-      load_chunk(g, xre, xim, a.n2, c1, (int)((a.n2 - c1) < CHC ? (a.n2 - c1) : CHC), rows, real);
-    }
+  staged_chunks<kGramStride, kGramDepth>(xre, xim, a.n2, rows, real, stage_r, stage_i, [&](int64_t, int) {
 #pragma unroll 4
     for (int kk = 0; kk < CHC / 4; ++kk) {
       const int j = 4 * kk + (l >> 4);
@@ -213,8 +223,7 @@ __global__ __launch_bounds__(NT) void svt_pair_kernel(PairArgs a, int round) {
       gim = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, gim, 0, 0, 0);
       gim = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar, bi, gim, 0, 0, 0);
     }
-    __syncthreads();
-  }
+  });
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     sh.Hr[s0 + 4 * v + (l >> 4)][t0 + (l & 15)] = gre[v];
