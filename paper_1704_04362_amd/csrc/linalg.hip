@@ -69,21 +69,24 @@ __global__ void randn_kernel(T* re, T* im, int64_t K, int64_t per_slice, int rea
 // Partial cross products: workgroup (k, y) adds conj(x_i) y_j over the rows
 // [y rch, (y + 1) rch) of slice k, X_k rows x a and Y_k rows x b (planar,
 // a, b <= 64), and writes its a x b block to part[(k nch + y) a b] (float64).
-// Rows are staged through LDS 32 at a time; each thread owns a BR x BC block
-// of the output (i in BR (t / 16) .., j in BC (t % 16) ..; the 16 x 16 thread
-// grid covers 16 BR x 16 BC >= a x b), so each row costs it BR + BC complex
-// LDS reads for BR BC complex multiply-adds. The Gram matrix X^H X is the
-// case Y = X.
-template <typename T, int BR, int BC, bool SAME>
-__global__ __launch_bounds__(256) void xgram_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int a,
-                                                    int64_t ldx, int64_t sx, const T* __restrict__ yre,
-                                                    const T* __restrict__ yim, int b, int64_t ldy, int64_t sy,
-                                                    int64_t K, int64_t rows, int real_last, int64_t rch,
-                                                    double* __restrict__ pre, double* __restrict__ pim) {
-  // staged widths: 16 BR columns of X and 16 BC of Y; Y is not staged again when it is X
-  static_assert(!SAME || BR == BC, "a Gram matrix is square");
-  constexpr int CH = 32, WA = 16 * BR, WB = SAME ? 1 : 16 * BC;
-  __shared__ double xr_[CH][WA], xi_[CH][WA], yr_[CH][WB], yi_[CH][WB];
+// The Gram matrix X^H X is the case Y = X. On the float64 matrix cores
+// (v_mfma_f64_16x16x4f64; A lane l = A[l % 16][l / 16], B lane l =
+// B[l / 16][l % 16], D lane l register v = D[4 v + l / 16][l % 16]): the
+// a x b output is cut into 16 x 16 tiles, tile t owned by wavefront t % 4
+// (at most MAXT tiles each); rows are staged through LDS as float64, CH at
+// a time, with row strides of 16 mod 32 doubles (16 consecutive columns of
+// 4 rows per read). re = Xr^T Yr + Xi^T Yi, im = Xr^T Yi - Xi^T Yr.
+typedef double xg_d4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int WA, int WB, int MAXT, bool SAME>
+__global__ __launch_bounds__(256) void xgram_mfma_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int a,
+                                                         int64_t ldx, int64_t sx, const T* __restrict__ yre,
+                                                         const T* __restrict__ yim, int b, int64_t ldy, int64_t sy,
+                                                         int64_t K, int64_t rows, int real_last, int64_t rch,
+                                                         double* __restrict__ pre, double* __restrict__ pim) {
+  static_assert(!SAME || WA == WB, "a Gram matrix is square");
+  constexpr int CH = 16, SA = WA + 16, SB = SAME ? 1 : WB + 16;
+  __shared__ double xr_[CH][SA], xi_[CH][SA], yr_[CH][SB], yi_[CH][SB];
   const int64_t k = blockIdx.x;
   const int64_t nch = gridDim.y;
   const bool real = k == 0 || (real_last && k == K - 1);
@@ -91,72 +94,66 @@ __global__ __launch_bounds__(256) void xgram_kernel(const T* __restrict__ xre, c
   const T* xi = xim + k * sx;
   const T* yr = yre + k * sy;
   const T* yi = yim + k * sy;
-  const int tid = threadIdx.x;
-  const int i0 = BR * (tid >> 4), j0 = BC * (tid & 15);
-  const bool act = i0 < a && j0 < b;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int tb = (b + 15) >> 4, ntile = ((a + 15) >> 4) * tb;
   const int64_t rbeg = (int64_t)blockIdx.y * rch;
   const int64_t rend = (rbeg + rch) < rows ? (rbeg + rch) : rows;
-  double cr[BR][BC], ci[BR][BC];
+  xg_d4 cr[MAXT], ci[MAXT];
 #pragma unroll
-  for (int u = 0; u < BR; ++u)
-#pragma unroll
-    for (int v = 0; v < BC; ++v) cr[u][v] = ci[u][v] = 0.0;
+  for (int q = 0; q < MAXT; ++q) cr[q] = ci[q] = xg_d4{0.0, 0.0, 0.0, 0.0};
   for (int64_t r0 = rbeg; r0 < rend; r0 += CH) {
     for (int e = tid; e < CH * WA; e += 256) {
       const int rr = e / WA, c = e - rr * WA;
       const int64_t row = r0 + rr;
-      const bool live = row < rend;
-      xr_[rr][c] = (live && c < a) ? (double)xr[row * ldx + c] : 0.0;
-      xi_[rr][c] = (live && c < a && !real) ? (double)xi[row * ldx + c] : 0.0;
+      const bool live = row < rend && c < a;
+      xr_[rr][c] = live ? (double)xr[row * ldx + c] : 0.0;
+      xi_[rr][c] = (live && !real) ? (double)xi[row * ldx + c] : 0.0;
     }
     if constexpr (!SAME) {
       for (int e = tid; e < CH * WB; e += 256) {
         const int rr = e / WB, c = e - rr * WB;
         const int64_t row = r0 + rr;
-        const bool live = row < rend;
-        yr_[rr][c] = (live && c < b) ? (double)yr[row * ldy + c] : 0.0;
-        yi_[rr][c] = (live && c < b && !real) ? (double)yi[row * ldy + c] : 0.0;
+        const bool live = row < rend && c < b;
+        yr_[rr][c] = live ? (double)yr[row * ldy + c] : 0.0;
+        yi_[rr][c] = (live && !real) ? (double)yi[row * ldy + c] : 0.0;
       }
     }
     __syncthreads();
-    if (act) {
-      const int nr = (int)((rend - r0) < CH ? (rend - r0) : CH);
-      for (int rr = 0; rr < nr; ++rr) {
-        double pr[BR], pi[BR], qr[BC], qi[BC];
 #pragma unroll
-        for (int u = 0; u < BR; ++u) {
-          pr[u] = xr_[rr][i0 + u];
-          pi[u] = xi_[rr][i0 + u];
-        }
+    for (int kk = 0; kk < CH / 4; ++kk) {
+      const int rr = 4 * kk + (l >> 4);
 #pragma unroll
-        for (int v = 0; v < BC; ++v) {
-          qr[v] = SAME ? xr_[rr][j0 + v] : yr_[rr][j0 + v];
-          qi[v] = SAME ? xi_[rr][j0 + v] : yi_[rr][j0 + v];
-        }
-#pragma unroll
-        for (int u = 0; u < BR; ++u)
-#pragma unroll
-          for (int v = 0; v < BC; ++v) {
-            // conj(x_i) * y_j
-            cr[u][v] += pr[u] * qr[v] + pi[u] * qi[v];
-            ci[u][v] += pr[u] * qi[v] - pi[u] * qr[v];
-          }
+      for (int q = 0; q < MAXT; ++q) {
+        const int t = w + 4 * q;
+        if (t >= ntile) break;
+        const int ti = t / tb, tj = t - ti * tb;
+        const int ci_ = 16 * ti + (l & 15), cj = 16 * tj + (l & 15);
+        const double ar = xr_[rr][ci_], ai = xi_[rr][ci_];
+        const double br = SAME ? xr_[rr][cj] : yr_[rr][cj], bi = SAME ? xi_[rr][cj] : yi_[rr][cj];
+        cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr[q], 0, 0, 0);
+        cr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, cr[q], 0, 0, 0);
+        ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci[q], 0, 0, 0);
+        ci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, ci[q], 0, 0, 0);
       }
     }
     __syncthreads();
   }
-  if (!act) return;
   const int64_t base = (k * nch + blockIdx.y) * (int64_t)a * b;
 #pragma unroll
-  for (int u = 0; u < BR; ++u)
+  for (int q = 0; q < MAXT; ++q) {
+    const int t = w + 4 * q;
+    if (t >= ntile) break;
+    const int ti = t / tb, tj = t - ti * tb;
+    const int j = 16 * tj + (l & 15);
 #pragma unroll
-    for (int v = 0; v < BC; ++v) {
-      const int i = i0 + u, j = j0 + v;
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * ti + 4 * v + (l >> 4);
       if (i < a && j < b) {
-        pre[base + i * b + j] = cr[u][v];
-        pim[base + i * b + j] = real ? 0.0 : ci[u][v];
+        pre[base + i * b + j] = cr[q][v];
+        pim[base + i * b + j] = real ? 0.0 : ci[q][v];
       }
     }
+  }
 }
 
 // out[k][e] = sum over chunks y (in order) of part[k][y][e], as type TO.
@@ -486,32 +483,33 @@ int64_t gram_chunks(int64_t rows) {
 
 size_t gram_part_doubles(int64_t K, int64_t rows, int s) { return (size_t)(K * gram_chunks(rows) * s * s); }
 
-// launches the blocked cross product with the smallest blocks that cover a x b
+// launches the cross product on the matrix cores with the narrowest staging
+// that covers a and b (at most 16 tiles of 16 x 16, four per wavefront)
 template <typename T, bool SAME>
 void launch_xgram(dim3 grid, hipStream_t st, const T* xre, const T* xim, int a, int64_t ldx, int64_t sx,
                   const T* yre, const T* yim, int b, int64_t ldy, int64_t sy, int64_t K, int64_t rows, int rl,
                   int64_t rch, double* pre, double* pim) {
   if constexpr (SAME) {
     if (a <= 32)
-      hipLaunchKernelGGL((xgram_kernel<T, 2, 2, true>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy,
-                         sy, K, rows, rl, rch, pre, pim);
+      hipLaunchKernelGGL((xgram_mfma_kernel<T, 32, 32, 1, true>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre,
+                         yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
     else
-      hipLaunchKernelGGL((xgram_kernel<T, 4, 4, true>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy,
-                         sy, K, rows, rl, rch, pre, pim);
+      hipLaunchKernelGGL((xgram_mfma_kernel<T, 64, 64, 4, true>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre,
+                         yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
     return;
   }
   if (a <= 32 && b <= 32)
-    hipLaunchKernelGGL((xgram_kernel<T, 2, 2, SAME>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
-                       rows, rl, rch, pre, pim);
+    hipLaunchKernelGGL((xgram_mfma_kernel<T, 32, 32, 1, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre,
+                       yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
   else if (b <= 32)
-    hipLaunchKernelGGL((xgram_kernel<T, 4, 2, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
-                       rows, rl, rch, pre, pim);
+    hipLaunchKernelGGL((xgram_mfma_kernel<T, 64, 32, 2, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre,
+                       yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
   else if (a <= 32)
-    hipLaunchKernelGGL((xgram_kernel<T, 2, 4, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
-                       rows, rl, rch, pre, pim);
+    hipLaunchKernelGGL((xgram_mfma_kernel<T, 32, 64, 2, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre,
+                       yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
   else
-    hipLaunchKernelGGL((xgram_kernel<T, 4, 4, SAME>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre, yim, b, ldy, sy, K,
-                       rows, rl, rch, pre, pim);
+    hipLaunchKernelGGL((xgram_mfma_kernel<T, 64, 64, 4, false>), grid, dim3(256), 0, st, xre, xim, a, ldx, sx, yre,
+                       yim, b, ldy, sy, K, rows, rl, rch, pre, pim);
 }
 
 size_t xgram_part_doubles(int64_t K, int64_t rows, int a, int b) {
