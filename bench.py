@@ -261,19 +261,22 @@ def learned_protocol(args, api, torch):
     }
 
 
-def pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, reps=20, Z=None):
+def pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, reps=20, Z=None, factored=False):
     """Median time (HIP events) of the whole t-CUR pipeline at c = l:
     proposal (the network's inference for the learned kind, the range finder
-    for exact leverage), picks, gathers, transforms, core and Z."""
+    for exact leverage), picks, gathers, transforms, core and Z; factored:
+    the same without forming Z (the output is the picks and the core, the
+    C, U, R of Algorithm 5)."""
     Z = torch.empty_like(A) if Z is None else Z
     st = torch.cuda.current_stream()
+    out = dict(want_z=False, want_core=True) if factored else dict(out=Z)
 
     def pipeline():
         if kind == "learned":
             wl = trainer.proposal(A, phi)
-            api.tcur(A, c, c, r, col_kind="user", row_kind="lev", col_w=wl, seed=0, prec=prec, out=Z)
+            api.tcur(A, c, c, r, col_kind="user", row_kind="lev", col_w=wl, seed=0, prec=prec, **out)
         else:
-            api.tcur(A, c, c, r, col_kind=kind, row_kind="lev", seed=0, prec=prec, out=Z)
+            api.tcur(A, c, c, r, col_kind=kind, row_kind="lev", seed=0, prec=prec, **out)
     pipeline()
     torch.cuda.synchronize()
     ts = []
@@ -328,12 +331,15 @@ def time_to_target(args, api, torch, trainer):
             entry = {"c": c, "err_median": err}
             if c is not None:
                 entry["ms"] = pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, Z=Z)
+                entry["ms_factored"] = pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, Z=Z,
+                                                   factored=True)
             res[f"{prec}+{kind}"] = entry
             log(f"time-to-1e-3 {prec}+{kind}: {entry}")
     out = {
         "workload": "t-CUR of a 1024x1024x128 tensor of tubal rank 20 (Gaussian factors) plus N(0,1e-3) noise, r=20, "
                     f"c=l on {{40,60,...,400}}, {args.seeds} seeds, median err <= 1e-3 and p90 <= 1.5e-3, rows by "
-                    "leverage of C, i.i.d. picks; time = whole pipeline at that c (median of 20 runs)",
+                    "leverage of C, i.i.d. picks; time = whole pipeline at that c (median of 20 runs), "
+                    "ms_factored = the same without forming Z (picks and core)",
         "variants": res,
     }
     a, b = res.get("f32+lev", {}).get("ms"), res.get("bf16x3+learned", {}).get("ms")
