@@ -235,11 +235,23 @@ __global__ __launch_bounds__(256) void sketch_sum_kernel(const float* __restrict
 }
 
 // G and sum a from the block shares (fixed order), then the whitening
-// W = G^{-1/2} sqrt(n2) by the float64 Jacobi solver on the 16 x 16 Gram.
+// W = G^{-1/2} sqrt(n2) (the symmetric inverse square root, unique for a
+// positive definite G). With A = G / tr(G) (eigenvalues in (0, 1)), the
+// coupled Newton-Schulz iteration T = (3 I - Z Y) / 2, Y <- Y T, Z <- T Z
+// from Y = A, Z = I takes Z to A^{-1/2} (Higham, Functions of Matrices,
+// sec. 6.3); it stops once max |T - I| <= 1e-12 (the T applied last is then
+// I to second order). If it has not converged after kNsIters steps (G
+// singular or nearly so) the float64 Jacobi solver diagonalises G instead
+// and W = V diag(lambda^{-1/2}) V^T over the positive eigenvalues.
 // wt[0..DS*DS) = W (row-major), wt[DS*DS] = sum a.
+constexpr int kNsIters = 64;
+
 __global__ __launch_bounds__(256) void sketch_whiten_kernel(const double* __restrict__ gpart, int64_t nblk,
                                                              int64_t n2, double* __restrict__ wt) {
+  static_assert(DS * DS == 256, "one Gram entry per thread");
   __shared__ JacobiShared<DS, 256> sh;
+  __shared__ double Y[DS][DS + 1], Z[DS][DS + 1], T[DS][DS + 1];
+  __shared__ double dev[4];
   const int tid = threadIdx.x;
   const int p = tid / DS, q = tid % DS;
   double g = 0.0;
@@ -252,6 +264,47 @@ __global__ __launch_bounds__(256) void sketch_whiten_kernel(const double* __rest
     wt[DS * DS] = at;
   }
   __syncthreads();
+  double tr = 0.0;
+  for (int c = 0; c < DS; ++c) tr += sh.Hr[c][c];
+  bool done = false;
+  if (tr > 0.0 && tr < INFINITY) {
+    const double inv = 1.0 / tr;
+    Y[p][q] = 0.5 * (sh.Hr[p][q] + sh.Hr[q][p]) * inv;
+    Z[p][q] = p == q ? 1.0 : 0.0;
+    __syncthreads();
+    for (int it = 0; it < kNsIters; ++it) {
+      double zy = 0.0;
+#pragma unroll
+      for (int c = 0; c < DS; ++c) zy += Z[p][c] * Y[c][q];
+      const double t = (p == q ? 1.5 : 0.0) - 0.5 * zy;
+      double d = fabs(t - (p == q ? 1.0 : 0.0));
+      d = d == d ? d : INFINITY;  // a NaN never converges
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o));
+      T[p][q] = t;
+      if ((tid & 63) == 0) dev[tid >> 6] = d;
+      __syncthreads();
+      double yn = 0.0, zn = 0.0;
+#pragma unroll
+      for (int c = 0; c < DS; ++c) {
+        yn += Y[p][c] * T[c][q];
+        zn += T[p][c] * Z[c][q];
+      }
+      const double m = fmax(fmax(dev[0], dev[1]), fmax(dev[2], dev[3]));
+      __syncthreads();
+      Y[p][q] = yn;
+      Z[p][q] = zn;
+      __syncthreads();
+      if (m <= 1e-12) {
+        done = true;
+        break;
+      }
+    }
+  }
+  if (done) {
+    wt[tid] = Z[p][q] * sqrt((double)n2 / tr);
+    return;
+  }
   jacobi_eig_lds<DS, 256>(sh, DS, 30, 1e-15);
   double t = 0.0;
   for (int c = 0; c < DS; ++c) {
