@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "tprod.h"
@@ -29,6 +30,19 @@ int fail(int status, const std::string& msg);
   } while (0)
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// A second stream per device (streams.cpp), created on first use, with the
+// events that fork it from, and join it to, a caller's stream: independent
+// work of one call runs on it beside the caller's stream and is joined back
+// before the call's later work. mu serialises the enqueue of one fork-join
+// section; cus is the device's compute-unit count.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int cus = 0;
+  std::mutex mu;
+};
+int side_stream(SideStream** out);
 
 // Bump allocator over a caller workspace. With a null base it only counts
 // (dry run), which is how the *_workspace queries size a call: they run the

@@ -1,0 +1,36 @@
+// Per-device side stream for calls that split independent work over two
+// streams (the two halves of the slices in the singular value
+// thresholding's Jacobi sweeps). Running the t-product's two operand
+// transforms on it measured no faster: the exact product's gained 0.6%, the
+// rt-product's small gathered transforms lost 5% to the fork and join.
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+namespace tp {
+namespace {
+
+std::mutex g_side_mu;
+std::vector<std::unique_ptr<SideStream>> g_side;
+
+}  // namespace
+
+int side_stream(SideStream** out) {
+  int dev = 0;
+  TP_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  if (dev >= (int)g_side.size()) g_side.resize(dev + 1);
+  if (!g_side[dev]) {
+    auto ss = std::make_unique<SideStream>();
+    TP_HIP_CHECK(hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking));
+    TP_HIP_CHECK(hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming));
+    TP_HIP_CHECK(hipEventCreateWithFlags(&ss->join, hipEventDisableTiming));
+    TP_HIP_CHECK(hipDeviceGetAttribute(&ss->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    g_side[dev] = std::move(ss);
+  }
+  *out = g_side[dev].get();
+  return TP_OK;
+}
+
+}  // namespace tp

@@ -18,9 +18,6 @@
 // At the end the rows of X are U^H M = Sigma V^H: sigma_i = ||x_i||, and
 //   L = U diag(max(1 - tau / sigma_i, 0)) X = Uh^H (D X).
 #include <cmath>
-#include <memory>
-#include <mutex>
-#include <vector>
 
 #include "common.hpp"
 #include "jacobi.hpp"
@@ -597,36 +594,9 @@ __global__ void gather_slices_kernel(const T* __restrict__ in, int64_t in_cols, 
 
 unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// Stream groups of the Jacobi sweeps: the caller's stream and one side
-// stream per device (three or four streams measured slower than two), with
-// the events that fork the side stream from, and join it to, the caller's
-// stream; mu serialises the enqueue of one call.
+// The Jacobi sweeps use at most two streams: the caller's and the side
+// stream (three or four streams measured slower than two).
 constexpr int kSvtStreams = 2;
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  int cus = 0;  // compute units of the device
-  std::mutex mu;
-};
-std::mutex g_side_mu;
-std::vector<std::unique_ptr<SideStream>> g_side;
-
-int side_stream(SideStream** out) {
-  int dev = 0;
-  TP_HIP_CHECK(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(g_side_mu);
-  if (dev >= (int)g_side.size()) g_side.resize(dev + 1);
-  if (!g_side[dev]) {
-    auto ss = std::make_unique<SideStream>();
-    TP_HIP_CHECK(hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking));
-    TP_HIP_CHECK(hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming));
-    TP_HIP_CHECK(hipEventCreateWithFlags(&ss->join, hipEventDisableTiming));
-    TP_HIP_CHECK(hipDeviceGetAttribute(&ss->cus, hipDeviceAttributeMultiprocessorCount, dev));
-    g_side[dev] = std::move(ss);
-  }
-  *out = g_side[dev].get();
-  return TP_OK;
-}
 
 }  // namespace
 
