@@ -375,7 +375,17 @@ int cur_core(TcurLayout& lay, int64_t n1, int64_t n2, int64_t n3, int64_t K, int
   if (!Z) return TP_OK;
   // Zhat_k = Chat_k Uhat_k Rhat_k = (Chat_k P_k) (U_r,k^H Rhat_k), then ifft
   if (int rc = mm(lay.Ch, 0, n1, capc, Pw, 0, capc, r, lay.F, K, real_last, dt, prec, st)) return rc;
-  if (int rc = mm(Uw, 1, capl, r, lay.Rh, 0, capl, n2, lay.G, K, real_last, dt, prec, st)) return rc;
+  if (dt == TP_F32) {
+    // U_r^H Rhat as the conjugate transpose of Rhat^H U_r, a narrow product
+    // (r columns) that the streaming kernel takes; staged in Zhat's buffer,
+    // which the next product overwrites
+    if (int rc = mm(lay.Rh, 1, capl, n2, Uw, 0, capl, r, lay.Zh, K, real_last, dt, prec, st)) return rc;
+    if (int rc = spec_conj_transpose((const float*)lay.Zh.re, (const float*)lay.Zh.im, K, n2, r, (float*)lay.G.re,
+                                     (float*)lay.G.im, st))
+      return rc;
+  } else if (int rc = mm(Uw, 1, capl, r, lay.Rh, 0, capl, n2, lay.G, K, real_last, dt, prec, st)) {
+    return rc;
+  }
   if (int rc = mm(lay.F, 0, n1, r, lay.G, 0, r, n2, lay.Zh, K, real_last, dt, prec, st)) return rc;
   return fft_inverse(lay.Zh.re, lay.Zh.im, dt, n3, n1, n2, Z, st);
 }
