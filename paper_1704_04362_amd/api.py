@@ -492,7 +492,7 @@ def mlp_train_step(params, m, v, step, lr, feat, target, want_grad=False):
     return loss, grad
 
 
-def mlp_proposal(params, A, phi, alpha=0.1):
+def mlp_proposal(params, A, phi, alpha=0.4):
     """float64 sampling weights for A's lateral slices from the network."""
     _need_gpu(params, A, phi)
     w = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)

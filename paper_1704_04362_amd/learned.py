@@ -96,7 +96,10 @@ class Trainer:
     def logits(self, feat):
         return api.mlp_forward(self.params, feat)
 
-    def proposal(self, A, phi, alpha=0.1):
+    def proposal(self, A, phi, alpha=0.4):
         """float64 sampling weights for A's lateral slices: (1 - alpha) times
-        the network's softmax plus alpha / n2."""
+        the network's softmax plus alpha / n2. The default weight was chosen
+        on generated tensors outside the training and held-out sets (the
+        largest share of them needing no more slices than uniform sampling
+        for a 1e-3 t-CUR, among 0.1 ... 0.5)."""
         return api.mlp_proposal(self.params, A, phi, alpha)
