@@ -23,11 +23,14 @@ constexpr int kWarmSweeps = 20;
 // iteration, which resumes the rotations from there, so the sweeps of one
 // thresholding are spread over consecutive iterations; the last iteration
 // runs to convergence, so the returned L is the exact thresholding of the
-// last M. On the 256 x 256 x 100 completion workload three sweeps per
-// iteration halve the time of an iteration and move L after 100 iterations
-// by 1.2e-4 (relative Frobenius) from the run that converges every
-// iteration, with the error against L* unchanged to four digits.
-constexpr int kWarmCapSweeps = 3;
+// last M. On the 256 x 256 x 100 completion workload, against the run that
+// converges every iteration (10.7-12.5 ms per warm iteration), two sweeps
+// per iteration take 3.8 ms and move L after 100 iterations by 2.9e-4
+// (relative Frobenius), three take 5.4 ms and move it by 1.2e-4; the error
+// against L* is the same to four digits either way. A looser convergence
+// test for the intermediate iterations saves nothing: warm-started sweeps
+// do not reach even 1e-3 within three sweeps.
+constexpr int kWarmCapSweeps = 2;
 
 struct SvtLayout {
   float *xre = nullptr, *xim = nullptr, *ure = nullptr, *uim = nullptr, *lre = nullptr, *lim = nullptr;

@@ -229,10 +229,10 @@ def test_admm_cap_before_the_stop_test_reports_no_convergence():
 
 
 def test_fixed_count_sweep_budget_at_full_size():
-    """A fixed-count ADMM spends at most three Jacobi sweeps on each
+    """A fixed-count ADMM spends at most two Jacobi sweeps on each
     warm-started iteration but the last; with the stop test (here an
     unreachable one) every iteration runs to convergence. On the
-    256x256x100 completion workload the two runs differ by 1.2e-4 in L after
+    256x256x100 completion workload the two runs differ by 2.9e-4 in L after
     100 iterations (bar: twice that) and agree on the error against L*."""
     G1, G2, N, mask = W.completion_problem()
     Ls = api.tprod(dev(G1), dev(G2), prec="f32")
@@ -242,7 +242,7 @@ def test_fixed_count_sweep_budget_at_full_size():
     info = {}
     Lx, _, _, ranks_x = api.tcomplete(X, m, iters=100, tol=1e-30, info=info)
     assert info == {"iters": 100, "converged": False}
-    assert rel(L.cpu().numpy(), Lx.cpu().numpy()) < 2.5e-4
+    assert rel(L.cpu().numpy(), Lx.cpu().numpy()) < 6e-4
     rse = float(torch.linalg.vector_norm(L - Ls) / torch.linalg.vector_norm(Ls))
     rse_x = float(torch.linalg.vector_norm(Lx - Ls) / torch.linalg.vector_norm(Ls))
     assert abs(rse - rse_x) < 2e-4 * rse_x
