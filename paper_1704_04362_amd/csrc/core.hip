@@ -12,8 +12,9 @@
 //   leading r with sigma_i > rtol sigma_1.
 // orth(X) is CholeskyQR: X^H X = R^H R (pivots at or below 1e-24 of the
 // largest diagonal entry dropped), X <- X R^{-1} by forward substitution
-// along the rows of X. W (l c <= 3600 entries)
-// is read into LDS once and used by every product.
+// along the rows of X. W (l c <= 3600 entries) is read into LDS once and
+// used by every product; the products and Gram matrices run on the float64
+// matrix cores from LDS.
 #include "common.hpp"
 #include "jacobi.hpp"
 #include "linalg.hpp"
@@ -54,83 +55,67 @@ struct CoreArgs {
   float *p32re, *p32im, *u32re, *u32im;   // optional float32 copies
 };
 
-// The products give each thread one row (or column) of W and the result
-// columns t = tq, tq + 16 (s <= 32): the W entries are loaded once for both,
-// and the contraction is unrolled four deep so that eight loads are in
-// flight. 64 rows x 16 column groups = 1024 threads.
+// Products of LDS-resident matrices on the float64 matrix cores
+// (v_mfma_f64_16x16x4f64: A lane l = A[l % 16][l / 16], B lane l =
+// B[l / 16][l % 16], D lane l register v = D[4 v + l / 16][l % 16]):
+// C (M x N) = op(A) B, op(A)[i][k] = A[i lda + k], or conj(A[k lda + i])
+// with CA, all row-major, M, N <= 64 (one 16 x 16 output tile per
+// wavefront of the 16), entries past M, N or K read as zero. C must not
+// overlap A or B.
+typedef double cd4 __attribute__((ext_vector_type(4)));
 
-// Y (m x s) = W Z (Z: n x s in zr / zi)
-__device__ void prod_wz(const CoreArgs& a, CoreShared& sh) {
-  const int tid = threadIdx.x, i = tid >> 4, tq = tid & 15;
-  if (i < a.m) {
-    const bool t1 = tq + 16 < a.s, t0 = tq < a.s;
-    const int u0 = t0 ? tq : 0, u1 = t1 ? tq + 16 : 0;
-    double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
-    const double* pr = sh.wr + i * a.n;
-    const double* pi = sh.wi + i * a.n;
-#pragma unroll 4
-    for (int j = 0; j < a.n; ++j) {
-      const double xr = pr[j], xi = pi[j];
-      ar0 += xr * sh.zr[j][u0] - xi * sh.zi[j][u0];
-      ai0 += xr * sh.zi[j][u0] + xi * sh.zr[j][u0];
-      ar1 += xr * sh.zr[j][u1] - xi * sh.zi[j][u1];
-      ai1 += xr * sh.zi[j][u1] + xi * sh.zr[j][u1];
+template <bool CA>
+__device__ void mm_lds(const double* ar, const double* ai, int lda, const double* br, const double* bi, int ldb,
+                       int M, int N, int K, double* cr, double* ci, int ldc) {
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int tn = (N + 15) >> 4, nt = ((M + 15) >> 4) * tn;
+  if (w < nt) {
+    const int ti = w / tn, tj = w - ti * tn;
+    const int i = 16 * ti + (l & 15), j = 16 * tj + (l & 15);
+    cd4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + (l >> 4);
+      double xr = 0.0, xi = 0.0, yr = 0.0, yi = 0.0;
+      if (k < K && i < M) {
+        const int e = CA ? k * lda + i : i * lda + k;
+        xr = ar[e];
+        xi = CA ? -ai[e] : ai[e];
+      }
+      if (k < K && j < N) {
+        yr = br[k * ldb + j];
+        yi = bi[k * ldb + j];
+      }
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yr, accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi, yi, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(xr, yi, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, yr, acci, 0, 0, 0);
     }
-    if (t0) {
-      sh.yr[i][tq] = ar0;
-      sh.yi[i][tq] = ai0;
-    }
-    if (t1) {
-      sh.yr[i][tq + 16] = ar1;
-      sh.yi[i][tq + 16] = ai1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * ti + 4 * v + (l >> 4);
+      if (row < M && j < N) {
+        cr[row * ldc + j] = accr[v];
+        ci[row * ldc + j] = acci[v];
+      }
     }
   }
   __syncthreads();
+}
+
+// Y (m x s) = W Z (Z: n x s in zr / zi)
+__device__ void prod_wz(const CoreArgs& a, CoreShared& sh) {
+  mm_lds<false>(sh.wr, sh.wi, a.n, &sh.zr[0][0], &sh.zi[0][0], LDY, a.m, a.s, a.n, &sh.yr[0][0], &sh.yi[0][0], LDY);
 }
 
 // Bh (n x s, into zr / zi) = W^H Q (Q: m x s in yr / yi)
 __device__ void prod_whq(const CoreArgs& a, CoreShared& sh) {
-  const int tid = threadIdx.x, j = tid >> 4, tq = tid & 15;
-  if (j < a.n) {
-    const bool t1 = tq + 16 < a.s, t0 = tq < a.s;
-    const int u0 = t0 ? tq : 0, u1 = t1 ? tq + 16 : 0;
-    double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
-#pragma unroll 4
-    for (int i = 0; i < a.m; ++i) {
-      const double xr = sh.wr[i * a.n + j], xi = sh.wi[i * a.n + j];
-      // conj(x) * q
-      ar0 += xr * sh.yr[i][u0] + xi * sh.yi[i][u0];
-      ai0 += xr * sh.yi[i][u0] - xi * sh.yr[i][u0];
-      ar1 += xr * sh.yr[i][u1] + xi * sh.yi[i][u1];
-      ai1 += xr * sh.yi[i][u1] - xi * sh.yr[i][u1];
-    }
-    if (t0) {
-      sh.zr[j][tq] = ar0;
-      sh.zi[j][tq] = ai0;
-    }
-    if (t1) {
-      sh.zr[j][tq + 16] = ar1;
-      sh.zi[j][tq + 16] = ai1;
-    }
-  }
-  __syncthreads();
+  mm_lds<true>(sh.wr, sh.wi, a.n, &sh.yr[0][0], &sh.yi[0][0], LDY, a.n, a.s, a.m, &sh.zr[0][0], &sh.zi[0][0], LDY);
 }
 
 // G (s x s) = X^H X, X rows x s
 __device__ void gram_lds(const double (*xr)[LDY], const double (*xi)[LDY], int rows, int s, CoreShared& sh) {
-  const int tid = threadIdx.x;
-  if (tid < s * s) {
-    const int p = tid / s, q = tid - p * s;
-    double vr = 0.0, vi = 0.0;
-#pragma unroll 4
-    for (int i = 0; i < rows; ++i) {
-      vr += xr[i][p] * xr[i][q] + xi[i][p] * xi[i][q];
-      vi += xr[i][p] * xi[i][q] - xi[i][p] * xr[i][q];
-    }
-    sh.f.gr[p][q] = vr;
-    sh.f.gi[p][q] = vi;
-  }
-  __syncthreads();
+  mm_lds<true>(&xr[0][0], &xi[0][0], LDY, &xr[0][0], &xi[0][0], LDY, s, s, rows, &sh.f.gr[0][0], &sh.f.gi[0][0],
+               CS + 1);
 }
 
 // R from the Gram matrix in gr / gi: register-resident right-looking
