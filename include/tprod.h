@@ -456,7 +456,8 @@ size_t tp_trpca_workspace(const tp_tensor* X);
  * values, mask is tube-major uint8 of X's shape, nonzero where observed) and
  * lambda is ignored; mask == NULL: robust PCA (eq. tlow7) with weight
  * lambda > 0 (0: 1/sqrt(max(n1, n2) n3) of X), the same for C and R; both
- * ADMM runs take exactly `iters` iterations. col_mode and row_mode are
+ * ADMM runs take exactly `iters` iterations (with the sweep budget of
+ * tp_tcomplete's fixed-count iterations). col_mode and row_mode are
  * TP_S_IID or TP_S_UNIFORM (exactly c and l picks; TP_S_UNIFORM with
  * TP_P_UNIFORM); 1 <= r <= min(c, l), r + 10 <= 64; float32 data, prec
  * TP_PREC_F32. L (float32, X's shape) is overwritten. Workspace:
