@@ -58,6 +58,21 @@ def test_tsvt_matches_oracle(shape, frac):
     np.testing.assert_array_equal(ranks.cpu().numpy(), rr)
 
 
+@pytest.mark.parametrize("shape", [(256, 256, 65), (192, 256, 90)])
+def test_tsvt_two_stream_sweeps_match_oracle(shape):
+    # enough pair steps per launch for the sweeps to split the slices over
+    # two streams: 33 slices of 256 x 256 (odd count, no real Nyquist slice,
+    # halves of 16 and 17) and 46 slices of 192 x 256 (a real Nyquist slice
+    # in the second half)
+    rs = np.random.default_rng(sum(shape))
+    M = rs.standard_normal(shape).astype(np.float32)
+    tau = _tau_in_gap(M.astype(np.float64), 0.5)
+    L, ranks = api.tsvt(dev(M), tau)
+    Lr, rr = D.tsvt(M.astype(np.float64), tau)
+    assert rel(L.cpu().numpy(), Lr) < 1e-5
+    np.testing.assert_array_equal(ranks.cpu().numpy(), rr)
+
+
 @pytest.mark.parametrize("shape", [(72, 40, 6), (40, 72, 5)])
 def test_tsvt_graded_spectrum(shape):
     # singular values spread over four decades: pairs of rows whose norms
