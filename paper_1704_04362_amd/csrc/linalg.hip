@@ -164,6 +164,7 @@ __global__ void xgram_reduce_kernel(const double* __restrict__ pre, const double
   if (t >= K * ne) return;
   const int64_t k = t / ne, e = t - k * ne;
   double sr = 0.0, si = 0.0;
+#pragma unroll 8
   for (int64_t y = 0; y < nch; ++y) {
     sr += pre[(k * nch + y) * ne + e];
     si += pim[(k * nch + y) * ne + e];

@@ -280,6 +280,7 @@ __global__ void svt_conv_kernel(const float* __restrict__ ratio, int64_t K, int6
   if (conv[k]) return;
   float m = 0.f;
   for (int r = 0; r < nrounds; ++r)
+#pragma unroll 8
     for (int p = 0; p < npairs; ++p) m = fmaxf(m, ratio[((int64_t)r * K + k) * npairs + p]);
   if (m < tol) conv[k] = 1;
 }
