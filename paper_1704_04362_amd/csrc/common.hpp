@@ -35,11 +35,10 @@ inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // events that fork it from, and join it to, a caller's stream: independent
 // work of one call runs on it beside the caller's stream and is joined back
 // before the call's later work. mu serialises the enqueue of one fork-join
-// section; cus is the device's compute-unit count.
+// section.
 struct SideStream {
   hipStream_t s = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
-  int cus = 0;
   std::mutex mu;
 };
 int side_stream(SideStream** out);

@@ -26,7 +26,6 @@ int side_stream(SideStream** out) {
     TP_HIP_CHECK(hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking));
     TP_HIP_CHECK(hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming));
     TP_HIP_CHECK(hipEventCreateWithFlags(&ss->join, hipEventDisableTiming));
-    TP_HIP_CHECK(hipDeviceGetAttribute(&ss->cus, hipDeviceAttributeMultiprocessorCount, dev));
     g_side[dev] = std::move(ss);
   }
   *out = g_side[dev].get();

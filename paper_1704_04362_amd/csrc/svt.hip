@@ -655,10 +655,13 @@ int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_
   // other half's launch leaves idle. Measured on 51 slices of 256 x 256 (408
   // pair steps per launch on 256 units): 7% faster than one stream; on 85
   // slices of 192 x 1140 (510 pair steps, every slot taken): 7% slower.
+  int dev = 0, cus = 0;
+  TP_HIP_CHECK(hipGetDevice(&dev));
+  TP_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t w = K * (nb / 2);
+  if (K < kSvtStreams || w <= cus || 8 * w > 7 * 2 * (int64_t)cus) return sweeps(0, K, st);
   SideStream* ss = nullptr;
   if (int rc = side_stream(&ss)) return rc;
-  const int64_t w = K * (nb / 2);
-  if (K < kSvtStreams || w <= ss->cus || 8 * w > 7 * 2 * ss->cus) return sweeps(0, K, st);
   std::lock_guard<std::mutex> lk(ss->mu);
   const int64_t kh = K / 2;
   TP_HIP_CHECK(hipEventRecord(ss->fork, st));
