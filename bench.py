@@ -261,6 +261,24 @@ def learned_protocol(args, api, torch):
     }
 
 
+def tcur_hbm_bytes(n1, n2, n3, c, kind, factored=False):
+    """Algorithmic HBM bytes of one t-CUR call at c = l (float32 data, float32
+    spectra): the proposal's passes (learned and norm2: one read of A;
+    exact leverage: the transform of A, read and written, and the four passes
+    of the q = 1 range finder over its spectrum), the gathered C and R read
+    and their spectra written, four passes over C's spectrum for the row
+    leverage, and, unless factored, Z's spectrum written and read back and Z
+    written."""
+    K = n3 // 2 + 1
+    a = 4 * n1 * n2 * n3
+    spec = 8 * K * n1 * n2
+    prop = {"uniform": 0, "norm2": a, "learned": a, "lev": a + spec + 4 * spec}[kind]
+    cr = 4 * (n1 * c + c * n2) * n3 + 8 * K * (n1 * c + c * n2)
+    rows = 4 * 8 * K * n1 * c
+    z = 0 if factored else 2 * spec + a
+    return prop + cr + rows + z
+
+
 def pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, reps=20, Z=None, factored=False):
     """Median time (HIP events) of the whole t-CUR pipeline at c = l:
     proposal (the network's inference for the learned kind, the range finder
@@ -333,13 +351,20 @@ def time_to_target(args, api, torch, trainer):
                 entry["ms"] = pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, Z=Z)
                 entry["ms_factored"] = pipeline_ms(api, torch, A, r, kind, prec, c, trainer, phi, Z=Z,
                                                    factored=True)
+                # the HBM floor of the call at 8 TB/s (algorithmic bytes) and the fraction reached
+                n1, n2, n3 = A.shape
+                for key, fac in (("", False), ("_factored", True)):
+                    floor = tcur_hbm_bytes(n1, n2, n3, c, kind, fac) / 8e12 * 1e3
+                    entry["hbm_floor_ms" + key] = round(floor, 4)
+                    entry["frac_of_hbm_floor" + key] = round(floor / entry["ms" + key], 3)
             res[f"{prec}+{kind}"] = entry
             log(f"time-to-1e-3 {prec}+{kind}: {entry}")
     out = {
         "workload": "t-CUR of a 1024x1024x128 tensor of tubal rank 20 (Gaussian factors) plus N(0,1e-3) noise, r=20, "
                     f"c=l on {{40,60,...,400}}, {args.seeds} seeds, median err <= 1e-3 and p90 <= 1.5e-3, rows by "
                     "leverage of C, i.i.d. picks; time = whole pipeline at that c (median of 20 runs), "
-                    "ms_factored = the same without forming Z (picks and core)",
+                    "ms_factored = the same without forming Z (picks and core); hbm_floor_ms = the call's "
+                    "algorithmic HBM bytes (tcur_hbm_bytes) at 8 TB/s",
         "variants": res,
     }
     a, b = res.get("f32+lev", {}).get("ms"), res.get("bf16x3+learned", {}).get("ms")
