@@ -412,6 +412,21 @@ def traced(fn, api):
     return {k: round(v[1], 3) for k, v in tr.items()}
 
 
+def svt_floor_ms(n1, n2, n3, sweeps=2):
+    """Float64 floor of one warm ADMM iteration's slice SVDs in this design:
+    `sweeps` block Jacobi sweeps (16-row blocks, the tournament's nb - 1
+    rounds of nb / 2 pair steps on the shorter side m) whose pair steps each
+    form a 32 x 32 Gram matrix over the long side n and rotate 32 rows of
+    length n and m (8 flops per complex multiply-add), at the 78.6 TFLOP/s
+    float64 peak."""
+    K = n3 // 2 + 1
+    m, n = min(n1, n2), max(n1, n2)
+    nb = max(2, (m + 15) // 16)
+    nb += nb % 2
+    flops = sweeps * (nb - 1) * (nb // 2) * K * 8 * 32 * 32 * (2 * n + m)
+    return flops / 78.6e12 * 1e3
+
+
 def tnn_protocol(args, api, torch):
     """The ADMM of Algorithm 7 on the whole tensor against CUR t-NN
     (Algorithm 6), for completion (256x256x100, tubal rank 15, 50% observed)
@@ -433,8 +448,10 @@ def tnn_protocol(args, api, torch):
     del G1, G2, N, mask
     api.tcomplete(X, m, iters=2)
     ms, (L, _, _, ranks) = timed_once(lambda: api.tcomplete(X, m, iters=it), torch)
+    fl = svt_floor_ms(*X.shape)
     comp = {"full_admm": {"ms": round(ms, 2), "ms_per_iter": round(ms / it, 3), "rse": rse(L, Ls),
-                          "max_rank": int(ranks.max()),
+                          "max_rank": int(ranks.max()), "svt_fp64_floor_ms_per_iter": round(fl, 3),
+                          "frac_of_svt_floor": round(fl / (ms / it), 3),
                           "stages_ms": traced(lambda: api.tcomplete(X, m, iters=it), api)}}
     for c in (64, 128):
         def run(c=c):
@@ -464,8 +481,11 @@ def tnn_protocol(args, api, torch):
     rp = {}
     api.trpca(X, lam, iters=2)
     ms, (L, E, _, ranks) = timed_once(lambda: api.trpca(X, lam, iters=it), torch)
+    fl = svt_floor_ms(n1, n2, n3)
     rp["full_admm"] = {"ms": round(ms, 2), "ms_per_iter": round(ms / it, 3), "rse": rse(L, Ls),
-                       "max_rank": int(ranks.max()), "stages_ms": traced(lambda: api.trpca(X, lam, iters=it), api)}
+                       "max_rank": int(ranks.max()), "svt_fp64_floor_ms_per_iter": round(fl, 3),
+                       "frac_of_svt_floor": round(fl / (ms / it), 3),
+                       "stages_ms": traced(lambda: api.trpca(X, lam, iters=it), api)}
     log(f"robust PCA full ADMM: {rp['full_admm']['ms']} ms, rse {rp['full_admm']['rse']}")
     for c, l in ((300, 96),):
         def run(c=c, l=l):
