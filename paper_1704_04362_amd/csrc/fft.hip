@@ -20,8 +20,9 @@
 //      and each slice k is written with one coalesced store per wavefront.
 // The inverse kernel runs these steps backwards. Long tubes (n3 above 256
 // without a specialised kernel, prime factors up to 13) use a
-// workgroup-per-tube mixed-radix transform in LDS; other lengths without a
-// specialised kernel use a direct O(n3^2) transform per tube.
+// workgroup-per-tube mixed-radix transform in LDS; even ones beyond its LDS
+// budget (up to 2^19) a four-step transform through HBM; other lengths
+// without a specialised kernel use a direct O(n3^2) transform per tube.
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -695,6 +696,360 @@ bool long_plan(int64_t n, int elem_bytes, LongPlan& pl) {
   return r == 1;
 }
 
+// --------------------------------------------------------------------------
+// Tubes beyond the LDS budget: a four-step transform through HBM, with the
+// caller's output as the only intermediate storage. The real tube x of even
+// length n is packed as z[m] = x[2m] + i x[2m+1], m < N = n/2, and with
+// N = N1 N2, m = j1 + N1 j2, k = k2 + N2 k1 its DFT factors as
+//   Z[k2 + N2 k1] = sum_j1 W_N1^{j1 k1} W_N^{j1 k2} sum_j2 z[j1 + N1 j2] W_N2^{j2 k2}
+// (W_L = exp(-2 pi i / L)). Forward:
+//   tube pass: per tube and j1 the inner length-N2 transform over j2 and the
+//     twiddle W_N^{j1 k2}, written to spectrum slice k2 + N2 j1 of that
+//     tube's slot;
+//   slice pass: per slot block and pair {k2, N2 - k2} the outer length-N1
+//     transforms over j1 (the partner Z[N - k] of every Z[k] of the pair is
+//     in the pair), then X[k] = E[k] + W_n^k O[k] for k <= N, with
+//     E[k] = (Z[k] + conj Z[N-k]) / 2, O[k] = (Z[k] - conj Z[N-k]) / 2i, written
+//     to slice k: exactly the slices the pair's intermediate values occupy, so
+//     each workgroup overwrites only what it has read.
+// Inverse (the steps reversed, conjugated, into the output tensor):
+//   slice pass: per slot block and k2, Z[k] = E[k] + i O[k] from the half
+//     spectrum (E = (X[k] + conj X[N-k]) / 2, O = (X[k] - conj X[N-k]) W_n^-k / 2),
+//     the inverse transform over k1 and the twiddle W_N^{-j1 k2}, written
+//     into the tube at packed position j1 + N1 k2;
+//   tube pass: per tube and j1 the inverse transform over k2, 1/N, and the
+//     real and imaginary parts as x[2m], x[2m+1] at the positions it read.
+// Both short transforms run in LDS as the mixed-radix stages above, several
+// sequences per workgroup (FsGeom: slots x j1 values of length N2 <= 256 in
+// the tube pass, slots x the pair of length N1 <= 1024 in the slice pass, at
+// most 64 KB of LDS), so tubes up to n = 2 x 256 x 1024 with no prime factor
+// above 13 take this path; longer or other lengths beyond the LDS budget
+// take the direct transform.
+// --------------------------------------------------------------------------
+constexpr int kFsMaxN2 = 256, kFsMaxN1 = 1024, kFsNT = 256;
+
+template <typename T>
+struct FsGeom;
+template <>
+struct FsGeom<float> {
+  static constexpr int tubes = 8, j1s = 4, stubes = 4;  // tube pass: 8 slots x 4 j1; slice pass: 4 slots
+};
+template <>
+struct FsGeom<double> {
+  static constexpr int tubes = 4, j1s = 4, stubes = 2;
+};
+
+struct FourStep {
+  int N1, N2;
+  LongPlan p1, p2;  // radix plans of lengths N1 and N2
+};
+
+// mixed-radix stages of `nseq` sequences of length pl.n, sequence s at
+// offset s * pl.n (loaded in digit-reversed order)
+template <typename T>
+__device__ void multi_stages(const LongPlan& pl, T* ar, T* ai, int nseq) {
+  const int n = pl.n;
+  int m = 1;
+  for (int q = 0; q < pl.nst; ++q) {
+    const int p = pl.rad[q], span = m * p, per = n / p;
+    double cw[kLongMaxRadix], sw[kLongMaxRadix];
+    for (int e = 0; e < p; ++e) sincospi(-2.0 * e / p, &sw[e], &cw[e]);
+    for (int b = threadIdx.x; b < nseq * per; b += kFsNT) {
+      const int sq = b / per, bb = b - sq * per;
+      const int j = bb % m, g = sq * n + (bb / m) * span;
+      double vr[kLongMaxRadix], vi[kLongMaxRadix];
+      for (int t = 0; t < p; ++t) {
+        const double xr = (double)ar[g + j + t * m], xi = (double)ai[g + j + t * m];
+        double sn, cs;
+        sincospi(-2.0 * ((j * t) % span) / span, &sn, &cs);
+        vr[t] = xr * cs - xi * sn;
+        vi[t] = xr * sn + xi * cs;
+      }
+      for (int t = 0; t < p; ++t) {
+        double accr = 0.0, acci = 0.0;
+        for (int u = 0; u < p; ++u) {
+          const int e = (u * t) % p;
+          accr += vr[u] * cw[e] - vi[u] * sw[e];
+          acci += vr[u] * sw[e] + vi[u] * cw[e];
+        }
+        ar[g + j + t * m] = (T)accr;
+        ai[g + j + t * m] = (T)acci;
+      }
+    }
+    __syncthreads();
+    m = span;
+  }
+}
+
+// exp(-2 pi i e / L) for 0 <= e < L
+__device__ __forceinline__ void fs_root(int64_t e, int64_t L, double& c, double& s) {
+  sincospi(-2.0 * (double)e / (double)L, &s, &c);
+}
+
+// forward tube pass: workgroup (slot block, j1 block)
+template <typename T>
+__global__ __launch_bounds__(kFsNT) void fs_fwd_tube_kernel(const T* __restrict__ x, FwdArgs a, FourStep fs,
+                                                            T* __restrict__ ore, T* __restrict__ oim) {
+  constexpr int TB = FsGeom<T>::tubes, JB = FsGeom<T>::j1s;
+  extern __shared__ unsigned char fs_lds[];
+  const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2;
+  T* ar = reinterpret_cast<T*>(fs_lds);
+  T* ai = ar + TB * JB * N2;
+  const int64_t t0 = (int64_t)blockIdx.x * TB;
+  const int j10 = blockIdx.y * JB;
+  const int64_t ks = a.ntubes;
+  // load: sequence (tube u, j1 offset v) at (u JB + v) N2, position pos holds
+  // z[j1 + N1 j2] with j2 = long_src(pos)
+  for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
+    const int sq = e / N2, pos = e - sq * N2;
+    const int u = sq / JB, v = sq - u * JB;
+    const int64_t t = t0 + u;
+    const int j1 = j10 + v;
+    T vr = T(0), vi = T(0);
+    int64_t src;
+    double sc;
+    if (t < ks && j1 < N1 && tube_source(a, t, src, sc)) {
+      const int64_t m = j1 + (int64_t)N1 * long_src(fs.p2, pos);
+      const T* xt = x + src * (int64_t)(2 * N);
+      vr = (sc == 1.0) ? xt[2 * m] : (T)((double)xt[2 * m] * sc);
+      vi = (sc == 1.0) ? xt[2 * m + 1] : (T)((double)xt[2 * m + 1] * sc);
+    }
+    ar[e] = vr;
+    ai[e] = vi;
+  }
+  __syncthreads();
+  multi_stages<T>(fs.p2, ar, ai, TB * JB);
+  // twiddle W_N^{j1 k2}; value (t, j1, k2) goes to slice k2 + N2 j1 of slot t
+  for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
+    const int k2 = e / (TB * JB), r = e - k2 * (TB * JB);
+    const int v = r / TB, u = r - v * TB;  // slots fastest: neighbouring stores
+    const int64_t t = t0 + u;
+    const int j1 = j10 + v;
+    if (t >= ks || j1 >= N1) continue;
+    const int li = (u * JB + v) * N2 + k2;
+    double c, sn;
+    fs_root(((int64_t)j1 * k2) % N, N, c, sn);
+    const double xr = (double)ar[li], xi = (double)ai[li];
+    const int64_t o = ((int64_t)k2 + (int64_t)N2 * j1) * ks + t;
+    ore[o] = (T)(xr * c - xi * sn);
+    oim[o] = (T)(xr * sn + xi * c);
+  }
+}
+
+// forward slice pass: workgroup (slot block, pair {k2, N2 - k2})
+template <typename T>
+__global__ __launch_bounds__(kFsNT) void fs_fwd_slice_kernel(FourStep fs, int64_t ks, T* __restrict__ ore,
+                                                             T* __restrict__ oim) {
+  constexpr int TB = FsGeom<T>::stubes;
+  extern __shared__ unsigned char fs_lds[];
+  const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2;
+  T* ar = reinterpret_cast<T*>(fs_lds);
+  T* ai = ar + 2 * TB * N1;
+  const int64_t t0 = (int64_t)blockIdx.x * TB;
+  const int ka = blockIdx.y, kb = (N2 - ka) % N2;
+  const int nk = ka == kb ? 1 : 2;
+  // sequence (h, u) at (h TB + u) N1 holds the values of slice k2 = (ka, kb)[h]
+  // of slot t0 + u, position pos holding j1 = long_src(pos)
+  for (int e = threadIdx.x; e < nk * TB * N1; e += kFsNT) {
+    const int pos = e / (nk * TB), r = e - pos * (nk * TB);
+    const int h = r / TB, u = r - h * TB;
+    const int64_t t = t0 + u;
+    const int k2 = h ? kb : ka;
+    T vr = T(0), vi = T(0);
+    if (t < ks) {
+      const int64_t o = ((int64_t)k2 + (int64_t)N2 * long_src(fs.p1, pos)) * ks + t;
+      vr = ore[o];
+      vi = oim[o];
+    }
+    ar[(h * TB + u) * N1 + pos] = vr;
+    ai[(h * TB + u) * N1 + pos] = vi;
+  }
+  __syncthreads();
+  multi_stages<T>(fs.p1, ar, ai, nk * TB);
+  // X[k] = E[k] + W_n^k O[k] for the k of this pair (and k = N with k2 = 0)
+  const int n = 2 * N;
+  const int nout = nk * N1 + (ka == 0 ? 1 : 0);
+  for (int e = threadIdx.x; e < nout * TB; e += kFsNT) {
+    const int q = e / TB, u = e - q * TB;
+    const int64_t t = t0 + u;
+    if (t >= ks) continue;
+    // the q-th output of the pair: slice (ka, kb)[q / N1] + N2 (q mod N1), or N
+    const int k = q < nk * N1 ? (q < N1 ? ka : kb) + N2 * (q % N1) : N;
+    // Z[k mod N] and Z[(N - k) mod N], both among the pair's sequences
+    const int kk = k % N, km = (N - kk) % N;
+    const int ha = kk % N2 == ka ? 0 : 1, hb = km % N2 == ka ? 0 : 1;
+    const int ia = (ha * TB + u) * N1 + kk / N2, ib = (hb * TB + u) * N1 + km / N2;
+    const double zr = (double)ar[ia], zi = (double)ai[ia];
+    const double wr = (double)ar[ib], wi = -(double)ai[ib];  // conj Z[N - k]
+    const double er = 0.5 * (zr + wr), ei = 0.5 * (zi + wi);
+    const double orr = 0.5 * (zi - wi), oi = -0.5 * (zr - wr);  // (Z - conj Z[N-k]) / 2i
+    double c, sn;
+    fs_root(k, n, c, sn);
+    const double xr = er + (orr * c - oi * sn);
+    const double xi = (k == 0 || k == N) ? 0.0 : ei + (orr * sn + oi * c);
+    const int64_t o = (int64_t)k * ks + t;
+    ore[o] = (T)xr;
+    oim[o] = (T)xi;
+  }
+}
+
+// inverse slice pass: workgroup (slot block, k2)
+template <typename T>
+__global__ __launch_bounds__(kFsNT) void fs_inv_slice_kernel(const T* __restrict__ xre, const T* __restrict__ xim,
+                                                             int64_t ntubes, FourStep fs, T* __restrict__ y) {
+  constexpr int TB = FsGeom<T>::stubes;
+  extern __shared__ unsigned char fs_lds[];
+  const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2, n = 2 * N;
+  T* ar = reinterpret_cast<T*>(fs_lds);
+  T* ai = ar + TB * N1;
+  const int64_t t0 = (int64_t)blockIdx.x * TB;
+  const int k2 = blockIdx.y;
+  // conj Z[k2 + N2 k1] at position pos of sequence u (k1 = long_src(pos)):
+  // the forward stages of the conjugate give the conjugate of the inverse
+  for (int e = threadIdx.x; e < TB * N1; e += kFsNT) {
+    const int pos = e / TB, u = e - pos * TB;
+    const int64_t t = t0 + u;
+    T vr = T(0), vi = T(0);
+    if (t < ntubes) {
+      const int k = k2 + N2 * long_src(fs.p1, pos);
+      const int km = N - k;  // 1 <= km <= N
+      const double ar0 = (double)xre[(int64_t)k * ntubes + t];
+      const double ai0 = k == 0 ? 0.0 : (double)xim[(int64_t)k * ntubes + t];
+      const double br = (double)xre[(int64_t)km * ntubes + t];
+      const double bi = km == N ? 0.0 : -(double)xim[(int64_t)km * ntubes + t];  // conj X[N-k]
+      const double er = 0.5 * (ar0 + br), ei = 0.5 * (ai0 + bi);
+      const double dr = 0.5 * (ar0 - br), di = 0.5 * (ai0 - bi);
+      double c, sn;
+      fs_root(k, n, c, sn);  // W_n^k; O = D conj(W_n^k)
+      const double orr = dr * c + di * sn, oi = di * c - dr * sn;
+      // Z = E + i O
+      vr = (T)(er - oi);
+      vi = (T)(-(ei + orr));  // conjugated
+    }
+    ar[u * N1 + pos] = vr;
+    ai[u * N1 + pos] = vi;
+  }
+  __syncthreads();
+  multi_stages<T>(fs.p1, ar, ai, TB);
+  // u[j1] = conj(stage result) W_N^{-j1 k2}, stored at packed position
+  // j1 + N1 k2 of the slot's tube
+  for (int e = threadIdx.x; e < TB * N1; e += kFsNT) {
+    const int u = e / N1, j1 = e - u * N1;
+    const int64_t t = t0 + u;
+    if (t >= ntubes) continue;
+    const double vr = (double)ar[u * N1 + j1], vi = -(double)ai[u * N1 + j1];
+    double c, sn;
+    fs_root(((int64_t)j1 * k2) % N, N, c, sn);  // W_N^{j1 k2}; multiply by its conjugate
+    const int64_t o = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * k2);
+    y[o] = (T)(vr * c + vi * sn);
+    y[o + 1] = (T)(vi * c - vr * sn);
+  }
+}
+
+// inverse tube pass: workgroup (slot block, j1 block), in place in y
+template <typename T>
+__global__ __launch_bounds__(kFsNT) void fs_inv_tube_kernel(int64_t ntubes, FourStep fs, T* __restrict__ y) {
+  constexpr int TB = FsGeom<T>::tubes, JB = FsGeom<T>::j1s;
+  extern __shared__ unsigned char fs_lds[];
+  const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2, n = 2 * N;
+  T* ar = reinterpret_cast<T*>(fs_lds);
+  T* ai = ar + TB * JB * N2;
+  const int64_t t0 = (int64_t)blockIdx.x * TB;
+  const int j10 = blockIdx.y * JB;
+  for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
+    const int sq = e / N2, pos = e - sq * N2;
+    const int u = sq / JB, v = sq - u * JB;
+    const int64_t t = t0 + u;
+    const int j1 = j10 + v;
+    T vr = T(0), vi = T(0);
+    if (t < ntubes && j1 < N1) {
+      const int64_t o = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * long_src(fs.p2, pos));
+      vr = y[o];
+      vi = -y[o + 1];  // conjugate in, conjugate out
+    }
+    ar[e] = vr;
+    ai[e] = vi;
+  }
+  __syncthreads();
+  multi_stages<T>(fs.p2, ar, ai, TB * JB);
+  const double inv = 1.0 / (double)N;
+  for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
+    const int u = e / (JB * N2), r = e - u * (JB * N2);
+    const int j2 = r / JB, v = r - j2 * JB;  // j1 fastest: neighbouring stores
+    const int64_t t = t0 + u;
+    const int j1 = j10 + v;
+    if (t >= ntubes || j1 >= N1) continue;
+    const int li = (u * JB + v) * N2 + j2;
+    const int64_t o = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * j2);
+    y[o] = (T)((double)ar[li] * inv);
+    y[o + 1] = (T)(-(double)ai[li] * inv);
+  }
+}
+
+// radix plan of a short length (factors 4, 2, 3, 5, 7, 11, 13), no size limits
+bool radix_plan(int64_t n, LongPlan& pl) {
+  pl.n = (int)n;
+  pl.nst = 0;
+  int64_t r = n;
+  for (int p : {4, 2, 3, 5, 7, 11, 13}) {
+    while (r % p == 0) {
+      if (pl.nst == kLongMaxStages) return false;
+      pl.rad[pl.nst++] = p;
+      r /= p;
+    }
+  }
+  return r == 1;
+}
+
+// Four-step plan of an even n: N = n/2 = N1 N2 with N2 the largest divisor
+// <= kFsMaxN2 that leaves N1 <= kFsMaxN1, both without prime factors above 13.
+bool four_step_plan(int64_t n, FourStep& fs) {
+  if (n % 2 || n < 4) return false;
+  const int64_t N = n / 2;
+  if (N > (int64_t)kFsMaxN1 * kFsMaxN2) return false;
+  for (int64_t n2 = kFsMaxN2 < N ? kFsMaxN2 : N; n2 >= 1; --n2) {
+    if (N % n2) continue;
+    const int64_t n1 = N / n2;
+    if (n1 > kFsMaxN1) break;
+    if (radix_plan(n1, fs.p1) && radix_plan(n2, fs.p2)) {
+      fs.N1 = (int)n1;
+      fs.N2 = (int)n2;
+      return true;
+    }
+  }
+  return false;
+}
+
+template <typename T>
+int fs_forward(const T* x, const FwdArgs& a, const FourStep& fs, T* re, T* im, hipStream_t st) {
+  constexpr int TB = FsGeom<T>::tubes, JB = FsGeom<T>::j1s, SB = FsGeom<T>::stubes;
+  const int64_t bt = (a.ntubes + TB - 1) / TB, bs = (a.ntubes + SB - 1) / SB;
+  if (bt > 0x7fffffffLL || bs > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+  const size_t lt = size_t(2) * TB * JB * fs.N2 * sizeof(T), ls = size_t(2) * 2 * SB * fs.N1 * sizeof(T);
+  hipLaunchKernelGGL(fs_fwd_tube_kernel<T>, dim3((unsigned)bt, (unsigned)((fs.N1 + JB - 1) / JB)), dim3(kFsNT), lt,
+                     st, x, a, fs, re, im);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(fs_fwd_slice_kernel<T>, dim3((unsigned)bs, (unsigned)(fs.N2 / 2 + 1)), dim3(kFsNT), ls, st, fs,
+                     a.ntubes, re, im);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+template <typename T>
+int fs_inverse(const T* re, const T* im, int64_t ntubes, const FourStep& fs, T* y, hipStream_t st) {
+  constexpr int TB = FsGeom<T>::tubes, JB = FsGeom<T>::j1s, SB = FsGeom<T>::stubes;
+  const int64_t bt = (ntubes + TB - 1) / TB, bs = (ntubes + SB - 1) / SB;
+  if (bt > 0x7fffffffLL || bs > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+  const size_t lt = size_t(2) * TB * JB * fs.N2 * sizeof(T), ls = size_t(2) * SB * fs.N1 * sizeof(T);
+  hipLaunchKernelGGL(fs_inv_slice_kernel<T>, dim3((unsigned)bs, (unsigned)fs.N2), dim3(kFsNT), ls, st, re, im, ntubes,
+                     fs, y);
+  TP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(fs_inv_tube_kernel<T>, dim3((unsigned)bt, (unsigned)((fs.N1 + JB - 1) / JB)), dim3(kFsNT), lt,
+                     st, ntubes, fs, y);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
 template <typename T>
 using FwdKernel = void (*)(const T*, FwdArgs, T*, T*);
 template <typename T>
@@ -752,6 +1107,8 @@ int fwd_impl(const T* x, int64_t n3, const TubeGather& g, T* re, T* im, hipStrea
     if (a.ntubes > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
     hipLaunchKernelGGL(rfft_long_kernel<T>, dim3((unsigned)a.ntubes), dim3(kLongNT), 2 * n3 * sizeof(T), st, x, a,
                        pl, re, im);
+  } else if (FourStep fs; n3 >= kLongMin && four_step_plan(n3, fs)) {
+    return fs_forward<T>(x, a, fs, (T*)re, (T*)im, st);
   } else {
     const int64_t blocks = (a.ntubes + 127) / 128;
     if (n3 <= kDirectTable)
@@ -775,6 +1132,8 @@ int inv_impl(const T* re, const T* im, int64_t n3, int64_t ntubes, T* y, hipStre
     if (ntubes > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
     hipLaunchKernelGGL(irfft_long_kernel<T>, dim3((unsigned)ntubes), dim3(kLongNT), 2 * n3 * sizeof(T), st, re, im,
                        ntubes, pl, y);
+  } else if (FourStep fs; n3 >= kLongMin && four_step_plan(n3, fs)) {
+    return fs_inverse<T>(re, im, ntubes, fs, y, st);
   } else {
     const int64_t blocks = (ntubes + 127) / 128;
     if (n3 <= kDirectTable)

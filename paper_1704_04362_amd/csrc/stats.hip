@@ -85,6 +85,42 @@ __global__ __launch_bounds__(LNT) void lateral_partial_kernel(const T* __restric
   }
 }
 
+// Long tubes (the piece table of the kernel above would exceed 64 KB): one
+// workgroup per (tube j, block of LROWS rows), each thread summing fixed
+// 16-byte pieces of the block's tubes, then a fixed-order tree over the
+// threads.
+template <typename T>
+__global__ __launch_bounds__(LNT) void lateral_long_kernel(const T* __restrict__ a, int64_t n1, int64_t n2,
+                                                            int64_t n3, double* __restrict__ partial) {
+  using V = typename V16<T>::type;
+  constexpr int VN = V16<T>::n;
+  __shared__ double red[LNT];
+  const int64_t j = blockIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * LROWS;
+  const int64_t rows = (n1 - i0) < LROWS ? (n1 - i0) : LROWS;
+  double s = 0.0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const T* tube = a + ((i0 + r) * n2 + j) * n3;
+    if (n3 % VN == 0) {
+      for (int64_t f = threadIdx.x; f < n3 / VN; f += LNT) {
+        const V w = *reinterpret_cast<const V*>(tube + f * VN);
+        const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) s += (double)wp[e] * (double)wp[e];
+      }
+    } else {
+      for (int64_t f = threadIdx.x; f < n3; f += LNT) s += (double)tube[f] * (double)tube[f];
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = LNT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * n2 + j] = red[0];
+}
+
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, int64_t nb, int64_t n,
                                        double* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,17 +189,25 @@ int lateral_norms(const void* a, int dtype, int64_t n1, int64_t n2, int64_t n3, 
   const int vn = dtype == TP_F64 ? 2 : 4;
   const int64_t CH = (n3 % vn == 0) ? n3 / vn : n3;
   const size_t lds = size_t(LT) * CH * sizeof(double);
-  if (lds > 64 * 1024) return fail(TP_EUNSUPPORTED, "tube length too large for the slice-norm kernel");
   if (n1 == 0) {
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, out, n2);
     TP_LAUNCH_CHECK();
     return TP_OK;
   }
-  dim3 grid((unsigned)((n2 + LT - 1) / LT), (unsigned)nb);
-  if (dtype == TP_F64)
-    hipLaunchKernelGGL(lateral_partial_kernel<double>, grid, dim3(LNT), lds, st, (const double*)a, n1, n2, n3, ws);
-  else
-    hipLaunchKernelGGL(lateral_partial_kernel<float>, grid, dim3(LNT), lds, st, (const float*)a, n1, n2, n3, ws);
+  if (lds > 64 * 1024) {
+    if (n2 > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many lateral slices");
+    dim3 grid((unsigned)n2, (unsigned)nb);
+    if (dtype == TP_F64)
+      hipLaunchKernelGGL(lateral_long_kernel<double>, grid, dim3(LNT), 0, st, (const double*)a, n1, n2, n3, ws);
+    else
+      hipLaunchKernelGGL(lateral_long_kernel<float>, grid, dim3(LNT), 0, st, (const float*)a, n1, n2, n3, ws);
+  } else {
+    dim3 grid((unsigned)((n2 + LT - 1) / LT), (unsigned)nb);
+    if (dtype == TP_F64)
+      hipLaunchKernelGGL(lateral_partial_kernel<double>, grid, dim3(LNT), lds, st, (const double*)a, n1, n2, n3, ws);
+    else
+      hipLaunchKernelGGL(lateral_partial_kernel<float>, grid, dim3(LNT), lds, st, (const float*)a, n1, n2, n3, ws);
+  }
   TP_LAUNCH_CHECK();
   hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, ws, nb, n2, out);
   TP_LAUNCH_CHECK();

@@ -193,9 +193,13 @@ def test_rtprod_full_size_sampled_entries(full_rtprod_case, prec, tol):
     assert rel(Z[ii, jj, kk], ref) < tol
 
 
-@pytest.mark.parametrize("shape", [(64, 300, 16), (33, 1000, 7), (5, 64, 1), (10, 700, 64), (7, 3, 128)])
+@pytest.mark.parametrize(
+    "shape", [(64, 300, 16), (33, 1000, 7), (5, 64, 1), (10, 700, 64), (7, 3, 128), (20, 9, 2000), (17, 5, 10001)]
+)
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_slice_norms(shape, dtype):
+    """Lateral and horizontal squared slice norms, including long tubes (a
+    workgroup per tube and row block) of even and odd length."""
     rs = np.random.default_rng(shape[1])
     A = rs.standard_normal(shape).astype(dtype) * np.exp(rs.standard_normal(shape[1]))[None, :, None].astype(dtype)
     lat = api.slice_norms(dev(A), "lateral").cpu().numpy()
@@ -513,6 +517,51 @@ def test_long_tube_transforms(n3, dtype):
     Xi = api.tifft(dev(G.real.astype(dtype)), dev(G.imag.astype(dtype)), n3).cpu().numpy()
     ref = T.from_half_spectrum((G.real.astype(dtype) + 1j * G.imag.astype(dtype)).astype(np.complex128), n3)
     assert rel(Xi, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize(
+    "n3,dtype",
+    [(10000, np.float32), (30030, np.float32), (65536, np.float32), (500000, np.float32), (5000, np.float64),
+     (9000, np.float64)],
+)
+def test_four_step_transforms(n3, dtype):
+    """Even tubes beyond the LDS budget of the workgroup-per-tube transform
+    take the four-step transform through HBM (n3/2 = N1 N2: 10000 -> 20 x 250,
+    30030 -> 65 x 231 (odd factors, odd pair count), 65536 -> 128 x 256,
+    500000 (the lung MSI tube length) -> 1000 x 250; float64 5000 -> 10 x 250,
+    9000 -> 18 x 250); both directions, the round trip, and slot counts that
+    are not multiples of the workgroups' slot blocks."""
+    rs = np.random.default_rng(n3)
+    shape = (3, 5, n3) if n3 <= 65536 else (2, 3, n3)
+    X = rs.standard_normal(shape).astype(dtype)
+    re, im = api.tfft(dev(X))
+    H = T.half_spectrum(X.astype(np.float64))
+    assert rel(re.cpu().numpy() + 1j * im.cpu().numpy(), H) < TOL[dtype]
+    assert not im[0].any()
+    assert not im[-1].any()
+    Y = api.tifft(re, im, n3).cpu().numpy()
+    assert rel(Y, X) < TOL[dtype]
+    K = n3 // 2 + 1
+    G = rs.standard_normal((K, 3, 2)) + 1j * rs.standard_normal((K, 3, 2))
+    Gr, Gi = G.real.astype(dtype), G.imag.astype(dtype)
+    Xi = api.tifft(dev(Gr), dev(Gi), n3).cpu().numpy()
+    assert rel(Xi, T.from_half_spectrum((Gr + 1j * Gi).astype(np.complex128), n3)) < TOL[dtype]
+
+
+def test_four_step_rtprod_gathers():
+    """The four-step forward transform with picked, scaled slices (the
+    rt-product's gathers of A's lateral and B's horizontal slices) on
+    10000-long tubes, against the oracle rt-product."""
+    g = np.random.default_rng(41)
+    A = g.standard_normal((6, 40, 10000)).astype(np.float32)
+    B = g.standard_normal((40, 5, 10000)).astype(np.float32)
+    picks = api.tsample("norm2", 11, mode="iid", seed=3, A=dev(A))
+    Zg = api.tprod(dev(A), dev(B), picks=picks, prec="f32").cpu().numpy()
+    idx, sc = picks.host()
+    i, s = idx.numpy().astype(np.int64), sc.numpy()
+    C = A[:, i, :].astype(np.float64) * s[None, :, None]
+    R = B[i, :, :].astype(np.float64) * s[:, None, None]
+    assert rel(Zg, T.tprod_fft(C, R)) < 2e-6
 
 
 def test_msi_shaped_tcur():
