@@ -167,7 +167,12 @@ int tp_version(void);
  * ------------------------------------------------------------------------- */
 
 /* Forward transform of every tube: Xh = first K slices of fft(X, [], 3).
- * Xh must be K x n1 x n2 with X's dtype. n3 >= 1. */
+ * Xh must be K x n1 x n2 with X's dtype. n3 >= 1. Tube lengths: any; even
+ * lengths beyond one workgroup's LDS (float32 above 8192, float64 above
+ * 4096) up to 2^19 with no prime factor above 13 (e.g. 500000) run a
+ * four-step transform that uses Xh itself as its intermediate storage;
+ * other lengths without a fast kernel fall back to a direct O(n3^2)
+ * transform. The same holds for tp_tifft (which then uses X). */
 int tp_tfft(const tp_tensor* X, tp_spectrum* Xh, void* stream);
 
 /* Inverse transform: X = ifft of the conjugate-symmetric extension of Xh.
