@@ -93,6 +93,7 @@ def parse():
     p.add_argument("--no-protocol", action="store_true", help="skip the t-CUR / learned-proposal comparison")
     p.add_argument("--no-tnn", action="store_true", help="skip the completion / robust PCA / CUR t-NN comparison")
     p.add_argument("--no-table1", action="store_true", help="skip the replay of the rt-product experiment")
+    p.add_argument("--no-long", action="store_true", help="skip the lung-MSI-length tube transforms")
     p.add_argument("--tnn-iters", type=int, default=100)
     p.add_argument("--learned-train", type=int, default=1800)
     p.add_argument("--learned-test", type=int, default=40)
@@ -571,6 +572,50 @@ def table1_replay(args, api, torch):
     return out
 
 
+def long_tubes(api, torch, n1=122, n2=120, n3=500000, reps=5):
+    """Tube transforms at the lung MSI tensor's shape (122 x 120 x 500,000,
+    Table 4; a Gaussian stand-in): the four-step forward and inverse
+    transforms, HIP-event times, rates against the algorithmic bytes, and
+    the error of sampled tubes against the float64 oracle."""
+    from oracle import tensor as T
+    g = torch.Generator(device="cuda")
+    g.manual_seed(20170413)
+    X = torch.randn((n1, n2, n3), generator=g, device="cuda", dtype=torch.float32)
+    K = n3 // 2 + 1
+    re = torch.empty((K, n1, n2), device="cuda", dtype=torch.float32)
+    im = torch.empty_like(re)
+    Y = torch.empty_like(X)
+    fwd = lambda: api.tfft(X, out=(re, im))  # noqa: E731
+    inv = lambda: api.tifft(re, im, n3, out=Y)  # noqa: E731
+    ms_f = time_events(fwd, reps, torch)
+    ms_i = time_events(inv, reps, torch)
+    fwd()
+    inv()
+    torch.cuda.synchronize()
+    tubes = n1 * n2
+    b_f = tubes * (4 * n3 + 8 * K)
+    rs = np.random.default_rng(5)
+    picks = [(int(rs.integers(n1)), int(rs.integers(n2))) for _ in range(3)]
+    errs_f, errs_i = [], []
+    for (i, j) in picks:
+        x = X[i, j].double().cpu().numpy()
+        H = T.half_spectrum(x[None, None, :])[:, 0, 0]
+        got = re[:, i, j].double().cpu().numpy() + 1j * im[:, i, j].double().cpu().numpy()
+        errs_f.append(float(np.linalg.norm(got - H) / np.linalg.norm(H)))
+        errs_i.append(float(np.linalg.norm(Y[i, j].double().cpu().numpy() - x) / np.linalg.norm(x)))
+    del X, Y, re, im
+    torch.cuda.empty_cache()
+    return {"workload": f"{n1}x{n2}x{n3} float32 N(0,1) tensor (lung MSI shape), four-step tube transforms "
+                        "(n3/2 = 1000 x 250)",
+            "fwd_ms": round(ms_f, 3), "inv_ms": round(ms_i, 3),
+            "fwd_GBs_algorithmic": round(b_f / (ms_f * 1e-3) / 1e9, 1),
+            "inv_GBs_algorithmic": round(b_f / (ms_i * 1e-3) / 1e9, 1),
+            "algorithmic_bytes": b_f,
+            "note": "algorithmic bytes = read 4 n3 + write 8 (n3/2 + 1) per tube (the reverse for the inverse); "
+                    "each direction makes two passes through HBM, so it moves about twice that",
+            "sampled_tube_rel_err_fwd_max": max(errs_f), "sampled_tube_rel_err_roundtrip_max": max(errs_i)}
+
+
 def time_events(fn, reps, torch):
     """Average duration of fn() over reps launches, HIP events on the
     current stream (the one the library enqueues on)."""
@@ -908,6 +953,9 @@ def main():
     if not args.no_table1:
         log("replay of the rt-product experiment (Table 1 shapes)")
         out["table1_replay"] = table1_replay(args, api, torch)
+    if not args.no_long:
+        log("tube transforms at the lung MSI shape")
+        out["long_tubes"] = long_tubes(api, torch)
     if not args.no_tnn:
         log("completion / robust PCA: full ADMM against CUR t-NN")
         out["tensor_nn"] = tnn_protocol(args, api, torch)

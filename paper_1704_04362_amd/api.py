@@ -78,20 +78,21 @@ def half_count(n3):
     return n3 // 2 + 1
 
 
-def tfft(X):
-    """Half spectrum (re, im), each K x n1 x n2, of fft(X, [], 3)."""
+def tfft(X, out=None):
+    """Half spectrum (re, im), each K x n1 x n2, of fft(X, [], 3); out =
+    (re, im) to write into existing tensors."""
     _need_gpu(X)
-    K = half_count(X.shape[2])
-    re = torch.empty((K, X.shape[0], X.shape[1]), dtype=X.dtype, device=X.device)
-    im = torch.empty_like(re)
+    shape = (half_count(X.shape[2]), X.shape[0], X.shape[1])
+    re = _out(out[0] if out else None, shape, X.dtype, X.device)
+    im = _out(out[1] if out else None, shape, X.dtype, X.device)
     L.check(L.load().tp_tfft(C.byref(_tensor(X)), C.byref(_spectrum(re, im)), _stream()))
     return re, im
 
 
-def tifft(re, im, n3):
+def tifft(re, im, n3, out=None):
     """Real tensor rows x cols x n3 whose half spectrum is (re, im)."""
     _need_gpu(re, im)
-    X = torch.empty((re.shape[1], re.shape[2], n3), dtype=re.dtype, device=re.device)
+    X = _out(out, (re.shape[1], re.shape[2], n3), re.dtype, re.device)
     L.check(L.load().tp_tifft(C.byref(_spectrum(re, im)), C.byref(_tensor(X)), _stream()))
     return X
 

@@ -744,36 +744,93 @@ struct FourStep {
   LongPlan p1, p2;  // radix plans of lengths N1 and N2
 };
 
+// Launch order. Workgroup L runs on XCD L mod 8, each XCD with its own L2;
+// the logical index (L mod 8) q + L / 8 (q = ceil(total / 8)) gives every XCD
+// a contiguous range of logical work, so the workgroups that share cache
+// lines (neighbouring slots, neighbouring j1) run together on one XCD.
+// Returns false for the padding beyond `total`.
+__device__ __forceinline__ bool fs_logical(int64_t total, int64_t& G) {
+  const int64_t L = blockIdx.x, q = (total + 7) / 8;
+  G = (L % 8) * q + L / 8;
+  return G < total;
+}
+
+// tube passes: 4 x 4 groups of (slot block, j1 block), j1 groups fastest,
+// so that reads (contiguous in j1) and writes (contiguous in slots) both
+// share lines within a group
+__device__ __forceinline__ bool fs_tube_block(int64_t nslot_blocks, int64_t nj_blocks, int64_t& sb, int64_t& jb) {
+  const int64_t ngj = (nj_blocks + 3) / 4, ngs = (nslot_blocks + 3) / 4;
+  int64_t G;
+  if (!fs_logical(ngj * ngs * 16, G)) return false;
+  const int64_t g = G / 16, w = G % 16;
+  jb = (g % ngj) * 4 + (w % 4);
+  sb = (g / ngj) * 4 + (w / 4);
+  return jb < nj_blocks && sb < nslot_blocks;
+}
+
+// sincospi in the arithmetic of the data (float tubes take float roots:
+// their rounding is that of the data)
+__device__ __forceinline__ void fs_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void fs_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// One radix-P butterfly of a decimation-in-time stage of span m P: the P
+// inputs a[base + t m] take the twiddle W_{mP}^{j t} (j t < m P) and go through
+// a P-point DFT with roots (cw, sw); P is a compile-time constant, so the DFT
+// is fully unrolled with its root indices folded.
+template <int P, typename T>
+__device__ __forceinline__ void fs_bfly(T* ar, T* ai, int base, int m, int j, int span, const T* cw, const T* sw) {
+  T vr[P], vi[P];
+  vr[0] = ar[base];
+  vi[0] = ai[base];
+#pragma unroll
+  for (int t = 1; t < P; ++t) {
+    const T xr = ar[base + t * m], xi = ai[base + t * m];
+    T sn, cs;
+    fs_sincospi(T(-2) * T(j * t) / T(span), &sn, &cs);
+    vr[t] = xr * cs - xi * sn;
+    vi[t] = xr * sn + xi * cs;
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    T accr = vr[0], acci = vi[0];
+#pragma unroll
+    for (int u = 1; u < P; ++u) {
+      const int e = (u * t) % P;
+      accr += vr[u] * cw[e] - vi[u] * sw[e];
+      acci += vr[u] * sw[e] + vi[u] * cw[e];
+    }
+    ar[base + t * m] = accr;
+    ai[base + t * m] = acci;
+  }
+}
+
 // mixed-radix stages of `nseq` sequences of length pl.n, sequence s at
-// offset s * pl.n (loaded in digit-reversed order)
+// offset s * pl.n (loaded in digit-reversed order), in the data's precision
 template <typename T>
 __device__ void multi_stages(const LongPlan& pl, T* ar, T* ai, int nseq) {
   const int n = pl.n;
   int m = 1;
   for (int q = 0; q < pl.nst; ++q) {
     const int p = pl.rad[q], span = m * p, per = n / p;
-    double cw[kLongMaxRadix], sw[kLongMaxRadix];
-    for (int e = 0; e < p; ++e) sincospi(-2.0 * e / p, &sw[e], &cw[e]);
+    T cw[kLongMaxRadix], sw[kLongMaxRadix];
+#pragma unroll
+    for (int e = 0; e < kLongMaxRadix; ++e) {
+      cw[e] = T(1);
+      sw[e] = T(0);
+      if (e < p) fs_sincospi(T(-2) * T(e) / T(p), &sw[e], &cw[e]);
+    }
     for (int b = threadIdx.x; b < nseq * per; b += kFsNT) {
       const int sq = b / per, bb = b - sq * per;
-      const int j = bb % m, g = sq * n + (bb / m) * span;
-      double vr[kLongMaxRadix], vi[kLongMaxRadix];
-      for (int t = 0; t < p; ++t) {
-        const double xr = (double)ar[g + j + t * m], xi = (double)ai[g + j + t * m];
-        double sn, cs;
-        sincospi(-2.0 * ((j * t) % span) / span, &sn, &cs);
-        vr[t] = xr * cs - xi * sn;
-        vi[t] = xr * sn + xi * cs;
-      }
-      for (int t = 0; t < p; ++t) {
-        double accr = 0.0, acci = 0.0;
-        for (int u = 0; u < p; ++u) {
-          const int e = (u * t) % p;
-          accr += vr[u] * cw[e] - vi[u] * sw[e];
-          acci += vr[u] * sw[e] + vi[u] * cw[e];
-        }
-        ar[g + j + t * m] = (T)accr;
-        ai[g + j + t * m] = (T)acci;
+      const int bm = bb / m, j = bb - bm * m;
+      const int base = sq * n + bm * span + j;
+      switch (p) {
+        case 2: fs_bfly<2, T>(ar, ai, base, m, j, span, cw, sw); break;
+        case 3: fs_bfly<3, T>(ar, ai, base, m, j, span, cw, sw); break;
+        case 4: fs_bfly<4, T>(ar, ai, base, m, j, span, cw, sw); break;
+        case 5: fs_bfly<5, T>(ar, ai, base, m, j, span, cw, sw); break;
+        case 7: fs_bfly<7, T>(ar, ai, base, m, j, span, cw, sw); break;
+        case 11: fs_bfly<11, T>(ar, ai, base, m, j, span, cw, sw); break;
+        default: fs_bfly<13, T>(ar, ai, base, m, j, span, cw, sw); break;
       }
     }
     __syncthreads();
@@ -781,8 +838,24 @@ __device__ void multi_stages(const LongPlan& pl, T* ar, T* ai, int nseq) {
   }
 }
 
+// position at which the digit-reversed load puts source index src (the
+// inverse of long_src)
+__device__ __forceinline__ int long_dst(const LongPlan& pl, int src) {
+  int pos = 0, w = 1;
+  int digits[kLongMaxStages];
+  for (int q = pl.nst - 1; q >= 0; --q) {
+    digits[q] = src % pl.rad[q];
+    src /= pl.rad[q];
+  }
+  for (int q = 0; q < pl.nst; ++q) {
+    pos += digits[q] * w;
+    w *= pl.rad[q];
+  }
+  return pos;
+}
+
 // exp(-2 pi i e / L) for 0 <= e < L
-__device__ __forceinline__ void fs_root(int64_t e, int64_t L, double& c, double& s) {
+__device__ __forceinline__ void fs_root(int e, int L, double& c, double& s) {
   sincospi(-2.0 * (double)e / (double)L, &s, &c);
 }
 
@@ -795,27 +868,31 @@ __global__ __launch_bounds__(kFsNT) void fs_fwd_tube_kernel(const T* __restrict_
   const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2;
   T* ar = reinterpret_cast<T*>(fs_lds);
   T* ai = ar + TB * JB * N2;
-  const int64_t t0 = (int64_t)blockIdx.x * TB;
-  const int j10 = blockIdx.y * JB;
   const int64_t ks = a.ntubes;
-  // load: sequence (tube u, j1 offset v) at (u JB + v) N2, position pos holds
-  // z[j1 + N1 j2] with j2 = long_src(pos)
+  int64_t sbk, jbk;
+  if (!fs_tube_block((ks + TB - 1) / TB, (N1 + JB - 1) / JB, sbk, jbk)) return;
+  const int64_t t0 = sbk * TB;
+  const int j10 = (int)jbk * JB;
+  // sequence (tube u, j1 offset v) at (u JB + v) N2 holds z[j1 + N1 j2] at
+  // the digit-reversed position of j2
+  // threads take consecutive j1 of one (tube, j2): contiguous input runs
   for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
-    const int sq = e / N2, pos = e - sq * N2;
-    const int u = sq / JB, v = sq - u * JB;
+    const int v = e % JB, r = e / JB;
+    const int j2 = r % N2, u = r / N2;
     const int64_t t = t0 + u;
     const int j1 = j10 + v;
     T vr = T(0), vi = T(0);
     int64_t src;
     double sc;
     if (t < ks && j1 < N1 && tube_source(a, t, src, sc)) {
-      const int64_t m = j1 + (int64_t)N1 * long_src(fs.p2, pos);
+      const int64_t m = j1 + (int64_t)N1 * j2;
       const T* xt = x + src * (int64_t)(2 * N);
       vr = (sc == 1.0) ? xt[2 * m] : (T)((double)xt[2 * m] * sc);
       vi = (sc == 1.0) ? xt[2 * m + 1] : (T)((double)xt[2 * m + 1] * sc);
     }
-    ar[e] = vr;
-    ai[e] = vi;
+    const int li = (u * JB + v) * N2 + long_dst(fs.p2, j2);
+    ar[li] = vr;
+    ai[li] = vi;
   }
   __syncthreads();
   multi_stages<T>(fs.p2, ar, ai, TB * JB);
@@ -828,7 +905,7 @@ __global__ __launch_bounds__(kFsNT) void fs_fwd_tube_kernel(const T* __restrict_
     if (t >= ks || j1 >= N1) continue;
     const int li = (u * JB + v) * N2 + k2;
     double c, sn;
-    fs_root(((int64_t)j1 * k2) % N, N, c, sn);
+    fs_root((int)((unsigned)(j1 * k2) % (unsigned)N), N, c, sn);  // j1 k2 < 2^18
     const double xr = (double)ar[li], xi = (double)ai[li];
     const int64_t o = ((int64_t)k2 + (int64_t)N2 * j1) * ks + t;
     ore[o] = (T)(xr * c - xi * sn);
@@ -845,8 +922,11 @@ __global__ __launch_bounds__(kFsNT) void fs_fwd_slice_kernel(FourStep fs, int64_
   const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2;
   T* ar = reinterpret_cast<T*>(fs_lds);
   T* ai = ar + 2 * TB * N1;
-  const int64_t t0 = (int64_t)blockIdx.x * TB;
-  const int ka = blockIdx.y, kb = (N2 - ka) % N2;
+  const int64_t nsb = (ks + TB - 1) / TB;
+  int64_t G;
+  if (!fs_logical(nsb * (N2 / 2 + 1), G)) return;
+  const int64_t t0 = (G % nsb) * TB;  // slot blocks fastest
+  const int ka = (int)(G / nsb), kb = (N2 - ka) % N2;
   const int nk = ka == kb ? 1 : 2;
   // sequence (h, u) at (h TB + u) N1 holds the values of slice k2 = (ka, kb)[h]
   // of slot t0 + u, position pos holding j1 = long_src(pos)
@@ -902,8 +982,11 @@ __global__ __launch_bounds__(kFsNT) void fs_inv_slice_kernel(const T* __restrict
   const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2, n = 2 * N;
   T* ar = reinterpret_cast<T*>(fs_lds);
   T* ai = ar + TB * N1;
-  const int64_t t0 = (int64_t)blockIdx.x * TB;
-  const int k2 = blockIdx.y;
+  const int64_t nsb = (ntubes + TB - 1) / TB;
+  int64_t G;
+  if (!fs_logical(nsb * N2, G)) return;
+  const int64_t t0 = (G % nsb) * TB;  // slot blocks fastest
+  const int k2 = (int)(G / nsb);
   // conj Z[k2 + N2 k1] at position pos of sequence u (k1 = long_src(pos)):
   // the forward stages of the conjugate give the conjugate of the inverse
   for (int e = threadIdx.x; e < TB * N1; e += kFsNT) {
@@ -939,7 +1022,7 @@ __global__ __launch_bounds__(kFsNT) void fs_inv_slice_kernel(const T* __restrict
     if (t >= ntubes) continue;
     const double vr = (double)ar[u * N1 + j1], vi = -(double)ai[u * N1 + j1];
     double c, sn;
-    fs_root(((int64_t)j1 * k2) % N, N, c, sn);  // W_N^{j1 k2}; multiply by its conjugate
+    fs_root((int)((unsigned)(j1 * k2) % (unsigned)N), N, c, sn);  // W_N^{j1 k2}; times its conjugate
     const int64_t o = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * k2);
     y[o] = (T)(vr * c + vi * sn);
     y[o + 1] = (T)(vi * c - vr * sn);
@@ -954,21 +1037,24 @@ __global__ __launch_bounds__(kFsNT) void fs_inv_tube_kernel(int64_t ntubes, Four
   const int N1 = fs.N1, N2 = fs.N2, N = N1 * N2, n = 2 * N;
   T* ar = reinterpret_cast<T*>(fs_lds);
   T* ai = ar + TB * JB * N2;
-  const int64_t t0 = (int64_t)blockIdx.x * TB;
-  const int j10 = blockIdx.y * JB;
+  int64_t sbk, jbk;
+  if (!fs_tube_block((ntubes + TB - 1) / TB, (N1 + JB - 1) / JB, sbk, jbk)) return;
+  const int64_t t0 = sbk * TB;
+  const int j10 = (int)jbk * JB;
   for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
-    const int sq = e / N2, pos = e - sq * N2;
-    const int u = sq / JB, v = sq - u * JB;
+    const int v = e % JB, r = e / JB;
+    const int k2 = r % N2, u = r / N2;
     const int64_t t = t0 + u;
     const int j1 = j10 + v;
     T vr = T(0), vi = T(0);
     if (t < ntubes && j1 < N1) {
-      const int64_t o = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * long_src(fs.p2, pos));
+      const int64_t o = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * k2);
       vr = y[o];
       vi = -y[o + 1];  // conjugate in, conjugate out
     }
-    ar[e] = vr;
-    ai[e] = vi;
+    const int li = (u * JB + v) * N2 + long_dst(fs.p2, k2);
+    ar[li] = vr;
+    ai[li] = vi;
   }
   __syncthreads();
   multi_stages<T>(fs.p2, ar, ai, TB * JB);
@@ -1020,17 +1106,23 @@ bool four_step_plan(int64_t n, FourStep& fs) {
   return false;
 }
 
+// 1D grid of a launch with `total` logical workgroups (padded to whole
+// rounds over the eight XCDs)
+inline int64_t fs_grid(int64_t total) { return (total + 7) / 8 * 8; }
+inline int64_t fs_tube_grid(int64_t nslot_blocks, int64_t nj_blocks) {
+  return fs_grid(((nj_blocks + 3) / 4) * ((nslot_blocks + 3) / 4) * 16);
+}
+
 template <typename T>
 int fs_forward(const T* x, const FwdArgs& a, const FourStep& fs, T* re, T* im, hipStream_t st) {
   constexpr int TB = FsGeom<T>::tubes, JB = FsGeom<T>::j1s, SB = FsGeom<T>::stubes;
-  const int64_t bt = (a.ntubes + TB - 1) / TB, bs = (a.ntubes + SB - 1) / SB;
-  if (bt > 0x7fffffffLL || bs > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+  const int64_t gt = fs_tube_grid((a.ntubes + TB - 1) / TB, (fs.N1 + JB - 1) / JB);
+  const int64_t gs = fs_grid((a.ntubes + SB - 1) / SB * (fs.N2 / 2 + 1));
+  if (gt > 0x7fffffffLL || gs > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
   const size_t lt = size_t(2) * TB * JB * fs.N2 * sizeof(T), ls = size_t(2) * 2 * SB * fs.N1 * sizeof(T);
-  hipLaunchKernelGGL(fs_fwd_tube_kernel<T>, dim3((unsigned)bt, (unsigned)((fs.N1 + JB - 1) / JB)), dim3(kFsNT), lt,
-                     st, x, a, fs, re, im);
+  hipLaunchKernelGGL(fs_fwd_tube_kernel<T>, dim3((unsigned)gt), dim3(kFsNT), lt, st, x, a, fs, re, im);
   TP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(fs_fwd_slice_kernel<T>, dim3((unsigned)bs, (unsigned)(fs.N2 / 2 + 1)), dim3(kFsNT), ls, st, fs,
-                     a.ntubes, re, im);
+  hipLaunchKernelGGL(fs_fwd_slice_kernel<T>, dim3((unsigned)gs), dim3(kFsNT), ls, st, fs, a.ntubes, re, im);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }
@@ -1038,14 +1130,13 @@ int fs_forward(const T* x, const FwdArgs& a, const FourStep& fs, T* re, T* im, h
 template <typename T>
 int fs_inverse(const T* re, const T* im, int64_t ntubes, const FourStep& fs, T* y, hipStream_t st) {
   constexpr int TB = FsGeom<T>::tubes, JB = FsGeom<T>::j1s, SB = FsGeom<T>::stubes;
-  const int64_t bt = (ntubes + TB - 1) / TB, bs = (ntubes + SB - 1) / SB;
-  if (bt > 0x7fffffffLL || bs > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+  const int64_t gt = fs_tube_grid((ntubes + TB - 1) / TB, (fs.N1 + JB - 1) / JB);
+  const int64_t gs = fs_grid((ntubes + SB - 1) / SB * fs.N2);
+  if (gt > 0x7fffffffLL || gs > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
   const size_t lt = size_t(2) * TB * JB * fs.N2 * sizeof(T), ls = size_t(2) * SB * fs.N1 * sizeof(T);
-  hipLaunchKernelGGL(fs_inv_slice_kernel<T>, dim3((unsigned)bs, (unsigned)fs.N2), dim3(kFsNT), ls, st, re, im, ntubes,
-                     fs, y);
+  hipLaunchKernelGGL(fs_inv_slice_kernel<T>, dim3((unsigned)gs), dim3(kFsNT), ls, st, re, im, ntubes, fs, y);
   TP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(fs_inv_tube_kernel<T>, dim3((unsigned)bt, (unsigned)((fs.N1 + JB - 1) / JB)), dim3(kFsNT), lt,
-                     st, ntubes, fs, y);
+  hipLaunchKernelGGL(fs_inv_tube_kernel<T>, dim3((unsigned)gt), dim3(kFsNT), lt, st, ntubes, fs, y);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }
