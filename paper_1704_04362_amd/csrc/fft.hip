@@ -726,7 +726,8 @@ bool long_plan(int64_t n, int elem_bytes, LongPlan& pl) {
 // above 13 take this path; longer or other lengths beyond the LDS budget
 // take the direct transform.
 // --------------------------------------------------------------------------
-constexpr int kFsMaxN2 = 256, kFsMaxN1 = 1024, kFsNT = 256;
+constexpr int kFsMaxN2 = 256, kFsMaxN1 = 1024, kFsNT = 512;
+constexpr int kFsBatch = 8;  // elements whose loads a thread keeps in flight
 
 template <typename T>
 struct FsGeom;
@@ -873,26 +874,60 @@ __global__ __launch_bounds__(kFsNT) void fs_fwd_tube_kernel(const T* __restrict_
   if (!fs_tube_block((ks + TB - 1) / TB, (N1 + JB - 1) / JB, sbk, jbk)) return;
   const int64_t t0 = sbk * TB;
   const int j10 = (int)jbk * JB;
+  // input tube and scale of each slot of the block
+  __shared__ int64_t s_src[TB];
+  __shared__ double s_sc[TB];
+  if (threadIdx.x < TB) {
+    const int64_t t = t0 + threadIdx.x;
+    int64_t src = -1;
+    double sc = 1.0;
+    if (!(t < ks && tube_source(a, t, src, sc))) src = -1;
+    s_src[threadIdx.x] = src;
+    s_sc[threadIdx.x] = sc;
+  }
+  __syncthreads();
   // sequence (tube u, j1 offset v) at (u JB + v) N2 holds z[j1 + N1 j2] at
-  // the digit-reversed position of j2
-  // threads take consecutive j1 of one (tube, j2): contiguous input runs
-  for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
-    const int v = e % JB, r = e / JB;
-    const int j2 = r % N2, u = r / N2;
-    const int64_t t = t0 + u;
-    const int j1 = j10 + v;
-    T vr = T(0), vi = T(0);
-    int64_t src;
-    double sc;
-    if (t < ks && j1 < N1 && tube_source(a, t, src, sc)) {
-      const int64_t m = j1 + (int64_t)N1 * j2;
-      const T* xt = x + src * (int64_t)(2 * N);
-      vr = (sc == 1.0) ? xt[2 * m] : (T)((double)xt[2 * m] * sc);
-      vi = (sc == 1.0) ? xt[2 * m + 1] : (T)((double)xt[2 * m + 1] * sc);
+  // the digit-reversed position of j2; threads take consecutive j1 of one
+  // (tube, j2) (contiguous input runs), kFsBatch loads in flight per thread
+  // (indices first, then the batch's loads unconditionally from clamped
+  // addresses so that they all stay in flight, then the LDS stores)
+  const int total = TB * JB * N2;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kFsBatch * kFsNT) {
+    int64_t off[kFsBatch];
+    double sc[kFsBatch];
+    int li[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      const int e = e0 + q * kFsNT;
+      off[q] = -1;
+      sc[q] = 1.0;
+      li[q] = -1;
+      if (e < total) {
+        const int v = e % JB, r = e / JB;
+        const int j2 = r % N2, u = r / N2;
+        const int j1 = j10 + v;
+        li[q] = (u * JB + v) * N2 + long_dst(fs.p2, j2);
+        const int64_t src = s_src[u];
+        if (src >= 0 && j1 < N1) {
+          off[q] = src * (int64_t)(2 * N) + 2 * ((int64_t)j1 + (int64_t)N1 * j2);
+          sc[q] = s_sc[u];
+        }
+      }
     }
-    const int li = (u * JB + v) * N2 + long_dst(fs.p2, j2);
-    ar[li] = vr;
-    ai[li] = vi;
+    T vr[kFsBatch], vi[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      const int64_t o = off[q] < 0 ? 0 : off[q];
+      vr[q] = x[o];
+      vi[q] = x[o + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      if (li[q] < 0) continue;
+      const bool ok = off[q] >= 0;
+      ar[li[q]] = !ok ? T(0) : (sc[q] == 1.0) ? vr[q] : (T)((double)vr[q] * sc[q]);
+      ai[li[q]] = !ok ? T(0) : (sc[q] == 1.0) ? vi[q] : (T)((double)vi[q] * sc[q]);
+    }
   }
   __syncthreads();
   multi_stages<T>(fs.p2, ar, ai, TB * JB);
@@ -929,20 +964,38 @@ __global__ __launch_bounds__(kFsNT) void fs_fwd_slice_kernel(FourStep fs, int64_
   const int ka = (int)(G / nsb), kb = (N2 - ka) % N2;
   const int nk = ka == kb ? 1 : 2;
   // sequence (h, u) at (h TB + u) N1 holds the values of slice k2 = (ka, kb)[h]
-  // of slot t0 + u, position pos holding j1 = long_src(pos)
-  for (int e = threadIdx.x; e < nk * TB * N1; e += kFsNT) {
-    const int pos = e / (nk * TB), r = e - pos * (nk * TB);
-    const int h = r / TB, u = r - h * TB;
-    const int64_t t = t0 + u;
-    const int k2 = h ? kb : ka;
-    T vr = T(0), vi = T(0);
-    if (t < ks) {
-      const int64_t o = ((int64_t)k2 + (int64_t)N2 * long_src(fs.p1, pos)) * ks + t;
-      vr = ore[o];
-      vi = oim[o];
+  // of slot t0 + u, position pos holding j1 = long_src(pos); kFsBatch loads
+  // in flight per thread
+  const int total = nk * TB * N1;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kFsBatch * kFsNT) {
+    int64_t off[kFsBatch];
+    int li[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      const int e = e0 + q * kFsNT;
+      off[q] = -1;
+      li[q] = -1;
+      if (e < total) {
+        const int pos = e / (nk * TB), r = e - pos * (nk * TB);
+        const int h = r / TB, u = r - h * TB;
+        const int64_t t = t0 + u;
+        li[q] = (h * TB + u) * N1 + pos;
+        if (t < ks) off[q] = ((int64_t)(h ? kb : ka) + (int64_t)N2 * long_src(fs.p1, pos)) * ks + t;
+      }
     }
-    ar[(h * TB + u) * N1 + pos] = vr;
-    ai[(h * TB + u) * N1 + pos] = vi;
+    T vr[kFsBatch], vi[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      const int64_t o = off[q] < 0 ? 0 : off[q];
+      vr[q] = ore[o];
+      vi[q] = oim[o];
+    }
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      if (li[q] < 0) continue;
+      ar[li[q]] = off[q] < 0 ? T(0) : vr[q];
+      ai[li[q]] = off[q] < 0 ? T(0) : vi[q];
+    }
   }
   __syncthreads();
   multi_stages<T>(fs.p1, ar, ai, nk * TB);
@@ -988,29 +1041,58 @@ __global__ __launch_bounds__(kFsNT) void fs_inv_slice_kernel(const T* __restrict
   const int64_t t0 = (G % nsb) * TB;  // slot blocks fastest
   const int k2 = (int)(G / nsb);
   // conj Z[k2 + N2 k1] at position pos of sequence u (k1 = long_src(pos)):
-  // the forward stages of the conjugate give the conjugate of the inverse
-  for (int e = threadIdx.x; e < TB * N1; e += kFsNT) {
-    const int pos = e / TB, u = e - pos * TB;
-    const int64_t t = t0 + u;
-    T vr = T(0), vi = T(0);
-    if (t < ntubes) {
-      const int k = k2 + N2 * long_src(fs.p1, pos);
-      const int km = N - k;  // 1 <= km <= N
-      const double ar0 = (double)xre[(int64_t)k * ntubes + t];
-      const double ai0 = k == 0 ? 0.0 : (double)xim[(int64_t)k * ntubes + t];
-      const double br = (double)xre[(int64_t)km * ntubes + t];
-      const double bi = km == N ? 0.0 : -(double)xim[(int64_t)km * ntubes + t];  // conj X[N-k]
-      const double er = 0.5 * (ar0 + br), ei = 0.5 * (ai0 + bi);
-      const double dr = 0.5 * (ar0 - br), di = 0.5 * (ai0 - bi);
-      double c, sn;
-      fs_root(k, n, c, sn);  // W_n^k; O = D conj(W_n^k)
-      const double orr = dr * c + di * sn, oi = di * c - dr * sn;
-      // Z = E + i O
-      vr = (T)(er - oi);
-      vi = (T)(-(ei + orr));  // conjugated
+  // the forward stages of the conjugate give the conjugate of the inverse;
+  // kFsBatch elements' loads in flight per thread
+  const int total = TB * N1;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kFsBatch * kFsNT) {
+    int64_t oa[kFsBatch], ob[kFsBatch];
+    int kq[kFsBatch], li[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      const int e = e0 + q * kFsNT;
+      oa[q] = ob[q] = 0;
+      kq[q] = -1;
+      li[q] = -1;
+      if (e < total) {
+        const int pos = e / TB, u = e - pos * TB;
+        const int64_t t = t0 + u;
+        li[q] = u * N1 + pos;
+        if (t < ntubes) {
+          const int k = k2 + N2 * long_src(fs.p1, pos);
+          kq[q] = k;
+          oa[q] = (int64_t)k * ntubes + t;
+          ob[q] = (int64_t)(N - k) * ntubes + t;  // 1 <= N - k <= N
+        }
+      }
     }
-    ar[u * N1 + pos] = vr;
-    ai[u * N1 + pos] = vi;
+    T ar0[kFsBatch], ai0[kFsBatch], br0[kFsBatch], bi0[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      ar0[q] = xre[oa[q]];
+      ai0[q] = xim[oa[q]];
+      br0[q] = xre[ob[q]];
+      bi0[q] = xim[ob[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      if (li[q] < 0) continue;
+      T vr = T(0), vi = T(0);
+      const int k = kq[q];
+      if (k >= 0) {
+        const double xr = (double)ar0[q], xi = k == 0 ? 0.0 : (double)ai0[q];
+        const double yr = (double)br0[q], yi = (N - k) == N ? 0.0 : -(double)bi0[q];  // conj X[N-k]
+        const double er = 0.5 * (xr + yr), ei = 0.5 * (xi + yi);
+        const double dr = 0.5 * (xr - yr), di = 0.5 * (xi - yi);
+        double c, sn;
+        fs_root(k, n, c, sn);  // W_n^k; O = D conj(W_n^k)
+        const double orr = dr * c + di * sn, oi = di * c - dr * sn;
+        // Z = E + i O, conjugated
+        vr = (T)(er - oi);
+        vi = (T)(-(ei + orr));
+      }
+      ar[li[q]] = vr;
+      ai[li[q]] = vi;
+    }
   }
   __syncthreads();
   multi_stages<T>(fs.p1, ar, ai, TB);
@@ -1041,20 +1123,37 @@ __global__ __launch_bounds__(kFsNT) void fs_inv_tube_kernel(int64_t ntubes, Four
   if (!fs_tube_block((ntubes + TB - 1) / TB, (N1 + JB - 1) / JB, sbk, jbk)) return;
   const int64_t t0 = sbk * TB;
   const int j10 = (int)jbk * JB;
-  for (int e = threadIdx.x; e < TB * JB * N2; e += kFsNT) {
-    const int v = e % JB, r = e / JB;
-    const int k2 = r % N2, u = r / N2;
-    const int64_t t = t0 + u;
-    const int j1 = j10 + v;
-    T vr = T(0), vi = T(0);
-    if (t < ntubes && j1 < N1) {
-      const int64_t o = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * k2);
-      vr = y[o];
-      vi = -y[o + 1];  // conjugate in, conjugate out
+  const int total = TB * JB * N2;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kFsBatch * kFsNT) {
+    int64_t off[kFsBatch];
+    int li[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      const int e = e0 + q * kFsNT;
+      off[q] = -1;
+      li[q] = -1;
+      if (e < total) {
+        const int v = e % JB, r = e / JB;
+        const int k2 = r % N2, u = r / N2;
+        const int64_t t = t0 + u;
+        const int j1 = j10 + v;
+        li[q] = (u * JB + v) * N2 + long_dst(fs.p2, k2);
+        if (t < ntubes && j1 < N1) off[q] = t * (int64_t)n + 2 * ((int64_t)j1 + (int64_t)N1 * k2);
+      }
     }
-    const int li = (u * JB + v) * N2 + long_dst(fs.p2, k2);
-    ar[li] = vr;
-    ai[li] = vi;
+    T vr[kFsBatch], vi[kFsBatch];
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      const int64_t o = off[q] < 0 ? 0 : off[q];
+      vr[q] = y[o];
+      vi[q] = y[o + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < kFsBatch; ++q) {
+      if (li[q] < 0) continue;
+      ar[li[q]] = off[q] < 0 ? T(0) : vr[q];
+      ai[li[q]] = off[q] < 0 ? T(0) : -vi[q];  // conjugate in, conjugate out
+    }
   }
   __syncthreads();
   multi_stages<T>(fs.p2, ar, ai, TB * JB);
