@@ -564,6 +564,16 @@ def test_four_step_rtprod_gathers():
     assert rel(Zg, T.tprod_fft(C, R)) < 2e-6
 
 
+def test_four_step_tcur_exact_rank():
+    """t-CUR on 10,000-long tubes (four-step transforms of the gathered C and
+    R and the inverse of Z, 5,001 Fourier slices) reproduces an exact
+    tubal-rank-2 tensor."""
+    g = np.random.default_rng(43)
+    A = T.tprod_fft(g.standard_normal((20, 2, 10000)), g.standard_normal((2, 18, 10000))).astype(np.float32)
+    Z, cols, rows = api.tcur(dev(A), 6, 6, 2, col_kind="norm2", row_kind="lev", seed=4, prec="f32")
+    assert rel(Z.cpu().numpy(), A) < 1e-4
+
+
 def test_msi_shaped_tcur():
     """t-CUR of a 122 x 120 x 2000 tensor (the MSI shape) of tubal rank 3:
     the exact-rank input is reproduced; long-tube transforms throughout."""
