@@ -534,7 +534,10 @@ size_t tp_mlp_train_workspace(int64_t ntensors, int64_t nslices);
  * slice the network underrates is still reachable). One pass over A
  * (features), the forward pass and the mixture. Feed w to tp_tsample or
  * tp_tcur as TP_P_USER weights; the exact leverage kind stays the
- * reference. */
+ * reference. If any network output is not finite (diverged or corrupted
+ * parameters), w is the uniform distribution 1 / n2 instead, so the picks
+ * drawn from it stay valid (no host synchronisation is needed to detect
+ * it; compare w with 1 / n2 to see it). */
 int tp_mlp_proposal(const float* params, const tp_tensor* A, const float* phi, double alpha, double* w, void* ws,
                     size_t ws_bytes, void* stream);
 size_t tp_mlp_proposal_workspace(const tp_tensor* A);

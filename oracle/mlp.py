@@ -119,6 +119,10 @@ def adam_step(P, G, M, V, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 def proposal(P, X, alpha=0.1):
     """Sampling probabilities (1 - alpha) softmax(o) + alpha / n, the
-    network's distribution mixed with the uniform one."""
-    o, _ = forward(P, X)
+    network's distribution mixed with the uniform one; outputs that are not
+    all finite give the uniform distribution (the defensive part alone)."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        o, _ = forward(P, X)
+    if not np.all(np.isfinite(o)):
+        return np.full(o.size, 1.0 / o.size)
     return (1 - alpha) * softmax(o) + alpha / o.size

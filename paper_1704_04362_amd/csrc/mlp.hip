@@ -590,15 +590,30 @@ __global__ void adam_kernel(float* __restrict__ P, float* __restrict__ M, float*
 }
 
 // w = (1 - alpha) softmax(o) + alpha / n (a defensive mixture with the
-// uniform distribution), float64, one workgroup.
+// uniform distribution), float64, one workgroup. A network output that is
+// not finite (diverged or corrupted parameters) gives the uniform
+// distribution, the mixture's defensive part, so the picks stay valid.
 __global__ __launch_bounds__(256) void proposal_kernel(const float* __restrict__ o, int64_t n, double alpha,
                                                        double* __restrict__ w) {
   __shared__ double red[256];
+  __shared__ int bad;
   const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  __syncthreads();
   double m = -INFINITY;
-  for (int64_t j = tid; j < n; j += 256) m = fmax(m, (double)o[j]);
+  int nonfinite = 0;
+  for (int64_t j = tid; j < n; j += 256) {
+    const float v = o[j];
+    nonfinite |= !isfinite(v);
+    m = fmax(m, (double)v);
+  }
+  if (nonfinite) bad = 1;  // benign race: every writer stores 1
   red[tid] = m;
   __syncthreads();
+  if (bad) {
+    for (int64_t j = tid; j < n; j += 256) w[j] = 1.0 / (double)n;
+    return;
+  }
   for (int s = 128; s > 0; s >>= 1) {
     if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
     __syncthreads();

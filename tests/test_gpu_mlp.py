@@ -166,6 +166,25 @@ def test_training_gains_over_norm_sampling():
     assert np.mean(kl_learned) < np.mean(kl_norm)
 
 
+def test_proposal_nonfinite_falls_back_to_uniform():
+    """Non-finite network outputs (a NaN output bias) give the uniform
+    distribution, as in the oracle, and a t-CUR with the learned kind still
+    draws its c picks from it."""
+    n1, n2, n3 = 24, 40, 8
+    A = coherent(n1, n2, n3, 3, 1.0, seed=5)
+    phi = phi_for(n1, n3)
+    P = _params(11)
+    P["b3"] = np.array([np.nan])
+    params = api.mlp_pack(P)
+    w = api.mlp_proposal(params, dev(A), dev(phi), alpha=0.2).cpu().numpy()
+    np.testing.assert_array_equal(w, np.full(n2, 1.0 / n2))
+    Z, cols, rows = api.tcur(dev(A), 10, 10, 3, col_kind="learned", row_kind="lev", seed=1, prec="f32",
+                             mlp=(params, dev(phi), 0.2))
+    idx, _ = cols.host()
+    assert idx.numel() == 10 and int(idx.min()) >= 0 and int(idx.max()) < n2
+    assert np.isfinite(Z.cpu().numpy()).all()
+
+
 def test_proposal_weights():
     n1, n2, n3 = 24, 40, 8
     A = coherent(n1, n2, n3, 3, 1.0, seed=3)

@@ -75,3 +75,18 @@ def test_proposal_is_a_distribution():
     # alpha = 1 is the uniform distribution, alpha = 0 the network's softmax
     np.testing.assert_allclose(M.proposal(P, X, alpha=1.0), np.full(25, 1 / 25), rtol=1e-14)
     np.testing.assert_allclose(M.proposal(P, X, alpha=0.0), M.softmax(M.forward(P, X)[0]), rtol=1e-14)
+
+
+def test_proposal_nonfinite_output_gives_uniform():
+    """A network whose outputs are not finite (here an infinite and a NaN
+    output bias) gives the uniform distribution, the defensive part of the
+    mixture, instead of NaN weights; finite outputs are untouched."""
+    P = M.init_params(4)
+    X = rs.standard_normal((13, M.D_IN))
+    for bad in (np.nan, np.inf):
+        Q = dict(P)
+        Q["b3"] = np.array([bad])
+        np.testing.assert_array_equal(M.proposal(Q, X, alpha=0.3), np.full(13, 1 / 13))
+    p = M.proposal(P, X, alpha=0.3)
+    assert abs(p.sum() - 1) < 1e-12 and not np.allclose(p, 1 / 13)
+
