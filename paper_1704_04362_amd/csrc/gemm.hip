@@ -9,6 +9,8 @@
 // LDS-tiled on the vector ALUs) and the dispatch. The matrix-core kernels
 // live in gemm_f32.hip (float32 arithmetic), gemm_mfma.hip (split bf16),
 // gemm_short.hip (short contractions) and gemm_tall.hip (narrow results).
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace tp {
@@ -199,8 +201,37 @@ __global__ __launch_bounds__(NT) void cgemm_simt_kernel(GemmArgs g) {
 
 }  // namespace
 
+// Most launches put the Fourier slices on a grid dimension that holds at
+// most 65,535 values. Longer spectra (tubes above 131,070) are taken in
+// chunks of that many slices. Every kernel treats slice 0 of its launch as
+// the real DC slice, so a chunk after the first starts one slice early: that
+// slice comes out wrong (imaginary part dropped) and is then recomputed by
+// the preceding chunk, which runs later because the chunks are enqueued
+// last first.
+constexpr int64_t kLaunchSlices = 65535;
+
 int cgemm(const CGemm& p, int dtype, int prec, hipStream_t st) {
   if (p.K == 0 || p.M == 0 || p.N == 0) return TP_OK;
+  if (p.K > kLaunchSlices) {
+    const size_t es = dtype == TP_F64 ? 8 : 4;
+    const int64_t step = kLaunchSlices - 1;
+    const int64_t nlater = (p.K - kLaunchSlices + step - 1) / step;
+    for (int64_t c = nlater; c >= 0; --c) {
+      const int64_t lo = c == 0 ? 0 : kLaunchSlices + (c - 1) * step - 1;
+      const int64_t hi = c == 0 ? kLaunchSlices : std::min(p.K, kLaunchSlices + c * step);
+      CGemm q = p;
+      q.K = hi - lo;
+      q.are = (const char*)p.are + lo * p.sa * es;
+      q.aim = (const char*)p.aim + lo * p.sa * es;
+      q.bre = (const char*)p.bre + lo * p.sb * es;
+      q.bim = (const char*)p.bim + lo * p.sb * es;
+      q.cre = (char*)p.cre + lo * p.sc * es;
+      q.cim = (char*)p.cim + lo * p.sc * es;
+      q.real_last = p.real_last && hi == p.K;
+      if (int rc = cgemm(q, dtype, prec, st)) return rc;
+    }
+    return TP_OK;
+  }
   if (dtype == TP_F32 && (prec == TP_PREC_F32 || prec == TP_PREC_BF16X3)) {
     const int split = prec == TP_PREC_BF16X3 ? 1 : 0;
     bool handled = false;

@@ -574,6 +574,26 @@ def test_four_step_tcur_exact_rank():
     assert rel(Z.cpu().numpy(), A) < 1e-4
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_tprod_more_than_65535_fourier_slices(prec):
+    """Tubes of 140,000 (K = 70,001 Fourier slices, beyond one launch
+    dimension): the per-slice products run in chunks; exact t-product and
+    an rt-product against the oracle's FFT route."""
+    dt = np.float64 if prec == "f64" else np.float32
+    g = np.random.default_rng(47)
+    A = g.standard_normal((3, 5, 140000)).astype(dt)
+    B = g.standard_normal((5, 2, 140000)).astype(dt)
+    tol = 1e-12 if prec == "f64" else 2e-6 if prec == "f32" else 1.3e-5
+    C = api.tprod(dev(A), dev(B), prec=prec).cpu().numpy()
+    assert rel(C, T.tprod_fft(A.astype(np.float64), B.astype(np.float64))) < tol
+    picks = api.tsample("norm2", 4, mode="iid", seed=9, A=dev(A))
+    Z = api.tprod(dev(A), dev(B), picks=picks, prec=prec).cpu().numpy()
+    idx, sc = picks.host()
+    i, s = idx.numpy().astype(np.int64), sc.numpy()
+    ref = T.tprod_fft(A[:, i, :].astype(np.float64) * s[None, :, None], B[i].astype(np.float64) * s[:, None, None])
+    assert rel(Z, ref) < tol
+
+
 def test_msi_shaped_tcur():
     """t-CUR of a 122 x 120 x 2000 tensor (the MSI shape) of tubal rank 3:
     the exact-rank input is reproduced; long-tube transforms throughout."""
