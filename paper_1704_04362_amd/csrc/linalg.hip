@@ -385,13 +385,14 @@ __global__ void transform_kernel(const double* __restrict__ vre, const double* _
 // part[k][j] = w_k sum_{i<r} |X_k[j, i]|^2 g_k[i], with g_k[i] = 1/lambda_k[i]
 // when scaled (so that X_k diag(1/sigma) is normalised), else 1; w_k the
 // conjugate weights of the half spectrum (1 for the real slices, 2 for the
-// others). One thread per (row j, slice k = blockIdx.y).
+// others). One thread per (row j, slice k = blockIdx.x): slices on the grid
+// dimension that holds more than 65,535 values.
 template <typename T>
 __global__ void leverage_kernel(const T* __restrict__ xre, const T* __restrict__ xim, int64_t K, int64_t n,
                                 int64_t ldx, int64_t sx, int r, int real_last, const double* __restrict__ evals,
                                 int s, double rtol, double* __restrict__ part) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t k = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  const int64_t k = blockIdx.x;
   if (j >= n) return;
   const double wk = (k == 0 || (real_last && k == K - 1)) ? 1.0 : 2.0;
   const double l0 = evals ? evals[k * s] : 0.0;
@@ -525,7 +526,7 @@ int xgram(const void* xre, const void* xim, int a, int64_t ldx, int64_t sx, cons
           double* pre, double* pim, hipStream_t st) {
   if (a < 1 || a > kMaxS || b < 1 || b > kMaxS) return fail(TP_EUNSUPPORTED, "cross product size outside 1..64");
   if (K == 0) return TP_OK;
-  if (K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
+  if (K > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many Fourier slices");  // slices on grid x
   if (!pre || !pim) return fail(TP_EWORKSPACE, "cross product partial buffer missing");
   const int64_t nch = gram_chunks(rows);
   const int64_t rch = (rows + nch - 1) / nch;
@@ -553,7 +554,7 @@ int gram(const void* xre, const void* xim, int dtype, int64_t K, int64_t rows, i
          bool real_last, double* gre, double* gim, double* pre, double* pim, hipStream_t st) {
   if (s < 1 || s > kMaxS) return fail(TP_EUNSUPPORTED, "Gram size outside 1..64");
   if (K == 0) return TP_OK;
-  if (K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
+  if (K > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many Fourier slices");  // slices on grid x
   if (!pre || !pim) return fail(TP_EWORKSPACE, "Gram partial buffer missing");
   const int64_t nch = gram_chunks(rows);
   const int64_t rch = (rows + nch - 1) / nch;
@@ -629,8 +630,9 @@ int eig_transform(const double* vre, const double* vim, const double* evals, int
 int leverage(const void* xre, const void* xim, int dtype, int64_t K, int64_t n, int64_t ldx, int64_t sx, int r,
              bool real_last, const double* evals, int s, double rtol, double* part, double* out, hipStream_t st) {
   if (n == 0) return TP_OK;
-  if (K > 65535) return fail(TP_EUNSUPPORTED, "more than 65535 Fourier slices");
-  const dim3 grid(blocks_for(n), (unsigned)K);
+  if (K > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many Fourier slices");
+  if (blocks_for(n) > 65535) return fail(TP_EUNSUPPORTED, "too many slices to score");
+  const dim3 grid((unsigned)K, blocks_for(n));
   if (dtype == TP_F64)
     hipLaunchKernelGGL(leverage_kernel<double>, grid, dim3(256), 0, st, (const double*)xre, (const double*)xim, K,
                        n, ldx, sx, r, real_last ? 1 : 0, evals, s, rtol, part);

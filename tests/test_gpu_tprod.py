@@ -594,6 +594,18 @@ def test_tprod_more_than_65535_fourier_slices(prec):
     assert rel(Z, ref) < tol
 
 
+@pytest.mark.parametrize("col_kind", ["lev", "norm2"])
+def test_tcur_more_than_65535_fourier_slices(col_kind):
+    """t-CUR on 140,000-long tubes (70,001 Fourier slices: chunked slice
+    products, slices on the unbounded grid dimension in the cross products,
+    Gram matrices and leverage scores) reproduces an exact tubal-rank-2
+    tensor."""
+    g = np.random.default_rng(53)
+    A = T.tprod_fft(g.standard_normal((12, 2, 140000)), g.standard_normal((2, 10, 140000))).astype(np.float32)
+    Z, cols, rows = api.tcur(dev(A), 5, 5, 2, col_kind=col_kind, row_kind="lev", seed=6, prec="f32")
+    assert rel(Z.cpu().numpy(), A) < 1e-4
+
+
 def test_msi_shaped_tcur():
     """t-CUR of a 122 x 120 x 2000 tensor (the MSI shape) of tubal rank 3:
     the exact-rank input is reproduced; long-tube transforms throughout."""
