@@ -636,11 +636,16 @@ int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_
   // slices [k0, k1) on stream s
   auto sweeps = [&](int64_t k0, int64_t k1, hipStream_t s) -> int {
     PairArgs g = a;
-    g.k0 = k0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
       for (int round = 0; round < nb - 1; ++round) {
-        hipLaunchKernelGGL(svt_pair_kernel, dim3(nb / 2, (unsigned)(k1 - k0)), dim3(NT), 0, s, g, round);
-        TP_LAUNCH_CHECK();
+        // the slices sit on a grid dimension of at most 65,535 values: longer
+        // spectra take several launches per round
+        for (int64_t c0 = k0; c0 < k1; c0 += 65535) {
+          g.k0 = c0;
+          const int64_t kc = k1 - c0 < 65535 ? k1 - c0 : 65535;
+          hipLaunchKernelGGL(svt_pair_kernel, dim3(nb / 2, (unsigned)kc), dim3(NT), 0, s, g, round);
+          TP_LAUNCH_CHECK();
+        }
       }
       hipLaunchKernelGGL(svt_conv_kernel, dim3(nblk(k1 - k0)), dim3(256), 0, s, ratio, K, k0, k1, nb - 1, nb / 2,
                          tol, conv);

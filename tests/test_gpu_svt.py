@@ -73,6 +73,21 @@ def test_tsvt_two_stream_sweeps_match_oracle(shape):
     np.testing.assert_array_equal(ranks.cpu().numpy(), rr)
 
 
+def test_tsvt_more_than_65535_fourier_slices():
+    """t-SVT on 140,000-long tubes (70,001 Fourier slices: the pair steps of
+    each round run in several launches) of an exact tubal-rank-2 tensor, with
+    the threshold far below the two nonzero singular values of every slice:
+    the slices' singular values are shrunk by tau and every rank is 2."""
+    g = np.random.default_rng(59)
+    M = T.tprod_fft(g.standard_normal((8, 2, 140000)), g.standard_normal((2, 6, 140000)))
+    tau = 1e-4 * float(np.median(np.linalg.norm(M, axis=(0, 1))))
+    L, ranks = api.tsvt(dev(M.astype(np.float32)), tau)
+    Lr, rr = D.tsvt(M, tau)
+    assert rel(L.cpu().numpy(), Lr) < 1e-5
+    np.testing.assert_array_equal(ranks.cpu().numpy(), rr)
+    assert (rr == 2).all()
+
+
 @pytest.mark.parametrize("shape", [(72, 40, 6), (40, 72, 5)])
 def test_tsvt_graded_spectrum(shape):
     # singular values spread over four decades: pairs of rows whose norms
