@@ -423,6 +423,29 @@ __global__ void sum_slices_kernel(const double* __restrict__ part, int64_t K, in
   out[j] = acc;
 }
 
+// Long spectra: thread (j, c) sums slices [c kc, (c + 1) kc) of column j in
+// order and leaves the sum in the chunk's first row (read by no other
+// thread); the chunk sums are then added in chunk order.
+__global__ void sum_chunks_kernel(double* __restrict__ part, int64_t K, int64_t n, int64_t kc) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.y * kc;
+  if (j >= n) return;
+  const int64_t k1 = k0 + kc < K ? k0 + kc : K;
+  double acc = 0.0;
+#pragma unroll 16
+  for (int64_t k = k0; k < k1; ++k) acc += part[k * n + j];
+  part[k0 * n + j] = acc;
+}
+
+__global__ void sum_chunk_heads_kernel(const double* __restrict__ part, int64_t K, int64_t n, int64_t kc,
+                                       double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int64_t k0 = 0; k0 < K; k0 += kc) acc += part[k0 * n + j];
+  out[j] = acc;
+}
+
 __global__ void sqrt_evals_kernel(const double* __restrict__ evals, int64_t K, int s, int r,
                                   double* __restrict__ sv) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -640,7 +663,17 @@ int leverage(const void* xre, const void* xim, int dtype, int64_t K, int64_t n, 
     hipLaunchKernelGGL(leverage_kernel<float>, grid, dim3(256), 0, st, (const float*)xre, (const float*)xim, K, n,
                        ldx, sx, r, real_last ? 1 : 0, evals, s, rtol, part);
   TP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sum_slices_kernel, dim3(blocks_for(n)), dim3(256), 0, st, part, K, n, out);
+  if (K > 4096) {
+    // many slices and few rows: chunks of 256 slices summed in parallel
+    constexpr int64_t kc = 256;
+    const int64_t nch = (K + kc - 1) / kc;
+    if (nch > 65535) return fail(TP_EUNSUPPORTED, "too many Fourier slices");
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(blocks_for(n), (unsigned)nch), dim3(256), 0, st, part, K, n, kc);
+    TP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sum_chunk_heads_kernel, dim3(blocks_for(n)), dim3(256), 0, st, part, K, n, kc, out);
+  } else {
+    hipLaunchKernelGGL(sum_slices_kernel, dim3(blocks_for(n)), dim3(256), 0, st, part, K, n, out);
+  }
   TP_LAUNCH_CHECK();
   return TP_OK;
 }
