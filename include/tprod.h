@@ -372,10 +372,13 @@ size_t tp_tcur_workspace(const tp_tensor* A, int64_t c, int64_t l, int64_t r, in
  * NULL) receives the number of singular values above tau in each
  * non-redundant slice. The slice SVDs are computed exactly (block one-sided
  * Jacobi on the shorter side of the slices, until every row inner product
- * is below 1e-6 of the larger squared row norm). float32 data, prec
- * TP_PREC_F32. */
-int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
-            void* stream);
+ * is below 1e-6 of the larger squared row norm, at most 30 sweeps).
+ * unconverged (device, one int32, may be NULL) receives the number of
+ * non-redundant slices whose sweeps reached that cap without meeting the
+ * test (their L is still written, from the last rotations; 0 in normal
+ * operation). float32 data, prec TP_PREC_F32. */
+int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int32_t* unconverged, int prec, void* ws,
+            size_t ws_bytes, void* stream);
 size_t tp_tsvt_workspace(const tp_tensor* M);
 
 /* Dense leading-r t-SVD (the t-SVD theorem of Section 2.1) without the
@@ -394,9 +397,12 @@ size_t tp_tsvt_workspace(const tp_tensor* M);
  * number: there singular values below ~1e-3 of the largest lose accuracy in
  * float32 and those below ~3e-4 of it (the square root of float32 rounding)
  * are not resolved. A column whose singular value is exactly zero is zero.
- * A float32; 1 <= r <= min(n1, n2) <= 4096. Workspace:
+ * unconverged (device, one int32, may be NULL) receives the number of
+ * Fourier slices whose Jacobi sweeps reached their cap without converging,
+ * as for tp_tsvt. A float32; 1 <= r <= min(n1, n2) <= 4096. Workspace:
  * tp_tsvd_full_workspace(A, r) bytes. */
-int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S, void* ws, size_t ws_bytes, void* stream);
+int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S, int32_t* unconverged, void* ws,
+                 size_t ws_bytes, void* stream);
 size_t tp_tsvd_full_workspace(const tp_tensor* A, int64_t r);
 
 /* Tensor completion by the ADMM of Algorithm 7 with the constraint

@@ -58,10 +58,11 @@ _SIGS = {
                           C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
     "tp_tcur_workspace": (C.c_size_t, [P(Tensor), C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
                                        C.c_int, C.c_int]),
-    "tp_tsvt": (C.c_int, [P(Tensor), C.c_double, P(Tensor), C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
+    "tp_tsvt": (C.c_int, [P(Tensor), C.c_double, P(Tensor), C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
                           C.c_void_p]),
     "tp_tsvt_workspace": (C.c_size_t, [P(Tensor)]),
-    "tp_tsvd_full": (C.c_int, [P(Tensor), C.c_int64, P(Tensor), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "tp_tsvd_full": (C.c_int, [P(Tensor), C.c_int64, P(Tensor), C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                 C.c_void_p]),
     "tp_tsvd_full_workspace": (C.c_size_t, [P(Tensor), C.c_int64]),
     "tp_tcomplete": (C.c_int, [P(Tensor), C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
                                P(Tensor), P(Tensor), P(Tensor), C.c_void_p, P(C.c_int32), C.c_int, C.c_void_p,

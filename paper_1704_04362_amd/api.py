@@ -307,33 +307,40 @@ def tcur(A, c, l, r, col_kind="lev", row_kind="lev", col_w=None, row_w=None, mod
     return Z, cols, rows
 
 
-def tsvd_full(A, r, out=None):
+def tsvd_full(A, r, out=None, with_unconverged=False):
     """Dense leading-r t-SVD (see tp_tsvd_full): returns (U, S) with U the
     n1 x r x n3 first left singular slices of A (float32) and S the K x r
-    singular values of the Fourier slices (float64, descending)."""
+    singular values of the Fourier slices (float64, descending); with
+    with_unconverged also a device int32 count of the Fourier slices whose
+    Jacobi sweeps hit their cap."""
     _need_gpu(A)
     n1, n2, n3 = A.shape
     U = _out(out, (n1, r, n3), torch.float32, A.device)
     S = torch.empty((half_count(n3), r), dtype=torch.float64, device=A.device)
+    unc = torch.zeros(1, dtype=torch.int32, device=A.device) if with_unconverged else None
     lib = L.load()
     t, tu = _tensor(A), _tensor(U)
     ws = _ws(lib.tp_tsvd_full_workspace(C.byref(t), int(r)), A.device)
-    L.check(lib.tp_tsvd_full(C.byref(t), int(r), C.byref(tu), S.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
-    return U, S
+    L.check(lib.tp_tsvd_full(C.byref(t), int(r), C.byref(tu), S.data_ptr(),
+                             unc.data_ptr() if unc is not None else None, ws.data_ptr(), ws.numel(), _stream()))
+    return (U, S, unc) if with_unconverged else (U, S)
 
 
-def tsvt(M, tau, out=None):
+def tsvt(M, tau, out=None, with_unconverged=False):
     """Per-Fourier-slice singular value thresholding with threshold tau:
-    returns (L, ranks)."""
+    returns (L, ranks), and with with_unconverged also a device int32 count
+    of the slices whose Jacobi sweeps hit their cap."""
     _need_gpu(M)
     L_ = _out(out, M.shape, M.dtype, M.device)
     ranks = torch.empty(half_count(M.shape[2]), dtype=torch.int32, device=M.device)
+    unc = torch.zeros(1, dtype=torch.int32, device=M.device) if with_unconverged else None
     lib = L.load()
     tm, tl = _tensor(M), _tensor(L_)
     ws = _ws(lib.tp_tsvt_workspace(C.byref(tm)), M.device)
-    L.check(lib.tp_tsvt(C.byref(tm), float(tau), C.byref(tl), ranks.data_ptr(), L.PREC["f32"], ws.data_ptr(),
-                        ws.numel(), _stream()))
-    return L_, ranks
+    L.check(lib.tp_tsvt(C.byref(tm), float(tau), C.byref(tl), ranks.data_ptr(),
+                        unc.data_ptr() if unc is not None else None, L.PREC["f32"], ws.data_ptr(), ws.numel(),
+                        _stream()))
+    return (L_, ranks, unc) if with_unconverged else (L_, ranks)
 
 
 def _admm_status(status, info, done):

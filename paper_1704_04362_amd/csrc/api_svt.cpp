@@ -354,8 +354,8 @@ size_t tp_tsvt_workspace(const tp_tensor* M) {
   return dry.used + 256;
 }
 
-int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int prec, void* ws, size_t ws_bytes,
-            void* stream) {
+int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int32_t* unconverged, int prec, void* ws,
+            size_t ws_bytes, void* stream) {
   if (int rc = check_f32_tensor(M, "M")) return rc;
   if (int rc = check_f32_tensor(L, "L")) return rc;
   if (prec != TP_PREC_F32) return fail(TP_EDTYPE, "thresholding supports TP_PREC_F32");
@@ -386,6 +386,7 @@ int tp_tsvt(const tp_tensor* M, double tau, tp_tensor* L, int32_t* ranks, int pr
   if (int rc = svt_jacobi(lay.svt.xre, lay.svt.xim, lay.svt.ure, lay.svt.uim, K, r, c, real_last, kColdSweeps,
                           kSvtTol, lay.svt.ratio, lay.svt.conv, st))
     return rc;
+  if (int rc = svt_count_unconverged(lay.svt.conv, K, unconverged, st)) return rc;
   if (!tall) return finish_svt(lay.svt, K, r, c, n3, tau, real_last, ranks, L->data, st);
   if (int rc = finish_svt(lay.svt, K, r, c, n3, tau, real_last, ranks, lay.lt, st)) return rc;
   return ttranspose(lay.lt, 4, r, c, n3, L->data, st);
@@ -399,8 +400,8 @@ size_t tp_tsvd_full_workspace(const tp_tensor* A, int64_t r) {
   return dry.used + 256;
 }
 
-int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, void* ws, size_t ws_bytes,
-                 void* stream) {
+int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, int32_t* unconverged, void* ws,
+                 size_t ws_bytes, void* stream) {
   if (int rc = check_f32_tensor(A, "A")) return rc;
   if (int rc = check_f32_tensor(U, "U")) return rc;
   const int64_t n1 = A->n1, n2 = A->n2, n3 = A->n3, m = std::min(n1, n2);
@@ -440,6 +441,7 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
     if (int rc = svt_jacobi(lay.are, lay.aim, lay.qre, lay.qim, K, m, n, real_last, kColdSweeps, kSvtTol,
                             lay.ratio, lay.conv, st))
       return rc;
+    if (int rc = svt_count_unconverged(lay.conv, K, unconverged, st)) return rc;
     // rows of X are sigma_i times conjugated singular vectors: U from Q
     // (wide, X = U^H A) or from X / sigma (tall, X = Sigma U^H)
     if (tall) {
@@ -488,6 +490,7 @@ int tp_tsvd_full(const tp_tensor* A, int64_t r, tp_tensor* U, double* S_out, voi
   if (int rc = svt_jacobi(lay.xre, lay.xim, lay.qre, lay.qim, K, m, m, real_last, kColdSweeps, kSvtTol, lay.ratio,
                           lay.conv, st))
     return rc;
+  if (int rc = svt_count_unconverged(lay.conv, K, unconverged, st)) return rc;
   if (!tall) {
     if (int rc = tsvd_pick(lay.xre, lay.xim, m, lay.qre, lay.qim, m, K, m, r, real_last, 0, true, gram_floor,
                            lay.ure, lay.uim, S_out, st))

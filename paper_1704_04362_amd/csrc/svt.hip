@@ -285,6 +285,22 @@ __global__ void svt_conv_kernel(const float* __restrict__ ratio, int64_t K, int6
   if (m < tol) conv[k] = 1;
 }
 
+// Number of slices whose sweeps ended without meeting the convergence test
+// (conv[k] == 0), one workgroup, integer sums in a fixed order.
+__global__ __launch_bounds__(256) void count_unconverged_kernel(const int* __restrict__ conv, int64_t K,
+                                                                int32_t* __restrict__ out) {
+  __shared__ int64_t red[256];
+  int64_t c = 0;
+  for (int64_t k = threadIdx.x; k < K; k += 256) c += conv[k] ? 0 : 1;
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (int32_t)(red[0] < 0x7fffffff ? red[0] : 0x7fffffff);
+}
+
 __global__ void identity_kernel(float* re, float* im, int64_t K, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= K * n * n) return;
@@ -623,6 +639,13 @@ int zero_f32(float* p, int64_t n, hipStream_t st) {
 int svt_identity(float* ure, float* uim, int64_t K, int64_t n, hipStream_t st) {
   if (K * n * n == 0) return TP_OK;
   hipLaunchKernelGGL(identity_kernel, dim3(nblk(K * n * n)), dim3(256), 0, st, ure, uim, K, n);
+  TP_LAUNCH_CHECK();
+  return TP_OK;
+}
+
+int svt_count_unconverged(const int* conv, int64_t K, int32_t* out, hipStream_t st) {
+  if (!out) return TP_OK;
+  hipLaunchKernelGGL(count_unconverged_kernel, dim3(1), dim3(256), 0, st, conv, K, out);
   TP_LAUNCH_CHECK();
   return TP_OK;
 }

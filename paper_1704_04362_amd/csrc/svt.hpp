@@ -13,6 +13,9 @@ int zero_f32(float* p, int64_t n, hipStream_t st);
 int svt_identity(float* ure, float* uim, int64_t K, int64_t n, hipStream_t st);
 // Block one-sided Jacobi on the rows of X (K x n1 x n2), accumulating the row
 // rotations in Uh (K x n1 x n1); conv receives per-slice convergence flags.
+// Writes (when out is not null) the number of the K slices whose last
+// svt_jacobi sweeps ended without meeting its convergence test.
+int svt_count_unconverged(const int* conv, int64_t K, int32_t* out, hipStream_t st);
 int svt_jacobi(float* xre, float* xim, float* ure, float* uim, int64_t K, int64_t n1, int64_t n2, bool real_last,
                int max_sweeps, double tol, float* ratio, int* conv, hipStream_t st);
 int svt_shrink(float* xre, float* xim, int64_t K, int64_t n1, int64_t n2, double tau, bool real_last,

@@ -157,7 +157,7 @@ def test_tsvt_validation(case):
     else:
         wsb = 16
         want = -4
-    rc = lib.tp_tsvt(C.byref(M), tau, C.byref(Lt), None, prec, C.c_void_p(0x2000), wsb, None)
+    rc = lib.tp_tsvt(C.byref(M), tau, C.byref(Lt), None, None, prec, C.c_void_p(0x2000), wsb, None)
     assert rc == want, lib.tp_last_error()
     assert lib.tp_last_error()
 
@@ -298,7 +298,7 @@ def test_tsvd_full_validation(case):
     else:
         wsb = 16
         want = -4
-    rc = lib.tp_tsvd_full(C.byref(A), r, C.byref(U), None, C.c_void_p(0x2000), wsb, None)
+    rc = lib.tp_tsvd_full(C.byref(A), r, C.byref(U), None, None, C.c_void_p(0x2000), wsb, None)
     assert rc == want, lib.tp_last_error()
 
 

@@ -73,6 +73,21 @@ def test_tsvt_two_stream_sweeps_match_oracle(shape):
     np.testing.assert_array_equal(ranks.cpu().numpy(), rr)
 
 
+def test_tsvt_reports_unconverged_slices():
+    """The count of slices whose sweeps hit the cap (0 for ordinary inputs,
+    including a graded spectrum and a tall slice), and the same L with and
+    without asking for it."""
+    rs = np.random.default_rng(61)
+    for shape in [(48, 40, 9), (30, 70, 8)]:
+        M = rs.standard_normal(shape).astype(np.float32) * np.logspace(0, -3, shape[1])[None, :, None].astype(
+            np.float32)
+        tau = _tau_in_gap(M.astype(np.float64), 0.5)
+        L, ranks, unc = api.tsvt(dev(M), tau, with_unconverged=True)
+        L2, _ = api.tsvt(dev(M), tau)
+        assert int(unc.item()) == 0
+        np.testing.assert_array_equal(L.cpu().numpy(), L2.cpu().numpy())
+
+
 def test_tsvt_more_than_65535_fourier_slices():
     """t-SVT on 140,000-long tubes (70,001 Fourier slices: the pair steps of
     each round run in several launches) of an exact tubal-rank-2 tensor, with

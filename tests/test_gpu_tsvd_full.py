@@ -115,3 +115,18 @@ def test_tsvd_full_direct_path_resolves_a_graded_spectrum(shape):
     assert np.all(np.abs(S_.cpu().numpy() - s_ref) <= 1e-5 * s_ref + 2e-6 * sv.max())
     U = U.cpu().numpy().astype(np.float64)
     assert rel(T.tprod_fft(T.ttranspose(U), U), T.teye(r, n3)) < 1e-5
+
+
+def test_tsvd_full_reports_unconverged_slices():
+    """Both routes (near-square slices and the Gram route) report 0 slices
+    whose sweeps hit the cap on ordinary inputs, and give the same U and S
+    with and without the count."""
+    rs = np.random.default_rng(67)
+    for shape, r in [((40, 48, 6), 5), ((300, 20, 5), 4)]:
+        A = rs.standard_normal(shape).astype(np.float32)
+        U, S, unc = api.tsvd_full(dev(A), r, with_unconverged=True)
+        U2, S2 = api.tsvd_full(dev(A), r)
+        assert int(unc.item()) == 0
+        np.testing.assert_array_equal(U.cpu().numpy(), U2.cpu().numpy())
+        np.testing.assert_array_equal(S.cpu().numpy(), S2.cpu().numpy())
+
