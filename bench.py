@@ -580,11 +580,15 @@ def long_tubes(api, torch, n1=122, n2=120, n3=500000, reps=5):
     from oracle import tensor as T
     g = torch.Generator(device="cuda")
     g.manual_seed(20170413)
-    X = torch.randn((n1, n2, n3), generator=g, device="cuda", dtype=torch.float32)
     K = n3 // 2 + 1
-    re = torch.empty((K, n1, n2), device="cuda", dtype=torch.float32)
-    im = torch.empty_like(re)
-    Y = torch.empty_like(X)
+    try:
+        X = torch.randn((n1, n2, n3), generator=g, device="cuda", dtype=torch.float32)
+        re = torch.empty((K, n1, n2), device="cuda", dtype=torch.float32)
+        im = torch.empty_like(re)
+        Y = torch.empty_like(X)
+    except torch.OutOfMemoryError as e:
+        torch.cuda.empty_cache()
+        return {"skipped": f"out of device memory: {str(e)[:120]}"}
     fwd = lambda: api.tfft(X, out=(re, im))  # noqa: E731
     inv = lambda: api.tifft(re, im, n3, out=Y)  # noqa: E731
     ms_f = time_events(fwd, reps, torch)
