@@ -49,52 +49,59 @@ constexpr int SJ = 64;   // lateral slices per workgroup (4 tiles of 16)
 constexpr int SIR = 16;  // horizontal slices per workgroup
 constexpr int SNT = 256;
 
-__device__ __forceinline__ int sketch_ldk(int64_t n3) { return (int)((n3 + 15) / 16 * 16 + 4); }
+// Tubes are taken in chunks of at most kSketchChunk entries (a multiple of
+// 16), so that two chunks of Phi_i fit in 64 KB of LDS at any tube length.
+constexpr int kSketchChunk = 496;
+__device__ __host__ __forceinline__ int sketch_chunk(int64_t n3) {
+  const int64_t r = (n3 + 15) / 16 * 16;
+  return (int)(r < kSketchChunk ? r : kSketchChunk);
+}
+__device__ __host__ __forceinline__ int sketch_ldk(int64_t n3) { return sketch_chunk(n3) + 4; }
 
 // partial[(y n2 + j) (DS + 1) + d]: the chunk-y sums (float32) of the
 // sketch (d < DS) and of the squared norm (d = DS) of lateral slice j.
 __global__ __launch_bounds__(SNT) void sketch_mfma_kernel(const float* __restrict__ a, const float* __restrict__ phi,
                                                            int64_t n1, int64_t n2, int64_t n3,
                                                            float* __restrict__ partial) {
-  extern __shared__ float phs[];  // [2][DS][ldk]: Phi_i transposed, double buffered
+  extern __shared__ float phs[];  // [2][DS][ldk]: a tube chunk of Phi_i transposed, double buffered
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ldk = sketch_ldk(n3);
-  const int nkb = (int)((n3 + 15) / 16);
+  const int kc = sketch_chunk(n3), ldk = kc + 4;
   const int64_t j0 = (int64_t)blockIdx.x * SJ;
   const int64_t i0 = (int64_t)blockIdx.y * SIR;
   const int64_t rows = (n1 - i0) < SIR ? (n1 - i0) : SIR;
   const int g = lane >> 4, r = lane & 15;
   const int64_t j = j0 + wave * 16 + r;
   const bool jok = j < n2;
-  // zero the tube padding of both buffers once
-  for (int e = tid; e < 2 * DS * (ldk - (int)n3); e += SNT) {
-    const int w = ldk - (int)n3;
-    const int b = e / (DS * w), rem = e - b * DS * w;
-    phs[(b * DS + rem / w) * ldk + n3 + rem % w] = 0.f;
-  }
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   float nrm = 0.f;
+  // steps over (horizontal slice, tube chunk); the buffer written in a step
+  // was last read two steps earlier, before the previous step's barrier
+  int step = 0;
   for (int64_t ii = 0; ii < rows; ++ii) {
     const int64_t i = i0 + ii;
-    float* buf = phs + (ii & 1) * DS * ldk;
     const float* src = phi + i * n3 * DS;
-    for (int64_t e = tid; e < n3 * DS; e += SNT) {
-      const int64_t k = e / DS;
-      const int d = (int)(e - k * DS);
-      buf[d * ldk + k] = src[e];
-    }
-    __syncthreads();
     const float* arow = a + (i * n2 + j) * n3;
-    for (int kb = 0; kb < nkb; ++kb) {
-      const int64_t k = (int64_t)kb * 16 + 4 * g;
-      float4 x = {0.f, 0.f, 0.f, 0.f};
-      if (jok && k < n3) x = *reinterpret_cast<const float4*>(arow + k);
-      const float4 p = *reinterpret_cast<const float4*>(buf + r * ldk + k);
-      nrm += x.x * x.x + x.y * x.y + x.z * x.z + x.w * x.w;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, p.x, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, p.y, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, p.z, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, p.w, acc, 0, 0, 0);
+    for (int64_t k0 = 0; k0 < n3; k0 += kc, ++step) {
+      float* buf = phs + (step & 1) * DS * ldk;
+      // this chunk of Phi_i, zero beyond the tube's end
+      for (int e = tid; e < kc * DS; e += SNT) {
+        const int kk = e / DS, d = e - kk * DS;
+        buf[d * ldk + kk] = k0 + kk < n3 ? src[(k0 + kk) * DS + d] : 0.f;
+      }
+      __syncthreads();
+      const int nkb = (int)((n3 - k0 < kc ? n3 - k0 : kc) + 15) / 16;
+      for (int kb = 0; kb < nkb; ++kb) {
+        const int kk = kb * 16 + 4 * g;
+        const int64_t k = k0 + kk;
+        float4 x = {0.f, 0.f, 0.f, 0.f};
+        if (jok && k < n3) x = *reinterpret_cast<const float4*>(arow + k);
+        const float4 p = *reinterpret_cast<const float4*>(buf + r * ldk + kk);
+        nrm += x.x * x.x + x.y * x.y + x.z * x.z + x.w * x.w;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, p.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, p.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, p.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, p.w, acc, 0, 0, 0);
+      }
     }
   }
   // lane l holds S[row 4 g + v][d = l % 16] of the wavefront's tile
@@ -645,8 +652,7 @@ size_t mlp_features_ws(int64_t n1, int64_t n2) {
 int mlp_features(const float* a, int64_t n1, int64_t n2, int64_t n3, const float* phi, float* feat, void* ws,
                  hipStream_t st, double* norms) {
   if (n3 % 4) return fail(TP_EUNSUPPORTED, "feature extraction needs n3 divisible by 4");
-  const size_t lds = size_t(2) * DS * ((n3 + 15) / 16 * 16 + 4) * 4;
-  if (lds > 64 * 1024) return fail(TP_EUNSUPPORTED, "tube length too large for feature extraction");
+  const size_t lds = size_t(2) * DS * sketch_ldk(n3) * 4;
   if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(phi)) % 16)
     return fail(TP_EINVAL, "A and phi must be 16-byte aligned");
   const int64_t nch = (n1 + SIR - 1) / SIR, nb = (n2 + SJ - 1) / SJ, nbs = (n2 + SJS - 1) / SJS;

@@ -49,8 +49,12 @@ def test_param_count():
     assert api.mlp_param_count() == 17 * 128 + 128 + 128 * 128 + 128 + 128 + 1
 
 
-@pytest.mark.parametrize("shape", [(32, 48, 64), (20, 100, 16), (8, 37, 100), (40, 70, 128), (6, 20, 136)])
+@pytest.mark.parametrize(
+    "shape", [(32, 48, 64), (20, 100, 16), (8, 37, 100), (40, 70, 128), (6, 20, 136), (6, 20, 1000), (10, 30, 2000)]
+)
 def test_features_match_oracle(shape):
+    """Sketch features against the oracle, including tubes longer than one
+    LDS chunk of the sketch matrix (1000 and the MSI length 2000)."""
     n1, n2, n3 = shape
     A = W.gaussian(shape, seed=n2).astype(np.float32) * np.exp(W.gaussian(n2, seed=1))[None, :, None].astype(np.float32)
     phi = phi_for(n1, n3)
