@@ -509,8 +509,9 @@ int tp_trace_entry(int i, char* name, size_t name_cap, int64_t* calls, double* t
 int tp_mlp_param_count(void);
 
 /* Per-lateral-slice features of a float32 tensor A (n3 % 4 == 0, any tube
- * length): the sketch s_j = Phi^T vec(A_{:j:}) (vec order i n3 + k; Phi a caller-supplied
- * device float32 (n1 n3) x 16 row-major matrix, e.g. Gaussian / 4), whitened
+ * length): the sketch s_j = Phi^T vec(A_{:j:}) (vec order i n3 + k; Phi a
+ * caller-supplied device float32 (n1 n3) x 16 row-major matrix, e.g.
+ * Gaussian / 4), whitened
  * as z_j = G^{-1/2} s_j sqrt(n2) with G = sum_j s_j s_j^T, followed by
  * log(n2 a_j / sum a), a_j = ||A_{:j:}||_F^2. feat: device n2 x 17 float32. */
 int tp_mlp_features(const tp_tensor* A, const float* phi, float* feat, void* ws, size_t ws_bytes, void* stream);
