@@ -21,8 +21,9 @@
 // The inverse kernel runs these steps backwards. Long tubes (n3 above 256
 // without a specialised kernel, prime factors up to 13) use a
 // workgroup-per-tube mixed-radix transform in LDS; even ones beyond its LDS
-// budget (up to 2^19) a four-step transform through HBM; other lengths
-// without a specialised kernel use a direct O(n3^2) transform per tube.
+// budget (up to 2^19) a four-step transform through HBM; lengths from 257
+// with a larger prime factor, up to 2048 (float32) / 1024 (float64),
+// Bluestein's chirp-z transform in LDS; the rest a direct O(n3^2) transform.
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -1186,6 +1187,157 @@ bool radix_plan(int64_t n, LongPlan& pl) {
   return r == 1;
 }
 
+// --------------------------------------------------------------------------
+// Lengths with a prime factor above 13 (up to kBlueMax): Bluestein's
+// chirp-z transform in LDS, one workgroup per tube. With the chirp
+// w[m] = exp(-i pi m^2 / n), the DFT is X[k] = w[k] sum_m (x[m] w[m])
+// conj(w[k - m]) (from 2 m k = m^2 + k^2 - (k - m)^2), a circular
+// convolution of length L >= 2n - 1 (L without prime factors above 13)
+// evaluated by three mixed-radix transforms of length L: a = x w and the
+// filter b (conj w at m and L - m) forward, then the inverse of A B through
+// the conjugate. The inverse tube transform is the forward one of the
+// conjugated Hermitian extension, conjugated and scaled by 1/n.
+// --------------------------------------------------------------------------
+constexpr int kBlueMax = 2048;  // float32 tubes; float64 up to half of it
+
+struct BluePlan {
+  int n;
+  LongPlan pl;  // length L
+};
+
+// chirp exp(-i pi m^2 / n) in double (m^2 reduced mod 2n, exact in int64)
+__device__ __forceinline__ void blue_chirp(int m, int n, double& c, double& s) {
+  const int64_t e = ((int64_t)m * m) % (2 * (int64_t)n);
+  sincospi(-(double)e / (double)n, &s, &c);
+}
+
+// DFT of n complex values: load(m) gives input m < n, store(k, re, im)
+// takes output k < nout (<= n). LDS: ar | br (2L values, br = ar + L) and
+// ai | bi, so the two forward transforms run as one two-sequence pass.
+constexpr int kBluePer = 2 * kBlueMax / kFsNT;  // L / threads at most
+
+template <typename T, typename Load, typename Store>
+__device__ void bluestein(const BluePlan& bp, T* ar, T* ai, Load load, int nout, Store store) {
+  const int n = bp.n, L = bp.pl.n;
+  T* br = ar + L;
+  T* bi = ai + L;
+  for (int m = threadIdx.x; m < L; m += kFsNT) {
+    T a_r = T(0), a_i = T(0), b_r = T(0), b_i = T(0);
+    if (m < n) {
+      double c, sn, xr, xi;
+      blue_chirp(m, n, c, sn);
+      load(m, xr, xi);
+      a_r = (T)(xr * c - xi * sn);
+      a_i = (T)(xr * sn + xi * c);
+      b_r = (T)c;
+      b_i = (T)(-sn);
+    } else if (m > L - n) {
+      double c, sn;
+      blue_chirp(L - m, n, c, sn);
+      b_r = (T)c;
+      b_i = (T)(-sn);
+    }
+    const int pos = long_dst(bp.pl, m);
+    ar[pos] = a_r;
+    ai[pos] = a_i;
+    br[pos] = b_r;
+    bi[pos] = b_i;
+  }
+  __syncthreads();
+  multi_stages<T>(bp.pl, ar, ai, 2);
+  // conj(A B), through registers, into ar/ai in digit-reversed order
+  T pr[kBluePer], pi[kBluePer];
+#pragma unroll
+  for (int q = 0; q < kBluePer; ++q) {
+    const int m = threadIdx.x + q * kFsNT;
+    if (m < L) {
+      const double xr = (double)ar[m], xi = (double)ai[m], yr = (double)br[m], yi = (double)bi[m];
+      pr[q] = (T)(xr * yr - xi * yi);
+      pi[q] = (T)(-(xr * yi + xi * yr));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kBluePer; ++q) {
+    const int m = threadIdx.x + q * kFsNT;
+    if (m < L) {
+      const int pos = long_dst(bp.pl, m);
+      ar[pos] = pr[q];
+      ai[pos] = pi[q];
+    }
+  }
+  __syncthreads();
+  multi_stages<T>(bp.pl, ar, ai, 1);
+  const double inv = 1.0 / (double)L;
+  for (int k = threadIdx.x; k < nout; k += kFsNT) {
+    double c, sn;
+    blue_chirp(k, n, c, sn);
+    const double yr = (double)ar[k] * inv, yi = -(double)ai[k] * inv;  // the convolution at k
+    store(k, yr * c - yi * sn, yr * sn + yi * c);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFsNT) void rdft_blue_kernel(const T* __restrict__ x, FwdArgs a, BluePlan bp,
+                                                          T* __restrict__ ore, T* __restrict__ oim) {
+  extern __shared__ unsigned char blue_lds[];
+  const int n = bp.n, L = bp.pl.n, K = n / 2 + 1;
+  T* ar = reinterpret_cast<T*>(blue_lds);
+  T* ai = ar + 2 * L;
+  const int64_t t = blockIdx.x;
+  const int64_t ks = a.ntubes;
+  int64_t src = -1;
+  double sc = 1.0;
+  const bool live = tube_source(a, t, src, sc);
+  auto load = [&](int m, double& xr, double& xi) {
+    xr = live ? (double)x[src * n + m] * sc : 0.0;
+    xi = 0.0;
+  };
+  auto store = [&](int k, double re, double im) {
+    ore[(int64_t)k * ks + t] = (T)re;
+    oim[(int64_t)k * ks + t] = (k == 0 || 2 * k == n) ? T(0) : (T)im;
+  };
+  bluestein<T>(bp, ar, ai, load, K, store);
+}
+
+// inverse: the forward transform of the conjugated Hermitian extension,
+// conjugated (only the real part is kept) and scaled by 1/n
+template <typename T>
+__global__ __launch_bounds__(kFsNT) void irdft_blue_kernel(const T* __restrict__ xre, const T* __restrict__ xim,
+                                                           int64_t ntubes, BluePlan bp, T* __restrict__ y) {
+  extern __shared__ unsigned char blue_lds[];
+  const int n = bp.n, L = bp.pl.n, K = n / 2 + 1;
+  T* ar = reinterpret_cast<T*>(blue_lds);
+  T* ai = ar + 2 * L;
+  const int64_t t = blockIdx.x;
+  auto load = [&](int k, double& re, double& im) {
+    if (k < K) {
+      re = (double)xre[(int64_t)k * ntubes + t];
+      im = (k == 0 || 2 * k == n) ? 0.0 : (double)xim[(int64_t)k * ntubes + t];
+    } else {
+      re = (double)xre[(int64_t)(n - k) * ntubes + t];
+      im = -(double)xim[(int64_t)(n - k) * ntubes + t];
+    }
+    im = -im;
+  };
+  const double inv = 1.0 / (double)n;
+  auto store = [&](int e, double re, double) { y[t * n + e] = (T)(re * inv); };
+  bluestein<T>(bp, ar, ai, load, n, store);
+}
+
+// Bluestein plan: L = the smallest length >= 2n - 1 without prime factors
+// above 13; the four L-long sequences must fit in 64 KB of LDS.
+bool blue_plan(int64_t n, int elem_bytes, BluePlan& bp) {
+  if (n < 2 || n > (elem_bytes == 4 ? kBlueMax : kBlueMax / 2)) return false;
+  for (int64_t L = 2 * n - 1;; ++L) {
+    if (4 * L * elem_bytes > 64 * 1024) return false;
+    if (radix_plan(L, bp.pl)) {
+      bp.n = (int)n;
+      return true;
+    }
+  }
+}
+
 // Four-step plan of an even n: N = n/2 = N1 N2 with N2 the largest divisor
 // <= kFsMaxN2 that leaves N1 <= kFsMaxN1, both without prime factors above 13.
 bool four_step_plan(int64_t n, FourStep& fs) {
@@ -1299,6 +1451,10 @@ int fwd_impl(const T* x, int64_t n3, const TubeGather& g, T* re, T* im, hipStrea
                        pl, re, im);
   } else if (FourStep fs; n3 >= kLongMin && four_step_plan(n3, fs)) {
     return fs_forward<T>(x, a, fs, (T*)re, (T*)im, st);
+  } else if (BluePlan bp; n3 >= kLongMin && blue_plan(n3, (int)sizeof(T), bp)) {
+    if (a.ntubes > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+    hipLaunchKernelGGL(rdft_blue_kernel<T>, dim3((unsigned)a.ntubes), dim3(kFsNT), 4 * bp.pl.n * sizeof(T), st, x, a,
+                       bp, re, im);
   } else {
     const int64_t blocks = (a.ntubes + 127) / 128;
     if (n3 <= kDirectTable)
@@ -1324,6 +1480,10 @@ int inv_impl(const T* re, const T* im, int64_t n3, int64_t ntubes, T* y, hipStre
                        ntubes, pl, y);
   } else if (FourStep fs; n3 >= kLongMin && four_step_plan(n3, fs)) {
     return fs_inverse<T>(re, im, ntubes, fs, y, st);
+  } else if (BluePlan bp; n3 >= kLongMin && blue_plan(n3, (int)sizeof(T), bp)) {
+    if (ntubes > 0x7fffffffLL) return fail(TP_EUNSUPPORTED, "too many tubes");
+    hipLaunchKernelGGL(irdft_blue_kernel<T>, dim3((unsigned)ntubes), dim3(kFsNT), 4 * bp.pl.n * sizeof(T), st, re, im,
+                       ntubes, bp, y);
   } else {
     const int64_t blocks = (ntubes + 127) / 128;
     if (n3 <= kDirectTable)

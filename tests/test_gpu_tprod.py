@@ -496,12 +496,14 @@ def test_rtprod_split_contraction_with_device_count(prec, tol):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("n3", [300, 1001, 2000, 4096, 257, 2003])
+@pytest.mark.parametrize("n3", [300, 1001, 2000, 4096, 257, 2003, 499, 1021, 1338])
 def test_long_tube_transforms(n3, dtype):
     """Tubes above 256 without a specialised kernel: the workgroup-per-tube
     mixed-radix transform (300 = 4*3*5*5, 1001 = 7*11*13, 2000 = 4*4*5*5*5,
-    4096), or the direct transform for a prime factor above 13 (257, 2003);
-    both directions and the round trip."""
+    4096), or, for a prime factor above 13 (257, 499, 1021, 1338 = 2*3*223,
+    2003), Bluestein's chirp-z transform (up to 2048 in float32, 1024 in
+    float64) and beyond it the direct transform (2003 in float64); both
+    directions and the round trip."""
     rs = np.random.default_rng(n3)
     X = rs.standard_normal((9, 13, n3)).astype(dtype)
     re, im = api.tfft(dev(X))
